@@ -1,0 +1,523 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check compares the oracle with something other than itself: numpy's
+Philox-4x64-10, schoolbook negacyclic convolution and CRT in Python integers,
+numpy's polynomial evaluation at the roots of unity, numpy's Chebyshev
+routines, closed forms and invariants.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import bigref
+from paper_2604_00546_amd import synth
+
+
+# --------------------------------------------------------------------------
+# randomness
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("ctr,key", [((1, 0, 0, 0), (0, 0)), ((5, 7, 9, 11), (123, 456)),
+                                     ((2**64 - 5, 3, 2**63, 1), (2**64 - 1, 77))])
+def test_philox_matches_numpy(oracle_mod, ctr, key):
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                         counter=np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], dtype=np.uint64))
+    assert list(g.random_raw(4)) == list(oracle_mod.philox(ctr, key))
+
+
+def _np_block(seed, dom, poly, limb, idx):
+    g = np.random.Philox(key=np.array([seed, dom], dtype=np.uint64),
+                         counter=np.array([idx - 1, limb, poly, 0], dtype=np.uint64))
+    return [int(v) for v in g.random_raw(4)]
+
+
+def test_sampler_definitions_from_numpy_philox(oracle_mod):
+    seed, poly, N = 0xABCDEF, 77, 64
+    q = (1 << 59) - 55  # any modulus works for the definition
+    u = oracle_mod.sample_uniform(seed, poly, 3, q, N)
+    t = oracle_mod.sample_ternary(seed, poly, N)
+    e = oracle_mod.sample_gauss(seed, poly, N)
+    cdt = [int(x) for x in oracle_mod.gauss_cdt()]
+    for b in range(1, N // 4):
+        r = _np_block(seed, 2, poly, 0, b)
+        for k in range(4):
+            assert t[4 * b + k] == r[k] % 3 - 1
+        r = _np_block(seed, 3, poly, 0, b)
+        for k in range(4):
+            sign, v = r[k] >> 63, r[k] & ((1 << 63) - 1)
+            mag = next(i for i in range(20) if v < cdt[i])
+            assert e[4 * b + k] == (-mag if sign and mag else mag)
+    for b in range(1, N // 2):
+        r = _np_block(seed, 1, poly, 3, b)
+        assert int(u[2 * b]) == ((r[1] << 64) | r[0]) % q
+        assert int(u[2 * b + 1]) == ((r[3] << 64) | r[2]) % q
+
+
+def test_gauss_cdt_is_the_distribution(oracle_mod):
+    cdt = [int(x) for x in oracle_mod.gauss_cdt()]
+    rho = [math.exp(-x * x / (2 * 3.2 ** 2)) for x in range(20)]
+    S = rho[0] + 2 * sum(rho[1:])
+    cum = 0.0
+    for t in range(19):
+        cum += (rho[0] if t == 0 else 2 * rho[t]) / S
+        assert abs(cdt[t] / 2.0 ** 63 - cum) < 1e-14
+    assert cdt[19] == 1 << 63 and all(a < b for a, b in zip(cdt, cdt[1:]))
+
+
+def test_sampler_statistics(oracle_mod):
+    N = 1 << 16
+    e = oracle_mod.sample_gauss(99, 5, N)
+    assert np.abs(e).max() <= 19
+    assert abs(e.std() - 3.2) < 0.05 and abs(e.mean()) < 0.05
+    t = oracle_mod.sample_ternary(99, 5, N)
+    assert set(np.unique(t)) <= {-1, 0, 1}
+    for v in (-1, 0, 1):
+        assert abs((t == v).mean() - 1 / 3) < 0.01
+
+
+# --------------------------------------------------------------------------
+# parameters: the prime rule
+# --------------------------------------------------------------------------
+def _check_prime_rule(ctx, q0_bits, mid_bits, special_bits):
+    twoN = 2 * ctx.N
+    for m in ctx.moduli:
+        assert m % twoN == 1 and bigref.probable_prime(m)
+    assert len(set(ctx.moduli)) == len(ctx.moduli)
+    assert ctx.q[0].bit_length() == q0_bits
+    assert all(q.bit_length() == mid_bits for q in ctx.q[1:])
+    assert all(p.bit_length() == special_bits for p in ctx.p)
+    # descending, and no eligible prime skipped between 2^b and the last one
+    mids = ctx.q[1:]
+    assert mids == sorted(mids, reverse=True)
+    if mids:
+        c = (1 << mid_bits) - twoN + 1
+        found = []
+        while c >= mids[-1]:
+            if bigref.probable_prime(c) and c not in (ctx.q[0],):
+                found.append(c)
+            c -= twoN
+        assert found == mids
+    c = (1 << q0_bits) - twoN + 1
+    while not bigref.probable_prime(c):
+        c -= twoN
+    assert c == ctx.q[0]
+
+
+def test_prime_rule_small(small_ctx):
+    _check_prime_rule(small_ctx, 50, 40, 60)
+    assert small_ctx.L == 2 and small_ctx.nP == 1 and small_ctx.alpha == 1
+
+
+def test_prime_rule_paper(oracle_mod):
+    ctx = oracle_mod.Context(**oracle_mod.paper_params())
+    _check_prime_rule(ctx, 60, 40, 60)
+    assert ctx.L == 14 and ctx.nP == 5 and ctx.alpha == 5
+    # special primes: the largest 60-bit primes after q_0
+    twoN = 2 * ctx.N
+    c, found = ctx.q[0] - twoN, []
+    while len(found) < 5:
+        if bigref.probable_prime(c):
+            found.append(c)
+        c -= twoN
+    assert found == ctx.p
+
+
+# --------------------------------------------------------------------------
+# polynomial arithmetic
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("logN", [3, 4, 5, 6])
+def test_polymul_is_negacyclic_convolution(oracle_mod, logN):
+    ctx = oracle_mod.Context(logN=logN, q0_bits=30, n_mid=2, mid_bits=28, n_special=1, special_bits=31, dnum=1)
+    rnd = np.random.default_rng(logN)
+    for gi, q in enumerate(ctx.moduli):
+        a = [int(x) for x in rnd.integers(0, q, ctx.N)]
+        b = [int(x) for x in rnd.integers(0, q, ctx.N)]
+        got = ctx.polymul(gi, np.array(a, dtype=np.uint64), np.array(b, dtype=np.uint64))
+        assert [int(x) for x in got] == bigref.negacyclic_schoolbook(a, b, q)
+
+
+def test_automorphism_properties(small_ctx):
+    ctx, q, N = small_ctx, small_ctx.q[1], small_ctx.N
+    rnd = np.random.default_rng(1)
+    a = rnd.integers(0, q, N, dtype=np.uint64)
+    b = rnd.integers(0, q, N, dtype=np.uint64)
+    g, h = ctx.galois(3), ctx.galois(11)
+    # ring homomorphism
+    lhs = ctx.automorphism(1, g, ctx.polymul(1, a, b))
+    rhs = ctx.polymul(1, ctx.automorphism(1, g, a), ctx.automorphism(1, g, b))
+    assert np.array_equal(lhs, rhs)
+    # composition: sigma_g o sigma_h = sigma_{gh}
+    comp = ctx.automorphism(1, g, ctx.automorphism(1, h, a))
+    assert np.array_equal(comp, ctx.automorphism(1, (g * h) % (2 * N), a))
+    # closed form on the monomial X: sigma_g(X) = X^g (with X^N = -1)
+    x = np.zeros(N, dtype=np.uint64)
+    x[1] = 1
+    y = ctx.automorphism(1, g, x)
+    e = g % (2 * N)
+    want = np.zeros(N, dtype=np.uint64)
+    if e < N:
+        want[e] = 1
+    else:
+        want[e - N] = q - 1
+    assert np.array_equal(y, want)
+    # Galois elements: 5^k mod 2N, order N/2
+    assert ctx.galois(0) == 1 and ctx.galois(1) == 5 and ctx.galois(N // 2) == 1
+    assert ctx.galois(-1) == pow(5, N // 2 - 1, 2 * N)
+
+
+def test_modup_is_x_plus_small_multiple_of_digit(deep_ctx):
+    ctx, N = deep_ctx, deep_ctx.N
+    level = ctx.L
+    rnd = np.random.default_rng(2)
+    x = np.stack([rnd.integers(0, q, N, dtype=np.uint64) for q in ctx.q])
+    for t in range(3):
+        out = ctx.modup_digit(level, t, x)
+        digit = list(range(t * ctx.alpha, min(t * ctx.alpha + ctx.alpha, level + 1)))
+        D = math.prod(ctx.q[i] for i in digit)
+        ext = list(range(level + 1)) + [ctx.L + 1 + j for j in range(ctx.nP)]
+        for k in range(0, N, 97):
+            X = bigref.crt([int(x[i][k]) for i in digit], [ctx.q[i] for i in digit])
+            es = set()
+            for pos, gm in enumerate(ext):
+                r = ctx.moduli[gm]
+                y = int(out[pos][k])
+                if gm in digit:
+                    assert y == int(x[gm][k])
+                    continue
+                # y = X + e D (mod r) for one small e shared by every target modulus
+                e = next(e for e in range(len(digit)) if (X + e * D) % r == y)
+                es.add(e)
+            assert len(es) == 1
+
+
+def test_moddown_divides_by_P(deep_ctx):
+    ctx, N = deep_ctx, deep_ctx.N
+    level = 9
+    ext = list(range(level + 1)) + [ctx.L + 1 + j for j in range(ctx.nP)]
+    P = math.prod(ctx.p)
+    rnd = np.random.default_rng(3)
+    w = [int(v) for v in rnd.integers(0, 2**62, N)]
+    v = [int(s) for s in rnd.integers(0, 2**40, N)]
+    u = np.zeros((len(ext), N), dtype=np.uint64)
+    for pos, gm in enumerate(ext):
+        r = ctx.moduli[gm]
+        u[pos] = [(P * w[k] + v[k]) % r for k in range(N)]
+    out = ctx.moddown(level, u)
+    for k in range(N):
+        # (P w + v - v - e P) / P = w - e, 0 <= e < nP, the same e on every limb
+        diffs = {(w[k] - int(out[i][k])) % ctx.q[i] for i in range(level + 1)}
+        assert len(diffs) == 1 and diffs.pop() < ctx.nP
+
+
+# --------------------------------------------------------------------------
+# encoding / decoding
+# --------------------------------------------------------------------------
+def _eval_at_slots(ctx, coeffs, n):
+    """m(zeta^(5^j)) for j < n, by numpy's polynomial evaluation."""
+    N = ctx.N
+    zeta = np.exp(1j * np.pi / N)
+    pts = np.array([zeta ** pow(5, j, 2 * N) for j in range(n)])
+    return np.polynomial.polynomial.polyval(pts, coeffs)
+
+
+def test_encode_constant_is_constant_polynomial(small_ctx):
+    ctx = small_ctx
+    pt = ctx.encode(np.full(ctx.N // 2, 0.75), ctx.L, 2.0 ** 40)
+    m = ctx.lift(pt)
+    assert m[0] == round(0.75 * 2 ** 40) and np.all(m[1:] == 0)
+
+
+def test_encode_matches_canonical_embedding(small_ctx):
+    ctx = small_ctx
+    rnd = np.random.default_rng(4)
+    z = rnd.uniform(-1, 1, ctx.N // 2)
+    pt = ctx.encode(z, ctx.L, 2.0 ** 40)
+    m = ctx.lift(pt)
+    vals = _eval_at_slots(ctx, m / 2.0 ** 40, 64)
+    assert np.max(np.abs(vals.real - z[:64])) < 1e-9 and np.max(np.abs(vals.imag)) < 1e-9
+    # decode (both methods) recovers the slots
+    assert np.max(np.abs(ctx.decode(pt) - z)) < 1e-9
+    assert np.max(np.abs(ctx.decode(pt, "direct") - z)) < 1e-9
+
+
+def test_slot_order_rotation_by_sigma5(small_ctx):
+    ctx = small_ctx
+    rnd = np.random.default_rng(5)
+    z = rnd.uniform(-1, 1, ctx.N // 2)
+    pt = ctx.encode(z, 0, 2.0 ** 30)
+    rot = ctx.pt_import(np.stack([ctx.automorphism(0, ctx.galois(3), pt.coeffs()[0])]), 0, 2.0 ** 30)
+    assert np.max(np.abs(ctx.decode(rot) - np.roll(z, -3))) < 1e-6
+
+
+def test_encode_fft_within_one_of_direct(small_ctx):
+    ctx = small_ctx
+    rnd = np.random.default_rng(6)
+    z = rnd.standard_normal(ctx.N // 2) / 20
+    a = ctx.lift(ctx.encode(z, ctx.L, 2.0 ** 40, "direct"))
+    b = ctx.lift(ctx.encode(z, ctx.L, 2.0 ** 40, "fft"))
+    assert np.max(np.abs(a - b)) <= 1
+
+
+def test_lift_is_exact_crt(deep_ctx):
+    ctx = deep_ctx
+    rnd = np.random.default_rng(7)
+    vals = [int(v) for v in rnd.integers(-2**62, 2**62, ctx.N)]
+    m = np.stack([[v % q for v in vals] for q in ctx.q]).astype(np.uint64)
+    got = ctx.lift(ctx.pt_import(m, ctx.L, 1.0))
+    assert all(float(v) == g for v, g in zip(vals, got))
+    Q = math.prod(ctx.q)
+    res = [int(r) for r in m[:, 5]]
+    assert bigref.centered(bigref.crt(res, ctx.q), Q) == vals[5]
+
+
+# --------------------------------------------------------------------------
+# encryption, rotation, rescale, relinearisation
+# --------------------------------------------------------------------------
+ROTS_C1 = list(range(1, 8)) + [8 * j for j in range(1, 16)]
+
+
+@pytest.fixture(scope="module")
+def small_keys(small_ctx):
+    return small_ctx.keygen(synth.int_seed(1, synth.SUB_KEYS), ROTS_C1)
+
+
+def test_pk_and_secret(small_ctx, small_keys):
+    ctx, K = small_ctx, small_keys
+    s = K.secret()
+    assert set(np.unique(s)) <= {-1, 0, 1}
+    pk = K.pk()
+    # b + a s = e small
+    for i, q in enumerate(ctx.q):
+        sres = np.array([v % q for v in s], dtype=np.uint64)
+        e = (pk[0][i].astype(object) + ctx.polymul(i, pk[1][i], sres).astype(object)) % q
+        e = np.array([bigref.centered(int(v), q) for v in e])
+        assert np.abs(e).max() <= 19
+
+
+def test_ksk_decrypts_to_gadget(small_ctx, small_keys):
+    ctx, K = small_ctx, small_keys
+    g = ctx.galois(3)
+    ksk = K.ksk(g)
+    s = K.secret()
+    P = math.prod(ctx.p)
+    for t in range(ctx.dnum):
+        for gm, r in enumerate(ctx.moduli):
+            sres = np.array([v % r for v in s], dtype=np.uint64)
+            v = (ksk[t][0][gm].astype(object) + ctx.polymul(gm, ksk[t][1][gm], sres).astype(object)) % r
+            in_digit = gm <= ctx.L and t * ctx.alpha <= gm < (t + 1) * ctx.alpha
+            want = ctx.automorphism(gm, g, sres).astype(object) * (P % r) % r if in_digit else 0
+            e = (v - want) % r
+            assert max(abs(bigref.centered(int(x), r)) for x in e) <= 19
+
+
+def test_encrypt_decrypt_noise_bound(small_ctx, small_keys):
+    ctx = small_ctx
+    z = np.random.default_rng(8).uniform(-1, 1, ctx.N // 2)
+    pt = ctx.encode(z, ctx.L, 2.0 ** 40)
+    ct = ctx.encrypt(small_keys, pt, 1234)
+    d = ctx.decrypt(small_keys, ct)
+    noise = ctx.lift(d) - ctx.lift(pt)
+    assert np.abs(noise).max() < 20 * math.sqrt(ctx.N) * 3.2
+    # fresh noise: ~2^-26.6 per slot at N = 2^12, max over 2048 slots ~2^-24.5
+    assert np.max(np.abs(ctx.decode(d) - z)) < 2 ** -22
+
+
+def test_rotation_identity(small_ctx, small_keys):
+    ctx = small_ctx
+    z = np.random.default_rng(9).uniform(-1, 1, ctx.N // 2)
+    ct = ctx.encrypt(small_keys, ctx.encode(z, ctx.L, 2.0 ** 40), 55)
+    outs = ctx.rotate_hoisted(small_keys, ct, ROTS_C1)
+    for k, o in zip(ROTS_C1, outs):
+        assert np.max(np.abs(ctx.decrypt_decode(small_keys, o) - np.roll(z, -k))) < 2 ** -22
+    # Rot_a o Rot_b = Rot_{a+b} (after decryption)
+    ab = ctx.rotate_hoisted(small_keys, outs[2], [8])[0]
+    assert np.max(np.abs(ctx.decrypt_decode(small_keys, ab) - np.roll(z, -11))) < 2 ** -22
+
+
+def test_missing_key_is_an_error(small_ctx, small_keys):
+    ct = small_ctx.encrypt(small_keys, small_ctx.encode(np.zeros(4), 2, 2.0 ** 40), 1)
+    with pytest.raises(Exception):
+        small_ctx.rotate_hoisted(small_keys, ct, [9])
+
+
+def test_rescale_is_rounded_division(deep_ctx, oracle_mod):
+    ctx = deep_ctx
+    l = 6
+    rnd = np.random.default_rng(10)
+    c = np.stack([np.stack([rnd.integers(0, q, ctx.N, dtype=np.uint64) for q in ctx.q[: l + 1]]) for _ in range(2)])
+    x = ctx.ct_import(c, l, 2.0 ** 80)
+    y = ctx.rescale(x)
+    assert y.level == l - 1 and y.scale == 2.0 ** 80 / ctx.q[l]
+    Q = math.prod(ctx.q[: l + 1])
+    Q1 = math.prod(ctx.q[:l])
+    yc = y.coeffs()
+    for p in range(2):
+        for k in range(0, ctx.N, 131):
+            X = bigref.centered(bigref.crt([int(c[p][i][k]) for i in range(l + 1)], ctx.q[: l + 1]), Q)
+            want = (2 * X + ctx.q[l]) // (2 * ctx.q[l])  # round(X / q_l), q_l odd: no ties
+            got = bigref.crt([int(yc[p][i][k]) for i in range(l)], ctx.q[:l])
+            assert got == want % Q1
+
+
+@pytest.fixture(scope="module")
+def deep_keys(deep_ctx):
+    return deep_ctx.keygen(synth.int_seed(2, synth.SUB_KEYS), [1, 2, 3])
+
+
+def test_mul_relin_rescale(deep_ctx, deep_keys):
+    ctx = deep_ctx
+    rnd = np.random.default_rng(11)
+    x = rnd.uniform(-1, 1, ctx.N // 2)
+    y = rnd.uniform(-1, 1, ctx.N // 2)
+    a = ctx.encrypt(deep_keys, ctx.encode(x, ctx.L, 2.0 ** 40), 1)
+    b = ctx.encrypt(deep_keys, ctx.encode(y, ctx.L, 2.0 ** 40), 2)
+    z = ctx.mul_relin_rescale(deep_keys, a, b)
+    assert z.level == ctx.L - 1 and z.scale == 2.0 ** 80 / ctx.q[ctx.L]
+    assert np.max(np.abs(ctx.decrypt_decode(deep_keys, z) - x * y)) < 2 ** -22
+
+
+def test_plain_mult_and_integer_ops(deep_ctx, deep_keys):
+    ctx = deep_ctx
+    rnd = np.random.default_rng(12)
+    x = rnd.uniform(-1, 1, ctx.N // 2)
+    w = rnd.uniform(-1, 1, ctx.N // 2)
+    a = ctx.encrypt(deep_keys, ctx.encode(x, ctx.L, 2.0 ** 40), 3)
+    p = ctx.mul_plain(a, ctx.encode(w, ctx.L, 2.0 ** 40))
+    assert np.max(np.abs(ctx.decrypt_decode(deep_keys, ctx.rescale(p)) - x * w)) < 2 ** -22
+    m = ctx.mul_int(a, -3)
+    m.scale = a.scale
+    assert np.max(np.abs(ctx.decrypt_decode(deep_keys, m) + 3 * x)) < 2 ** -20
+    c = ctx.add_const(a, 0.25)
+    assert np.max(np.abs(ctx.decrypt_decode(deep_keys, c) - (x + 0.25))) < 2 ** -22
+
+
+# --------------------------------------------------------------------------
+# the BSGS matrix-vector product
+# --------------------------------------------------------------------------
+def _layout_identity(ctx, wl, ell, B, n1):
+    """Eq. diag / bsgs2 with the pre-rotated slot vectors, in FP64 numpy."""
+    h = ctx.N // 2
+    qv = synth.replicate_query(wl.query, h)
+    n2 = -(-ell // n1)
+    out = np.zeros(h)
+    for j in range(n2):
+        Pj = np.zeros(h)
+        for i in range(min(n1, ell - j * n1)):
+            d = ctx.db_slots(wl.templates, wl.K, ell, B, n1, 0, j * n1 + i)
+            Pj += np.roll(qv, -i) * d
+        out += np.roll(Pj, -j * n1)
+    return out
+
+
+def test_layout_and_prerotation_identity(small_ctx):
+    wl = synth.make_workload(1, 64, 128)
+    for B, n1 in [(16, 8), (1, 8), (16, 128), (3, 5)]:
+        out = _layout_identity(small_ctx, wl, 128, B, n1)
+        want = np.zeros(small_ctx.N // 2)
+        want[:64] = wl.exact_scores()
+        assert np.max(np.abs(out - want)) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def config1(small_ctx, small_keys):
+    ctx = small_ctx
+    wl = synth.make_workload(1, 64, 128)
+    qv = synth.replicate_query(wl.query, ctx.N // 2)
+    ct = ctx.encrypt(small_keys, ctx.encode(qv, ctx.L, 2.0 ** 40), synth.int_seed(1, synth.SUB_ENC))
+    baby = [ct] + ctx.rotate_hoisted(small_keys, ct, list(range(1, 8)))
+    db = ctx.db_build(wl.templates, wl.K, 128, 16, 8, ctx.L, 2.0 ** 40)
+    S = ctx.bsgs_matvec(small_keys, baby, db, 0)
+    return wl, ct, baby, db, S
+
+
+def test_matvec_scores_within_2m20(small_ctx, small_keys, config1):
+    wl, ct, baby, db, S = config1
+    dec = small_ctx.decrypt_decode(small_keys, S)
+    assert S.level == small_ctx.L - 1
+    assert np.max(np.abs(dec[:64] - wl.exact_scores())) <= 2 ** -20
+    assert np.max(np.abs(dec[64:])) <= 2 ** -20
+
+
+def test_matvec_equals_diagonal_method_and_B1(small_ctx, config1):
+    """BSGS (n1 = 8) vs the plain diagonal method (n1 = ell, n2 = 1), and the
+    paper's packing B = numSlots/ell vs one block per plaintext."""
+    ctx = small_ctx
+    wl, ct, baby, db, S = config1
+    keys = ctx.keygen(synth.int_seed(1, synth.SUB_KEYS), list(range(1, 128)))
+    ct2 = ctx.encrypt(keys, ctx.encode(synth.replicate_query(wl.query, ctx.N // 2), ctx.L, 2.0 ** 40), 9)
+    baby_all = [ct2] + ctx.rotate_hoisted(keys, ct2, list(range(1, 128)))
+    db_diag = ctx.db_build(wl.templates, wl.K, 128, 16, 128, ctx.L, 2.0 ** 40)
+    s_diag = ctx.decrypt_decode(keys, ctx.bsgs_matvec(keys, baby_all, db_diag, 0))
+    db_b1 = ctx.db_build(wl.templates, wl.K, 128, 1, 8, ctx.L, 2.0 ** 40)
+    assert db_b1.G == 1
+    s_b1 = ctx.decrypt_decode(keys, ctx.bsgs_matvec(keys, baby_all[:8], db_b1, 0))
+    want = wl.exact_scores()
+    assert np.max(np.abs(s_diag[:64] - want)) <= 2 ** -20
+    assert np.max(np.abs(s_b1[:64] - want)) <= 2 ** -20
+
+
+# --------------------------------------------------------------------------
+# Chebyshev threshold
+# --------------------------------------------------------------------------
+def _step(delta):
+    return lambda x: (np.asarray(x) >= delta).astype(float)
+
+
+def test_cheb_coefficients_match_numpy_interpolation(oracle_mod):
+    for n, delta in [(63, 0.3), (13, 0.0), (27, -0.2)]:
+        c = oracle_mod.cheb_step_coeffs(n, delta)
+        ref = np.polynomial.chebyshev.chebinterpolate(_step(delta), n)
+        assert np.max(np.abs(c - ref)) < 1e-13
+        nodes = np.cos(np.pi * (np.arange(n + 1) + 0.5) / (n + 1))
+        assert np.max(np.abs(np.polynomial.chebyshev.chebval(nodes, c) - _step(delta)(nodes))) < 1e-12
+
+
+def test_cheb_odd_step_has_no_even_terms(oracle_mod):
+    """The step at 0 is 1/2 + an odd function, so c_k = 0 for even k > 0."""
+    c = oracle_mod.cheb_step_coeffs(63, 0.0)
+    assert abs(c[0] - 0.5) < 1e-14 and np.max(np.abs(c[2::2])) < 1e-14
+
+
+def test_clenshaw_matches_numpy(oracle_mod):
+    c = oracle_mod.cheb_step_coeffs(63, 0.3)
+    for x in np.linspace(-1, 1, 41):
+        assert abs(oracle_mod.cheb_clenshaw(c, x) - np.polynomial.chebyshev.chebval(x, c)) < 1e-12
+    # T_k(cos t) = cos(k t)
+    for k in (1, 5, 17):
+        e = np.zeros(k + 1)
+        e[k] = 1
+        assert abs(oracle_mod.cheb_clenshaw(e, math.cos(0.3)) - math.cos(0.3 * k)) < 1e-13
+
+
+def test_chebyshev_division_identity():
+    """p = q T_M + r with q_0 = c_M, q_i = 2 c_{M+i}, r_0 = c_0, r_k = c_k - c_{2M-k}."""
+    C = np.polynomial.chebyshev
+    rnd = np.random.default_rng(13)
+    for m, M in [(64, 32), (14, 8), (9, 8), (3, 2)]:
+        c = rnd.standard_normal(m)
+        q = np.array([c[M]] + [2 * c[M + i] for i in range(1, m - M)])
+        r = np.array([c[0]] + [c[k] - (c[2 * M - k] if 2 * M - k < m else 0.0) for k in range(1, M)])
+        TM = np.zeros(M + 1)
+        TM[M] = 1
+        rec = C.chebadd(C.chebmul(q, TM), r)
+        assert np.max(np.abs(rec[:m] - c)) < 1e-12 and np.max(np.abs(rec[m:]), initial=0) < 1e-12
+    # tiny closed form: T_3 = (2 T_1) T_2 - T_1
+    assert np.allclose(C.chebsub(C.chebmul([0, 2], [0, 0, 1]), [0, 1]), [0, 0, 0, 1])
+
+
+def test_chebyshev_mult_counts(oracle_mod):
+    assert oracle_mod.cheb_count_mults(63, 2) == 36
+    assert oracle_mod.cheb_count_mults(63, 8) == 16
+
+
+def test_homomorphic_chebyshev_within_2m12(deep_ctx, deep_keys, oracle_mod):
+    ctx = deep_ctx
+    rnd = np.random.default_rng(14)
+    x = np.concatenate([rnd.uniform(-1, 1, ctx.N // 2 - 6), [0.29, 0.31, -1.0, 1.0, 0.0, 0.3]])
+    ct = ctx.encrypt(deep_keys, ctx.encode(x, ctx.L - 1, 2.0 ** 40), 21)
+    c = oracle_mod.cheb_step_coeffs(63, 0.3)
+    for d1 in (2, 8):
+        y = ctx.chebyshev(deep_keys, ct, c, d1)
+        want = np.polynomial.chebyshev.chebval(x, c)
+        assert np.max(np.abs(ctx.decrypt_decode(deep_keys, y) - want)) <= 2 ** -12
+    assert y.level >= 0
