@@ -1,0 +1,208 @@
+/*
+ * fr.h -- C ABI of the MI355X (gfx950) library for encrypted face-template
+ * search: the RNS-CKKS baby-step giant-step diagonal matrix-vector product of
+ * one encrypted query against a plaintext template database, followed by the
+ * homomorphic Chebyshev threshold (arXiv 2604.00546).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: FR_OK (0) or a negative fr_status; fr_last_error() then
+ *   holds a thread-local message.  A failing call leaves its outputs' level
+ *   and scale untouched and never frees caller memory.
+ * - Ring: R = Z[X]/(X^N + 1), N = 2^log_n.  Ciphertext modulus
+ *   Q_l = q_0 ... q_l, special modulus P = p_0 ... p_{nP-1} (§3.2).
+ * - fr_ct / fr_pt describe CALLER-OWNED device memory of uint64 words:
+ *   a ciphertext at level l uses [2][l+1][N] words (c0 limbs, then c1 limbs),
+ *   a plaintext [l+1][N].  `cap` is the largest level the buffer can hold
+ *   (buffer size 2*(cap+1)*N resp. (cap+1)*N words); an output whose level
+ *   would exceed `cap` is FR_EINVAL.  The words hold residues in the
+ *   library's evaluation (NTT) form and order, which is private: use
+ *   fr_ct_export / fr_pt_export for canonical coefficients.
+ * - Keys and databases are LIBRARY-OWNED device objects (opaque handles),
+ *   created by fr_keygen / fr_db_load / fr_db_import and freed by the
+ *   matching destroy call.
+ * - Every device call is asynchronous on the context's stream (set with
+ *   fr_ctx_set_stream; default: the null stream).  Calls that return data
+ *   to the host (exports, fr_decode) synchronise that stream.  Inputs are
+ *   never modified; an output may not alias an input unless stated.
+ * - Host buffers for import/export hold COEFFICIENT form, natural order,
+ *   canonical residues in [0, q_i), limb-major.
+ */
+#ifndef FR_H
+#define FR_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fr_status {
+    FR_OK = 0,
+    FR_EINVAL = -1, /* bad argument, shape or capacity */
+    FR_ENOMEM = -2, /* device allocation failed */
+    FR_ELEVEL = -3, /* level or scale mismatch, or no level left */
+    FR_ENOKEY = -4, /* a needed rotation / relinearisation key is absent */
+    FR_EHIP = -5,   /* a HIP runtime call failed */
+    FR_ERANGE = -6  /* a value does not fit the encoding (|coefficient| >= 2^62) */
+} fr_status;
+
+typedef struct fr_ctx fr_ctx;
+typedef struct fr_keys fr_keys;
+typedef struct fr_db fr_db;
+
+/* Parameter set (§3.2; primes by the rule documented in the design notes:
+ * q_0 = the largest q0_bits-bit prime = 1 mod 2N, q_1..q_L the next
+ * largest mid_bits-bit primes in descending order, p_j the largest
+ * special_bits-bit primes not already used). */
+typedef struct fr_params {
+    int32_t log_n;        /* 10 .. 16 */
+    int32_t q0_bits;      /* 30 .. 61 */
+    int32_t n_mid;        /* L: number of primes after q_0 */
+    int32_t mid_bits;     /* 30 .. 61 */
+    int32_t n_special;    /* number of special primes */
+    int32_t special_bits; /* 30 .. 61 */
+    int32_t dnum;         /* key-switching digits; alpha = ceil((L+1)/dnum) */
+} fr_params;
+
+typedef struct fr_ct {
+    uint64_t *data; /* device, [2][level+1][N] */
+    int32_t level;
+    int32_t cap;
+    double scale;
+} fr_ct;
+
+typedef struct fr_pt {
+    uint64_t *data; /* device, [level+1][N] */
+    int32_t level;
+    int32_t cap;
+    double scale;
+} fr_pt;
+
+const char *fr_last_error(void);
+
+/* ---- context (setup of §3.2: primes, roots, RNS constants) ---- */
+int fr_ctx_create(const fr_params *params, fr_ctx **out);
+void fr_ctx_destroy(fr_ctx *ctx);
+/* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) */
+int fr_ctx_set_stream(fr_ctx *ctx, void *stream);
+int fr_ctx_sync(fr_ctx *ctx);
+/* N, L, nP, alpha, dnum */
+int fr_ctx_dims(const fr_ctx *ctx, int32_t *n, int32_t *L, int32_t *n_special, int32_t *alpha,
+                int32_t *dnum);
+/* modulus by global index: 0..L = q_i, L+1 .. L+nP = p_j */
+uint64_t fr_ctx_modulus(const fr_ctx *ctx, int32_t gidx);
+
+/* ---- keys (§3.2 encryption; rotation keys of §4.2.3 / §5.3.2) ----
+ * Secret key s uniform ternary, public key (b, a) = (-a s + e, a) mod Q_L,
+ * one hybrid key-switching key per distinct Galois element 5^rot mod 2N of
+ * `rots` (rotation 0 needs none) and one for s^2 (relinearisation).  All
+ * randomness comes from Philox-4x64-10 keyed by `seed`. */
+int fr_keygen(fr_ctx *ctx, uint64_t seed, const int32_t *rots, int32_t nrot, fr_keys **out);
+void fr_keys_destroy(fr_keys *keys);
+/* Export key material as canonical coefficients (test hook; synchronises).
+ * what = 0: secret s as N int64 coefficients in {-1, 0, 1} (host_out is
+ *           read as int64_t[N]);
+ * what = 1: public key (b, a), [2][L+1][N];
+ * what = 2: key-switching key for key id kid (Galois element, 0 = s^2),
+ *           [dnum][2][L+1+nP][N] indexed by global modulus.
+ * FR_ENOKEY if kid has no key. */
+int fr_keys_export(fr_ctx *ctx, const fr_keys *keys, int32_t what, uint64_t kid, uint64_t *host_out);
+
+/* ---- encode / encrypt / decrypt / decode (§3.2) ---- */
+/* Encode n <= N/2 real slot values (host doubles, zero padded) at `level`
+ * with `scale`: m_k = round(scale * (2/N) * sum_j z_j cos(pi 5^j k / N)),
+ * computed by an FP64 FFT on the device. */
+int fr_encode(fr_ctx *ctx, const double *z_host, int32_t n, int32_t level, double scale, fr_pt *out);
+/* Same for a device slot vector (double, n entries). */
+int fr_encode_device(fr_ctx *ctx, const double *z_dev, int32_t n, int32_t level, double scale,
+                     fr_pt *out);
+int fr_pt_import(fr_ctx *ctx, const uint64_t *coeff_host, int32_t level, double scale, fr_pt *out);
+int fr_pt_export(fr_ctx *ctx, const fr_pt *pt, uint64_t *coeff_host);
+/* ct = (v b + e0 + m, v a + e1) mod Q_l, v ternary, e0/e1 Gaussian from `seed`. */
+int fr_encrypt(fr_ctx *ctx, const fr_keys *keys, const fr_pt *pt, uint64_t seed, fr_ct *out);
+/* m = c0 + c1 s mod Q_l */
+int fr_decrypt(fr_ctx *ctx, const fr_keys *keys, const fr_ct *ct, fr_pt *out);
+/* Centered CRT lift and forward canonical embedding: n <= N/2 slot values
+ * z_j = Re m(zeta^(5^j)) / scale.  Requires |m_k| < 2^62 (FR_ERANGE). */
+int fr_decode(fr_ctx *ctx, const fr_pt *pt, double *z_host, int32_t n);
+int fr_ct_import(fr_ctx *ctx, const uint64_t *coeff_host, int32_t level, double scale, fr_ct *out);
+int fr_ct_export(fr_ctx *ctx, const fr_ct *ct, uint64_t *coeff_host);
+
+/* ---- homomorphic operations ---- */
+/* Single-hoisted rotations (§3.4.2): outs[i] = Rot_{rots[i]}(in), a left
+ * slot rotation, for every i, sharing one ModUp of c1.  Each Rot is
+ * (sigma_g(c0) + ModDown(U0), ModDown(U1)) with U = sum_t sigma_g(ModUp_t(c1))
+ * * ksk_{g,t}.  outs must not alias in.  FR_ENOKEY if a key is absent. */
+int fr_rotate_hoisted(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const int32_t *rots,
+                      int32_t nrot, fr_ct *outs);
+/* Rescale (§3.2): drop q_l with centered rounding; scale /= q_l. */
+int fr_rescale(fr_ctx *ctx, const fr_ct *in, fr_ct *out);
+int fr_add(fr_ctx *ctx, const fr_ct *a, const fr_ct *b, fr_ct *out);
+int fr_sub(fr_ctx *ctx, const fr_ct *a, const fr_ct *b, fr_ct *out);
+/* plaintext x ciphertext product (no rescale); scale multiplies */
+int fr_mul_plain(fr_ctx *ctx, const fr_ct *a, const fr_pt *p, fr_ct *out);
+/* ciphertext x ciphertext: tensor, relinearise with the s^2 key, rescale */
+int fr_mul_relin_rescale(fr_ctx *ctx, const fr_keys *keys, const fr_ct *a, const fr_ct *b, fr_ct *out);
+/* multiply by a signed integer (scale *= k) / add round(c * scale) / drop limbs */
+int fr_mul_int(fr_ctx *ctx, const fr_ct *a, int64_t k, fr_ct *out);
+int fr_add_const(fr_ctx *ctx, const fr_ct *a, double c, fr_ct *out);
+int fr_drop_to(fr_ctx *ctx, const fr_ct *a, int32_t level, fr_ct *out);
+
+/* ---- database of pre-rotated plaintext diagonals (§3.3.1 packing,
+ * Eq. diag, Eq. prerotation of §5.3.1 applied in the slot domain by the
+ * enroller as in §5.3.3) ----
+ * T_host: K rows of ell float32 values (unit-norm templates).  B blocks of
+ * ell x ell per plaintext (B * ell <= N/2), G = ceil(K / (B ell)) groups of ell
+ * plaintexts, n1 baby steps.  Diagonal d = j n1 + i of group g is the slot
+ * vector diag_d[b ell + r] = T[(g B + b) ell + r][(r + d) mod ell], rotated
+ * left by -j n1 over all N/2 slots, encoded at `level` with `scale`, kept
+ * resident in HBM. */
+int fr_db_load(fr_ctx *ctx, const float *T_host, int32_t K, int32_t ell, int32_t B, int32_t n1,
+               int32_t level, double scale, fr_db **out);
+/* The same from integer plaintexts [G][ell][level+1][N] (coefficient form). */
+int fr_db_import(fr_ctx *ctx, const uint64_t *coeff_host, int32_t G, int32_t ell, int32_t B,
+                 int32_t n1, int32_t level, double scale, fr_db **out);
+int fr_db_export(fr_ctx *ctx, const fr_db *db, int32_t group, int32_t diag, uint64_t *coeff_host);
+int fr_db_groups(const fr_db *db);
+void fr_db_destroy(fr_db *db);
+
+/* ---- the hot path (Eq. bsgs2 of §3.4, Alg. gpu-bsgs-index of §5.4) ----
+ * baby[i] = Rot_i(query), i < n1 (baby[0] = query), all at one level and
+ * scale.  For group g:
+ *   P_j = Rescale( sum_{i < min(n1, ell - j n1)} baby[i] * diag'_{g, j n1 + i} )
+ *   out = P_0 + sum_{j >= 1} Rot_{j n1}(P_j),
+ * the giant rotations sharing one ModDown.  Slot s of out is the score of
+ * template g B ell + s. */
+int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t n1,
+                        const fr_db *db, int32_t group, fr_ct *out);
+
+/* ---- Chebyshev threshold (§5.1.4, Eq. cheb-sign) ----
+ * out = p(in) slot-wise, p = sum_{k <= degree} c[k] T_k (c[0] the full T_0
+ * coefficient), evaluated by recursive Chebyshev-basis division over
+ * baby-step powers T_1..T_{d1-1} and giant powers T_{d1 2^j}, with
+ * canonical per-level scales (reading documented in the design notes). */
+int fr_chebyshev_eval(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const double *c,
+                      int32_t degree, int32_t d1, fr_ct *out);
+
+/* ---- host-only planning helpers (no device work) ---- */
+/* degree-n interpolant of the 0/1 step at delta through the n+1 first-kind
+ * Chebyshev nodes ("DCT-based interpolation" of §5.1.4); c[0] full T_0. */
+int fr_cheb_step_coeffs(int32_t degree, double delta, double *c);
+/* Paterson-Stockmeyer split of §5.1.4: minimise d1 + d2 subject to
+ * d1 2^(d2-1) >= degree, d1 >= 2, ties to the smaller d1. */
+int fr_cheb_ps_params(int32_t degree, int32_t *d1, int32_t *d2);
+/* Output level of fr_chebyshev_eval for an input at in_level (-1 if the
+ * levels run out); number of relinearised products it performs. */
+int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1);
+int fr_cheb_mult_count(int32_t degree, int32_t d1);
+/* Eq. stream-pool of §5.1.2: S = min(floor(units/4), floor(0.2 F / (40 C)), 32), S >= 2. */
+int fr_stream_pool_size(int32_t compute_units, double free_bytes, double ct_bytes);
+/* Rotation-key index set of §4.2.3: S_baby = {1..n1-1}, S_giant = {j n1 : 1 <= j < n2},
+ * n2 = ceil(ell / n1).  Writes up to cap indices, returns the count. */
+int fr_bsgs_rotation_set(int32_t ell, int32_t n1, int32_t *out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

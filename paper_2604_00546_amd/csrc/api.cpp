@@ -1,0 +1,1423 @@
+// api.cpp -- the C ABI of include/fr.h: context tables, keys, encoding,
+// encryption, and the operation sequences of the hot path, each a short
+// chain of kernel launches on the context's stream.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+
+#include "fr_core.h"
+
+using namespace frh;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+int fr_fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+extern "C" const char *fr_last_error(void) { return g_err; }
+
+#define CHECK(cond, code, ...) \
+    do {                       \
+        if (!(cond)) return fr_fail(code, __VA_ARGS__); \
+    } while (0)
+
+// stream ids of the key material and of an encryption (one Philox stream
+// per polynomial: counter (index, limb, poly, 0), key (seed, domain))
+static const u64 POLY_SECRET = 1, POLY_PK_A = 2, POLY_PK_E = 3;
+static const u64 POLY_ENC_V = 0x2000001, POLY_ENC_E0 = 0x2000002, POLY_ENC_E1 = 0x2000003;
+static u64 poly_ksk(u64 kid, int t) { return 0x1000000ull + kid * 16ull + (u64)t; }
+static const int KIND_TERNARY = 2, KIND_GAUSS = 3;
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+void *Arena::get(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (auto &ch : chunks) {
+        if (ch.size - ch.used >= bytes) {
+            void *p = ch.base + ch.used;
+            ch.used += bytes;
+            return p;
+        }
+    }
+    size_t sz = std::max(bytes, (size_t)256 << 20);
+    char *b = nullptr;
+    if (hipMalloc(&b, sz) != hipSuccess) return nullptr;
+    chunks.push_back({b, sz, bytes});
+    return b;
+}
+void Arena::reset() {
+    size_t used = 0;
+    for (auto &ch : chunks) {
+        used += ch.used;
+        ch.used = 0;
+    }
+    peak = std::max(peak, used);
+}
+void Arena::release() {
+    for (auto &ch : chunks) (void)hipFree(ch.base);
+    chunks.clear();
+}
+
+namespace {
+
+// RAII scope: everything taken from the arena inside is given back at exit
+// (stream order makes reuse by later launches safe).
+struct Scope {
+    Arena &a;
+    std::vector<size_t> used;
+    explicit Scope(Arena &ar) : a(ar) {
+        for (auto &ch : a.chunks) used.push_back(ch.used);
+    }
+    ~Scope() {
+        size_t tot = 0;
+        for (auto &ch : a.chunks) tot += ch.used;
+        a.peak = std::max(a.peak, tot);
+        for (size_t i = 0; i < a.chunks.size(); ++i) a.chunks[i].used = i < used.size() ? used[i] : 0;
+    }
+};
+
+inline LimbMap qmap() { return LimbMap{0, INT_MAX, 0, INT_MAX, 0}; }
+inline LimbMap allmap(const fr_ctx *c) { return LimbMap{0, INT_MAX, 0, c->nmod, 0}; }
+inline LimbMap pmap(const fr_ctx *c) { return LimbMap{0, INT_MAX, 0, 0, c->L + 1}; }
+inline LimbMap single(int mod) { return LimbMap{0, INT_MAX, 0, 0, mod}; }
+
+// device scratch from the arena; a failed allocation stops the process on
+// the host rather than letting a kernel run on a null pointer
+u64 *scratch(fr_ctx *c, size_t words) {
+    void *p = c->arena.get(std::max<size_t>(words, 1) * 8);
+    if (!p) {
+        std::fprintf(stderr, "libfrhip: device scratch allocation of %zu bytes failed\n", words * 8);
+        std::abort();
+    }
+    return (u64 *)p;
+}
+
+// internal ciphertext view
+struct Ct {
+    u64 *d;
+    int level;
+    double scale;
+    u64 *c0() const { return d; }
+    u64 *c1(const fr_ctx *c) const { return d + (size_t)(level + 1) * c->N; }
+};
+
+int check_ct(const fr_ctx *c, const fr_ct *x, const char *what) {
+    CHECK(x && x->data, FR_EINVAL, "%s: null ciphertext", what);
+    CHECK(x->level >= 0 && x->level <= c->L && x->level <= x->cap, FR_EINVAL, "%s: bad level %d (cap %d)", what,
+          x->level, x->cap);
+    return FR_OK;
+}
+int check_out(const fr_ctx *c, const fr_ct *x, int level, const char *what) {
+    CHECK(x && x->data, FR_EINVAL, "%s: null output", what);
+    CHECK(level >= 0 && level <= x->cap && level <= c->L, FR_EINVAL, "%s: output level %d exceeds capacity %d", what,
+          level, x->cap);
+    return FR_OK;
+}
+
+int flag_check(fr_ctx *c, const char *what) {
+    int h = 0;
+    FR_HIP(hipMemcpyAsync(&h, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    FR_HIP(hipStreamSynchronize(c->stream));
+    if (h) {
+        FR_HIP(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+        return fr_fail(FR_ERANGE, "%s: value out of the representable range (flag %d)", what, h);
+    }
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// key switching pieces
+// ---------------------------------------------------------------------------
+// D[t] (t < ndig) = ModUp of digit t of c1 (eval domain) over Q_level U P.
+void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D) {
+    const int N = c->N, nE = level + 1 + c->nP, ndig = num_digits(c, level);
+    u64 *X = scratch(c, (size_t)(level + 1) * N);
+    (void)hipMemcpyAsync(X, c1, (size_t)(level + 1) * N * 8, hipMemcpyDeviceToDevice, c->stream);
+    frk::ntt_inv(c, X, level + 1, qmap(), 1, 0);
+    for (int t = 0; t < ndig; ++t) {
+        u64 *Dt = D + (size_t)t * nE * N;
+        const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
+        frk::modup_digit(c, Dt, X, level, t);
+        LimbMap m{0, lo, nd, level + 1, c->L + 1};
+        frk::ntt_fwd(c, Dt, nE - nd, m, 1, 0);
+        (void)hipMemcpyAsync(Dt + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)nd * N * 8, hipMemcpyDeviceToDevice,
+                             c->stream);
+    }
+}
+
+// out (ciphertext [2][level+1][N]) (+)= ModDown(U), U = [2][nE][N]
+void ks_moddown(fr_ctx *c, const u64 *U, int level, u64 *out, bool accumulate) {
+    const int N = c->N, nE = level + 1 + c->nP, nP = c->nP;
+    u64 *Upc = scratch(c, (size_t)2 * nP * N);
+    for (int p = 0; p < 2; ++p)
+        (void)hipMemcpyAsync(Upc + (size_t)p * nP * N, U + ((size_t)p * nE + level + 1) * N, (size_t)nP * N * 8,
+                             hipMemcpyDeviceToDevice, c->stream);
+    frk::ntt_inv(c, Upc, nP, pmap(c), 2, (size_t)nP * N);
+    u64 *V = scratch(c, (size_t)2 * (level + 1) * N);
+    frk::moddown_fbc(c, V, Upc, level);
+    frk::ntt_fwd(c, V, level + 1, qmap(), 2, (size_t)(level + 1) * N);
+    frk::moddown_finish(c, out, U, V, level, 2, (size_t)(level + 1) * N, (size_t)nE * N, (size_t)(level + 1) * N,
+                        accumulate);
+}
+
+// out = Rescale(in); in at level l >= 1, out at l - 1; out != in
+void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out) {
+    Scope sc(c->arena);
+    const int N = c->N;
+    u64 *xt = scratch(c, (size_t)2 * N);
+    for (int p = 0; p < 2; ++p)
+        (void)hipMemcpyAsync(xt + (size_t)p * N, in + ((size_t)p * (l + 1) + l) * N, (size_t)N * 8,
+                             hipMemcpyDeviceToDevice, c->stream);
+    frk::ntt_inv(c, xt, 1, single(l), 2, (size_t)N);
+    u64 *Y = scratch(c, (size_t)2 * l * N);
+    frk::rescale_prep(c, Y, xt, l, 2, (size_t)l * N, (size_t)N);
+    frk::ntt_fwd(c, Y, l, qmap(), 2, (size_t)l * N);
+    frk::rescale_finish(c, out, in, Y, l, 2, (size_t)l * N, (size_t)(l + 1) * N, (size_t)l * N);
+}
+
+// d = relinearise + rescale of a x b (both at level l) into out at l - 1
+int mul_relin_rescale_dev(fr_ctx *c, const fr_keys *K, const Ct &a, const Ct &b, u64 *out) {
+    const KeyEntry *rk = K->find(0);
+    CHECK(rk, FR_ENOKEY, "relinearisation key missing");
+    Scope sc(c->arena);
+    const int N = c->N, l = a.level, nE = l + 1 + c->nP;
+    const size_t lw = (size_t)(l + 1) * N;
+    u64 *T3 = scratch(c, 3 * lw);
+    frk::tensor(c, T3, T3 + lw, T3 + 2 * lw, a.c0(), a.c1(c), b.c0(), b.c1(c), l + 1);
+    u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+    ks_modup(c, T3 + 2 * lw, l, D);
+    u64 *U = scratch(c, (size_t)2 * nE * N);
+    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false);
+    ks_moddown(c, U, l, T3, true);
+    rescale_dev(c, T3, l, out);
+    return FR_OK;
+}
+
+void residues_of(const fr_ctx *c, long long v, int nl, u64 *r, u64 *rsh) {
+    for (int i = 0; i < nl; ++i) {
+        const u64 q = c->mod[i];
+        u64 x;
+        if (v >= 0) x = (u64)v % q;
+        else {
+            u64 a = (u64)(-(v + 1)) % q;  // avoids overflow at LLONG_MIN
+            a = (a + 1) % q;
+            x = a ? q - a : 0;
+        }
+        r[i] = x;
+        if (rsh) rsh[i] = shoup_companion(x, q);
+    }
+}
+
+// out = k * a (every limb), a and out at the same level
+void mul_int_dev(fr_ctx *c, const u64 *a, size_t sa, int nl, long long k, u64 *out, size_t so) {
+    u64 r[FR_MAXMOD], rs[FR_MAXMOD];
+    residues_of(c, k, nl, r, rs);
+    frk::mul_const(c, out, a, r, rs, nl, 2, so, sa);
+}
+
+// c0 += round(cst * scale) as a constant polynomial (in place)
+void add_const_dev(fr_ctx *c, u64 *c0, int level, double cst, double scale) {
+    long long v = (long long)std::nearbyint(cst * scale);
+    u64 r[FR_MAXMOD];
+    residues_of(c, v, level + 1, r, nullptr);
+    frk::add_const(c, c0, c0, r, level + 1);
+}
+
+// ---------------------------------------------------------------------------
+// ciphertext pool for the Chebyshev ladder (buffers kept for reuse)
+// ---------------------------------------------------------------------------
+struct CtPool {
+    fr_ctx *c;
+    struct Buf { u64 *p; size_t words; bool used; };
+    std::vector<Buf> bufs;
+    u64 *get(size_t words) {
+        for (auto &b : bufs)
+            if (!b.used && b.words >= words) {
+                b.used = true;
+                return b.p;
+            }
+        u64 *p = nullptr;
+        if (hipMalloc(&p, words * 8) != hipSuccess) return nullptr;
+        bufs.push_back({p, words, true});
+        return p;
+    }
+    void put(u64 *p) {
+        for (auto &b : bufs)
+            if (b.p == p) b.used = false;
+    }
+    ~CtPool() {
+        for (auto &b : bufs) (void)hipFree(b.p);
+    }
+};
+
+}  // namespace
+
+// pools live per context (attached lazily)
+struct fr_ctx_pools {
+    CtPool pool;
+};
+static std::vector<std::pair<const fr_ctx *, fr_ctx_pools *>> g_pools;
+
+static CtPool &pool_of(fr_ctx *c) {
+    for (auto &pr : g_pools)
+        if (pr.first == c) return pr.second->pool;
+    auto *p = new fr_ctx_pools{CtPool{c, {}}};
+    g_pools.push_back({c, p});
+    return p->pool;
+}
+static void drop_pool(const fr_ctx *c) {
+    for (size_t i = 0; i < g_pools.size(); ++i)
+        if (g_pools[i].first == c) {
+            delete g_pools[i].second;
+            g_pools.erase(g_pools.begin() + i);
+            return;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+template <class T>
+static int upload(T **dst, const std::vector<T> &src) {
+    FR_HIP(hipMalloc(dst, std::max<size_t>(src.size(), 1) * sizeof(T)));
+    FR_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FR_OK;
+}
+
+static u64 prod_mod(const fr_ctx *c, const std::vector<int> &idx, int skip, u64 r) {
+    u64 p = 1 % r;
+    for (int i : idx)
+        if (i != skip) p = mulmod_h(p, c->mod[i] % r, r);
+    return p;
+}
+
+static int ctx_build(fr_ctx *c) {
+    const int N = c->N, nm = c->nmod, L = c->L, nP = c->nP;
+    // per-modulus constants and twiddles
+    std::vector<ModConst> mc(nm);
+    std::vector<u64> tw((size_t)nm * N), tws((size_t)nm * N), itw((size_t)nm * N), itws((size_t)nm * N);
+    for (int m = 0; m < nm; ++m) {
+        const u64 q = c->mod[m];
+        mc[m] = make_modconst(q, N);
+        c->hmod[m] = mc[m];
+        const u64 psi = primitive_2n_root(q, N), ipsi = invmod_h(psi, q);
+        std::vector<u64> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (int k = 1; k < N; ++k) {
+            pw[k] = mulmod_h(pw[k - 1], psi, q);
+            ipw[k] = mulmod_h(ipw[k - 1], ipsi, q);
+        }
+        for (int k = 0; k < N; ++k) {
+            u32 r = 0, x = (u32)k;
+            for (int b = 0; b < c->logN; ++b) {
+                r = (r << 1) | (x & 1);
+                x >>= 1;
+            }
+            const size_t o = (size_t)m * N + k;
+            tw[o] = pw[r];
+            tws[o] = shoup_companion(tw[o], q);
+            itw[o] = ipw[r];
+            itws[o] = shoup_companion(itw[o], q);
+        }
+    }
+    if (int e = upload(&c->d_mod, mc)) return e;
+    if (int e = upload(&c->d_tw, tw)) return e;
+    if (int e = upload(&c->d_tw_sh, tws)) return e;
+    if (int e = upload(&c->d_itw, itw)) return e;
+    if (int e = upload(&c->d_itw_sh, itws)) return e;
+
+    // ModUp tables
+    std::vector<u64> mu;
+    for (int l = 0; l <= L; ++l) {
+        const int nE = l + 1 + nP, ndig = num_digits(c, l);
+        for (int t = 0; t < ndig; ++t) {
+            c->modup_off[l][t] = mu.size();
+            const int lo = t * c->alpha, nd = std::min(c->alpha, l + 1 - lo);
+            std::vector<int> dig;
+            for (int d = 0; d < nd; ++d) dig.push_back(lo + d);
+            for (int d = 0; d < nd; ++d) {
+                const u64 qi = c->mod[lo + d];
+                const u64 inv = invmod_h(prod_mod(c, dig, lo + d, qi), qi);
+                mu.push_back(inv);
+            }
+            for (int d = 0; d < nd; ++d) mu.push_back(shoup_companion(mu[c->modup_off[l][t] + d], c->mod[lo + d]));
+            for (int e = 0; e < nE; ++e) {
+                const int gm = e <= l ? e : L + 1 + (e - l - 1);
+                for (int d = 0; d < nd; ++d) mu.push_back(prod_mod(c, dig, lo + d, c->mod[gm]));
+            }
+        }
+    }
+    if (int e = upload(&c->d_modup, mu)) return e;
+
+    // ModDown tables
+    std::vector<u64> md;
+    std::vector<int> pidx;
+    for (int j = 0; j < nP; ++j) pidx.push_back(L + 1 + j);
+    for (int j = 0; j < nP; ++j) md.push_back(invmod_h(prod_mod(c, pidx, L + 1 + j, c->mod[L + 1 + j]), c->mod[L + 1 + j]));
+    for (int j = 0; j < nP; ++j) md.push_back(shoup_companion(md[j], c->mod[L + 1 + j]));
+    for (int i = 0; i <= L; ++i)
+        for (int j = 0; j < nP; ++j) md.push_back(prod_mod(c, pidx, L + 1 + j, c->mod[i]));
+    std::vector<u64> pinv(L + 1), pinvs(L + 1);
+    for (int i = 0; i <= L; ++i) {
+        const u64 pm = prod_mod(c, pidx, -1, c->mod[i]);
+        c->P_mod_q[i] = pm;
+        c->P_mod_q_sh[i] = shoup_companion(pm, c->mod[i]);
+        pinv[i] = invmod_h(pm, c->mod[i]);
+        pinvs[i] = shoup_companion(pinv[i], c->mod[i]);
+    }
+    md.insert(md.end(), pinv.begin(), pinv.end());
+    md.insert(md.end(), pinvs.begin(), pinvs.end());
+    if (int e = upload(&c->d_moddown, md)) return e;
+
+    // rescale tables
+    std::vector<u64> rs((size_t)(L + 1) * (L + 1) * 2, 0);
+    for (int l = 1; l <= L; ++l)
+        for (int i = 0; i < l; ++i) {
+            const u64 qi = c->mod[i];
+            const u64 v = invmod_h(c->mod[l] % qi, qi);
+            rs[(size_t)l * (L + 1) * 2 + i] = v;
+            rs[(size_t)l * (L + 1) * 2 + (L + 1) + i] = shoup_companion(v, qi);
+        }
+    if (int e = upload(&c->d_rescale, rs)) return e;
+
+    // CRT lift tables
+    const int W = 4 * (L + 1) + 1;
+    std::vector<u64> crt((size_t)(L + 1) * W, 0);
+    for (int l = 0; l <= L; ++l) {
+        u64 *t = crt.data() + (size_t)l * W;
+        std::vector<int> qs;
+        for (int i = 0; i <= l; ++i) qs.push_back(i);
+        u64 Q64 = 1;
+        for (int i = 0; i <= l; ++i) Q64 *= c->mod[i];
+        for (int i = 0; i <= l; ++i) {
+            const u64 qi = c->mod[i];
+            t[i] = invmod_h(prod_mod(c, qs, i, qi), qi);
+            t[(L + 1) + i] = shoup_companion(t[i], qi);
+            u64 h64 = 1;
+            for (int j = 0; j <= l; ++j)
+                if (j != i) h64 *= c->mod[j];
+            t[2 * (L + 1) + i] = h64;
+            double inv = 1.0 / (double)qi;
+            std::memcpy(&t[3 * (L + 1) + i], &inv, 8);
+        }
+        t[4 * (L + 1)] = Q64;
+    }
+    if (int e = upload(&c->d_crt, crt)) return e;
+
+    // FFT tables
+    std::vector<double> fw((size_t)N), zt((size_t)2 * N);
+    for (int k = 0; k < N / 2; ++k) {
+        const double a = 2.0 * M_PI * (double)k / (double)N;
+        fw[2 * k] = std::cos(a);
+        fw[2 * k + 1] = -std::sin(a);
+    }
+    for (int k = 0; k < N; ++k) {
+        const double a = M_PI * (double)k / (double)N;
+        zt[2 * k] = std::cos(a);
+        zt[2 * k + 1] = std::sin(a);
+    }
+    std::vector<u32> sp(N / 2);
+    u64 e5 = 1;
+    for (int j = 0; j < N / 2; ++j) {
+        sp[j] = (u32)((e5 - 1) / 2);
+        e5 = (e5 * 5) % (2ull * N);
+    }
+    if (int e = upload(&c->d_fft_w, fw)) return e;
+    if (int e = upload(&c->d_zeta, zt)) return e;
+    if (int e = upload(&c->d_slot_pos, sp)) return e;
+    gauss_cdt(c->cdt);
+    FR_HIP(hipMalloc(&c->d_flag, sizeof(int)));
+    FR_HIP(hipMemset(c->d_flag, 0, sizeof(int)));
+    return FR_OK;
+}
+
+extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
+    CHECK(p && out, FR_EINVAL, "fr_ctx_create: null argument");
+    CHECK(p->log_n >= 10 && p->log_n <= 16, FR_EINVAL, "fr_ctx_create: log_n must be in [10, 16]");
+    CHECK(p->n_mid >= 0 && p->n_special >= 1 && p->dnum >= 1 && 1 + p->n_mid + p->n_special <= FR_MAXMOD &&
+              p->n_mid + 1 <= FR_MAXLEVEL,
+          FR_EINVAL, "fr_ctx_create: bad prime counts");
+    CHECK(p->q0_bits >= 30 && p->q0_bits <= 61 && p->mid_bits >= 30 && p->mid_bits <= 61 && p->special_bits >= 30 &&
+              p->special_bits <= 61,
+          FR_EINVAL, "fr_ctx_create: prime sizes must be 30..61 bits");
+    const int alpha = (p->n_mid + 1 + p->dnum - 1) / p->dnum;
+    CHECK(alpha <= 8 && p->n_special <= 8 && p->dnum <= 8, FR_EINVAL,
+          "fr_ctx_create: digit size and special primes limited to 8");
+    fr_ctx *c = new fr_ctx();
+    c->logN = p->log_n;
+    c->N = 1 << p->log_n;
+    c->L = p->n_mid;
+    c->nP = p->n_special;
+    c->dnum = p->dnum;
+    c->alpha = alpha;
+    c->nmod = c->L + 1 + c->nP;
+    if (choose_primes(c->logN, p->q0_bits, p->n_mid, p->mid_bits, p->n_special, p->special_bits, c->mod) != c->nmod) {
+        delete c;
+        return fr_fail(FR_EINVAL, "fr_ctx_create: not enough primes of the requested sizes");
+    }
+    int e = ctx_build(c);
+    if (e) {
+        fr_ctx_destroy(c);
+        return e;
+    }
+    *out = c;
+    return FR_OK;
+}
+
+extern "C" void fr_ctx_destroy(fr_ctx *c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    drop_pool(c);
+    for (void *p : {(void *)c->d_mod, (void *)c->d_tw, (void *)c->d_tw_sh, (void *)c->d_itw, (void *)c->d_itw_sh,
+                    (void *)c->d_modup, (void *)c->d_moddown, (void *)c->d_rescale, (void *)c->d_crt,
+                    (void *)c->d_fft_w, (void *)c->d_zeta, (void *)c->d_slot_pos, (void *)c->d_flag})
+        if (p) (void)hipFree(p);
+    c->arena.release();
+    delete c;
+}
+
+extern "C" int fr_ctx_set_stream(fr_ctx *c, void *stream) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (c->stream != (hipStream_t)stream) FR_HIP(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)stream;
+    return FR_OK;
+}
+
+extern "C" int fr_ctx_sync(fr_ctx *c) {
+    CHECK(c, FR_EINVAL, "null context");
+    FR_HIP(hipStreamSynchronize(c->stream));
+    return FR_OK;
+}
+
+extern "C" int fr_ctx_dims(const fr_ctx *c, int32_t *n, int32_t *L, int32_t *ns, int32_t *alpha, int32_t *dnum) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (n) *n = c->N;
+    if (L) *L = c->L;
+    if (ns) *ns = c->nP;
+    if (alpha) *alpha = c->alpha;
+    if (dnum) *dnum = c->dnum;
+    return FR_OK;
+}
+
+extern "C" uint64_t fr_ctx_modulus(const fr_ctx *c, int32_t g) { return (c && g >= 0 && g < c->nmod) ? c->mod[g] : 0; }
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+extern "C" void fr_keys_destroy(fr_keys *k) {
+    if (!k) return;
+    (void)hipStreamSynchronize(k->ctx->stream);
+    for (auto &e : k->ksk) (void)hipFree(e.data);
+    (void)hipFree(k->s_eval);
+    (void)hipFree(k->s_mont);
+    (void)hipFree(k->pk);
+    delete k;
+}
+
+extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t nrot, fr_keys **out) {
+    CHECK(c && out && (nrot == 0 || rots), FR_EINVAL, "fr_keygen: null argument");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int N = c->N, nm = c->nmod, L = c->L;
+    const size_t lw = (size_t)N;
+    std::unique_ptr<fr_keys, void (*)(fr_keys *)> K(new fr_keys(), fr_keys_destroy);
+    K->ctx = c;
+    FR_HIP(hipMalloc(&K->s_eval, nm * lw * 8));
+    FR_HIP(hipMalloc(&K->s_mont, nm * lw * 8));
+    FR_HIP(hipMalloc(&K->pk, 2 * (L + 1) * lw * 8));
+    const LimbMap all = allmap(c);
+    frk::sample_small(c, K->s_eval, seed, POLY_SECRET, KIND_TERNARY, all, nm);
+    frk::ntt_fwd(c, K->s_eval, nm, all, 1, 0);
+    FR_HIP(hipMemcpyAsync(K->s_mont, K->s_eval, nm * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+    frk::mont_scale(c, K->s_mont, nm, all, 1, 0, true);
+    // public key
+    u64 *e = scratch(c, nm * lw);
+    CHECK(e, FR_ENOMEM, "fr_keygen: scratch");
+    u64 *pka = K->pk + (size_t)(L + 1) * lw;
+    frk::sample_uniform(c, pka, seed, POLY_PK_A, qmap(), L + 1);
+    frk::ntt_fwd(c, pka, L + 1, qmap(), 1, 0);
+    frk::sample_small(c, e, seed, POLY_PK_E, KIND_GAUSS, qmap(), L + 1);
+    frk::ntt_fwd(c, e, L + 1, qmap(), 1, 0);
+    frk::key_combine(c, K->pk, pka, e, K->s_mont, nullptr, 0, 0, L + 1);
+    // key ids: s^2 (0) and the distinct Galois elements
+    std::vector<u64> kids{0};
+    for (int r = 0; r < nrot; ++r) {
+        const u64 g = galois_element(N, rots[r]);
+        if (g != 1 && std::find(kids.begin(), kids.end(), g) == kids.end()) kids.push_back(g);
+    }
+    u64 *sp = scratch(c, (size_t)(L + 1) * lw);
+    CHECK(sp, FR_ENOMEM, "fr_keygen: scratch");
+    for (u64 kid : kids) {
+        KeyEntry ke{kid, nullptr};
+        FR_HIP(hipMalloc(&ke.data, (size_t)c->dnum * 2 * nm * lw * 8));
+        K->ksk.push_back(ke);
+        if (kid == 0) frk::mul_pt(c, sp, K->s_eval, K->s_eval, L + 1, 1, 0, 0);
+        else frk::automorph(c, sp, K->s_eval, kid, L + 1, 1, 0, 0, false);
+        for (int t = 0; t < c->dnum; ++t) {
+            u64 *b = ke.data + (size_t)(t * 2 + 0) * nm * lw;
+            u64 *a = ke.data + (size_t)(t * 2 + 1) * nm * lw;
+            frk::sample_uniform(c, a, seed, poly_ksk(kid, t), all, nm);
+            frk::ntt_fwd(c, a, nm, all, 1, 0);
+            frk::sample_small(c, e, seed, poly_ksk(kid, t), KIND_GAUSS, all, nm);
+            frk::ntt_fwd(c, e, nm, all, 1, 0);
+            const int dlo = t * c->alpha, dhi = std::min(dlo + c->alpha, L + 1);
+            frk::key_combine(c, b, a, e, K->s_mont, sp, dlo, dhi, nm);
+        }
+        frk::mont_scale(c, ke.data, nm, all, 2 * c->dnum, (size_t)nm * lw, true);
+    }
+    FR_HIP(hipGetLastError());
+    FR_HIP(hipStreamSynchronize(c->stream));
+    *out = K.release();
+    return FR_OK;
+}
+
+extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_t kid, uint64_t *host) {
+    CHECK(c && K && host, FR_EINVAL, "fr_keys_export: null argument");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int N = c->N, nm = c->nmod, L = c->L;
+    if (what == 0) {
+        u64 *t = scratch(c, N);
+        FR_HIP(hipMemcpyAsync(t, K->s_eval, (size_t)N * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::ntt_inv(c, t, 1, qmap(), 1, 0);
+        std::vector<u64> h(N);
+        FR_HIP(hipMemcpyAsync(h.data(), t, (size_t)N * 8, hipMemcpyDeviceToHost, c->stream));
+        FR_HIP(hipStreamSynchronize(c->stream));
+        int64_t *o = reinterpret_cast<int64_t *>(host);
+        for (int k = 0; k < N; ++k) o[k] = h[k] == 0 ? 0 : (h[k] == 1 ? 1 : -1);
+        return FR_OK;
+    }
+    if (what == 1) {
+        const size_t w = (size_t)2 * (L + 1) * N;
+        u64 *t = scratch(c, w);
+        FR_HIP(hipMemcpyAsync(t, K->pk, w * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::ntt_inv(c, t, L + 1, qmap(), 2, (size_t)(L + 1) * N);
+        FR_HIP(hipMemcpyAsync(host, t, w * 8, hipMemcpyDeviceToHost, c->stream));
+        FR_HIP(hipStreamSynchronize(c->stream));
+        return FR_OK;
+    }
+    if (what == 2) {
+        const KeyEntry *ke = K->find(kid);
+        CHECK(ke, FR_ENOKEY, "fr_keys_export: no key for id %llu", (unsigned long long)kid);
+        const size_t w = (size_t)c->dnum * 2 * nm * N;
+        u64 *t = scratch(c, w);
+        CHECK(t, FR_ENOMEM, "fr_keys_export: scratch");
+        FR_HIP(hipMemcpyAsync(t, ke->data, w * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::mont_scale(c, t, nm, allmap(c), 2 * c->dnum, (size_t)nm * N, false);
+        frk::ntt_inv(c, t, nm, allmap(c), 2 * c->dnum, (size_t)nm * N);
+        FR_HIP(hipMemcpyAsync(host, t, w * 8, hipMemcpyDeviceToHost, c->stream));
+        FR_HIP(hipStreamSynchronize(c->stream));
+        return FR_OK;
+    }
+    return fr_fail(FR_EINVAL, "fr_keys_export: unknown selector %d", what);
+}
+
+// ---------------------------------------------------------------------------
+// encode / import / export / encrypt / decrypt / decode
+// ---------------------------------------------------------------------------
+static int encode_common(fr_ctx *c, const double *zdev, int n, int level, double scale, fr_pt *out) {
+    const int N = c->N;
+    double *work = (double *)c->arena.get((size_t)N * 16);
+    CHECK(work, FR_ENOMEM, "fr_encode: scratch");
+    frk::encode_slots(c, out->data, zdev, n, level, scale, 1, 0, 0, work);
+    frk::ntt_fwd(c, out->data, level + 1, qmap(), 1, 0);
+    if (int e = flag_check(c, "fr_encode")) return e;
+    out->level = level;
+    out->scale = scale;
+    return FR_OK;
+}
+
+extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) {
+    CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode: null argument");
+    CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
+          "fr_encode: bad size or level");
+    c->arena.reset();
+    Scope sc(c->arena);
+    double *zd = (double *)c->arena.get((size_t)std::max(n, 1) * 8);
+    CHECK(zd, FR_ENOMEM, "fr_encode: scratch");
+    if (n) FR_HIP(hipMemcpyAsync(zd, z, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+    FR_HIP(hipStreamSynchronize(c->stream));
+    return encode_common(c, zd, n, level, scale, out);
+}
+
+extern "C" int fr_encode_device(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) {
+    CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode_device: null argument");
+    CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
+          "fr_encode_device: bad size or level");
+    c->arena.reset();
+    Scope sc(c->arena);
+    return encode_common(c, z, n, level, scale, out);
+}
+
+static int import_poly(fr_ctx *c, const uint64_t *host, int nl, int npoly, u64 *dst) {
+    const size_t w = (size_t)npoly * nl * c->N;
+    std::vector<u64> h(host, host + w);
+    for (int p = 0; p < npoly; ++p)
+        for (int i = 0; i < nl; ++i)
+            for (int k = 0; k < c->N; ++k) {
+                u64 &x = h[((size_t)p * nl + i) * c->N + k];
+                if (x >= c->mod[i]) return fr_fail(FR_EINVAL, "import: residue not canonical (limb %d)", i);
+            }
+    FR_HIP(hipMemcpyAsync(dst, h.data(), w * 8, hipMemcpyHostToDevice, c->stream));
+    frk::ntt_fwd(c, dst, nl, qmap(), npoly, (size_t)nl * c->N);
+    FR_HIP(hipStreamSynchronize(c->stream));
+    return FR_OK;
+}
+
+static int export_poly(fr_ctx *c, const u64 *src, int nl, int npoly, uint64_t *host) {
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t w = (size_t)npoly * nl * c->N;
+    u64 *t = scratch(c, w);
+    CHECK(t, FR_ENOMEM, "export: scratch");
+    FR_HIP(hipMemcpyAsync(t, src, w * 8, hipMemcpyDeviceToDevice, c->stream));
+    frk::ntt_inv(c, t, nl, qmap(), npoly, (size_t)nl * c->N);
+    FR_HIP(hipMemcpyAsync(host, t, w * 8, hipMemcpyDeviceToHost, c->stream));
+    FR_HIP(hipStreamSynchronize(c->stream));
+    return FR_OK;
+}
+
+extern "C" int fr_pt_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_pt *out) {
+    CHECK(c && host && out && out->data, FR_EINVAL, "fr_pt_import: null argument");
+    CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_pt_import: bad level");
+    if (int e = import_poly(c, host, level + 1, 1, out->data)) return e;
+    out->level = level;
+    out->scale = scale;
+    return FR_OK;
+}
+
+extern "C" int fr_pt_export(fr_ctx *c, const fr_pt *p, uint64_t *host) {
+    CHECK(c && p && p->data && host, FR_EINVAL, "fr_pt_export: null argument");
+    CHECK(p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_pt_export: bad level");
+    return export_poly(c, p->data, p->level + 1, 1, host);
+}
+
+extern "C" int fr_ct_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_ct *out) {
+    CHECK(c && host && out && out->data, FR_EINVAL, "fr_ct_import: null argument");
+    CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_ct_import: bad level");
+    if (int e = import_poly(c, host, level + 1, 2, out->data)) return e;
+    out->level = level;
+    out->scale = scale;
+    return FR_OK;
+}
+
+extern "C" int fr_ct_export(fr_ctx *c, const fr_ct *x, uint64_t *host) {
+    CHECK(c && host, FR_EINVAL, "fr_ct_export: null argument");
+    if (int e = check_ct(c, x, "fr_ct_export")) return e;
+    return export_poly(c, x->data, x->level + 1, 2, host);
+}
+
+extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t seed, fr_ct *out) {
+    CHECK(c && K && p && p->data, FR_EINVAL, "fr_encrypt: null argument");
+    const int l = p->level;
+    CHECK(l >= 0 && l <= c->L, FR_EINVAL, "fr_encrypt: bad plaintext level");
+    if (int e = check_out(c, out, l, "fr_encrypt")) return e;
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int N = c->N;
+    const size_t lw = (size_t)(l + 1) * N;
+    u64 *v = scratch(c, 3 * lw);
+    CHECK(v, FR_ENOMEM, "fr_encrypt: scratch");
+    u64 *e0 = v + lw, *e1 = v + 2 * lw;
+    frk::sample_small(c, v, seed, POLY_ENC_V, KIND_TERNARY, qmap(), l + 1);
+    frk::sample_small(c, e0, seed, POLY_ENC_E0, KIND_GAUSS, qmap(), l + 1);
+    frk::sample_small(c, e1, seed, POLY_ENC_E1, KIND_GAUSS, qmap(), l + 1);
+    frk::ntt_fwd(c, v, l + 1, qmap(), 3, lw);
+    frk::encrypt_combine(c, out->data, out->data + lw, v, e0, e1, p->data, K->pk, K->pk + (size_t)(c->L + 1) * N, l + 1);
+    FR_HIP(hipGetLastError());
+    out->level = l;
+    out->scale = p->scale;
+    return FR_OK;
+}
+
+extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *out) {
+    CHECK(c && K && out && out->data, FR_EINVAL, "fr_decrypt: null argument");
+    if (int e = check_ct(c, x, "fr_decrypt")) return e;
+    CHECK(x->level <= out->cap, FR_EINVAL, "fr_decrypt: output capacity");
+    const size_t lw = (size_t)(x->level + 1) * c->N;
+    frk::decrypt_combine(c, out->data, x->data, x->data + lw, K->s_mont, x->level + 1);
+    FR_HIP(hipGetLastError());
+    out->level = x->level;
+    out->scale = x->scale;
+    return FR_OK;
+}
+
+extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) {
+    CHECK(c && p && p->data && z, FR_EINVAL, "fr_decode: null argument");
+    CHECK(n >= 0 && n <= c->N / 2 && p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_decode: bad size or level");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int N = c->N;
+    const size_t lw = (size_t)(p->level + 1) * N;
+    u64 *m = scratch(c, lw);
+    double *work = (double *)c->arena.get((size_t)N * 16);
+    double *zd = (double *)c->arena.get((size_t)N / 2 * 8);
+    CHECK(m && work && zd, FR_ENOMEM, "fr_decode: scratch");
+    FR_HIP(hipMemcpyAsync(m, p->data, lw * 8, hipMemcpyDeviceToDevice, c->stream));
+    frk::ntt_inv(c, m, p->level + 1, qmap(), 1, 0);
+    frk::decode_slots(c, zd, m, p->level, p->scale, work);
+    if (n) FR_HIP(hipMemcpyAsync(z, zd, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    return flag_check(c, "fr_decode");
+}
+
+// ---------------------------------------------------------------------------
+// homomorphic operations
+// ---------------------------------------------------------------------------
+static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots, int nrot,
+                               fr_ct *outs) {
+    const int N = c->N, l = in->level, nE = l + 1 + c->nP;
+    const size_t lw = (size_t)(l + 1) * N;
+    std::vector<u64> gs(nrot);
+    for (int r = 0; r < nrot; ++r) {
+        gs[r] = galois_element(N, rots[r]);
+        CHECK(gs[r] == 1 || K->find(gs[r]), FR_ENOKEY, "fr_rotate_hoisted: no key for rotation %d", rots[r]);
+        if (int e = check_out(c, &outs[r], l, "fr_rotate_hoisted")) return e;
+        CHECK(outs[r].data != in->data, FR_EINVAL, "fr_rotate_hoisted: output aliases input");
+    }
+    Scope sc(c->arena);
+    u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+    u64 *U = scratch(c, (size_t)2 * nE * N);
+    CHECK(D && U, FR_ENOMEM, "fr_rotate_hoisted: scratch");
+    bool need_modup = false;
+    for (u64 g : gs) need_modup |= (g != 1);
+    if (need_modup) ks_modup(c, in->data + lw, l, D);
+    for (int r = 0; r < nrot; ++r) {
+        u64 *o = outs[r].data;
+        if (gs[r] == 1) {
+            FR_HIP(hipMemcpyAsync(o, in->data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            Scope inner(c->arena);
+            frk::ks_inner(c, U, U + (size_t)nE * N, D, K->find(gs[r])->data, gs[r], l, false);
+            ks_moddown(c, U, l, o, false);
+            frk::automorph(c, o, in->data, gs[r], l + 1, 1, 0, 0, true);
+        }
+        outs[r].level = l;
+        outs[r].scale = in->scale;
+    }
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+extern "C" int fr_rotate_hoisted(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots, int32_t nrot,
+                                 fr_ct *outs) {
+    CHECK(c && K && (nrot == 0 || (rots && outs)), FR_EINVAL, "fr_rotate_hoisted: null argument");
+    if (int e = check_ct(c, in, "fr_rotate_hoisted")) return e;
+    c->arena.reset();
+    return rotate_hoisted_impl(c, K, in, rots, nrot, outs);
+}
+
+extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (int e = check_ct(c, in, "fr_rescale")) return e;
+    CHECK(in->level >= 1, FR_ELEVEL, "fr_rescale: level 0 cannot be rescaled");
+    if (int e = check_out(c, out, in->level - 1, "fr_rescale")) return e;
+    CHECK(out->data != in->data, FR_EINVAL, "fr_rescale: output aliases input");
+    c->arena.reset();
+    rescale_dev(c, in->data, in->level, out->data);
+    FR_HIP(hipGetLastError());
+    out->scale = in->scale / (double)c->mod[in->level];
+    out->level = in->level - 1;
+    return FR_OK;
+}
+
+static int addsub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out, bool sub) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (int e = check_ct(c, a, "fr_add")) return e;
+    if (int e = check_ct(c, b, "fr_add")) return e;
+    CHECK(a->level == b->level, FR_ELEVEL, "fr_add: level mismatch %d vs %d", a->level, b->level);
+    if (int e = check_out(c, out, a->level, "fr_add")) return e;
+    const size_t lw = (size_t)(a->level + 1) * c->N;
+    frk::add(c, out->data, a->data, b->data, a->level + 1, 2, lw, lw, lw, sub);
+    FR_HIP(hipGetLastError());
+    out->level = a->level;
+    out->scale = a->scale;
+    return FR_OK;
+}
+extern "C" int fr_add(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, false); }
+extern "C" int fr_sub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, true); }
+
+extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *out) {
+    CHECK(c && p && p->data, FR_EINVAL, "fr_mul_plain: null argument");
+    if (int e = check_ct(c, a, "fr_mul_plain")) return e;
+    const int l = std::min(a->level, p->level);
+    if (int e = check_out(c, out, l, "fr_mul_plain")) return e;
+    const size_t la = (size_t)(a->level + 1) * c->N, lo = (size_t)(l + 1) * c->N;
+    CHECK(out->data != a->data || l == a->level, FR_EINVAL, "fr_mul_plain: aliasing with a level change");
+    frk::mul_pt(c, out->data, a->data, p->data, l + 1, 2, lo, la);
+    FR_HIP(hipGetLastError());
+    out->level = l;
+    out->scale = a->scale * p->scale;
+    return FR_OK;
+}
+
+extern "C" int fr_mul_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, fr_ct *out) {
+    CHECK(c && K, FR_EINVAL, "null argument");
+    if (int e = check_ct(c, a, "fr_mul_relin_rescale")) return e;
+    if (int e = check_ct(c, b, "fr_mul_relin_rescale")) return e;
+    CHECK(a->level == b->level, FR_ELEVEL, "fr_mul_relin_rescale: level mismatch");
+    CHECK(a->level >= 1, FR_ELEVEL, "fr_mul_relin_rescale: no level left");
+    if (int e = check_out(c, out, a->level - 1, "fr_mul_relin_rescale")) return e;
+    c->arena.reset();
+    Ct A{a->data, a->level, a->scale}, B{b->data, b->level, b->scale};
+    if (int e = mul_relin_rescale_dev(c, K, A, B, out->data)) return e;
+    FR_HIP(hipGetLastError());
+    out->level = a->level - 1;
+    out->scale = (a->scale * b->scale) / (double)c->mod[a->level];
+    return FR_OK;
+}
+
+extern "C" int fr_mul_int(fr_ctx *c, const fr_ct *a, int64_t k, fr_ct *out) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (int e = check_ct(c, a, "fr_mul_int")) return e;
+    if (int e = check_out(c, out, a->level, "fr_mul_int")) return e;
+    const size_t lw = (size_t)(a->level + 1) * c->N;
+    mul_int_dev(c, a->data, lw, a->level + 1, (long long)k, out->data, lw);
+    FR_HIP(hipGetLastError());
+    out->level = a->level;
+    out->scale = a->scale * (double)k;
+    return FR_OK;
+}
+
+extern "C" int fr_add_const(fr_ctx *c, const fr_ct *a, double cst, fr_ct *out) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (int e = check_ct(c, a, "fr_add_const")) return e;
+    if (int e = check_out(c, out, a->level, "fr_add_const")) return e;
+    const size_t lw = (size_t)(a->level + 1) * c->N;
+    if (out->data != a->data) FR_HIP(hipMemcpyAsync(out->data, a->data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+    add_const_dev(c, out->data, a->level, cst, a->scale);
+    FR_HIP(hipGetLastError());
+    out->level = a->level;
+    out->scale = a->scale;
+    return FR_OK;
+}
+
+extern "C" int fr_drop_to(fr_ctx *c, const fr_ct *a, int32_t level, fr_ct *out) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (int e = check_ct(c, a, "fr_drop_to")) return e;
+    CHECK(level >= 0 && level <= a->level, FR_ELEVEL, "fr_drop_to: bad level");
+    if (int e = check_out(c, out, level, "fr_drop_to")) return e;
+    CHECK(out->data != a->data || level == a->level, FR_EINVAL, "fr_drop_to: aliasing");
+    const size_t lw = (size_t)(level + 1) * c->N;
+    for (int p = 0; p < 2; ++p)
+        FR_HIP(hipMemcpyAsync(out->data + p * lw, a->data + (size_t)p * (a->level + 1) * c->N, lw * 8,
+                              hipMemcpyDeviceToDevice, c->stream));
+    out->level = level;
+    out->scale = a->scale;
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// database
+// ---------------------------------------------------------------------------
+extern "C" void fr_db_destroy(fr_db *db) {
+    if (!db) return;
+    (void)hipStreamSynchronize(db->ctx->stream);
+    (void)hipFree(db->data);
+    delete db;
+}
+
+extern "C" int fr_db_groups(const fr_db *db) { return db ? db->G : 0; }
+
+static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double scale, fr_db **out) {
+    fr_db *db = new fr_db();
+    db->ctx = c;
+    db->G = G;
+    db->ell = ell;
+    db->B = B;
+    db->n1 = n1;
+    db->level = level;
+    db->scale = scale;
+    if (hipMalloc(&db->data, (size_t)G * ell * (level + 1) * c->N * 8) != hipSuccess) {
+        delete db;
+        return fr_fail(FR_ENOMEM, "fr_db: cannot allocate %zu bytes of diagonals",
+                       (size_t)G * ell * (level + 1) * c->N * 8);
+    }
+    *out = db;
+    return FR_OK;
+}
+
+extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int32_t B, int32_t n1, int32_t level,
+                          double scale, fr_db **out) {
+    CHECK(c && out && (K == 0 || T), FR_EINVAL, "fr_db_load: null argument");
+    const int h = c->N / 2;
+    CHECK(K >= 0 && ell > 0 && B > 0 && (long long)B * ell <= h && n1 > 0 && n1 <= ell && level >= 0 &&
+              level <= c->L,
+          FR_EINVAL, "fr_db_load: bad layout");
+    const int G = std::max(1, (int)((K + (long long)B * ell - 1) / ((long long)B * ell)));
+    fr_db *db = nullptr;
+    if (int e = db_alloc(c, G, ell, B, n1, level, scale, &db)) return e;
+    std::unique_ptr<fr_db, void (*)(fr_db *)> guard(db, fr_db_destroy);
+    c->arena.reset();
+    Scope sc(c->arena);
+    float *Td = (float *)c->arena.get((size_t)std::max(K, 1) * ell * 4);
+    CHECK(Td, FR_ENOMEM, "fr_db_load: scratch");
+    if (K) FR_HIP(hipMemcpyAsync(Td, T, (size_t)K * ell * 4, hipMemcpyHostToDevice, c->stream));
+    FR_HIP(hipStreamSynchronize(c->stream));
+    const int batch = std::min(ell, 32);
+    double *slots = (double *)c->arena.get((size_t)batch * h * 8);
+    double *work = (double *)c->arena.get((size_t)batch * c->N * 16);
+    CHECK(slots && work, FR_ENOMEM, "fr_db_load: scratch");
+    const size_t pw = (size_t)(level + 1) * c->N;
+    for (int g = 0; g < G; ++g)
+        for (int d0 = 0; d0 < ell; d0 += batch) {
+            const int nd = std::min(batch, ell - d0);
+            u64 *dst = db->data + ((size_t)g * ell + d0) * pw;
+            frk::db_slots(c, slots, Td, K, ell, B, n1, g, d0, nd);
+            frk::encode_slots(c, dst, slots, h, level, scale, nd, (size_t)h, pw, work);
+            frk::ntt_fwd(c, dst, level + 1, qmap(), nd, pw);
+            frk::mont_scale(c, dst, level + 1, qmap(), nd, pw, true);
+        }
+    if (int e = flag_check(c, "fr_db_load")) return e;
+    *out = guard.release();
+    return FR_OK;
+}
+
+extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t ell, int32_t B, int32_t n1,
+                            int32_t level, double scale, fr_db **out) {
+    CHECK(c && host && out, FR_EINVAL, "fr_db_import: null argument");
+    CHECK(G >= 1 && ell > 0 && B > 0 && (long long)B * ell <= c->N / 2 && n1 > 0 && n1 <= ell && level >= 0 &&
+              level <= c->L,
+          FR_EINVAL, "fr_db_import: bad layout");
+    fr_db *db = nullptr;
+    if (int e = db_alloc(c, G, ell, B, n1, level, scale, &db)) return e;
+    std::unique_ptr<fr_db, void (*)(fr_db *)> guard(db, fr_db_destroy);
+    const size_t pw = (size_t)(level + 1) * c->N;
+    for (int p = 0; p < G * ell; ++p) {
+        if (int e = import_poly(c, host + p * pw, level + 1, 1, db->data + p * pw)) return e;
+    }
+    frk::mont_scale(c, db->data, level + 1, qmap(), G * ell, pw, true);
+    FR_HIP(hipStreamSynchronize(c->stream));
+    *out = guard.release();
+    return FR_OK;
+}
+
+extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, uint64_t *host) {
+    CHECK(c && db && host, FR_EINVAL, "fr_db_export: null argument");
+    CHECK(g >= 0 && g < db->G && d >= 0 && d < db->ell, FR_EINVAL, "fr_db_export: bad index");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t pw = (size_t)(db->level + 1) * c->N;
+    u64 *t = scratch(c, pw);
+    CHECK(t, FR_ENOMEM, "fr_db_export: scratch");
+    FR_HIP(hipMemcpyAsync(t, db->data + ((size_t)g * db->ell + d) * pw, pw * 8, hipMemcpyDeviceToDevice, c->stream));
+    frk::mont_scale(c, t, db->level + 1, qmap(), 1, 0, false);
+    frk::ntt_inv(c, t, db->level + 1, qmap(), 1, 0);
+    FR_HIP(hipMemcpyAsync(host, t, pw * 8, hipMemcpyDeviceToHost, c->stream));
+    FR_HIP(hipStreamSynchronize(c->stream));
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the BSGS diagonal matrix-vector product
+// ---------------------------------------------------------------------------
+extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t n1, const fr_db *db,
+                                   int32_t group, fr_ct *out) {
+    CHECK(c && K && baby && db && out, FR_EINVAL, "fr_bsgs_diag_matvec: null argument");
+    CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
+    CHECK(group >= 0 && group < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range", group);
+    const int N = c->N, ell = db->ell, bl = baby[0].level;
+    for (int i = 0; i < n1; ++i) {
+        if (int e = check_ct(c, &baby[i], "fr_bsgs_diag_matvec")) return e;
+        CHECK(baby[i].level == bl && baby[i].scale == baby[0].scale, FR_ELEVEL,
+              "fr_bsgs_diag_matvec: baby steps differ in level or scale");
+    }
+    const int lv = std::min(bl, db->level);
+    CHECK(lv >= 1, FR_ELEVEL, "fr_bsgs_diag_matvec: no level left to rescale");
+    const int n2 = (ell + n1 - 1) / n1, l = lv - 1;
+    for (int j = 1; j < n2; ++j)
+        CHECK(K->find(galois_element(N, j * n1)), FR_ENOKEY, "fr_bsgs_diag_matvec: no key for giant step %d", j * n1);
+    if (int e = check_out(c, out, l, "fr_bsgs_diag_matvec")) return e;
+    for (int i = 0; i < n1; ++i) CHECK(out->data != baby[i].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N;
+    u64 *P = scratch(c, (size_t)n2 * pw);
+    u64 *R = scratch(c, (size_t)n2 * rw);
+    CHECK(P && R, FR_ENOMEM, "fr_bsgs_diag_matvec: scratch");
+    std::vector<const u64 *> bp(n1);
+    for (int i = 0; i < n1; ++i) bp[i] = baby[i].data;
+    const u64 *diag = db->data + (size_t)group * ell * (db->level + 1) * N;
+    frk::bsgs_mac(c, P, bp.data(), n1, diag, ell, db->level, lv, bl);
+    for (int j = 0; j < n2; ++j) rescale_dev(c, P + j * pw, lv, R + j * rw);
+    FR_HIP(hipMemcpyAsync(out->data, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (n2 > 1) {
+        const int nE = l + 1 + c->nP;
+        u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+        u64 *U = scratch(c, (size_t)2 * nE * N);
+        CHECK(D && U, FR_ENOMEM, "fr_bsgs_diag_matvec: scratch");
+        for (int j = 1; j < n2; ++j) {
+            Scope inner(c->arena);
+            const u64 g = galois_element(N, j * n1);
+            const u64 *Rj = R + j * rw;
+            ks_modup(c, Rj + (size_t)(l + 1) * N, l, D);
+            frk::ks_inner(c, U, U + (size_t)nE * N, D, K->find(g)->data, g, l, j > 1);
+            frk::automorph(c, out->data, Rj, g, l + 1, 1, 0, 0, true);
+        }
+        ks_moddown(c, U, l, out->data, true);
+    }
+    FR_HIP(hipGetLastError());
+    out->level = l;
+    out->scale = (baby[0].scale * db->scale) / (double)c->mod[lv];
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev threshold
+// ---------------------------------------------------------------------------
+// The evaluator is written once over a backend: LevelSim tracks levels only
+// (planning helpers), DevBackend runs on the device.  Recursion: Chebyshev-
+// basis division p = q T_M + r (q_0 = c_M, q_i = 2 c_{M+i}, r_0 = c_0,
+// r_k = c_k - c_{2M-k}) with M = d1 2^j the largest below the number of
+// coefficients, leaves of at most d1 coefficients, powers from
+// T_i = 2 T_ceil(i/2) T_floor(i/2) - T_(i mod 2).
+namespace {
+
+struct SimCt {
+    int level;
+};
+
+struct LevelSim {
+    using H = std::shared_ptr<SimCt>;
+    int nmul = 0;
+    bool fail = false;
+    H make(int l) { return std::make_shared<SimCt>(SimCt{l}); }
+    int level(const H &h) const { return h->level; }
+    H adjust(const H &a, int lam) {
+        if (a->level == lam) return a;
+        if (lam < 0 || lam > a->level) fail = true;
+        return make(lam);
+    }
+    H mul(const H &a, const H &b) {
+        const int lam = std::min(a->level, b->level);
+        if (lam < 1) fail = true;
+        ++nmul;
+        return make(lam - 1);
+    }
+    H add(const H &a, const H &) { return make(a->level); }
+    H sub(const H &a, const H &) { return make(a->level); }
+    H twice_minus_const(const H &a) { return make(a->level); }
+    H scalar(const H &T, double) {
+        if (T->level < 1) fail = true;
+        return make(T->level - 1);
+    }
+    H leaf(const std::vector<H> &Ts, const double *, int m) {
+        int lam = INT_MAX;
+        for (int i = 1; i < m; ++i) lam = std::min(lam, Ts[i]->level - 1);
+        if (lam < 0) fail = true;
+        return make(lam);
+    }
+};
+
+struct DevBackend {
+    struct DCt {
+        u64 *d;
+        int level;
+        double scale;
+        CtPool *pool;
+        ~DCt() {
+            if (pool && d) pool->put(d);
+        }
+    };
+    using H = std::shared_ptr<DCt>;
+    fr_ctx *c;
+    const fr_keys *K;
+    CtPool *pool;
+    double D[FR_MAXLEVEL];
+    int nmul = 0;
+    bool fail = false;
+    int err = FR_OK;
+
+    H alloc(int level) {
+        u64 *p = pool->get((size_t)2 * (level + 1) * c->N);
+        if (!p) {
+            fail = true;
+            err = fr_fail(FR_ENOMEM, "fr_chebyshev_eval: out of device memory");
+            return nullptr;
+        }
+        return H(new DCt{p, level, D[level], pool});
+    }
+    int level(const H &h) const { return h->level; }
+    Ct view(const H &h) const { return Ct{h->d, h->level, h->scale}; }
+
+    // drop to lam+1 and multiply by k, then rescale to lam (canonical scale)
+    H scale_to(const H &a, int lam, long long k) {
+        H t = alloc(lam + 1);
+        H r = alloc(lam);
+        if (!t || !r) return nullptr;
+        mul_int_dev(c, a->d, (size_t)(a->level + 1) * c->N, lam + 2, k, t->d, (size_t)(lam + 2) * c->N);
+        rescale_dev(c, t->d, lam + 1, r->d);
+        return r;
+    }
+    H adjust(const H &a, int lam) {
+        if (!a) return nullptr;
+        if (a->level == lam) return a;
+        if (lam < 0 || lam > a->level) {
+            fail = true;
+            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
+            return nullptr;
+        }
+        const long long k = (long long)std::nearbyint((D[lam] * (double)c->mod[lam + 1]) / D[a->level]);
+        return scale_to(a, lam, k);
+    }
+    H mul(const H &a, const H &b) {
+        if (!a || !b) return nullptr;
+        const int lam = std::min(a->level, b->level);
+        if (lam < 1) {
+            fail = true;
+            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
+            return nullptr;
+        }
+        H x = adjust(a, lam), y = adjust(b, lam);
+        if (!x || !y) return nullptr;
+        H r = alloc(lam - 1);
+        if (!r) return nullptr;
+        int e = mul_relin_rescale_dev(c, K, view(x), view(y), r->d);
+        if (e) {
+            fail = true;
+            err = e;
+            return nullptr;
+        }
+        ++nmul;
+        return r;
+    }
+    H addsub(const H &a, const H &b, bool sub) {
+        if (!a || !b) return nullptr;
+        H r = alloc(a->level);
+        if (!r) return nullptr;
+        const size_t lw = (size_t)(a->level + 1) * c->N;
+        frk::add(c, r->d, a->d, b->d, a->level + 1, 2, lw, lw, lw, sub);
+        return r;
+    }
+    H add(const H &a, const H &b) { return addsub(a, b, false); }
+    H sub(const H &a, const H &b) { return addsub(a, b, true); }
+    // 2 a - 1
+    H twice_minus_const(const H &a) {
+        H r = addsub(a, a, false);
+        if (r) add_const_dev(c, r->d, r->level, -1.0, D[r->level]);
+        return r;
+    }
+    H scalar(const H &T, double cst) {
+        if (!T) return nullptr;
+        const int lv = T->level, lam = lv - 1;
+        if (lam < 0) {
+            fail = true;
+            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
+            return nullptr;
+        }
+        const long long k = (long long)std::nearbyint(((cst * D[lam]) * (double)c->mod[lv]) / D[lv]);
+        return scale_to(T, lam, k);
+    }
+    H leaf(const std::vector<H> &Ts, const double *cf, int m) {
+        int lam = INT_MAX;
+        for (int i = 1; i < m; ++i) {
+            if (!Ts[i]) return nullptr;
+            lam = std::min(lam, Ts[i]->level - 1);
+        }
+        if (lam < 0) {
+            fail = true;
+            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
+            return nullptr;
+        }
+        H acc = alloc(lam + 1), t = alloc(lam + 1), r = alloc(lam);
+        if (!acc || !t || !r) return nullptr;
+        const size_t lw = (size_t)(lam + 2) * c->N;
+        for (int i = 1; i < m; ++i) {
+            const long long k =
+                (long long)std::nearbyint(((cf[i] * D[lam]) * (double)c->mod[lam + 1]) / D[Ts[i]->level]);
+            u64 *dst = i == 1 ? acc->d : t->d;
+            mul_int_dev(c, Ts[i]->d, (size_t)(Ts[i]->level + 1) * c->N, lam + 2, k, dst, lw);
+            if (i > 1) frk::add(c, acc->d, acc->d, t->d, lam + 2, 2, lw, lw, lw, false);
+        }
+        rescale_dev(c, acc->d, lam + 1, r->d);
+        add_const_dev(c, r->d, lam, cf[0], D[lam]);
+        return r;
+    }
+};
+
+template <class B>
+struct Cheb {
+    B &be;
+    int d1;
+    std::vector<typename B::H> T;
+    using H = typename B::H;
+
+    H power(int i) {
+        if (T[i]) return T[i];
+        const int a = (i + 1) / 2, b = i / 2;
+        H Ta = power(a), Tb = power(b);
+        if (be.fail) return nullptr;
+        H prod = be.mul(Ta, Tb);
+        if (!prod) return nullptr;
+        H res;
+        if (a == b) {
+            res = be.twice_minus_const(prod);
+        } else {
+            H two = be.add(prod, prod);
+            if (!two) return nullptr;
+            H t1 = be.adjust(T[1], be.level(two));
+            res = be.sub(two, t1);
+        }
+        T[i] = res;
+        return res;
+    }
+
+    H eval(const std::vector<double> &cf, int m) {
+        if (be.fail) return nullptr;
+        if (m <= d1) {
+            for (int i = 1; i < m; ++i)
+                if (!power(i)) return nullptr;
+            return be.leaf(T, cf.data(), m);
+        }
+        int M = d1;
+        while (2 * M < m) M *= 2;
+        const int nq = m - M;
+        std::vector<double> q(nq), r(M);
+        q[0] = cf[M];
+        for (int i = 1; i < nq; ++i) q[i] = 2.0 * cf[M + i];
+        r[0] = cf[0];
+        for (int k = 1; k < M; ++k) r[k] = cf[k] - ((2 * M - k < m) ? cf[2 * M - k] : 0.0);
+        H TM = power(M);
+        if (!TM) return nullptr;
+        H A;
+        if (nq == 1) {
+            A = be.scalar(TM, q[0]);
+        } else {
+            H Q = eval(q, nq);
+            if (!Q) return nullptr;
+            A = be.mul(Q, TM);
+        }
+        if (!A) return nullptr;
+        H R = eval(r, M);
+        if (!R) return nullptr;
+        const int lam = std::min(be.level(A), be.level(R));
+        H x = be.adjust(A, lam), y = be.adjust(R, lam);
+        return be.add(x, y);
+    }
+};
+
+}  // namespace
+
+extern "C" int fr_chebyshev_eval(fr_ctx *c, const fr_keys *K, const fr_ct *in, const double *cf, int32_t degree,
+                                 int32_t d1, fr_ct *out) {
+    CHECK(c && K && cf && out, FR_EINVAL, "fr_chebyshev_eval: null argument");
+    CHECK(degree >= 1 && d1 >= 2, FR_EINVAL, "fr_chebyshev_eval: need degree >= 1 and d1 >= 2");
+    if (int e = check_ct(c, in, "fr_chebyshev_eval")) return e;
+    const int ol = fr_cheb_out_level(in->level, degree, d1);
+    CHECK(ol >= 0, FR_ELEVEL, "fr_chebyshev_eval: not enough levels for degree %d from level %d", degree, in->level);
+    if (int e = check_out(c, out, ol, "fr_chebyshev_eval")) return e;
+    CHECK(K->find(0), FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
+    c->arena.reset();
+    DevBackend be;
+    be.c = c;
+    be.K = K;
+    be.pool = &pool_of(c);
+    be.D[in->level] = in->scale;
+    for (int l = in->level; l >= 1; --l) be.D[l - 1] = (be.D[l] * be.D[l]) / (double)c->mod[l];
+    int res_level = -1;
+    {
+        Cheb<DevBackend> ch{be, d1, std::vector<DevBackend::H>(std::max(degree + 2, 2 * d1 + 2))};
+        ch.T[1] = DevBackend::H(new DevBackend::DCt{in->data, in->level, in->scale, nullptr});
+        std::vector<double> coef(cf, cf + degree + 1);
+        DevBackend::H y = ch.eval(coef, degree + 1);
+        if (!y) return be.err ? be.err : fr_fail(FR_ELEVEL, "fr_chebyshev_eval: evaluation failed");
+        res_level = y->level;
+        FR_HIP(hipMemcpyAsync(out->data, y->d, (size_t)2 * (y->level + 1) * c->N * 8, hipMemcpyDeviceToDevice,
+                              c->stream));
+    }
+    FR_HIP(hipGetLastError());
+    out->level = res_level;
+    out->scale = be.D[res_level];
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-only planning helpers
+// ---------------------------------------------------------------------------
+extern "C" int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1) {
+    if (degree < 1 || d1 < 2 || in_level < 0) return -1;
+    LevelSim sim;
+    Cheb<LevelSim> ch{sim, d1, std::vector<LevelSim::H>(std::max(degree + 2, 2 * d1 + 2))};
+    ch.T[1] = sim.make(in_level);
+    std::vector<double> coef(degree + 1, 1.0);
+    auto y = ch.eval(coef, degree + 1);
+    if (!y || sim.fail) return -1;
+    return y->level;
+}
+
+extern "C" int fr_cheb_mult_count(int32_t degree, int32_t d1) {
+    if (degree < 1 || d1 < 2) return -1;
+    LevelSim sim;
+    Cheb<LevelSim> ch{sim, d1, std::vector<LevelSim::H>(std::max(degree + 2, 2 * d1 + 2))};
+    ch.T[1] = sim.make(1 << 20);
+    std::vector<double> coef(degree + 1, 1.0);
+    ch.eval(coef, degree + 1);
+    return sim.nmul;
+}
+
+extern "C" int fr_cheb_step_coeffs(int32_t degree, double delta, double *c) {
+    if (degree < 1 || !c) return fr_fail(FR_EINVAL, "fr_cheb_step_coeffs: bad arguments");
+    const int n = degree + 1;
+    std::vector<double> f(n), th(n);
+    for (int j = 0; j < n; ++j) {
+        th[j] = M_PI * ((double)j + 0.5) / (double)n;
+        f[j] = std::cos(th[j]) >= delta ? 1.0 : 0.0;
+    }
+    for (int k = 0; k < n; ++k) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += f[j] * std::cos((double)k * th[j]);
+        c[k] = 2.0 * acc / (double)n;
+    }
+    c[0] *= 0.5;
+    return FR_OK;
+}
+
+extern "C" int fr_cheb_ps_params(int32_t degree, int32_t *d1, int32_t *d2) {
+    if (degree < 1 || !d1 || !d2) return fr_fail(FR_EINVAL, "fr_cheb_ps_params: bad arguments");
+    int best = INT_MAX;
+    for (int a = 2; a <= degree + 1; ++a) {
+        int b = 1;
+        while ((long long)a << (b - 1) < degree) ++b;
+        if (a + b < best) {
+            best = a + b;
+            *d1 = a;
+            *d2 = b;
+        }
+    }
+    return FR_OK;
+}
+
+extern "C" int fr_stream_pool_size(int32_t units, double free_bytes, double ct_bytes) {
+    if (units <= 0 || ct_bytes <= 0) return fr_fail(FR_EINVAL, "fr_stream_pool_size: bad arguments");
+    long long s = std::min<long long>(units / 4, (long long)std::floor(0.2 * free_bytes / (40.0 * ct_bytes)));
+    s = std::min<long long>(s, 32);
+    return (int)std::max<long long>(s, 2);
+}
+
+extern "C" int fr_bsgs_rotation_set(int32_t ell, int32_t n1, int32_t *out, int32_t cap) {
+    if (ell <= 0 || n1 <= 0 || n1 > ell) return fr_fail(FR_EINVAL, "fr_bsgs_rotation_set: bad arguments");
+    const int n2 = (ell + n1 - 1) / n1;
+    int n = 0;
+    for (int i = 1; i < n1; ++i) {
+        if (out && n < cap) out[n] = i;
+        ++n;
+    }
+    for (int j = 1; j < n2; ++j) {
+        if (out && n < cap) out[n] = j * n1;
+        ++n;
+    }
+    return n;
+}

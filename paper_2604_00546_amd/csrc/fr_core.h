@@ -1,0 +1,274 @@
+// fr_core.h -- internal declarations of the gfx950 library behind include/fr.h.
+//
+// Storage conventions (private to the library):
+//  * every polynomial limb is N uint64 words holding a residue mod its prime,
+//    canonical in [0, q), in the evaluation (NTT) domain in bit-reversed
+//    order: word p of limb q_i is the value at psi_i^(2 brv(p) + 1);
+//  * ciphertexts are [2][level+1][N] (c0 limbs, then c1 limbs);
+//  * key-switching keys and database diagonals -- the constant operands of the
+//    two multiply-accumulate kernels -- are stored pre-multiplied by 2^64 mod q
+//    ("Montgomery-scaled"), so that a lazily accumulated 128-bit sum of
+//    products reduces to the canonical result with one Montgomery reduction.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+#define FR_MAXMOD 64
+#define FR_MAXLEVEL 48
+
+// ---------------------------------------------------------------------------
+// per-modulus constants
+// ---------------------------------------------------------------------------
+struct ModConst {
+    u64 q;
+    u64 mu;        // floor(2^64 / q): Barrett quotient for 64-bit inputs
+    u64 qinv_neg;  // -q^-1 mod 2^64: Montgomery
+    u64 r64;       // 2^64 mod q
+    u64 r64_sh;    // Shoup companion of r64
+    u64 r128;      // 2^128 mod q
+    u64 ninv;      // N^-1 mod q
+    u64 ninv_sh;
+};
+
+// ---------------------------------------------------------------------------
+// device modular arithmetic
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// x mod q for any 64-bit x (q < 2^62): quotient estimate is at most 1 short
+__device__ __forceinline__ u64 reduce64(u64 x, const ModConst &m) {
+    u64 r = x - mulhi64(x, m.mu) * m.q;
+    return r >= m.q ? r - m.q : r;
+}
+// a * w mod q with the Shoup companion wp = floor(w 2^64 / q); any 64-bit a
+__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 wp, u64 q) {
+    u64 r = a * w - mulhi64(a, wp) * q;
+    return r >= q ? r - q : r;
+}
+__device__ __forceinline__ u64 addq(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 subq(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// Montgomery reduction of (hi:lo) with hi < q: returns (hi:lo) 2^-64 mod q
+__device__ __forceinline__ u64 redc(u64 lo, u64 hi, const ModConst &m) {
+    u64 t = lo * m.qinv_neg;
+    u64 r = hi + mulhi64(t, m.q) + (lo != 0 ? 1u : 0u);
+    return r >= m.q ? r - m.q : r;
+}
+// 128-bit accumulator (hi:lo) of products with one Montgomery-scaled factor:
+// returns (hi:lo) 2^-64 mod q for any hi
+__device__ __forceinline__ u64 redc_any(u64 lo, u64 hi, const ModConst &m) {
+    return redc(lo, reduce64(hi, m), m);
+}
+// canonical a * b mod q (a, b < q)
+__device__ __forceinline__ u64 mulmod(u64 a, u64 b, const ModConst &m) {
+    u64 lo = a * b, hi = mulhi64(a, b);
+    return shoup(redc(lo, hi, m), m.r64, m.r64_sh, m.q);
+}
+// any 128-bit value mod q
+__device__ __forceinline__ u64 reduce128(u64 lo, u64 hi, const ModConst &m) {
+    return shoup(redc_any(lo, hi, m), m.r64, m.r64_sh, m.q);
+}
+// (hi:lo) += a * b
+__device__ __forceinline__ void mac128(u64 &lo, u64 &hi, u64 a, u64 b) {
+    u64 pl = a * b, ph = mulhi64(a, b);
+    lo += pl;
+    hi += ph + (lo < pl ? 1u : 0u);
+}
+
+__device__ __forceinline__ u32 brv(u32 x, int logN) { return __brev(x) >> (32 - logN); }
+// evaluation-domain automorphism sigma_g: output word p reads input word
+// brv(((2 brv(p) + 1) g mod 2N - 1) / 2)
+__device__ __forceinline__ u32 auto_src(u32 p, u64 g, int logN) {
+    u64 e = ((2ull * brv(p, logN) + 1ull) * g) & ((2ull << logN) - 1ull);
+    return brv((u32)((e - 1) >> 1), logN);
+}
+
+// ---------------------------------------------------------------------------
+// limb addressing inside a launch: launch limb y -> storage limb s ->
+// global modulus index (Q limbs first, then P limbs)
+// ---------------------------------------------------------------------------
+struct LimbMap {
+    int first;    // storage limb of launch limb 0
+    int skip_lo;  // storage limbs [skip_lo, skip_lo + skip_n) are skipped
+    int skip_n;
+    int nq;       // storage limbs below nq are q_s; the rest are p_(s - nq)
+    int pbase;    // global index of p_0 (= L + 1)
+    __host__ __device__ int storage(int y) const {
+        int s = first + y;
+        return s >= skip_lo ? s + skip_n : s;
+    }
+    __host__ __device__ int modidx(int s) const { return s < nq ? s : pbase + (s - nq); }
+};
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Arena {  // bump allocator over device chunks, reset per top-level call
+    struct Chunk { char *base; size_t size, used; };
+    std::vector<Chunk> chunks;
+    size_t peak = 0;
+    void *get(size_t bytes);  // 256-byte aligned; nullptr on failure
+    void reset();
+    void release();
+};
+
+struct KsTables;  // RNS conversion constants (device)
+
+struct fr_ctx {
+    int logN, N, L, nP, dnum, alpha, nmod;
+    u64 mod[FR_MAXMOD];
+    ModConst hmod[FR_MAXMOD];
+    ModConst *d_mod = nullptr;
+    // twiddles [nmod][N]: psi^brv(k), Shoup companions, inverses
+    u64 *d_tw = nullptr, *d_tw_sh = nullptr, *d_itw = nullptr, *d_itw_sh = nullptr;
+    // ModUp tables, per (level, digit): dinv[nd], dinv_sh[nd], dhat[nE][nd]
+    u64 *d_modup = nullptr;
+    size_t modup_off[FR_MAXLEVEL][8];
+    // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP],
+    // Pinv[L+1], Pinv_sh[L+1]; P mod q_i [L+1]
+    u64 *d_moddown = nullptr;
+    u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
+    // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each
+    u64 *d_rescale = nullptr;
+    // CRT lift per level: qhat_inv[i], qhat_inv_sh[i], qhat_mod64[i], Q_mod64,
+    // inv_q (double) -- laid out as [L+1][4 * (L+1) + 1] words
+    u64 *d_crt = nullptr;
+    // FFT twiddles exp(-2 pi i k / N), k < N/2, and zeta^k, k < N
+    double *d_fft_w = nullptr, *d_zeta = nullptr;
+    u32 *d_slot_pos = nullptr;  // (5^j mod 2N - 1) / 2, j < N/2
+    u64 cdt[20];
+    hipStream_t stream = nullptr;
+    Arena arena;
+    int *d_flag = nullptr;  // device error flag
+};
+
+struct KeyEntry {
+    u64 kid;
+    u64 *data;  // [dnum][2][nmod][N], eval domain, Montgomery-scaled
+};
+
+struct fr_keys {
+    fr_ctx *ctx;
+    u64 *s_eval = nullptr;   // [nmod][N] canonical eval-domain s
+    u64 *s_mont = nullptr;   // [nmod][N] Montgomery-scaled s
+    u64 *pk = nullptr;       // [2][L+1][N] eval domain canonical
+    std::vector<KeyEntry> ksk;
+    const KeyEntry *find(u64 kid) const {
+        for (auto &k : ksk)
+            if (k.kid == kid) return &k;
+        return nullptr;
+    }
+};
+
+struct fr_db {
+    fr_ctx *ctx;
+    int G, ell, B, n1, level;
+    double scale;
+    u64 *data = nullptr;  // [G][ell][level+1][N] eval domain, Montgomery-scaled
+};
+
+// ---------------------------------------------------------------------------
+// host parameter math (params.cpp)
+// ---------------------------------------------------------------------------
+namespace frh {
+u64 mulmod_h(u64 a, u64 b, u64 q);
+u64 powmod_h(u64 b, u64 e, u64 q);
+u64 invmod_h(u64 a, u64 q);
+u64 shoup_companion(u64 w, u64 q);
+bool is_prime(u64 n);
+int choose_primes(int logN, int q0_bits, int n_mid, int mid_bits, int n_special, int special_bits,
+                  u64 *out);
+u64 primitive_2n_root(u64 q, int N);
+ModConst make_modconst(u64 q, int N);
+void gauss_cdt(u64 cdt[20]);
+u64 galois_element(int N, int rot);
+int ext_limbs(const fr_ctx *c, int level);    // level+1+nP
+int num_digits(const fr_ctx *c, int level);   // ceil((level+1)/alpha)
+}  // namespace frh
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels_*.hip)
+// ---------------------------------------------------------------------------
+namespace frk {
+// NTT over `nlimbs` limbs x `npoly` polynomials; poly_stride in words
+void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride);
+void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride);
+
+void add(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly,
+         size_t so, size_t sa, size_t sb, bool subtract);
+// out[p][i] = a[p][i] * k_i (per-limb constants, Shoup)
+void mul_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, const u64 *k_sh, int nlimbs,
+               int npoly, size_t so, size_t sa);
+// out[i] = a[i] + k_i on every word (constant polynomial in eval domain)
+void add_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, int nlimbs);
+// out[p][i] = a[p][i] * b[i] (b canonical, eval domain)
+void mul_pt(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly, size_t so,
+            size_t sa);
+// tensor: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1
+void tensor(const fr_ctx *c, u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1, const u64 *b0,
+            const u64 *b1, int nlimbs);
+// out[i][p] = (accumulate ? out : 0) + in[i][auto_src(p, g)]
+void automorph(const fr_ctx *c, u64 *out, const u64 *in, u64 g, int nlimbs, int npoly, size_t so,
+               size_t si, bool accumulate);
+// multiply every limb by 2^64 mod q (to Montgomery-scaled) or by 2^-64 (back)
+void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly,
+                size_t poly_stride, bool to_mont);
+// fast base conversion of one digit: coefficient-form x[level+1][N] ->
+// D[nE][N] coefficient form on every extended limb outside the digit
+void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t);
+// U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p]
+void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
+              bool accumulate);
+// ModDown of U (eval domain, P limbs already coefficient form in Upc):
+// v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
+void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level);
+// out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)
+void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int level, int npoly,
+                    size_t so, size_t su, size_t sv, bool accumulate);
+// rescale helpers: Y[p][i] = centered(x_p) mod q_i, i < level
+void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly, size_t sy, size_t sx);
+// out[p][i] = (in[p][i] - Y[p][i]) q_level^-1
+void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly,
+                    size_t so, size_t si, size_t sy);
+// fused plaintext-diagonal multiply-accumulate of all giant steps
+void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell,
+              int db_level, int level, int baby_level);
+// key generation / encryption / decryption combiners (eval domain)
+void key_combine(const fr_ctx *c, u64 *b, const u64 *a, const u64 *e, const u64 *s_mont, const u64 *sp, int dlo,
+                 int dhi, int nlimbs);
+void encrypt_combine(const fr_ctx *c, u64 *c0, u64 *c1, const u64 *v, const u64 *e0, const u64 *e1, const u64 *msg,
+                     const u64 *pkb, const u64 *pka, int nlimbs);
+void decrypt_combine(const fr_ctx *c, u64 *out, const u64 *c0, const u64 *c1, const u64 *s_mont, int nlimbs);
+
+// randomness
+void sample_uniform(const fr_ctx *c, u64 *out, u64 seed, u64 poly, const LimbMap &map, int nlimbs);
+// signed small polynomial (ternary or Gaussian) to residues on every limb
+void sample_small(const fr_ctx *c, u64 *out, u64 seed, u64 poly, int kind, const LimbMap &map, int nlimbs);
+
+// encoding
+void encode_slots(const fr_ctx *c, u64 *out, const double *z, int n, int level, double scale, int batch,
+                  size_t zstride, size_t ostride, double *work);
+void decode_slots(const fr_ctx *c, double *z, const u64 *m_coeff, int level, double scale, double *work);
+// database slot vectors for diagonals [d0, d0 + nd) of group g
+void db_slots(const fr_ctx *c, double *out, const float *T, int K, int ell, int B, int n1, int g, int d0,
+              int nd);
+}  // namespace frk
+
+// error helpers (api.cpp)
+int fr_fail(int code, const char *fmt, ...);
+#define FR_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) return fr_fail(FR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)

@@ -1,0 +1,406 @@
+// kernels_rns.hip -- residue-number-system kernels of the hot path (gfx950):
+// pointwise ring arithmetic, the Galois automorphism, hybrid key switching
+// (ModUp fast base conversion, key inner product, ModDown), rescale and the
+// fused plaintext-diagonal multiply-accumulate of the BSGS inner sums.
+//
+// All kernels are HBM-streaming: one thread per (limb, coefficient) word,
+// 256 threads per workgroup, limbs on grid.y, polynomials on grid.z.
+#include <algorithm>
+
+#include "fr_core.h"
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kMaxDigit = 8;  // alpha <= 8 (checked at context creation)
+constexpr int kTargetsPerThread = 4;
+
+struct LimbConsts {
+    u64 v[FR_MAXMOD];
+    u64 sh[FR_MAXMOD];
+};
+
+__global__ __launch_bounds__(kT) void k_add(u64 *out, const u64 *a, const u64 *b, int N, size_t so,
+                                            size_t sa, size_t sb, const ModConst *mods, int subtract) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const u64 q = mods[i].q;
+    const size_t w = (size_t)i * N + k;
+    const u64 x = a[p * sa + w], y = b[p * sb + w];
+    out[p * so + w] = subtract ? subq(x, y, q) : addq(x, y, q);
+}
+
+__global__ __launch_bounds__(kT) void k_mul_const(u64 *out, const u64 *a, LimbConsts kc, int N, size_t so,
+                                                  size_t sa, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const size_t w = (size_t)i * N + k;
+    out[p * so + w] = shoup(a[p * sa + w], kc.v[i], kc.sh[i], mods[i].q);
+}
+
+__global__ __launch_bounds__(kT) void k_add_const(u64 *out, const u64 *a, LimbConsts kc, int N,
+                                                  const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const size_t w = (size_t)i * N + k;
+    out[w] = addq(a[w], kc.v[i], mods[i].q);
+}
+
+__global__ __launch_bounds__(kT) void k_mul_pt(u64 *out, const u64 *a, const u64 *b, int N, size_t so,
+                                               size_t sa, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const size_t w = (size_t)i * N + k;
+    out[p * so + w] = mulmod(a[p * sa + w], b[w], mods[i]);
+}
+
+__global__ __launch_bounds__(kT) void k_tensor(u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1,
+                                               const u64 *b0, const u64 *b1, int N, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const ModConst m = mods[i];
+    const size_t w = (size_t)i * N + k;
+    const u64 x0 = a0[w], x1 = a1[w], y0 = b0[w], y1 = b1[w];
+    d0[w] = mulmod(x0, y0, m);
+    d1[w] = addq(mulmod(x0, y1, m), mulmod(x1, y0, m), m.q);
+    d2[w] = mulmod(x1, y1, m);
+}
+
+__global__ __launch_bounds__(kT) void k_automorph(u64 *out, const u64 *in, u64 g, int N, int logN, size_t so,
+                                                  size_t si, const ModConst *mods, int accumulate) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const size_t w = (size_t)i * N + k;
+    const u64 v = in[p * si + (size_t)i * N + auto_src((u32)k, g, logN)];
+    out[p * so + w] = accumulate ? addq(out[p * so + w], v, mods[i].q) : v;
+}
+
+__global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, LimbMap map,
+                                                   const ModConst *mods, int to_mont) {
+    const int k = blockIdx.x * kT + threadIdx.x;
+    const int s = map.storage(blockIdx.y);
+    const ModConst m = mods[map.modidx(s)];
+    u64 &x = data[blockIdx.z * ps + (size_t)s * N + k];
+    x = to_mont ? shoup(x, m.r64, m.r64_sh, m.q) : redc(x, 0, m);
+}
+
+// ModUp of digit [lo, lo+nd): x coefficient form [level+1][N]; D[nE][N].
+// y_d = [x_{lo+d} * Dhat_d^-1]_{q_{lo+d}} (canonical), then for every
+// extended position e outside the digit: D[e] = sum_d y_d * [Dhat_d]_{r_e} mod r_e.
+__global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd, int nE, int level,
+                                              int pbase, const u64 *tab, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x;
+    const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
+    u64 y[kMaxDigit];
+#pragma unroll
+    for (int d = 0; d < kMaxDigit; ++d)
+        if (d < nd) y[d] = shoup(x[(size_t)(lo + d) * N + k], dinv[d], dinv_sh[d], mods[lo + d].q);
+    const int ntarget = nE - nd;
+    const int t0 = blockIdx.y * kTargetsPerThread, t1 = min(ntarget, t0 + kTargetsPerThread);
+    for (int te = t0; te < t1; ++te) {
+        const int e = te < lo ? te : te + nd;
+        const int gm = e <= level ? e : pbase + (e - level - 1);
+        u64 al = 0, ah = 0;
+#pragma unroll
+        for (int d = 0; d < kMaxDigit; ++d)
+            if (d < nd) mac128(al, ah, y[d], dhat[(size_t)e * nd + d]);
+        D[(size_t)e * N + k] = reduce128(al, ah, mods[gm]);
+    }
+}
+
+// U{0,1}[e][p] (+)= sum_t D_t[e][src(p)] * ksk_t{b,a}[gm(e)][p]; keys are
+// Montgomery-scaled so one reduction yields the canonical sum.
+__global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
+                                                 int logN, int nE, int level, int pbase, int ndig, int nmod,
+                                                 const ModConst *mods, int accumulate) {
+    const int p = blockIdx.x * kT + threadIdx.x, e = blockIdx.y;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
+    u64 l0 = 0, h0 = 0, l1 = 0, h1 = 0;
+    for (int t = 0; t < ndig; ++t) {
+        const u64 d = D[((size_t)t * nE + e) * N + src];
+        const u64 kb = ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
+        const u64 ka = ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+        mac128(l0, h0, d, kb);
+        mac128(l1, h1, d, ka);
+    }
+    u64 u0 = redc_any(l0, h0, m), u1 = redc_any(l1, h1, m);
+    const size_t w = (size_t)e * N + p;
+    if (accumulate) {
+        u0 = addq(u0, U0[w], m.q);
+        u1 = addq(u1, U1[w], m.q);
+    }
+    U0[w] = u0;
+    U1[w] = u1;
+}
+
+// ModDown base conversion P -> Q_level of the P limbs in coefficient form:
+// y_j = [u_j * Phat_j^-1]_{p_j}, V_i = sum_j y_j [Phat_j]_{q_i} mod q_i.
+// tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1], Pinv_sh[L+1]
+__global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP, int pbase,
+                                                    const u64 *tab, const ModConst *mods, size_t sv, size_t su) {
+    const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
+    const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
+    u64 y[kMaxDigit];
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; ++j)
+        if (j < nP) y[j] = shoup(Upc[poly * su + (size_t)j * N + k], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
+    const int i0 = blockIdx.y * kTargetsPerThread, i1 = min(level + 1, i0 + kTargetsPerThread);
+    for (int i = i0; i < i1; ++i) {
+        u64 al = 0, ah = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; ++j)
+            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
+        V[poly * sv + (size_t)i * N + k] = reduce128(al, ah, mods[i]);
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_moddown_finish(u64 *out, const u64 *U, const u64 *V, int N, const u64 *pinv,
+                                                       const u64 *pinv_sh, const ModConst *mods, size_t so,
+                                                       size_t su, size_t sv, int accumulate) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const u64 q = mods[i].q;
+    const size_t w = (size_t)i * N + k;
+    u64 r = shoup(subq(U[p * su + w], V[p * sv + w], q), pinv[i], pinv_sh[i], q);
+    if (accumulate) r = addq(r, out[p * so + w], q);
+    out[p * so + w] = r;
+}
+
+// Y[p][i] = centered(x_p) mod q_i, i < level; x_p canonical mod q_level
+__global__ __launch_bounds__(kT) void k_rescale_prep(u64 *Y, const u64 *xtop, int N, int level, size_t sy,
+                                                     size_t sx, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const u64 ql = mods[level].q;
+    const ModConst mi = mods[i];
+    const u64 x = xtop[p * sx + k];
+    u64 v;
+    if (x > (ql >> 1)) {
+        const u64 neg = reduce64(ql - x, mi);
+        v = neg ? mi.q - neg : 0;
+    } else {
+        v = reduce64(x, mi);
+    }
+    Y[p * sy + (size_t)i * N + k] = v;
+}
+
+__global__ __launch_bounds__(kT) void k_rescale_finish(u64 *out, const u64 *in, const u64 *Y, int N, const u64 *qinv,
+                                                       const u64 *qinv_sh, const ModConst *mods, size_t so,
+                                                       size_t si, size_t sy) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const u64 q = mods[i].q;
+    const size_t w = (size_t)i * N + k;
+    out[p * so + w] = shoup(subq(in[p * si + w], Y[p * sy + w], q), qinv[i], qinv_sh[i], q);
+}
+
+// Fused multiply-accumulate of the BSGS inner sums (Eq. bsgs2):
+//   P_j[c][m][k] = sum_i baby_i[c][m][k] * diag_{j n1 + i}[m][k]
+// for a chunk of <= 32 baby steps and NJ giant steps per launch; each thread
+// keeps 2 NJ lazy 128-bit accumulators in registers, reads every diagonal
+// word once and every baby word once per launch.
+struct BabyPtrs {
+    const u64 *p[32];
+};
+
+template <int NJ>
+__global__ __launch_bounds__(kT) void k_bsgs_mac(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
+                                                 int ell, const u64 *diag, int dbl, int bl, int lv, int N,
+                                                 const ModConst *mods, int accumulate) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y;
+    u64 a0l[NJ], a0h[NJ], a1l[NJ], a1h[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) a0l[jj] = a0h[jj] = a1l[jj] = a1h[jj] = 0;
+    for (int ii = 0; ii < nb; ++ii) {
+        const int i = i0 + ii;
+        const u64 b0 = bp.p[ii][(size_t)m * N + k];
+        const u64 b1 = bp.p[ii][(size_t)(bl + 1 + m) * N + k];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int d = (j0 + jj) * n1 + i;
+            if (jj < nj && d < ell) {
+                const u64 w = diag[((size_t)d * (dbl + 1) + m) * N + k];
+                mac128(a0l[jj], a0h[jj], b0, w);
+                mac128(a1l[jj], a1h[jj], b1, w);
+            }
+        }
+    }
+    const ModConst mc = mods[m];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        if (jj < nj) {
+            const size_t o0 = ((size_t)(j0 + jj) * 2 * (lv + 1) + m) * N + k;
+            const size_t o1 = o0 + (size_t)(lv + 1) * N;
+            u64 r0 = redc_any(a0l[jj], a0h[jj], mc), r1 = redc_any(a1l[jj], a1h[jj], mc);
+            if (accumulate) {
+                r0 = addq(r0, P[o0], mc.q);
+                r1 = addq(r1, P[o1], mc.q);
+            }
+            P[o0] = r0;
+            P[o1] = r1;
+        }
+    }
+}
+
+// b = e - a s + [limb in digit] (P mod q) s'   (key generation, eval domain;
+// limbs are global modulus indices; s_mont Montgomery-scaled)
+__global__ __launch_bounds__(kT) void k_key_combine(u64 *b, const u64 *a, const u64 *e, const u64 *s_mont,
+                                                    const u64 *sp, LimbConsts pm, int dlo, int dhi, int N,
+                                                    const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const ModConst m = mods[i];
+    const size_t w = (size_t)i * N + k;
+    const u64 x = a[w];
+    u64 r = subq(e[w], redc(x * s_mont[w], mulhi64(x, s_mont[w]), m), m.q);
+    if (sp && i >= dlo && i < dhi) r = addq(r, shoup(sp[w], pm.v[i], pm.sh[i], m.q), m.q);
+    b[w] = r;
+}
+
+// c0 = v b + e0 + m, c1 = v a + e1 (encryption, eval domain)
+__global__ __launch_bounds__(kT) void k_encrypt_combine(u64 *c0, u64 *c1, const u64 *v, const u64 *e0, const u64 *e1,
+                                                        const u64 *msg, const u64 *pkb, const u64 *pka, int N,
+                                                        const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const ModConst m = mods[i];
+    const size_t w = (size_t)i * N + k;
+    const u64 vv = v[w];
+    c0[w] = addq(addq(mulmod(vv, pkb[w], m), e0[w], m.q), msg[w], m.q);
+    c1[w] = addq(mulmod(vv, pka[w], m), e1[w], m.q);
+}
+
+// m = c0 + c1 s (decryption, eval domain; s_mont Montgomery-scaled)
+__global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0, const u64 *c1, const u64 *s_mont,
+                                                        int N, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const ModConst m = mods[i];
+    const size_t w = (size_t)i * N + k;
+    const u64 x = c1[w], s = s_mont[w];
+    out[w] = addq(c0[w], redc(x * s, mulhi64(x, s), m), m.q);
+}
+
+inline dim3 grid(const fr_ctx *c, int ny, int nz) { return dim3(c->N / kT, ny, nz); }
+
+}  // namespace
+
+namespace frk {
+
+void add(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly, size_t so, size_t sa,
+         size_t sb, bool subtract) {
+    hipLaunchKernelGGL(k_add, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, a, b, c->N, so, sa, sb, c->d_mod,
+                       (int)subtract);
+}
+
+void mul_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, const u64 *k_sh, int nlimbs, int npoly,
+               size_t so, size_t sa) {
+    LimbConsts kc;
+    for (int i = 0; i < nlimbs; ++i) {
+        kc.v[i] = k[i];
+        kc.sh[i] = k_sh[i];
+    }
+    hipLaunchKernelGGL(k_mul_const, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, a, kc, c->N, so, sa,
+                       c->d_mod);
+}
+
+void add_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, int nlimbs) {
+    LimbConsts kc;
+    for (int i = 0; i < nlimbs; ++i) kc.v[i] = k[i];
+    hipLaunchKernelGGL(k_add_const, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, out, a, kc, c->N, c->d_mod);
+}
+
+void mul_pt(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly, size_t so, size_t sa) {
+    hipLaunchKernelGGL(k_mul_pt, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, a, b, c->N, so, sa, c->d_mod);
+}
+
+void tensor(const fr_ctx *c, u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1, const u64 *b0, const u64 *b1,
+            int nlimbs) {
+    hipLaunchKernelGGL(k_tensor, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, d0, d1, d2, a0, a1, b0, b1, c->N,
+                       c->d_mod);
+}
+
+void automorph(const fr_ctx *c, u64 *out, const u64 *in, u64 g, int nlimbs, int npoly, size_t so, size_t si,
+               bool accumulate) {
+    hipLaunchKernelGGL(k_automorph, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, in, g, c->N, c->logN, so,
+                       si, c->d_mod, (int)accumulate);
+}
+
+void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
+                bool to_mont) {
+    hipLaunchKernelGGL(k_mont_scale, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, data, c->N, poly_stride, map,
+                       c->d_mod, (int)to_mont);
+}
+
+void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t) {
+    const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
+    const int nE = level + 1 + c->nP;
+    const int ntarget = nE - nd;
+    dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, 1);
+    hipLaunchKernelGGL(k_modup, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
+                       c->d_modup + c->modup_off[level][t], c->d_mod);
+}
+
+void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate) {
+    const int nE = level + 1 + c->nP;
+    const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
+    hipLaunchKernelGGL(k_ks_inner, grid(c, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN, nE,
+                       level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate);
+}
+
+void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level) {
+    dim3 g(c->N / kT, (level + 1 + kTargetsPerThread - 1) / kTargetsPerThread, 2);
+    hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->d_moddown,
+                       c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
+}
+
+void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int level, int npoly, size_t so,
+                    size_t su, size_t sv, bool accumulate) {
+    const u64 *pinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;
+    const u64 *pinv_sh = pinv + (c->L + 1);
+    hipLaunchKernelGGL(k_moddown_finish, grid(c, level + 1, npoly), dim3(kT), 0, c->stream, out, U, V, c->N, pinv,
+                       pinv_sh, c->d_mod, so, su, sv, (int)accumulate);
+}
+
+void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly, size_t sy, size_t sx) {
+    hipLaunchKernelGGL(k_rescale_prep, grid(c, level, npoly), dim3(kT), 0, c->stream, Y, xtop, c->N, level, sy, sx,
+                       c->d_mod);
+}
+
+void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly, size_t so,
+                    size_t si, size_t sy) {
+    const u64 *qinv = c->d_rescale + (size_t)level * (c->L + 1) * 2;
+    const u64 *qinv_sh = qinv + (c->L + 1);
+    hipLaunchKernelGGL(k_rescale_finish, grid(c, level, npoly), dim3(kT), 0, c->stream, out, in, Y, c->N, qinv,
+                       qinv_sh, c->d_mod, so, si, sy);
+}
+
+void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell, int db_level,
+              int level, int baby_level) {
+    const int n2 = (ell + n1 - 1) / n1;
+    constexpr int NJ = 16;
+    for (int j0 = 0; j0 < n2; j0 += NJ) {
+        const int nj = std::min(NJ, n2 - j0);
+        for (int i0 = 0; i0 < n1; i0 += 32) {
+            const int nb = std::min(32, n1 - i0);
+            BabyPtrs bp;
+            for (int ii = 0; ii < 32; ++ii) bp.p[ii] = ii < nb ? baby[i0 + ii] : nullptr;
+            hipLaunchKernelGGL(k_bsgs_mac<NJ>, grid(c, level + 1, 1), dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0,
+                               nj, ell, diag, db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+        }
+    }
+}
+
+void key_combine(const fr_ctx *c, u64 *b, const u64 *a, const u64 *e, const u64 *s_mont, const u64 *sp, int dlo,
+                 int dhi, int nlimbs) {
+    LimbConsts pm;
+    for (int i = 0; i < nlimbs && i < FR_MAXMOD; ++i) {
+        pm.v[i] = i <= c->L ? c->P_mod_q[i] : 0;
+        pm.sh[i] = i <= c->L ? c->P_mod_q_sh[i] : 0;
+    }
+    hipLaunchKernelGGL(k_key_combine, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, b, a, e, s_mont, sp, pm, dlo, dhi,
+                       c->N, c->d_mod);
+}
+
+void encrypt_combine(const fr_ctx *c, u64 *c0, u64 *c1, const u64 *v, const u64 *e0, const u64 *e1, const u64 *msg,
+                     const u64 *pkb, const u64 *pka, int nlimbs) {
+    hipLaunchKernelGGL(k_encrypt_combine, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, c0, c1, v, e0, e1, msg, pkb,
+                       pka, c->N, c->d_mod);
+}
+
+void decrypt_combine(const fr_ctx *c, u64 *out, const u64 *c0, const u64 *c1, const u64 *s_mont, int nlimbs) {
+    hipLaunchKernelGGL(k_decrypt_combine, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, out, c0, c1, s_mont, c->N,
+                       c->d_mod);
+}
+
+}  // namespace frk

@@ -1,0 +1,428 @@
+"""Python binding of the gfx950 library (include/fr.h), same names as the C ABI.
+
+Argument marshalling only: every homomorphic step runs in libfrhip.so's
+kernels.  PyTorch provides the device buffers of ciphertexts and plaintexts
+(int64 tensors holding the uint64 words) and the stream.  There is no
+fallback: if the built library is missing this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrhip.so")
+
+
+class FrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+FR_OK, FR_EINVAL, FR_ENOMEM, FR_ELEVEL, FR_ENOKEY, FR_EHIP, FR_ERANGE = 0, -1, -2, -3, -4, -5, -6
+
+
+class Params(C.Structure):
+    _fields_ = [("log_n", C.c_int32), ("q0_bits", C.c_int32), ("n_mid", C.c_int32), ("mid_bits", C.c_int32),
+                ("n_special", C.c_int32), ("special_bits", C.c_int32), ("dnum", C.c_int32)]
+
+
+class CtDesc(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("level", C.c_int32), ("cap", C.c_int32), ("scale", C.c_double)]
+
+
+PtDesc = CtDesc  # same layout (data, level, cap, scale)
+
+_P = C.c_void_p
+_U64P = C.POINTER(C.c_uint64)
+_DP = C.POINTER(C.c_double)
+_I32P = C.POINTER(C.c_int32)
+_CTP = C.POINTER(CtDesc)
+_lib = None
+
+# symbol -> (restype, argtypes); every symbol declared in include/fr.h
+SIGNATURES = {
+    "fr_last_error": (C.c_char_p, []),
+    "fr_ctx_create": (C.c_int, [C.POINTER(Params), C.POINTER(_P)]),
+    "fr_ctx_destroy": (None, [_P]),
+    "fr_ctx_set_stream": (C.c_int, [_P, _P]),
+    "fr_ctx_sync": (C.c_int, [_P]),
+    "fr_ctx_dims": (C.c_int, [_P, _I32P, _I32P, _I32P, _I32P, _I32P]),
+    "fr_ctx_modulus": (C.c_uint64, [_P, C.c_int32]),
+    "fr_keygen": (C.c_int, [_P, C.c_uint64, _I32P, C.c_int32, C.POINTER(_P)]),
+    "fr_keys_destroy": (None, [_P]),
+    "fr_keys_export": (C.c_int, [_P, _P, C.c_int32, C.c_uint64, _U64P]),
+    "fr_encode": (C.c_int, [_P, _DP, C.c_int32, C.c_int32, C.c_double, _CTP]),
+    "fr_encode_device": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_double, _CTP]),
+    "fr_pt_import": (C.c_int, [_P, _U64P, C.c_int32, C.c_double, _CTP]),
+    "fr_pt_export": (C.c_int, [_P, _CTP, _U64P]),
+    "fr_encrypt": (C.c_int, [_P, _P, _CTP, C.c_uint64, _CTP]),
+    "fr_decrypt": (C.c_int, [_P, _P, _CTP, _CTP]),
+    "fr_decode": (C.c_int, [_P, _CTP, _DP, C.c_int32]),
+    "fr_ct_import": (C.c_int, [_P, _U64P, C.c_int32, C.c_double, _CTP]),
+    "fr_ct_export": (C.c_int, [_P, _CTP, _U64P]),
+    "fr_rotate_hoisted": (C.c_int, [_P, _P, _CTP, _I32P, C.c_int32, _CTP]),
+    "fr_rescale": (C.c_int, [_P, _CTP, _CTP]),
+    "fr_add": (C.c_int, [_P, _CTP, _CTP, _CTP]),
+    "fr_sub": (C.c_int, [_P, _CTP, _CTP, _CTP]),
+    "fr_mul_plain": (C.c_int, [_P, _CTP, _CTP, _CTP]),
+    "fr_mul_relin_rescale": (C.c_int, [_P, _P, _CTP, _CTP, _CTP]),
+    "fr_mul_int": (C.c_int, [_P, _CTP, C.c_int64, _CTP]),
+    "fr_add_const": (C.c_int, [_P, _CTP, C.c_double, _CTP]),
+    "fr_drop_to": (C.c_int, [_P, _CTP, C.c_int32, _CTP]),
+    "fr_db_load": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                             C.c_double, C.POINTER(_P)]),
+    "fr_db_import": (C.c_int, [_P, _U64P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                               C.POINTER(_P)]),
+    "fr_db_export": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _U64P]),
+    "fr_db_groups": (C.c_int, [_P]),
+    "fr_db_destroy": (None, [_P]),
+    "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
+    "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
+    "fr_cheb_step_coeffs": (C.c_int, [C.c_int32, C.c_double, _DP]),
+    "fr_cheb_ps_params": (C.c_int, [C.c_int32, _I32P, _I32P]),
+    "fr_cheb_out_level": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
+    "fr_cheb_mult_count": (C.c_int, [C.c_int32, C.c_int32]),
+    "fr_stream_pool_size": (C.c_int, [C.c_int32, C.c_double, C.c_double]),
+    "fr_bsgs_rotation_set": (C.c_int, [C.c_int32, C.c_int32, _I32P, C.c_int32]),
+}
+
+
+def lib():
+    """Load libfrhip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc for gfx950) first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != FR_OK:
+        raise FrError(rc, f"{what}: {lib().fr_last_error().decode()}")
+
+
+def _u64(a: np.ndarray):
+    return a.ctypes.data_as(_U64P)
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------
+def cheb_step_coeffs(degree: int, delta: float) -> np.ndarray:
+    c = np.zeros(degree + 1)
+    _check(lib().fr_cheb_step_coeffs(degree, delta, c.ctypes.data_as(_DP)), "fr_cheb_step_coeffs")
+    return c
+
+
+def cheb_ps_params(degree: int):
+    a, b = C.c_int32(), C.c_int32()
+    _check(lib().fr_cheb_ps_params(degree, C.byref(a), C.byref(b)), "fr_cheb_ps_params")
+    return a.value, b.value
+
+
+def cheb_out_level(in_level: int, degree: int, d1: int) -> int:
+    return lib().fr_cheb_out_level(in_level, degree, d1)
+
+
+def cheb_mult_count(degree: int, d1: int) -> int:
+    return lib().fr_cheb_mult_count(degree, d1)
+
+
+def stream_pool_size(compute_units: int, free_bytes: float, ct_bytes: float) -> int:
+    return lib().fr_stream_pool_size(compute_units, free_bytes, ct_bytes)
+
+
+def bsgs_rotation_set(ell: int, n1: int) -> List[int]:
+    n = lib().fr_bsgs_rotation_set(ell, n1, None, 0)
+    out = (C.c_int32 * max(n, 1))()
+    lib().fr_bsgs_rotation_set(ell, n1, out, n)
+    return list(out[:n])
+
+
+# ---------------------------------------------------------------------------
+# device objects
+# ---------------------------------------------------------------------------
+class Ct:
+    """A ciphertext in a torch int64 buffer [2][cap+1][N] on the device."""
+
+    def __init__(self, ctx: "Context", cap: int):
+        import torch
+        self.ctx = ctx
+        self.buf = torch.empty((2 * (cap + 1) * ctx.N,), dtype=torch.int64, device=ctx.device)
+        self.desc = CtDesc(self.buf.data_ptr(), -1, cap, 0.0)
+
+    @property
+    def level(self) -> int:
+        return self.desc.level
+
+    @property
+    def scale(self) -> float:
+        return self.desc.scale
+
+    @property
+    def ref(self):
+        return C.byref(self.desc)
+
+
+class Pt(Ct):
+    """A plaintext in a torch int64 buffer [cap+1][N] on the device."""
+
+    def __init__(self, ctx: "Context", cap: int):
+        import torch
+        self.ctx = ctx
+        self.buf = torch.empty(((cap + 1) * ctx.N,), dtype=torch.int64, device=ctx.device)
+        self.desc = CtDesc(self.buf.data_ptr(), -1, cap, 0.0)
+
+
+class Keys:
+    def __init__(self, ctx, ptr, rots):
+        self.ctx, self.ptr, self.rots = ctx, ptr, list(rots)
+
+    def __del__(self):
+        try:
+            lib().fr_keys_destroy(self.ptr)
+        except Exception:
+            pass
+
+    def export_secret(self) -> np.ndarray:
+        out = np.zeros(self.ctx.N, dtype=np.uint64)
+        _check(lib().fr_keys_export(self.ctx.ptr, self.ptr, 0, 0, _u64(out)), "fr_keys_export")
+        return out.view(np.int64)
+
+    def export_pk(self) -> np.ndarray:
+        c = self.ctx
+        out = np.zeros(2 * (c.L + 1) * c.N, dtype=np.uint64)
+        _check(lib().fr_keys_export(c.ptr, self.ptr, 1, 0, _u64(out)), "fr_keys_export")
+        return out.reshape(2, c.L + 1, c.N)
+
+    def export_ksk(self, kid: int) -> np.ndarray:
+        c = self.ctx
+        nm = c.L + 1 + c.nP
+        out = np.zeros(c.dnum * 2 * nm * c.N, dtype=np.uint64)
+        _check(lib().fr_keys_export(c.ptr, self.ptr, 2, kid, _u64(out)), "fr_keys_export")
+        return out.reshape(c.dnum, 2, nm, c.N)
+
+
+class Db:
+    def __init__(self, ctx, ptr, ell, B, n1, level, scale):
+        self.ctx, self.ptr = ctx, ptr
+        self.ell, self.B, self.n1, self.level, self.scale = ell, B, n1, level, scale
+        self.G = lib().fr_db_groups(ptr)
+
+    def __del__(self):
+        try:
+            lib().fr_db_destroy(self.ptr)
+        except Exception:
+            pass
+
+    def export(self, g: int, d: int) -> np.ndarray:
+        out = np.zeros((self.level + 1) * self.ctx.N, dtype=np.uint64)
+        _check(lib().fr_db_export(self.ctx.ptr, self.ptr, g, d, _u64(out)), "fr_db_export")
+        return out.reshape(self.level + 1, self.ctx.N)
+
+
+class Context:
+    """fr_ctx: parameter set, tables and stream (torch's current stream)."""
+
+    def __init__(self, log_n, q0_bits, n_mid, mid_bits, n_special, special_bits, dnum, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2604_00546_amd needs a ROCm GPU (gfx950); none is visible")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        L = lib()
+        p = Params(log_n, q0_bits, n_mid, mid_bits, n_special, special_bits, dnum)
+        ptr = _P()
+        _check(L.fr_ctx_create(C.byref(p), C.byref(ptr)), "fr_ctx_create")
+        self.ptr = ptr
+        n, l, ns, a, d = (C.c_int32() for _ in range(5))
+        L.fr_ctx_dims(ptr, C.byref(n), C.byref(l), C.byref(ns), C.byref(a), C.byref(d))
+        self.N, self.L, self.nP, self.alpha, self.dnum = n.value, l.value, ns.value, a.value, d.value
+        self.moduli = [int(L.fr_ctx_modulus(ptr, i)) for i in range(self.L + 1 + self.nP)]
+        self.q, self.p = self.moduli[: self.L + 1], self.moduli[self.L + 1:]
+        self.set_stream()
+
+    def __del__(self):
+        try:
+            lib().fr_ctx_destroy(self.ptr)
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib().fr_ctx_set_stream(self.ptr, C.c_void_p(s.cuda_stream)), "fr_ctx_set_stream")
+
+    def sync(self):
+        _check(lib().fr_ctx_sync(self.ptr), "fr_ctx_sync")
+
+    # allocation -------------------------------------------------------------
+    def new_ct(self, cap: int) -> Ct:
+        return Ct(self, cap)
+
+    def new_pt(self, cap: int) -> Pt:
+        return Pt(self, cap)
+
+    # keys ------------------------------------------------------------------------
+    def keygen(self, seed: int, rots: Sequence[int]) -> Keys:
+        r = np.ascontiguousarray(list(rots), dtype=np.int32)
+        ptr = _P()
+        _check(lib().fr_keygen(self.ptr, seed, r.ctypes.data_as(_I32P), len(r), C.byref(ptr)), "fr_keygen")
+        return Keys(self, ptr, rots)
+
+    # encode / encrypt -----------------------------------------------------------------
+    def encode(self, z, level: int, scale: float) -> Pt:
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        pt = self.new_pt(level)
+        _check(lib().fr_encode(self.ptr, z.ctypes.data_as(_DP), len(z), level, scale, pt.ref), "fr_encode")
+        return pt
+
+    def pt_import(self, coeffs, level: int, scale: float) -> Pt:
+        m = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        pt = self.new_pt(level)
+        _check(lib().fr_pt_import(self.ptr, _u64(m), level, scale, pt.ref), "fr_pt_import")
+        return pt
+
+    def pt_export(self, pt: Pt) -> np.ndarray:
+        out = np.zeros((pt.level + 1) * self.N, dtype=np.uint64)
+        _check(lib().fr_pt_export(self.ptr, pt.ref, _u64(out)), "fr_pt_export")
+        return out.reshape(pt.level + 1, self.N)
+
+    def ct_import(self, coeffs, level: int, scale: float) -> Ct:
+        m = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        ct = self.new_ct(level)
+        _check(lib().fr_ct_import(self.ptr, _u64(m), level, scale, ct.ref), "fr_ct_import")
+        return ct
+
+    def ct_export(self, ct: Ct) -> np.ndarray:
+        out = np.zeros(2 * (ct.level + 1) * self.N, dtype=np.uint64)
+        _check(lib().fr_ct_export(self.ptr, ct.ref, _u64(out)), "fr_ct_export")
+        return out.reshape(2, ct.level + 1, self.N)
+
+    def encrypt(self, keys: Keys, pt: Pt, seed: int) -> Ct:
+        ct = self.new_ct(pt.level)
+        _check(lib().fr_encrypt(self.ptr, keys.ptr, pt.ref, seed, ct.ref), "fr_encrypt")
+        return ct
+
+    def decrypt(self, keys: Keys, ct: Ct) -> Pt:
+        pt = self.new_pt(ct.level)
+        _check(lib().fr_decrypt(self.ptr, keys.ptr, ct.ref, pt.ref), "fr_decrypt")
+        return pt
+
+    def decode(self, pt: Pt, n: int | None = None) -> np.ndarray:
+        n = self.N // 2 if n is None else n
+        out = np.zeros(n, dtype=np.float64)
+        _check(lib().fr_decode(self.ptr, pt.ref, out.ctypes.data_as(_DP), n), "fr_decode")
+        return out
+
+    def decrypt_decode(self, keys: Keys, ct: Ct, n: int | None = None) -> np.ndarray:
+        return self.decode(self.decrypt(keys, ct), n)
+
+    # homomorphic ops ----------------------------------------------------------------------
+    def rotate_hoisted(self, keys: Keys, ct: Ct, rots: Sequence[int], outs: List[Ct] | None = None) -> List[Ct]:
+        rots = list(rots)
+        if outs is None:
+            outs = [self.new_ct(ct.level) for _ in rots]
+        arr = (CtDesc * len(rots))(*[o.desc for o in outs])
+        r = np.ascontiguousarray(rots, dtype=np.int32)
+        _check(lib().fr_rotate_hoisted(self.ptr, keys.ptr, ct.ref, r.ctypes.data_as(_I32P), len(r), arr),
+               "fr_rotate_hoisted")
+        for o, d in zip(outs, arr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
+
+    def rescale(self, ct: Ct) -> Ct:
+        out = self.new_ct(max(ct.level - 1, 0))
+        _check(lib().fr_rescale(self.ptr, ct.ref, out.ref), "fr_rescale")
+        return out
+
+    def add(self, a: Ct, b: Ct) -> Ct:
+        out = self.new_ct(a.level)
+        _check(lib().fr_add(self.ptr, a.ref, b.ref, out.ref), "fr_add")
+        return out
+
+    def sub(self, a: Ct, b: Ct) -> Ct:
+        out = self.new_ct(a.level)
+        _check(lib().fr_sub(self.ptr, a.ref, b.ref, out.ref), "fr_sub")
+        return out
+
+    def mul_plain(self, a: Ct, p: Pt) -> Ct:
+        out = self.new_ct(min(a.level, p.level))
+        _check(lib().fr_mul_plain(self.ptr, a.ref, p.ref, out.ref), "fr_mul_plain")
+        return out
+
+    def mul_relin_rescale(self, keys: Keys, a: Ct, b: Ct) -> Ct:
+        out = self.new_ct(max(a.level - 1, 0))
+        _check(lib().fr_mul_relin_rescale(self.ptr, keys.ptr, a.ref, b.ref, out.ref), "fr_mul_relin_rescale")
+        return out
+
+    def mul_int(self, a: Ct, k: int) -> Ct:
+        out = self.new_ct(a.level)
+        _check(lib().fr_mul_int(self.ptr, a.ref, k, out.ref), "fr_mul_int")
+        return out
+
+    def add_const(self, a: Ct, c: float) -> Ct:
+        out = self.new_ct(a.level)
+        _check(lib().fr_add_const(self.ptr, a.ref, c, out.ref), "fr_add_const")
+        return out
+
+    def drop_to(self, a: Ct, level: int) -> Ct:
+        out = self.new_ct(level)
+        _check(lib().fr_drop_to(self.ptr, a.ref, level, out.ref), "fr_drop_to")
+        return out
+
+    # database / matvec / chebyshev -------------------------------------------------------------
+    def db_load(self, T, ell: int, B: int, n1: int, level: int, scale: float) -> Db:
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        ptr = _P()
+        _check(lib().fr_db_load(self.ptr, T.ctypes.data_as(C.POINTER(C.c_float)), T.shape[0], ell, B, n1, level,
+                                scale, C.byref(ptr)), "fr_db_load")
+        return Db(self, ptr, ell, B, n1, level, scale)
+
+    def db_import(self, coeffs, G: int, ell: int, B: int, n1: int, level: int, scale: float) -> Db:
+        m = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        ptr = _P()
+        _check(lib().fr_db_import(self.ptr, _u64(m), G, ell, B, n1, level, scale, C.byref(ptr)), "fr_db_import")
+        return Db(self, ptr, ell, B, n1, level, scale)
+
+    def bsgs_diag_matvec(self, keys: Keys, baby: Sequence[Ct], db: Db, group: int, out: Ct | None = None) -> Ct:
+        arr = (CtDesc * len(baby))(*[b.desc for b in baby])
+        if out is None:
+            out = self.new_ct(max(min(baby[0].level, db.level) - 1, 0))
+        _check(lib().fr_bsgs_diag_matvec(self.ptr, keys.ptr, arr, len(baby), db.ptr, group, out.ref),
+               "fr_bsgs_diag_matvec")
+        return out
+
+    def chebyshev_eval(self, keys: Keys, ct: Ct, coeffs, d1: int, out: Ct | None = None) -> Ct:
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        if out is None:
+            out = self.new_ct(max(cheb_out_level(ct.level, len(c) - 1, d1), 0))
+        _check(lib().fr_chebyshev_eval(self.ptr, keys.ptr, ct.ref, c.ctypes.data_as(_DP), len(c) - 1, d1, out.ref),
+               "fr_chebyshev_eval")
+        return out
+
+
+def small_params():
+    """N = 2^12; Q = one 50-bit + two 40-bit primes; P = one 60-bit prime; dnum 3."""
+    return dict(log_n=12, q0_bits=50, n_mid=2, mid_bits=40, n_special=1, special_bits=60, dnum=3)
+
+
+def deep_small_params():
+    """N = 2^12 with the paper-scale modulus chain (room for the Chebyshev ladder)."""
+    return dict(log_n=12, q0_bits=60, n_mid=14, mid_bits=40, n_special=5, special_bits=60, dnum=3)
+
+
+def paper_params():
+    """N = 2^16; Q = one 60-bit + fourteen 40-bit primes; P = five 60-bit primes; dnum 3."""
+    return dict(log_n=16, q0_bits=60, n_mid=14, mid_bits=40, n_special=5, special_bits=60, dnum=3)

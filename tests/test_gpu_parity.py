@@ -1,0 +1,243 @@
+"""GPU parity: the HIP library against the CPU oracle, op by op.
+
+Ciphertext limbs are compared bit-exactly in coefficient form after every
+homomorphic op, with the same key seed, encryption seeds and integer
+plaintexts on both sides (integer plaintexts come from the oracle's
+encoder).  The FP64 encoders are compared separately (within 1 per
+coefficient).  Decrypted scores are held to 2^-20 of the FP64 inner products
+and Chebyshev outputs to 2^-12 of an FP64 evaluation of the same polynomial.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_00546_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ROTS_C1 = list(range(1, 8)) + [8 * j for j in range(1, 16)]
+
+
+def _oparams(p):
+    return dict(logN=p["log_n"], q0_bits=p["q0_bits"], n_mid=p["n_mid"], mid_bits=p["mid_bits"],
+                n_special=p["n_special"], special_bits=p["special_bits"], dnum=p["dnum"])
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2604_00546_amd import fr
+    return fr
+
+
+@pytest.fixture(scope="module")
+def pair(F, oracle_mod):
+    """(gpu context, oracle context) at N = 2^12, the small modulus chain."""
+    p = F.small_params()
+    return F.Context(**p), oracle_mod.Context(**_oparams(p))
+
+
+@pytest.fixture(scope="module")
+def keys(pair):
+    g, o = pair
+    seed = synth.int_seed(1, synth.SUB_KEYS)
+    return g.keygen(seed, ROTS_C1), o.keygen(seed, ROTS_C1)
+
+
+def _enc_pair(pair, keys, z, level, scale, seed):
+    """Encrypt the oracle's integer encoding of z on both sides."""
+    g, o = pair
+    opt = o.encode(z, level, scale)
+    gpt = g.pt_import(opt.coeffs(), level, scale)
+    return g.encrypt(keys[0], gpt, seed), o.encrypt(keys[1], opt, seed)
+
+
+def _same(gctx, gct, oct_):
+    a, b = gctx.ct_export(gct), oct_.coeffs()
+    assert gct.level == oct_.level
+    assert gct.scale == oct_.scale
+    assert a.shape == b.shape
+    bad = np.argwhere(a != b)
+    assert len(bad) == 0, f"{len(bad)} words differ, first at {bad[:3].tolist()}"
+
+
+def test_primes_match_oracle(pair):
+    g, o = pair
+    assert g.moduli == o.moduli
+
+
+def test_pt_roundtrip_through_ntt(pair):
+    g, o = pair
+    rnd = np.random.default_rng(1)
+    m = np.stack([rnd.integers(0, q, g.N, dtype=np.uint64) for q in g.q])
+    pt = g.pt_import(m, g.L, 1.0)
+    assert np.array_equal(g.pt_export(pt), m)
+
+
+def test_keys_match_oracle(pair, keys):
+    g, o = pair
+    kg, ko = keys
+    assert np.array_equal(kg.export_secret(), ko.secret())
+    assert np.array_equal(kg.export_pk(), ko.pk())
+    for kid in [0, o.galois(1), o.galois(8), o.galois(120)]:
+        assert np.array_equal(kg.export_ksk(kid), ko.ksk(kid)), kid
+
+
+def test_encode_within_one(pair):
+    g, o = pair
+    z = np.random.default_rng(2).standard_normal(g.N // 2) / 10
+    a = g.pt_export(g.encode(z, g.L, 2.0 ** 40)).astype(object)
+    b = o.encode(z, g.L, 2.0 ** 40).coeffs().astype(object)
+    q0 = g.q[0]
+    d = (a[0] - b[0]) % q0
+    d = np.where(d > q0 // 2, d - q0, d)
+    assert np.max(np.abs(d)) <= 1
+    # all limbs carry the same integer
+    for i, q in enumerate(g.q):
+        assert np.all(((a[i] - b[i]) % q == d % q))
+
+
+def test_decode_matches_oracle(pair, keys):
+    g, o = pair
+    z = np.random.default_rng(3).uniform(-1, 1, g.N // 2)
+    gct, oct_ = _enc_pair(pair, keys, z, g.L, 2.0 ** 40, 77)
+    gd = g.decrypt_decode(keys[0], gct)
+    od = o.decrypt_decode(keys[1], oct_)
+    assert np.max(np.abs(gd - od)) < 1e-9
+    assert np.max(np.abs(gd - z)) < 2 ** -22
+
+
+def test_encrypt_decrypt_bitexact(pair, keys):
+    g, o = pair
+    z = np.random.default_rng(4).uniform(-1, 1, g.N // 2)
+    gct, oct_ = _enc_pair(pair, keys, z, g.L, 2.0 ** 40, 1234)
+    _same(g, gct, oct_)
+    assert np.array_equal(g.pt_export(g.decrypt(keys[0], gct)), o.decrypt(keys[1], oct_).coeffs())
+    # lower level encryption
+    gct, oct_ = _enc_pair(pair, keys, z, 1, 2.0 ** 30, 99)
+    _same(g, gct, oct_)
+
+
+def test_rotate_hoisted_bitexact(pair, keys):
+    g, o = pair
+    z = np.random.default_rng(5).uniform(-1, 1, g.N // 2)
+    gct, oct_ = _enc_pair(pair, keys, z, g.L, 2.0 ** 40, 5)
+    rots = ROTS_C1 + [0]
+    gr = g.rotate_hoisted(keys[0], gct, rots)
+    orr = o.rotate_hoisted(keys[1], oct_, rots)
+    for k, a, b in zip(rots, gr, orr):
+        _same(g, a, b)
+    dec = g.decrypt_decode(keys[0], gr[3])
+    assert np.max(np.abs(dec - np.roll(z, -rots[3]))) < 2 ** -22
+
+
+def test_missing_key_raises(pair, keys, F):
+    g, o = pair
+    gct, _ = _enc_pair(pair, keys, np.zeros(4), g.L, 2.0 ** 40, 5)
+    with pytest.raises(F.FrError) as e:
+        g.rotate_hoisted(keys[0], gct, [9])
+    assert e.value.code == F.FR_ENOKEY
+
+
+def test_rescale_add_mul_bitexact(pair, keys):
+    g, o = pair
+    rnd = np.random.default_rng(6)
+    x, y = rnd.uniform(-1, 1, g.N // 2), rnd.uniform(-1, 1, g.N // 2)
+    ga, oa = _enc_pair(pair, keys, x, g.L, 2.0 ** 40, 11)
+    gb, ob = _enc_pair(pair, keys, y, g.L, 2.0 ** 40, 12)
+    _same(g, g.rescale(ga), o.rescale(oa))
+    _same(g, g.add(ga, gb), o.add(oa, ob))
+    _same(g, g.sub(ga, gb), o.sub(oa, ob))
+    _same(g, g.mul_int(ga, -123456789), o.mul_int(oa, -123456789))
+    _same(g, g.add_const(ga, -0.37), o.add_const(oa, -0.37))
+    _same(g, g.drop_to(ga, 1), o.drop_to(oa, 1))
+    opt = o.encode(y, g.L, 2.0 ** 40)
+    gpt = g.pt_import(opt.coeffs(), g.L, 2.0 ** 40)
+    _same(g, g.mul_plain(ga, gpt), o.mul_plain(oa, opt))
+    _same(g, g.mul_relin_rescale(keys[0], ga, gb), o.mul_relin_rescale(keys[1], oa, ob))
+
+
+@pytest.fixture(scope="module")
+def config1(pair, keys):
+    """64 templates x 128-d, B = 16 blocks per plaintext, n1 = 8, n2 = 16."""
+    g, o = pair
+    wl = synth.make_workload(1, 64, 128)
+    qv = synth.replicate_query(wl.query, g.N // 2)
+    gq, oq = _enc_pair(pair, keys, qv, g.L, 2.0 ** 40, synth.int_seed(1, synth.SUB_ENC))
+    gb = [gq] + g.rotate_hoisted(keys[0], gq, range(1, 8))
+    ob = [oq] + o.rotate_hoisted(keys[1], oq, range(1, 8))
+    odb = o.db_build(wl.templates, wl.K, 128, 16, 8, g.L, 2.0 ** 40)
+    gdb = g.db_import(odb.export_all(), odb.G, 128, 16, 8, g.L, 2.0 ** 40)
+    return wl, gb, ob, gdb, odb
+
+
+def test_db_import_export(pair, config1):
+    g, o = pair
+    wl, gb, ob, gdb, odb = config1
+    for d in (0, 7, 127):
+        assert np.array_equal(gdb.export(0, d), odb.export(0, d))
+
+
+def test_matvec_bitexact_config1(pair, keys, config1):
+    g, o = pair
+    wl, gb, ob, gdb, odb = config1
+    gs = g.bsgs_diag_matvec(keys[0], gb, gdb, 0)
+    os_ = o.bsgs_matvec(keys[1], ob, odb, 0)
+    _same(g, gs, os_)
+    dec = g.decrypt_decode(keys[0], gs)
+    assert np.max(np.abs(dec[:64] - wl.exact_scores())) <= 2 ** -20
+    assert np.max(np.abs(dec[64:])) <= 2 ** -20
+
+
+def test_db_load_encoding_and_scores(pair, keys, config1):
+    """The device-side diagonal encoder: each coefficient within 1 of the
+    oracle's, and the scores it produces within 2^-20."""
+    g, o = pair
+    wl, gb, ob, gdb, odb = config1
+    gdb2 = g.db_load(wl.templates, 128, 16, 8, g.L, 2.0 ** 40)
+    q0 = g.q[0]
+    for d in (0, 5, 64, 127):
+        a = gdb2.export(0, d)[0].astype(object)
+        b = odb.export(0, d)[0].astype(object)
+        diff = (a - b) % q0
+        diff = np.where(diff > q0 // 2, diff - q0, diff)
+        assert np.max(np.abs(diff)) <= 1
+    dec = g.decrypt_decode(keys[0], g.bsgs_diag_matvec(keys[0], gb, gdb2, 0))
+    assert np.max(np.abs(dec[:64] - wl.exact_scores())) <= 2 ** -20
+
+
+# --------------------------------------------------------------------------
+# Chebyshev ladder on the deep modulus chain at N = 2^12
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def deep(F, oracle_mod):
+    p = F.deep_small_params()
+    g, o = F.Context(**p), oracle_mod.Context(**_oparams(p))
+    seed = synth.int_seed(2, synth.SUB_KEYS)
+    return (g, o), (g.keygen(seed, [1, 2, 3]), o.keygen(seed, [1, 2, 3]))
+
+
+@pytest.mark.parametrize("d1", [2, 8])
+def test_chebyshev_bitexact(deep, oracle_mod, d1):
+    pair, keys = deep
+    g, o = pair
+    rnd = np.random.default_rng(7)
+    x = np.concatenate([rnd.uniform(-1, 1, g.N // 2 - 6), [0.29, 0.31, -1.0, 1.0, 0.0, 0.3]])
+    gct, oct_ = _enc_pair(pair, keys, x, g.L - 1, 2.0 ** 40, 21)
+    c = oracle_mod.cheb_step_coeffs(63, 0.3)
+    gy = g.chebyshev_eval(keys[0], gct, c, d1)
+    oy = o.chebyshev(keys[1], oct_, c, d1)
+    _same(g, gy, oy)
+    want = np.polynomial.chebyshev.chebval(x, c)
+    assert np.max(np.abs(g.decrypt_decode(keys[0], gy) - want)) <= 2 ** -12
+
+
+def test_relin_bitexact_deep(deep):
+    pair, keys = deep
+    g, o = pair
+    rnd = np.random.default_rng(8)
+    ga, oa = _enc_pair(pair, keys, rnd.uniform(-1, 1, g.N // 2), 9, 2.0 ** 40, 31)
+    gb, ob = _enc_pair(pair, keys, rnd.uniform(-1, 1, g.N // 2), 9, 2.0 ** 40, 32)
+    _same(g, g.mul_relin_rescale(keys[0], ga, gb), o.mul_relin_rescale(keys[1], oa, ob))
+    gr = g.rotate_hoisted(keys[0], ga, [1, 3])
+    orr = o.rotate_hoisted(keys[1], oa, [1, 3])
+    for a, b in zip(gr, orr):
+        _same(g, a, b)
