@@ -185,6 +185,18 @@ int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int
 int fr_chebyshev_eval(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const double *c,
                       int32_t degree, int32_t d1, fr_ct *out);
 
+/* ---- kernel timing hook (for the benchmark's roofline figures) ----
+ * While a class is selected, every launch of that kernel class is bracketed
+ * by HIP events on the context's stream and its algorithmic HBM bytes (the
+ * words the operation must read and write once) are added up.  Classes:
+ * 1 NTT (one forward or inverse transform of a batch of limbs), 2 ModUp base
+ * conversion, 3 key-switching inner product, 4 ModDown base conversion,
+ * 5 plaintext-diagonal multiply-accumulate, 6 rescale, 7 tensor product,
+ * 8 element-wise arithmetic.  fr_prof_end synchronises, returns the launch
+ * count, summed event time (ms) and bytes, and deselects the class. */
+int fr_prof_begin(fr_ctx *ctx, int32_t kernel_class);
+int fr_prof_end(fr_ctx *ctx, int32_t *launches, double *total_ms, double *bytes);
+
 /* ---- host-only planning helpers (no device work) ---- */
 /* degree-n interpolant of the 0/1 step at delta through the n+1 first-kind
  * Chebyshev nodes ("DCT-based interpolation" of §5.1.4); c[0] full T_0. */

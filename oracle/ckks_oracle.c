@@ -90,6 +90,49 @@ static int bitrev(int x, int bits) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* exact CRT lift with little multi-word integers                            */
+/* ------------------------------------------------------------------------ */
+#define BW 40 /* words: enough for 40 primes of < 64 bits */
+typedef struct { uint64_t w[BW]; } big;
+static void big_zero(big *a) { memset(a, 0, sizeof *a); }
+static void big_mul_small(big *a, uint64_t m) {
+    u128 carry = 0;
+    for (int i = 0; i < BW; i++) {
+        u128 t = (u128)a->w[i] * m + carry;
+        a->w[i] = (uint64_t)t;
+        carry = t >> 64;
+    }
+}
+static void big_add(big *a, const big *b) {
+    u128 carry = 0;
+    for (int i = 0; i < BW; i++) {
+        u128 t = (u128)a->w[i] + b->w[i] + carry;
+        a->w[i] = (uint64_t)t;
+        carry = t >> 64;
+    }
+}
+static void big_sub(big *a, const big *b) { /* a >= b */
+    uint64_t borrow = 0;
+    for (int i = 0; i < BW; i++) {
+        uint64_t bi = b->w[i], ai = a->w[i];
+        uint64_t d = ai - bi - borrow;
+        borrow = (ai < bi) || (ai - bi < borrow);
+        a->w[i] = d;
+    }
+}
+static int big_cmp(const big *a, const big *b) {
+    for (int i = BW - 1; i >= 0; i--) {
+        if (a->w[i] != b->w[i]) return a->w[i] > b->w[i] ? 1 : -1;
+    }
+    return 0;
+}
+static double big_to_double(const big *a) {
+    double r = 0.0;
+    for (int i = BW - 1; i >= 0; i--) r = r * 18446744073709551616.0 + (double)a->w[i];
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
 /* context                                                                    */
 /* ------------------------------------------------------------------------ */
 struct or_ctx {
@@ -631,49 +674,6 @@ or_pt *or_encode(const or_ctx *c, const double *z, int n, int level, double scal
     return c->logN <= 13 ? or_encode_direct(c, z, n, level, scale) : or_encode_fft(c, z, n, level, scale);
 }
 
-/* ------------------------------------------------------------------------ */
-/* exact CRT lift with little multi-word integers                            */
-/* ------------------------------------------------------------------------ */
-#define BW 40 /* words: enough for 40 primes of < 64 bits */
-typedef struct { uint64_t w[BW]; } big;
-static void big_zero(big *a) { memset(a, 0, sizeof *a); }
-static void big_mul_small(big *a, uint64_t m) {
-    u128 carry = 0;
-    for (int i = 0; i < BW; i++) {
-        u128 t = (u128)a->w[i] * m + carry;
-        a->w[i] = (uint64_t)t;
-        carry = t >> 64;
-    }
-}
-static void big_add(big *a, const big *b) {
-    u128 carry = 0;
-    for (int i = 0; i < BW; i++) {
-        u128 t = (u128)a->w[i] + b->w[i] + carry;
-        a->w[i] = (uint64_t)t;
-        carry = t >> 64;
-    }
-}
-static void big_sub(big *a, const big *b) { /* a >= b */
-    uint64_t borrow = 0;
-    for (int i = 0; i < BW; i++) {
-        uint64_t bi = b->w[i], ai = a->w[i];
-        uint64_t d = ai - bi - borrow;
-        borrow = (ai < bi) || (ai - bi < borrow);
-        a->w[i] = d;
-    }
-}
-static int big_cmp(const big *a, const big *b) {
-    for (int i = BW - 1; i >= 0; i--) {
-        if (a->w[i] != b->w[i]) return a->w[i] > b->w[i] ? 1 : -1;
-    }
-    return 0;
-}
-static double big_to_double(const big *a) {
-    double r = 0.0;
-    for (int i = BW - 1; i >= 0; i--) r = r * 18446744073709551616.0 + (double)a->w[i];
-    return r;
-}
-
 /* m = sum_i [m_i Qhat_i^-1]_{q_i} Qhat_i mod Q, centered into (-Q/2, Q/2]. */
 int or_pt_lift(const or_ctx *c, const or_pt *p, double *out) {
     int l = p->level, N = c->N;
@@ -846,38 +846,65 @@ int or_modup_digit(const or_ctx *c, int l, int t, const uint64_t *x, uint64_t *o
     return 0;
 }
 
-/* ModDown: out_i = (u_{q_i} - sum_j [u_{p_j} (P/p_j)^-1]_{p_j} (P/p_j mod q_i)) * P^-1 mod q_i */
+/* ModDown (rounded): out_i = (u - [u]_P^{+-}) * P^-1 mod q_i, where [u]_P^{+-}
+ * is the centered residue of u modulo P in (-P/2, P/2]; i.e. out = round(u / P)
+ * coefficient-wise, the same rounding rule as the rescale by one prime.
+ * [u]_P is rebuilt exactly with big integers from the P limbs by the CRT:
+ * X = sum_j [u_j (P/p_j)^-1]_{p_j} (P/p_j), reduced into [0, P), then centered.
+ * Reading: the paper does not state the basis conversion; the uncentered
+ * variant (floor(u/P) minus up to nP) leaves a one-sided bias per coefficient
+ * that, multiplied by s, concentrates in the slots near the root 1. */
 int or_moddown(const or_ctx *c, int l, const uint64_t *u, uint64_t *out) {
     int N = c->N, nP = c->nP, L = c->L;
+    big P, halfP;
+    big *Phat = malloc(sizeof(big) * nP);
     uint64_t phat_inv[64];
+    big_zero(&P); P.w[0] = 1;
+    for (int j = 0; j < nP; j++) big_mul_small(&P, c->mod[L + 1 + j]);
+    halfP = P;
+    for (int i = 0; i < BW; i++) halfP.w[i] = (halfP.w[i] >> 1) | (i + 1 < BW ? (halfP.w[i + 1] << 63) : 0);
     for (int j = 0; j < nP; j++) {
         uint64_t pj = c->mod[L + 1 + j], prod = 1;
-        for (int jj = 0; jj < nP; jj++)
-            if (jj != j) prod = mulmod(prod, c->mod[L + 1 + jj] % pj, pj);
+        big_zero(&Phat[j]); Phat[j].w[0] = 1;
+        for (int jj = 0; jj < nP; jj++) {
+            if (jj == j) continue;
+            big_mul_small(&Phat[j], c->mod[L + 1 + jj]);
+            prod = mulmod(prod, c->mod[L + 1 + jj] % pj, pj);
+        }
         phat_inv[j] = invmod(prod, pj);
     }
-    #pragma omp parallel for
+    uint64_t Pinv[64];
     for (int i = 0; i <= l; i++) {
-        uint64_t q = c->mod[i];
-        uint64_t phat[64], Pmod = 1;
+        uint64_t q = c->mod[i], Pm = 1;
+        for (int j = 0; j < nP; j++) Pm = mulmod(Pm, c->mod[L + 1 + j] % q, q);
+        Pinv[i] = invmod(Pm, q);
+    }
+    #pragma omp parallel for
+    for (int k = 0; k < N; k++) {
+        big X, t;
+        big_zero(&X);
         for (int j = 0; j < nP; j++) {
-            uint64_t prod = 1;
-            for (int jj = 0; jj < nP; jj++)
-                if (jj != j) prod = mulmod(prod, c->mod[L + 1 + jj] % q, q);
-            phat[j] = prod;
-            Pmod = mulmod(Pmod, c->mod[L + 1 + j] % q, q);
+            uint64_t pj = c->mod[L + 1 + j];
+            uint64_t y = mulmod(u[(size_t)(l + 1 + j) * N + k], phat_inv[j], pj);
+            t = Phat[j];
+            big_mul_small(&t, y);
+            big_add(&X, &t);
         }
-        uint64_t Pinv = invmod(Pmod, q);
-        for (int k = 0; k < N; k++) {
-            uint64_t v = 0;
-            for (int j = 0; j < nP; j++) {
-                uint64_t pj = c->mod[L + 1 + j];
-                uint64_t y = mulmod(u[(size_t)(l + 1 + j) * N + k], phat_inv[j], pj);
-                v = addmod(v, mulmod(y, phat[j], q), q);
+        while (big_cmp(&X, &P) >= 0) big_sub(&X, &P);
+        int neg = big_cmp(&X, &halfP) > 0;  /* X > (P-1)/2: centered value X - P < 0 */
+        if (neg) { t = P; big_sub(&t, &X); X = t; }  /* X = |centered value| */
+        for (int i = 0; i <= l; i++) {
+            uint64_t q = c->mod[i];
+            uint64_t r = 0; /* |centered| mod q, Horner over the words */
+            for (int w = BW - 1; w >= 0; w--) {
+                u128 acc = ((u128)r << 64) | X.w[w];
+                r = (uint64_t)(acc % q);
             }
-            out[(size_t)i * N + k] = mulmod(submod(u[(size_t)i * N + k], v, q), Pinv, q);
+            uint64_t vq = neg ? (r ? q - r : 0) : r;
+            out[(size_t)i * N + k] = mulmod(submod(u[(size_t)i * N + k], vq, q), Pinv[i], q);
         }
     }
+    free(Phat);
     return 0;
 }
 

@@ -381,6 +381,13 @@ static int ctx_build(fr_ctx *c) {
     }
     md.insert(md.end(), pinv.begin(), pinv.end());
     md.insert(md.end(), pinvs.begin(), pinvs.end());
+    for (int i = 0; i <= L; ++i) md.push_back(c->P_mod_q[i]);
+    for (int j = 0; j < nP; ++j) {
+        const double inv = 1.0 / (double)c->mod[L + 1 + j];
+        u64 bits;
+        std::memcpy(&bits, &inv, 8);
+        md.push_back(bits);
+    }
     if (int e = upload(&c->d_moddown, md)) return e;
 
     // rescale tables
@@ -487,6 +494,10 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
                     (void *)c->d_fft_w, (void *)c->d_zeta, (void *)c->d_slot_pos, (void *)c->d_flag})
         if (p) (void)hipFree(p);
     c->arena.release();
+    if (c->prof) {
+        for (auto &e : c->prof->ev) (void)hipEventDestroy(e);
+        delete c->prof;
+    }
     delete c;
 }
 
@@ -1341,6 +1352,51 @@ extern "C" int fr_chebyshev_eval(fr_ctx *c, const fr_keys *K, const fr_ct *in, c
     FR_HIP(hipGetLastError());
     out->level = res_level;
     out->scale = be.D[res_level];
+    return FR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing hook
+// ---------------------------------------------------------------------------
+bool Prof::begin(int k, hipStream_t s) {
+    if (cls != k || 2 * used + 1 >= (int)ev.size()) return false;
+    return hipEventRecord(ev[2 * used], s) == hipSuccess;
+}
+void Prof::end(int, hipStream_t s, double b) {
+    (void)hipEventRecord(ev[2 * used + 1], s);
+    ++used;
+    bytes += b;
+}
+
+extern "C" int fr_prof_begin(fr_ctx *c, int32_t kernel_class) {
+    CHECK(c, FR_EINVAL, "null context");
+    CHECK(kernel_class >= 0 && kernel_class <= K_ELEM, FR_EINVAL, "fr_prof_begin: unknown class %d", kernel_class);
+    if (!c->prof) {
+        c->prof = new Prof();
+        c->prof->ev.resize(2 * 16384);
+        for (auto &e : c->prof->ev) FR_HIP(hipEventCreate(&e));
+    }
+    FR_HIP(hipStreamSynchronize(c->stream));
+    c->prof->cls = kernel_class;
+    c->prof->used = 0;
+    c->prof->bytes = 0.0;
+    return FR_OK;
+}
+
+extern "C" int fr_prof_end(fr_ctx *c, int32_t *launches, double *total_ms, double *bytes) {
+    CHECK(c && c->prof, FR_EINVAL, "fr_prof_end: no timing in progress");
+    FR_HIP(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (int i = 0; i < c->prof->used; ++i) {
+        float ms = 0.f;
+        FR_HIP(hipEventElapsedTime(&ms, c->prof->ev[2 * i], c->prof->ev[2 * i + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = c->prof->used;
+    if (total_ms) *total_ms = tot;
+    if (bytes) *bytes = c->prof->bytes;
+    c->prof->cls = K_NONE;
+    c->prof->used = 0;
     return FR_OK;
 }
 

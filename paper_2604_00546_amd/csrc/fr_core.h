@@ -123,7 +123,17 @@ struct Arena {  // bump allocator over device chunks, reset per top-level call
     void release();
 };
 
-struct KsTables;  // RNS conversion constants (device)
+// kernel timing hook: events around every launch of one kernel class
+enum KernelClass { K_NONE = 0, K_NTT = 1, K_MODUP = 2, K_KS = 3, K_MODDOWN = 4, K_MAC = 5, K_RESCALE = 6,
+                   K_TENSOR = 7, K_ELEM = 8 };
+struct Prof {
+    int cls = K_NONE;
+    std::vector<hipEvent_t> ev;  // pairs
+    int used = 0;
+    double bytes = 0.0;
+    bool begin(int k, hipStream_t s);
+    void end(int k, hipStream_t s, double b);
+};
 
 struct fr_ctx {
     int logN, N, L, nP, dnum, alpha, nmod;
@@ -136,7 +146,7 @@ struct fr_ctx {
     u64 *d_modup = nullptr;
     size_t modup_off[FR_MAXLEVEL][8];
     // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP],
-    // Pinv[L+1], Pinv_sh[L+1]; P mod q_i [L+1]
+    // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits)
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
     // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each
@@ -151,6 +161,21 @@ struct fr_ctx {
     hipStream_t stream = nullptr;
     Arena arena;
     int *d_flag = nullptr;  // device error flag
+    Prof *prof = nullptr;
+};
+
+// bracket a launch of class K with timing events when that class is selected
+struct ProfScope {
+    const fr_ctx *c;
+    int k;
+    double bytes;
+    bool on;
+    ProfScope(const fr_ctx *cc, int kk, double b) : c(cc), k(kk), bytes(b) {
+        on = c->prof && c->prof->begin(k, c->stream);
+    }
+    ~ProfScope() {
+        if (on) c->prof->end(k, c->stream, bytes);
+    }
 };
 
 struct KeyEntry {

@@ -190,6 +190,7 @@ namespace frk {
 
 void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride) {
     if (nlimbs <= 0 || npoly <= 0) return;
+    ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, false);
     const int lr = a.s1, lc = a.logN - a.s1;
     const int lcols = std::min(12 - lr, lc), lblks = std::min(12 - lc, lr);
@@ -200,6 +201,7 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
 
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride) {
     if (nlimbs <= 0 || npoly <= 0) return;
+    ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, true);
     const int lr = a.s1, lc = a.logN - a.s1;
     const int lcols = std::min(12 - lr, lc), lblks = std::min(12 - lc, lr);

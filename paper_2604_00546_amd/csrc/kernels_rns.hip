@@ -129,24 +129,37 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     U1[w] = u1;
 }
 
-// ModDown base conversion P -> Q_level of the P limbs in coefficient form:
-// y_j = [u_j * Phat_j^-1]_{p_j}, V_i = sum_j y_j [Phat_j]_{q_i} mod q_i.
-// tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1], Pinv_sh[L+1]
+// ModDown base conversion P -> Q_level of the P limbs in coefficient form,
+// to the CENTERED residue of u mod P: y_j = [u_j * Phat_j^-1]_{p_j},
+// X = sum_j y_j Phat_j in [0, nP P), e = round(X / P) estimated in FP64 as
+// rint(sum_j y_j / p_j) (fixed order, no contraction), and
+// V_i = (sum_j y_j [Phat_j]_{q_i} - e [P]_{q_i}) mod q_i.
+// tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1],
+//      Pinv_sh[L+1], P_mod_q[L+1], inv_p[nP] (double bits)
 __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP, int pbase,
-                                                    const u64 *tab, const ModConst *mods, size_t sv, size_t su) {
+                                                    int L1, const u64 *tab, const ModConst *mods, size_t sv,
+                                                    size_t su) {
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
+    const u64 *pmod = tab + 2 * nP + (size_t)L1 * nP + 2 * L1;
+    const double *invp = reinterpret_cast<const double *>(pmod + L1);
     u64 y[kMaxDigit];
+    double s = 0.0;
 #pragma unroll
     for (int j = 0; j < kMaxDigit; ++j)
-        if (j < nP) y[j] = shoup(Upc[poly * su + (size_t)j * N + k], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
+        if (j < nP) {
+            y[j] = shoup(Upc[poly * su + (size_t)j * N + k], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
+            s = s + (double)y[j] * invp[j];
+        }
+    const u64 e = (u64)rint(s);
     const int i0 = blockIdx.y * kTargetsPerThread, i1 = min(level + 1, i0 + kTargetsPerThread);
     for (int i = i0; i < i1; ++i) {
+        const ModConst mi = mods[i];
         u64 al = 0, ah = 0;
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
             if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        V[poly * sv + (size_t)i * N + k] = reduce128(al, ah, mods[i]);
+        V[poly * sv + (size_t)i * N + k] = subq(reduce128(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
     }
 }
 
@@ -279,12 +292,14 @@ namespace frk {
 
 void add(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly, size_t so, size_t sa,
          size_t sb, bool subtract) {
+    ProfScope ps(c, K_ELEM, 3.0 * nlimbs * npoly * 8.0 * c->N);
     hipLaunchKernelGGL(k_add, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, a, b, c->N, so, sa, sb, c->d_mod,
                        (int)subtract);
 }
 
 void mul_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, const u64 *k_sh, int nlimbs, int npoly,
                size_t so, size_t sa) {
+    ProfScope ps(c, K_ELEM, 2.0 * nlimbs * npoly * 8.0 * c->N);
     LimbConsts kc;
     for (int i = 0; i < nlimbs; ++i) {
         kc.v[i] = k[i];
@@ -295,34 +310,40 @@ void mul_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, const u64 
 }
 
 void add_const(const fr_ctx *c, u64 *out, const u64 *a, const u64 *k, int nlimbs) {
+    ProfScope ps(c, K_ELEM, 2.0 * nlimbs * 8.0 * c->N);
     LimbConsts kc;
     for (int i = 0; i < nlimbs; ++i) kc.v[i] = k[i];
     hipLaunchKernelGGL(k_add_const, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, out, a, kc, c->N, c->d_mod);
 }
 
 void mul_pt(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly, size_t so, size_t sa) {
+    ProfScope ps(c, K_ELEM, 3.0 * nlimbs * npoly * 8.0 * c->N);
     hipLaunchKernelGGL(k_mul_pt, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, a, b, c->N, so, sa, c->d_mod);
 }
 
 void tensor(const fr_ctx *c, u64 *d0, u64 *d1, u64 *d2, const u64 *a0, const u64 *a1, const u64 *b0, const u64 *b1,
             int nlimbs) {
+    ProfScope ps(c, K_TENSOR, 7.0 * nlimbs * 8.0 * c->N);
     hipLaunchKernelGGL(k_tensor, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, d0, d1, d2, a0, a1, b0, b1, c->N,
                        c->d_mod);
 }
 
 void automorph(const fr_ctx *c, u64 *out, const u64 *in, u64 g, int nlimbs, int npoly, size_t so, size_t si,
                bool accumulate) {
+    ProfScope ps(c, K_ELEM, (accumulate ? 3.0 : 2.0) * nlimbs * npoly * 8.0 * c->N);
     hipLaunchKernelGGL(k_automorph, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, out, in, g, c->N, c->logN, so,
                        si, c->d_mod, (int)accumulate);
 }
 
 void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
                 bool to_mont) {
+    ProfScope ps(c, K_ELEM, 2.0 * nlimbs * npoly * 8.0 * c->N);
     hipLaunchKernelGGL(k_mont_scale, grid(c, nlimbs, npoly), dim3(kT), 0, c->stream, data, c->N, poly_stride, map,
                        c->d_mod, (int)to_mont);
 }
 
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t) {
+    ProfScope ps(c, K_MODUP, (double)(level + 1 + c->nP) * 8.0 * c->N);
     const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
     const int nE = level + 1 + c->nP;
     const int ntarget = nE - nd;
@@ -332,6 +353,8 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t) {
 }
 
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate) {
+    const int nE_ = level + 1 + c->nP, nd_ = (level + 1 + c->alpha - 1) / c->alpha;
+    ProfScope ps(c, K_KS, (3.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
     hipLaunchKernelGGL(k_ks_inner, grid(c, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN, nE,
@@ -339,13 +362,15 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level) {
+    ProfScope ps(c, K_MODDOWN, (2.0 * c->nP + 2.0 * (level + 1)) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + 1 + kTargetsPerThread - 1) / kTargetsPerThread, 2);
-    hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->d_moddown,
-                       c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
+    hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
+                       c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
 }
 
 void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int level, int npoly, size_t so,
                     size_t su, size_t sv, bool accumulate) {
+    ProfScope ps(c, K_ELEM, (accumulate ? 4.0 : 3.0) * (level + 1) * npoly * 8.0 * c->N);
     const u64 *pinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;
     const u64 *pinv_sh = pinv + (c->L + 1);
     hipLaunchKernelGGL(k_moddown_finish, grid(c, level + 1, npoly), dim3(kT), 0, c->stream, out, U, V, c->N, pinv,
@@ -353,12 +378,14 @@ void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int l
 }
 
 void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly, size_t sy, size_t sx) {
+    ProfScope ps(c, K_RESCALE, (1.0 + level) * npoly * 8.0 * c->N);
     hipLaunchKernelGGL(k_rescale_prep, grid(c, level, npoly), dim3(kT), 0, c->stream, Y, xtop, c->N, level, sy, sx,
                        c->d_mod);
 }
 
 void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly, size_t so,
                     size_t si, size_t sy) {
+    ProfScope ps(c, K_RESCALE, 3.0 * level * npoly * 8.0 * c->N);
     const u64 *qinv = c->d_rescale + (size_t)level * (c->L + 1) * 2;
     const u64 *qinv_sh = qinv + (c->L + 1);
     hipLaunchKernelGGL(k_rescale_finish, grid(c, level, npoly), dim3(kT), 0, c->stream, out, in, Y, c->N, qinv,
@@ -375,6 +402,11 @@ void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64
             const int nb = std::min(32, n1 - i0);
             BabyPtrs bp;
             for (int ii = 0; ii < 32; ++ii) bp.p[ii] = ii < nb ? baby[i0 + ii] : nullptr;
+            long long used = 0;  // diagonal plaintexts this launch reads
+            for (int jj = 0; jj < nj; ++jj)
+                for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
+            ProfScope ps(c, K_MAC,
+                         8.0 * c->N * (level + 1) * (used + 2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj));
             hipLaunchKernelGGL(k_bsgs_mac<NJ>, grid(c, level + 1, 1), dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0,
                                nj, ell, diag, db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
         }

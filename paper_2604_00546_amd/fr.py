@@ -83,6 +83,8 @@ SIGNATURES = {
     "fr_db_destroy": (None, [_P]),
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
+    "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
+    "fr_prof_end": (C.c_int, [_P, _I32P, _DP, _DP]),
     "fr_cheb_step_coeffs": (C.c_int, [C.c_int32, C.c_double, _DP]),
     "fr_cheb_ps_params": (C.c_int, [C.c_int32, _I32P, _I32P]),
     "fr_cheb_out_level": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
@@ -266,6 +268,18 @@ class Context:
 
     def sync(self):
         _check(lib().fr_ctx_sync(self.ptr), "fr_ctx_sync")
+
+    # kernel timing hook ------------------------------------------------------
+    KERNEL_CLASSES = {"ntt": 1, "modup": 2, "ks_inner": 3, "moddown": 4, "mac": 5, "rescale": 6, "tensor": 7,
+                      "elementwise": 8}
+
+    def prof_begin(self, kernel_class: str):
+        _check(lib().fr_prof_begin(self.ptr, self.KERNEL_CLASSES[kernel_class]), "fr_prof_begin")
+
+    def prof_end(self):
+        n, ms, b = C.c_int32(), C.c_double(), C.c_double()
+        _check(lib().fr_prof_end(self.ptr, C.byref(n), C.byref(ms), C.byref(b)), "fr_prof_end")
+        return n.value, ms.value, b.value
 
     # allocation -------------------------------------------------------------
     def new_ct(self, cap: int) -> Ct:

@@ -1,0 +1,122 @@
+"""GPU tests at the paper-scale parameters (N = 2^16, Q = 60 + 14 x 40 bits,
+P = 5 x 60 bits, dnum = 3), in the launch configuration bench.py times.
+
+* The whole hot path of one query -- 31 hoisted baby-step rotations, the
+  BSGS matrix-vector product over one group of 512 diagonals, the degree-63
+  Chebyshev threshold -- is compared bit-exactly with the oracle on the
+  2^12-template database (same keys, seeds and integer plaintexts).
+* The 2^15-template identification workload with the device's own diagonal
+  encoder: every decrypted score within 2^-20 of the FP64 inner product,
+  every Chebyshev output within 2^-12 of the FP64 polynomial, and the set of
+  identified templates equal to the planted set.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_00546_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ELL, N1 = 512, 32
+
+
+def _oparams(p):
+    return dict(logN=p["log_n"], q0_bits=p["q0_bits"], n_mid=p["n_mid"], mid_bits=p["mid_bits"],
+                n_special=p["n_special"], special_bits=p["special_bits"], dnum=p["dnum"])
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2604_00546_amd import fr
+    return fr
+
+
+@pytest.fixture(scope="module")
+def gctx(F):
+    return F.Context(**F.paper_params())
+
+
+def _same(g, gct, oct_):
+    a, b = g.ct_export(gct), oct_.coeffs()
+    assert (gct.level, gct.scale) == (oct_.level, oct_.scale)
+    bad = np.argwhere(a != b)
+    assert len(bad) == 0, f"{len(bad)} words differ, first at {bad[:3].tolist()}"
+
+
+@pytest.fixture(scope="module")
+def config2(F, gctx, oracle_mod):
+    """Oracle side of the 2^12 x 512 query, and the GPU fed the same inputs."""
+    g = gctx
+    o = oracle_mod.Context(**_oparams(F.paper_params()))
+    assert g.moduli == o.moduli
+    rots = F.bsgs_rotation_set(ELL, N1)
+    seed = synth.int_seed(2, synth.SUB_KEYS)
+    kg, ko = g.keygen(seed, rots), o.keygen(seed, rots)
+    wl = synth.make_workload(2, 2 ** 12, ELL)
+    B = g.N // 2 // ELL
+    odb = o.db_build(wl.templates, wl.K, ELL, B, N1, o.L, 2.0 ** 40)
+    gdb = g.db_import(odb.export_all(), odb.G, ELL, B, N1, g.L, 2.0 ** 40)
+    opt = o.encode(synth.replicate_query(wl.query, g.N // 2), o.L, 2.0 ** 40)
+    es = synth.int_seed(2, synth.SUB_ENC)
+    gq = g.encrypt(kg, g.pt_import(opt.coeffs(), g.L, 2.0 ** 40), es)
+    oq = o.encrypt(ko, opt, es)
+    return dict(o=o, kg=kg, ko=ko, wl=wl, odb=odb, gdb=gdb, gq=gq, oq=oq, B=B)
+
+
+@pytest.mark.timeout(900)
+def test_full_hot_path_bitexact(F, gctx, config2):
+    g, c = gctx, config2
+    o, kg, ko = c["o"], c["kg"], c["ko"]
+    _same(g, c["gq"], c["oq"])
+    gb = [c["gq"]] + g.rotate_hoisted(kg, c["gq"], range(1, N1))
+    ob = [c["oq"]] + o.rotate_hoisted(ko, c["oq"], range(1, N1))
+    for i in (1, 2, 17, 31):
+        _same(g, gb[i], ob[i])
+    gs = g.bsgs_diag_matvec(kg, gb, c["gdb"], 0)
+    os_ = o.bsgs_matvec(ko, ob, c["odb"], 0)
+    _same(g, gs, os_)
+    coeffs = F.cheb_step_coeffs(63, 0.3)
+    gy = g.chebyshev_eval(kg, gs, coeffs, 2)
+    oy = o.chebyshev(ko, os_, coeffs, 2)
+    _same(g, gy, oy)
+    exact = c["wl"].exact_scores()
+    dec = g.decrypt_decode(kg, gs)
+    assert np.max(np.abs(dec[: len(exact)] - exact)) <= 2 ** -20
+    assert np.max(np.abs(dec[len(exact):])) <= 2 ** -20
+
+
+def test_full_size_encoder_within_one(F, gctx, config2):
+    """Device encoder of the pre-rotated diagonals vs the oracle's, sampled diagonals."""
+    g, c = gctx, config2
+    gdb = g.db_load(c["wl"].templates, ELL, c["B"], N1, g.L, 2.0 ** 40)
+    q0 = g.q[0]
+    for d in (0, 33, 257, 511):
+        a = gdb.export(0, d)[0].astype(object)
+        b = c["odb"].export(0, d)[0].astype(object)
+        diff = (a - b) % q0
+        diff = np.where(diff > q0 // 2, diff - q0, diff)
+        assert np.max(np.abs(diff)) <= 1
+
+
+@pytest.mark.timeout(600)
+def test_identification_2p15(F, gctx):
+    g = gctx
+    wl = synth.make_workload(3, 2 ** 15, ELL, planted_frac=0.01)
+    rots = F.bsgs_rotation_set(ELL, N1)
+    keys = g.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
+    B = g.N // 2 // ELL
+    db = g.db_load(wl.templates, ELL, B, N1, g.L, 2.0 ** 40)
+    assert db.G == 1
+    q = g.encrypt(keys, g.encode(synth.replicate_query(wl.query, g.N // 2), g.L, 2.0 ** 40),
+                  synth.int_seed(3, synth.SUB_ENC))
+    baby = [q] + g.rotate_hoisted(keys, q, range(1, N1))
+    S = g.bsgs_diag_matvec(keys, baby, db, 0)
+    exact = wl.exact_scores()
+    dec = g.decrypt_decode(keys, S)
+    assert np.max(np.abs(dec - exact)) <= 2 ** -20
+    coeffs = F.cheb_step_coeffs(63, 0.3)
+    for d1 in (2, 8):
+        Y = g.chebyshev_eval(keys, S, coeffs, d1)
+        y = g.decrypt_decode(keys, Y)
+        assert np.max(np.abs(y - np.polynomial.chebyshev.chebval(exact, coeffs))) <= 2 ** -12
+        assert np.array_equal(np.nonzero(y >= 0.5)[0], wl.planted)

@@ -190,23 +190,30 @@ def test_modup_is_x_plus_small_multiple_of_digit(deep_ctx):
             assert len(es) == 1
 
 
-def test_moddown_divides_by_P(deep_ctx):
+def test_moddown_is_rounded_division_by_P(deep_ctx):
+    """ModDown(u) = round(U / P) mod Q_level for the integer U whose residues
+    over Q_level U P are u (big-integer CRT), including an exact multiple."""
     ctx, N = deep_ctx, deep_ctx.N
     level = 9
     ext = list(range(level + 1)) + [ctx.L + 1 + j for j in range(ctx.nP)]
+    mods = [ctx.moduli[g] for g in ext]
     P = math.prod(ctx.p)
     rnd = np.random.default_rng(3)
-    w = [int(v) for v in rnd.integers(0, 2**62, N)]
-    v = [int(s) for s in rnd.integers(0, 2**40, N)]
-    u = np.zeros((len(ext), N), dtype=np.uint64)
-    for pos, gm in enumerate(ext):
-        r = ctx.moduli[gm]
-        u[pos] = [(P * w[k] + v[k]) % r for k in range(N)]
+    u = np.stack([rnd.integers(0, m, N, dtype=np.uint64) for m in mods])
+    # coefficient 0: U = P w exactly -> w; coefficient 1: U = P w + (P + 1)/2 -> w + 1
+    w = 123456789123456789
+    for pos, m in enumerate(mods):
+        u[pos][0] = (P * w) % m
+        u[pos][1] = (P * w + (P + 1) // 2) % m
     out = ctx.moddown(level, u)
-    for k in range(N):
-        # (P w + v - v - e P) / P = w - e, 0 <= e < nP, the same e on every limb
-        diffs = {(w[k] - int(out[i][k])) % ctx.q[i] for i in range(level + 1)}
-        assert len(diffs) == 1 and diffs.pop() < ctx.nP
+    Ql = math.prod(ctx.q[: level + 1])
+    assert [int(out[i][0]) for i in range(level + 1)] == [w % q for q in ctx.q[: level + 1]]
+    assert [int(out[i][1]) for i in range(level + 1)] == [(w + 1) % q for q in ctx.q[: level + 1]]
+    for k in range(2, N, 61):
+        U = bigref.crt([int(u[pos][k]) for pos in range(len(mods))], mods)
+        want = (2 * U + P) // (2 * P)   # round(U / P); P odd, no ties
+        got = bigref.crt([int(out[i][k]) for i in range(level + 1)], ctx.q[: level + 1])
+        assert got == want % Ql
 
 
 # --------------------------------------------------------------------------
