@@ -170,6 +170,223 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(NttLaunch a) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Radix-2^LE register kernels for even logN = 4 LE (N = 2^12, 2^16): every
+// 2^(2 LE)-point sub-transform is done by E = 2^LE threads, E coefficients
+// each, in two register rounds of LE stages with one LDS transpose between
+// them.  Butterflies are Harvey's lazy forms (forward values in [0, 4q),
+// inverse in [0, 2q)); outputs are reduced to [0, q).  Round-1 twiddles of
+// the column pass are uniform across the workgroup.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - mulhi64(a, wp) * q; }
+
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
+    u64 x = X >= q2 ? X - q2 : X;
+    const u64 t = shoup_lazy(Y, w, wp, q);
+    X = x + t;
+    Y = x - t + q2;
+}
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
+    u64 s = X + Y;
+    s = s >= q2 ? s - q2 : s;
+    const u64 d = X - Y + q2;
+    X = s;
+    Y = shoup_lazy(d, w, wp, q);
+}
+__device__ __forceinline__ u64 red4(u64 x, u64 q) {
+    x = x >= 2 * q ? x - 2 * q : x;
+    return x >= q ? x - q : x;
+}
+
+template <int LE>
+__global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
+    __shared__ u64 tile[R * COLS];
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
+    const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
+    const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
+    const int col = blockIdx.x * COLS + c;
+    u64 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = x[col + (size_t)(g + E * k) * R];
+#pragma unroll
+    for (int st = 0; st < LE; ++st) {
+        const int half = E >> (st + 1);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (1 << st) + (k >> (LE - st));
+                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tile[(g + E * k) * COLS + c] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = tile[(E * g + k) * COLS + c];
+#pragma unroll
+    for (int st = LE; st < LR; ++st) {
+        const int half = 1 << (LR - st - 1);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (1 << st) + ((E * g + k) >> (LR - st));
+                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) x[col + (size_t)(E * g + k) * R] = v[k];
+}
+
+template <int LE>
+__global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
+    __shared__ u64 tile[BLKS * R];
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
+    const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
+    const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
+    const int gb = blockIdx.x * BLKS + blk;
+    u64 *xb = x + (size_t)gb * R;
+    u64 *tb = tile + blk * R;
+    u64 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = xb[u0 + E * k];
+#pragma unroll
+    for (int sl = 0; sl < LE; ++sl) {
+        const int half = E >> (sl + 1);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (1 << (LR + sl)) + (gb << sl) + (k >> (LE - sl));
+                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tb[u0 + E * k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = tb[E * u0 + k];
+#pragma unroll
+    for (int sl = LE; sl < LR; ++sl) {
+        const int half = 1 << (LR - sl - 1);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (1 << (LR + sl)) + (gb << sl) + ((E * u0 + k) >> (LR - sl));
+                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tb[E * u0 + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) xb[u0 + E * k] = red4(tb[u0 + E * k], q);
+}
+
+template <int LE>
+__global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
+    __shared__ u64 tile[BLKS * R];
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    const int N = a.N;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
+    const u64 *tw = a.tw + (size_t)mi * N, *twsh = a.tw_sh + (size_t)mi * N;
+    const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
+    const int gb = blockIdx.x * BLKS + blk;
+    u64 *xb = x + (size_t)gb * R;
+    u64 *tb = tile + blk * R;
+    u64 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) tb[u0 + E * k] = xb[u0 + E * k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = tb[E * u0 + k];
+#pragma unroll
+    for (int lt = 0; lt < LE; ++lt) {
+        const int half = 1 << lt;
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + ((E * u0 + k) >> (lt + 1));
+                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tb[E * u0 + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = tb[u0 + E * k];
+#pragma unroll
+    for (int lt = LE; lt < LR; ++lt) {
+        const int half = 1 << (lt - LE);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (k >> (lt + 1 - LE));
+                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) xb[u0 + E * k] = v[k];
+}
+
+template <int LE>
+__global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
+    __shared__ u64 tile[R * COLS];
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const ModConst mc = a.mods[mi];
+    const u64 q = mc.q, q2 = 2 * q;
+    const int N = a.N;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
+    const u64 *tw = a.tw + (size_t)mi * N, *twsh = a.tw_sh + (size_t)mi * N;
+    const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
+    const int col = blockIdx.x * COLS + c;
+    u64 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = x[col + (size_t)(E * g + k) * R];
+#pragma unroll
+    for (int ltp = 0; ltp < LE; ++ltp) {
+        const int half = 1 << ltp;
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (N >> (LR + ltp + 1)) + ((E * g + k) >> (ltp + 1));
+                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) tile[(E * g + k) * COLS + c] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = tile[(g + E * k) * COLS + c];
+#pragma unroll
+    for (int ltp = LE; ltp < LR; ++ltp) {
+        const int half = 1 << (ltp - LE);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if ((k & half) == 0) {
+                const int ti = (N >> (LR + ltp + 1)) + (k >> (ltp + 1 - LE));
+                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        u64 r = shoup_lazy(v[k], mc.ninv, mc.ninv_sh, q);
+        x[col + (size_t)(g + E * k) * R] = r >= q ? r - q : r;
+    }
+}
+
 NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t poly_stride, bool inverse) {
     NttLaunch a;
     a.data = data;
@@ -192,6 +409,18 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     if (nlimbs <= 0 || npoly <= 0) return;
     ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, false);
+    if (c->logN == 16 || c->logN == 12) {
+        const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
+        dim3 g(R / (kThreads / E), nlimbs, npoly);
+        if (LE == 4) {
+            hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_fwd_rows2<4>, g, dim3(kThreads), 0, c->stream, a);
+        } else {
+            hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_fwd_rows2<3>, g, dim3(kThreads), 0, c->stream, a);
+        }
+        return;
+    }
     const int lr = a.s1, lc = a.logN - a.s1;
     const int lcols = std::min(12 - lr, lc), lblks = std::min(12 - lc, lr);
     dim3 g1(1 << (lc - lcols), nlimbs, npoly), g2(1 << (lr - lblks), nlimbs, npoly);
@@ -203,6 +432,18 @@ void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     if (nlimbs <= 0 || npoly <= 0) return;
     ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, true);
+    if (c->logN == 16 || c->logN == 12) {
+        const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
+        dim3 g(R / (kThreads / E), nlimbs, npoly);
+        if (LE == 4) {
+            hipLaunchKernelGGL(k_inv_rows2<4>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        } else {
+            hipLaunchKernelGGL(k_inv_rows2<3>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_inv_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
+        }
+        return;
+    }
     const int lr = a.s1, lc = a.logN - a.s1;
     const int lcols = std::min(12 - lr, lc), lblks = std::min(12 - lc, lr);
     dim3 g1(1 << (lc - lcols), nlimbs, npoly), g2(1 << (lr - lblks), nlimbs, npoly);
