@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--d1", type=int, default=2, help="Chebyshev baby-step degree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the steps, one device-to-device copy of this many MiB (the known-size "
+                         "reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding by matrix "
@@ -130,6 +133,17 @@ def main():
         step(s, args.d1)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
+    if args.calib_copy_mib:
+        # known-size device copy just before the timed steps: the reference
+        # for the HBM byte counters and the marker that opens the timed
+        # region in a kernel trace
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mib} MiB done")
+        del src, dst
 
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfrhip.so")
+MB_LIB = os.path.join(HERE, "libfrmb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["params.cpp", "kernels_ntt.hip", "kernels_rns.hip", "kernels_enc.hip", "api.cpp"]
@@ -40,6 +41,10 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # integer-VALU issue-rate probes (roofline denominator of the NTT)
+    mb = [HIPCC, *FLAGS, "-shared", "-o", MB_LIB + ".tmp", os.path.join(CSRC, "microbench.hip")]
+    subprocess.run(mb, check=True, capture_output=True)
+    os.replace(MB_LIB + ".tmp", MB_LIB)
     return LIB
 
 

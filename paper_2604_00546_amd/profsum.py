@@ -1,0 +1,100 @@
+"""Summaries of rocprofv3 CSV output for one benchmark run.
+
+bench.py --calib-copy-mib M issues one device-to-device copy of M MiB just
+before the timed steps; every dispatch after that copy belongs to the timed
+region.  This script restricts the trace (or the counter collection) to
+those dispatches and prints per-kernel figures per step.
+
+usage:
+  python -m paper_2604_00546_amd.profsum trace <run_kernel_trace.csv> --steps S --calib-mib M
+  python -m paper_2604_00546_amd.profsum counters <fetch.csv> <write.csv> --calib-mib M
+"""
+import argparse
+import collections
+import csv
+
+
+def _short(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return n.split("(")[0]
+
+
+def _after_marker(rows, calib_mib, size_key):
+    """Rows after the calibration copy (the copy kernel that moves calib_mib MiB)."""
+    start = None
+    for i, r in enumerate(rows):
+        if "copyBuffer" in r["Kernel_Name"] and size_key(r) >= calib_mib * 1024 * 0.45:
+            start = i
+    if start is None:
+        raise SystemExit("calibration copy not found in the trace")
+    return rows[start + 1:], rows[start]
+
+
+def trace(path, steps, calib_mib):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    # the copy kernel's grid covers M MiB; identify it as the last long copy
+    cand = [i for i, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+    dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    start = max(cand, key=lambda i: dur(rows[i]))
+    timed = rows[start + 1:]
+    agg = collections.defaultdict(lambda: [0, 0])
+    for r in timed:
+        a = agg[_short(r["Kernel_Name"])]
+        a[0] += 1
+        a[1] += dur(r)
+    total = sum(v[1] for v in agg.values())
+    span = int(timed[-1]["End_Timestamp"]) - int(timed[0]["Start_Timestamp"])
+    print(f"timed region: {len(timed)} dispatches over {steps} step(s); kernel time {total / 1e6 / steps:.3f} ms/step; "
+          f"wall span {span / 1e6 / steps:.3f} ms/step")
+    print(f"{'kernel':40s} {'calls/step':>10s} {'ms/step':>9s} {'avg us':>8s} {'share':>6s}")
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"{k[:40]:40s} {n / steps:10.1f} {t / 1e6 / steps:9.3f} {t / n / 1e3:8.2f} {100 * t / total:5.1f}%")
+
+
+def counters(fpath, wpath, calib_mib):
+    def load(path, ctr):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == ctr]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+    f, w = load(fpath, "FETCH_SIZE"), load(wpath, "WRITE_SIZE")
+    ref_kib = calib_mib * 1024.0
+    # calibration: the largest copy's counters against its known size
+    fc = max((r for r in f if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    wc = max((r for r in w if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    kf, kw = ref_kib / float(fc["Counter_Value"]), ref_kib / float(wc["Counter_Value"])
+    print(f"calibration copy of {calib_mib} MiB: FETCH_SIZE {float(fc['Counter_Value']):.1f} KiB -> factor {kf:.4f}; "
+          f"WRITE_SIZE {float(wc['Counter_Value']):.1f} KiB -> factor {kw:.4f}")
+    fi = [r for r in f if int(r["Dispatch_Id"]) > int(fc["Dispatch_Id"])]
+    wi = {r["Dispatch_Id"]: float(r["Counter_Value"]) for r in w}
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0])
+    for r in fi:
+        a = agg[_short(r["Kernel_Name"])]
+        a[0] += 1
+        a[1] += float(r["Counter_Value"]) * kf
+        a[2] += wi.get(r["Dispatch_Id"], 0.0) * kw
+    print(f"{'kernel':40s} {'dispatches':>10s} {'read MiB/disp':>14s} {'write MiB/disp':>15s}")
+    for k, (n, rd, wr) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"{k[:40]:40s} {n:10d} {rd / n / 1024:14.3f} {wr / n / 1024:15.3f}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("path")
+    t.add_argument("--steps", type=int, required=True)
+    t.add_argument("--calib-mib", type=int, required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("fetch")
+    c.add_argument("write")
+    c.add_argument("--calib-mib", type=int, required=True)
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        trace(a.path, a.steps, a.calib_mib)
+    else:
+        counters(a.fetch, a.write, a.calib_mib)
+
+
+if __name__ == "__main__":
+    main()
