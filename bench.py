@@ -191,6 +191,17 @@ def main():
                            "launches": n_launch, "avg_launch_ms": avg_ms,
                            "bytes_per_launch": k_bytes / n_launch}
     if args.breakdown:
+        ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev3[0].record(stream)
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, s["n1"]), outs=s["baby"][1:])
+        ev3[1].record(stream)
+        ctx.bsgs_diag_matvec(s["keys"], s["baby"], s["db"], 0, out=s["score"])
+        ev3[2].record(stream)
+        ctx.chebyshev_eval(s["keys"], s["score"], s["coeffs"], args.d1, out=s["cheb"])
+        ev3[3].record(stream)
+        torch.cuda.synchronize()
+        out["phase_ms"] = {"baby_rotations": ev3[0].elapsed_time(ev3[1]), "matvec": ev3[1].elapsed_time(ev3[2]),
+                           "chebyshev": ev3[2].elapsed_time(ev3[3])}
         bd = {}
         for cls in ctx.KERNEL_CLASSES:
             ctx.prof_begin(cls)

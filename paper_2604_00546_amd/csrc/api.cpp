@@ -142,51 +142,61 @@ int flag_check(fr_ctx *c, const char *what) {
 // ---------------------------------------------------------------------------
 // key switching pieces
 // ---------------------------------------------------------------------------
-// D[t] (t < ndig) = ModUp of digit t of c1 (eval domain) over Q_level U P.
-void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D) {
+// D[b][t] (b < batch, t < ndig) = ModUp of digit t of c1[b] (eval domain,
+// c1 polynomials c1_stride words apart) over Q_level U P; D items are
+// ndig * nE * N words apart.
+void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t c1_stride = 0) {
     const int N = c->N, nE = level + 1 + c->nP, ndig = num_digits(c, level);
-    u64 *X = scratch(c, (size_t)(level + 1) * N);
-    (void)hipMemcpyAsync(X, c1, (size_t)(level + 1) * N * 8, hipMemcpyDeviceToDevice, c->stream);
-    frk::ntt_inv(c, X, level + 1, qmap(), 1, 0);
+    const size_t lw = (size_t)(level + 1) * N, dstride = (size_t)ndig * nE * N;
+    u64 *X = scratch(c, (size_t)batch * lw);
+    frk::ntt_inv(c, X, level + 1, qmap(), batch, lw, c1, c1_stride);
     for (int t = 0; t < ndig; ++t) {
         u64 *Dt = D + (size_t)t * nE * N;
         const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
-        frk::modup_digit(c, Dt, X, level, t);
+        frk::modup_digit(c, Dt, X, level, t, batch, dstride, lw);
         LimbMap m{0, lo, nd, level + 1, c->L + 1};
-        frk::ntt_fwd(c, Dt, nE - nd, m, 1, 0);
-        (void)hipMemcpyAsync(Dt + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)nd * N * 8, hipMemcpyDeviceToDevice,
-                             c->stream);
+        frk::ntt_fwd(c, Dt, nE - nd, m, batch, dstride);
+        if (batch == 1)
+            (void)hipMemcpyAsync(Dt + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)nd * N * 8,
+                                 hipMemcpyDeviceToDevice, c->stream);
+        else
+            (void)hipMemcpy2DAsync(Dt + (size_t)lo * N, dstride * 8, c1 + (size_t)lo * N, c1_stride * 8,
+                                   (size_t)nd * N * 8, batch, hipMemcpyDeviceToDevice, c->stream);
     }
+}
+
+// V[b] = the eval-domain ModDown correction of U[b] (b < nblk): iNTT of the
+// P limbs, centered base conversion to Q_level, NTT.  U is [nblk][2][nE][N],
+// V is [nblk][2][level+1][N].
+void ks_moddown_prep(fr_ctx *c, const u64 *U, int nblk, int level, u64 *V) {
+    const int N = c->N, nE = level + 1 + c->nP, nP = c->nP;
+    u64 *Upc = scratch(c, (size_t)2 * nblk * nP * N);
+    frk::ntt_inv(c, Upc, nP, pmap(c), 2 * nblk, (size_t)nP * N, U + (size_t)(level + 1) * N, (size_t)nE * N);
+    frk::moddown_fbc(c, V, Upc, level, 2 * nblk);
+    frk::ntt_fwd(c, V, level + 1, qmap(), 2 * nblk, (size_t)(level + 1) * N);
 }
 
 // out (ciphertext [2][level+1][N]) (+)= ModDown(U), U = [2][nE][N]
 void ks_moddown(fr_ctx *c, const u64 *U, int level, u64 *out, bool accumulate) {
-    const int N = c->N, nE = level + 1 + c->nP, nP = c->nP;
-    u64 *Upc = scratch(c, (size_t)2 * nP * N);
-    for (int p = 0; p < 2; ++p)
-        (void)hipMemcpyAsync(Upc + (size_t)p * nP * N, U + ((size_t)p * nE + level + 1) * N, (size_t)nP * N * 8,
-                             hipMemcpyDeviceToDevice, c->stream);
-    frk::ntt_inv(c, Upc, nP, pmap(c), 2, (size_t)nP * N);
+    Scope sc(c->arena);
+    const int N = c->N, nE = level + 1 + c->nP;
     u64 *V = scratch(c, (size_t)2 * (level + 1) * N);
-    frk::moddown_fbc(c, V, Upc, level);
-    frk::ntt_fwd(c, V, level + 1, qmap(), 2, (size_t)(level + 1) * N);
+    ks_moddown_prep(c, U, 1, level, V);
     frk::moddown_finish(c, out, U, V, level, 2, (size_t)(level + 1) * N, (size_t)nE * N, (size_t)(level + 1) * N,
                         accumulate);
 }
 
-// out = Rescale(in); in at level l >= 1, out at l - 1; out != in
-void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out) {
+// out = Rescale(in) for ncts consecutive ciphertexts at level l >= 1 (in:
+// [ncts][2][l+1][N], out: [ncts][2][l][N]); out != in
+void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out, int ncts = 1) {
     Scope sc(c->arena);
-    const int N = c->N;
-    u64 *xt = scratch(c, (size_t)2 * N);
-    for (int p = 0; p < 2; ++p)
-        (void)hipMemcpyAsync(xt + (size_t)p * N, in + ((size_t)p * (l + 1) + l) * N, (size_t)N * 8,
-                             hipMemcpyDeviceToDevice, c->stream);
-    frk::ntt_inv(c, xt, 1, single(l), 2, (size_t)N);
-    u64 *Y = scratch(c, (size_t)2 * l * N);
-    frk::rescale_prep(c, Y, xt, l, 2, (size_t)l * N, (size_t)N);
-    frk::ntt_fwd(c, Y, l, qmap(), 2, (size_t)l * N);
-    frk::rescale_finish(c, out, in, Y, l, 2, (size_t)l * N, (size_t)(l + 1) * N, (size_t)l * N);
+    const int N = c->N, np = 2 * ncts;
+    u64 *xt = scratch(c, (size_t)np * N);
+    frk::ntt_inv(c, xt, 1, single(l), np, (size_t)N, in + (size_t)l * N, (size_t)(l + 1) * N);
+    u64 *Y = scratch(c, (size_t)np * l * N);
+    frk::rescale_prep(c, Y, xt, l, np, (size_t)l * N, (size_t)N);
+    frk::ntt_fwd(c, Y, l, qmap(), np, (size_t)l * N);
+    frk::rescale_finish(c, out, in, Y, l, np, (size_t)l * N, (size_t)(l + 1) * N, (size_t)l * N);
 }
 
 // d = relinearise + rescale of a x b (both at level l) into out at l - 1
@@ -793,29 +803,37 @@ static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, con
     const int N = c->N, l = in->level, nE = l + 1 + c->nP;
     const size_t lw = (size_t)(l + 1) * N;
     std::vector<u64> gs(nrot);
+    std::vector<int> live;  // rotations that need a key switch
     for (int r = 0; r < nrot; ++r) {
         gs[r] = galois_element(N, rots[r]);
         CHECK(gs[r] == 1 || K->find(gs[r]), FR_ENOKEY, "fr_rotate_hoisted: no key for rotation %d", rots[r]);
         if (int e = check_out(c, &outs[r], l, "fr_rotate_hoisted")) return e;
         CHECK(outs[r].data != in->data, FR_EINVAL, "fr_rotate_hoisted: output aliases input");
+        if (gs[r] != 1) live.push_back(r);
     }
     Scope sc(c->arena);
-    u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
-    u64 *U = scratch(c, (size_t)2 * nE * N);
-    CHECK(D && U, FR_ENOMEM, "fr_rotate_hoisted: scratch");
-    bool need_modup = false;
-    for (u64 g : gs) need_modup |= (g != 1);
-    if (need_modup) ks_modup(c, in->data + lw, l, D);
-    for (int r = 0; r < nrot; ++r) {
-        u64 *o = outs[r].data;
-        if (gs[r] == 1) {
-            FR_HIP(hipMemcpyAsync(o, in->data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
-        } else {
-            Scope inner(c->arena);
-            frk::ks_inner(c, U, U + (size_t)nE * N, D, K->find(gs[r])->data, gs[r], l, false);
-            ks_moddown(c, U, l, o, false);
+    const int nl = (int)live.size();
+    if (nl) {
+        u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+        u64 *U = scratch(c, (size_t)nl * 2 * nE * N);
+        u64 *V = scratch(c, (size_t)nl * 2 * lw);
+        ks_modup(c, in->data + lw, l, D);
+        for (int i = 0; i < nl; ++i) {
+            const u64 g = gs[live[i]];
+            u64 *Ui = U + (size_t)i * 2 * nE * N;
+            frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false);
+        }
+        ks_moddown_prep(c, U, nl, l, V);
+        for (int i = 0; i < nl; ++i) {
+            const int r = live[i];
+            u64 *o = outs[r].data;
+            frk::moddown_finish(c, o, U + (size_t)i * 2 * nE * N, V + (size_t)i * 2 * lw, l, 2, lw, (size_t)nE * N,
+                                lw, false);
             frk::automorph(c, o, in->data, gs[r], l + 1, 1, 0, 0, true);
         }
+    }
+    for (int r = 0; r < nrot; ++r) {
+        if (gs[r] == 1) FR_HIP(hipMemcpyAsync(outs[r].data, in->data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
         outs[r].level = l;
         outs[r].scale = in->scale;
     }
@@ -1063,20 +1081,20 @@ extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *bab
     for (int i = 0; i < n1; ++i) bp[i] = baby[i].data;
     const u64 *diag = db->data + (size_t)group * ell * (db->level + 1) * N;
     frk::bsgs_mac(c, P, bp.data(), n1, diag, ell, db->level, lv, bl);
-    for (int j = 0; j < n2; ++j) rescale_dev(c, P + j * pw, lv, R + j * rw);
+    rescale_dev(c, P, lv, R, n2);
     FR_HIP(hipMemcpyAsync(out->data, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
     if (n2 > 1) {
-        const int nE = l + 1 + c->nP;
-        u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+        const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
+        const size_t dstride = (size_t)ndig * nE * N;
+        u64 *D = scratch(c, (size_t)(n2 - 1) * dstride);
         u64 *U = scratch(c, (size_t)2 * nE * N);
         CHECK(D && U, FR_ENOMEM, "fr_bsgs_diag_matvec: scratch");
+        // ModUp of every P_j.c1, j >= 1, in one batch
+        ks_modup(c, R + rw + (size_t)(l + 1) * N, l, D, n2 - 1, rw);
         for (int j = 1; j < n2; ++j) {
-            Scope inner(c->arena);
             const u64 g = galois_element(N, j * n1);
-            const u64 *Rj = R + j * rw;
-            ks_modup(c, Rj + (size_t)(l + 1) * N, l, D);
-            frk::ks_inner(c, U, U + (size_t)nE * N, D, K->find(g)->data, g, l, j > 1);
-            frk::automorph(c, out->data, Rj, g, l + 1, 1, 0, 0, true);
+            frk::ks_inner(c, U, U + (size_t)nE * N, D + (size_t)(j - 1) * dstride, K->find(g)->data, g, l, j > 1);
+            frk::automorph(c, out->data, R + j * rw, g, l + 1, 1, 0, 0, true);
         }
         ks_moddown(c, U, l, out->data, true);
     }
@@ -1089,173 +1107,118 @@ extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *bab
 // ---------------------------------------------------------------------------
 // Chebyshev threshold
 // ---------------------------------------------------------------------------
-// The evaluator is written once over a backend: LevelSim tracks levels only
-// (planning helpers), DevBackend runs on the device.  Recursion: Chebyshev-
-// basis division p = q T_M + r (q_0 = c_M, q_i = 2 c_{M+i}, r_0 = c_0,
-// r_k = c_k - c_{2M-k}) with M = d1 2^j the largest below the number of
-// coefficients, leaves of at most d1 coefficients, powers from
-// T_i = 2 T_ceil(i/2) T_floor(i/2) - T_(i mod 2).
+// The recursion is written once (Cheb<B>) and run on a recording backend that
+// builds the DAG of operations: Chebyshev-basis division p = q T_M + r
+// (q_0 = c_M, q_i = 2 c_{M+i}, r_0 = c_0, r_k = c_k - c_{2M-k}) with M = d1 2^j
+// the largest below the number of coefficients, leaves of at most d1
+// coefficients, and powers T_i = 2 T_ceil(i/2) T_floor(i/2) - T_(i mod 2).
+// The DAG gives the planning answers (levels, product count) and is executed
+// on the device in waves: every operation whose inputs are ready runs in the
+// same wave, relinearised products and rescales of one wave in one batch.
 namespace {
 
-struct SimCt {
-    int level;
+enum COp { C_INPUT, C_ADJUST, C_MUL, C_ADD, C_SUB, C_TWICE_M1, C_SCALAR, C_LEAF };
+
+struct CNode {
+    COp op;
+    int a = -1, b = -1;
+    int level = 0;
+    double cst = 0.0;
+    std::vector<int> ins;    // leaf: T_1..T_{m-1}
+    std::vector<double> cf;  // leaf: c_0..c_{m-1}
 };
 
-struct LevelSim {
-    using H = std::shared_ptr<SimCt>;
-    int nmul = 0;
-    bool fail = false;
-    H make(int l) { return std::make_shared<SimCt>(SimCt{l}); }
-    int level(const H &h) const { return h->level; }
-    H adjust(const H &a, int lam) {
-        if (a->level == lam) return a;
-        if (lam < 0 || lam > a->level) fail = true;
-        return make(lam);
-    }
-    H mul(const H &a, const H &b) {
-        const int lam = std::min(a->level, b->level);
-        if (lam < 1) fail = true;
-        ++nmul;
-        return make(lam - 1);
-    }
-    H add(const H &a, const H &) { return make(a->level); }
-    H sub(const H &a, const H &) { return make(a->level); }
-    H twice_minus_const(const H &a) { return make(a->level); }
-    H scalar(const H &T, double) {
-        if (T->level < 1) fail = true;
-        return make(T->level - 1);
-    }
-    H leaf(const std::vector<H> &Ts, const double *, int m) {
-        int lam = INT_MAX;
-        for (int i = 1; i < m; ++i) lam = std::min(lam, Ts[i]->level - 1);
-        if (lam < 0) fail = true;
-        return make(lam);
-    }
+struct RH {
+    int id = -1;
+    explicit operator bool() const { return id >= 0; }
 };
 
-struct DevBackend {
-    struct DCt {
-        u64 *d;
-        int level;
-        double scale;
-        CtPool *pool;
-        ~DCt() {
-            if (pool && d) pool->put(d);
-        }
-    };
-    using H = std::shared_ptr<DCt>;
-    fr_ctx *c;
-    const fr_keys *K;
-    CtPool *pool;
-    double D[FR_MAXLEVEL];
+struct Recorder {
+    using H = RH;
+    std::vector<CNode> nodes;
     int nmul = 0;
     bool fail = false;
-    int err = FR_OK;
-
-    H alloc(int level) {
-        u64 *p = pool->get((size_t)2 * (level + 1) * c->N);
-        if (!p) {
-            fail = true;
-            err = fr_fail(FR_ENOMEM, "fr_chebyshev_eval: out of device memory");
-            return nullptr;
-        }
-        return H(new DCt{p, level, D[level], pool});
+    H push(CNode n) {
+        nodes.push_back(std::move(n));
+        return H{(int)nodes.size() - 1};
     }
-    int level(const H &h) const { return h->level; }
-    Ct view(const H &h) const { return Ct{h->d, h->level, h->scale}; }
-
-    // drop to lam+1 and multiply by k, then rescale to lam (canonical scale)
-    H scale_to(const H &a, int lam, long long k) {
-        H t = alloc(lam + 1);
-        H r = alloc(lam);
-        if (!t || !r) return nullptr;
-        mul_int_dev(c, a->d, (size_t)(a->level + 1) * c->N, lam + 2, k, t->d, (size_t)(lam + 2) * c->N);
-        rescale_dev(c, t->d, lam + 1, r->d);
-        return r;
+    H input(int level) {
+        CNode n{C_INPUT};
+        n.level = level;
+        return push(n);
     }
+    int level(const H &h) const { return nodes[h.id].level; }
     H adjust(const H &a, int lam) {
-        if (!a) return nullptr;
-        if (a->level == lam) return a;
-        if (lam < 0 || lam > a->level) {
+        if (!a) return H();
+        if (level(a) == lam) return a;
+        if (lam < 0 || lam > level(a)) {
             fail = true;
-            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
-            return nullptr;
+            return H();
         }
-        const long long k = (long long)std::nearbyint((D[lam] * (double)c->mod[lam + 1]) / D[a->level]);
-        return scale_to(a, lam, k);
+        CNode n{C_ADJUST};
+        n.a = a.id;
+        n.level = lam;
+        return push(n);
     }
     H mul(const H &a, const H &b) {
-        if (!a || !b) return nullptr;
-        const int lam = std::min(a->level, b->level);
+        if (!a || !b) return H();
+        const int lam = std::min(level(a), level(b));
         if (lam < 1) {
             fail = true;
-            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
-            return nullptr;
+            return H();
         }
         H x = adjust(a, lam), y = adjust(b, lam);
-        if (!x || !y) return nullptr;
-        H r = alloc(lam - 1);
-        if (!r) return nullptr;
-        int e = mul_relin_rescale_dev(c, K, view(x), view(y), r->d);
-        if (e) {
-            fail = true;
-            err = e;
-            return nullptr;
-        }
+        CNode n{C_MUL};
+        n.a = x.id;
+        n.b = y.id;
+        n.level = lam - 1;
         ++nmul;
-        return r;
+        return push(n);
     }
-    H addsub(const H &a, const H &b, bool sub) {
-        if (!a || !b) return nullptr;
-        H r = alloc(a->level);
-        if (!r) return nullptr;
-        const size_t lw = (size_t)(a->level + 1) * c->N;
-        frk::add(c, r->d, a->d, b->d, a->level + 1, 2, lw, lw, lw, sub);
-        return r;
+    H bin(COp op, const H &a, const H &b) {
+        if (!a || !b) return H();
+        CNode n{op};
+        n.a = a.id;
+        n.b = b.id;
+        n.level = level(a);
+        return push(n);
     }
-    H add(const H &a, const H &b) { return addsub(a, b, false); }
-    H sub(const H &a, const H &b) { return addsub(a, b, true); }
-    // 2 a - 1
+    H add(const H &a, const H &b) { return bin(C_ADD, a, b); }
+    H sub(const H &a, const H &b) { return bin(C_SUB, a, b); }
     H twice_minus_const(const H &a) {
-        H r = addsub(a, a, false);
-        if (r) add_const_dev(c, r->d, r->level, -1.0, D[r->level]);
-        return r;
+        if (!a) return H();
+        CNode n{C_TWICE_M1};
+        n.a = a.id;
+        n.level = level(a);
+        return push(n);
     }
     H scalar(const H &T, double cst) {
-        if (!T) return nullptr;
-        const int lv = T->level, lam = lv - 1;
-        if (lam < 0) {
+        if (!T) return H();
+        if (level(T) < 1) {
             fail = true;
-            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
-            return nullptr;
+            return H();
         }
-        const long long k = (long long)std::nearbyint(((cst * D[lam]) * (double)c->mod[lv]) / D[lv]);
-        return scale_to(T, lam, k);
+        CNode n{C_SCALAR};
+        n.a = T.id;
+        n.cst = cst;
+        n.level = level(T) - 1;
+        return push(n);
     }
     H leaf(const std::vector<H> &Ts, const double *cf, int m) {
         int lam = INT_MAX;
+        CNode n{C_LEAF};
         for (int i = 1; i < m; ++i) {
-            if (!Ts[i]) return nullptr;
-            lam = std::min(lam, Ts[i]->level - 1);
+            if (!Ts[i]) return H();
+            lam = std::min(lam, level(Ts[i]) - 1);
+            n.ins.push_back(Ts[i].id);
         }
         if (lam < 0) {
             fail = true;
-            err = fr_fail(FR_ELEVEL, "fr_chebyshev_eval: not enough levels");
-            return nullptr;
+            return H();
         }
-        H acc = alloc(lam + 1), t = alloc(lam + 1), r = alloc(lam);
-        if (!acc || !t || !r) return nullptr;
-        const size_t lw = (size_t)(lam + 2) * c->N;
-        for (int i = 1; i < m; ++i) {
-            const long long k =
-                (long long)std::nearbyint(((cf[i] * D[lam]) * (double)c->mod[lam + 1]) / D[Ts[i]->level]);
-            u64 *dst = i == 1 ? acc->d : t->d;
-            mul_int_dev(c, Ts[i]->d, (size_t)(Ts[i]->level + 1) * c->N, lam + 2, k, dst, lw);
-            if (i > 1) frk::add(c, acc->d, acc->d, t->d, lam + 2, 2, lw, lw, lw, false);
-        }
-        rescale_dev(c, acc->d, lam + 1, r->d);
-        add_const_dev(c, r->d, lam, cf[0], D[lam]);
-        return r;
+        n.cf.assign(cf, cf + m);
+        n.level = lam;
+        return push(n);
     }
 };
 
@@ -1270,15 +1233,15 @@ struct Cheb {
         if (T[i]) return T[i];
         const int a = (i + 1) / 2, b = i / 2;
         H Ta = power(a), Tb = power(b);
-        if (be.fail) return nullptr;
+        if (be.fail || !Ta || !Tb) return H();
         H prod = be.mul(Ta, Tb);
-        if (!prod) return nullptr;
+        if (!prod) return H();
         H res;
         if (a == b) {
             res = be.twice_minus_const(prod);
         } else {
             H two = be.add(prod, prod);
-            if (!two) return nullptr;
+            if (!two) return H();
             H t1 = be.adjust(T[1], be.level(two));
             res = be.sub(two, t1);
         }
@@ -1287,10 +1250,10 @@ struct Cheb {
     }
 
     H eval(const std::vector<double> &cf, int m) {
-        if (be.fail) return nullptr;
+        if (be.fail) return H();
         if (m <= d1) {
             for (int i = 1; i < m; ++i)
-                if (!power(i)) return nullptr;
+                if (!power(i)) return H();
             return be.leaf(T, cf.data(), m);
         }
         int M = d1;
@@ -1302,23 +1265,147 @@ struct Cheb {
         r[0] = cf[0];
         for (int k = 1; k < M; ++k) r[k] = cf[k] - ((2 * M - k < m) ? cf[2 * M - k] : 0.0);
         H TM = power(M);
-        if (!TM) return nullptr;
+        if (!TM) return H();
         H A;
         if (nq == 1) {
             A = be.scalar(TM, q[0]);
         } else {
             H Q = eval(q, nq);
-            if (!Q) return nullptr;
+            if (!Q) return H();
             A = be.mul(Q, TM);
         }
-        if (!A) return nullptr;
+        if (!A) return H();
         H R = eval(r, M);
-        if (!R) return nullptr;
+        if (!R) return H();
         const int lam = std::min(be.level(A), be.level(R));
         H x = be.adjust(A, lam), y = be.adjust(R, lam);
         return be.add(x, y);
     }
 };
+
+// records the evaluation of a degree-`degree` series from an input at in_level
+struct ChebPlan {
+    Recorder rec;
+    RH out;
+    bool ok = false;
+    ChebPlan(int in_level, const double *cf, int degree, int d1) {
+        Cheb<Recorder> ch{rec, d1, std::vector<RH>(std::max(degree + 2, 2 * d1 + 2))};
+        ch.T[1] = rec.input(in_level);
+        std::vector<double> coef(cf, cf + degree + 1);
+        out = ch.eval(coef, degree + 1);
+        ok = out && !rec.fail;
+    }
+};
+
+long long rne_ll(double x) { return (long long)std::nearbyint(x); }
+
+// Executes the recorded DAG in waves.  Node outputs live in the arena for the
+// duration of the call; every ciphertext of a wave that needs a rescale is
+// staged contiguously so that one batched rescale serves the wave.
+int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, const double *D, const u64 *in,
+                 std::vector<u64 *> &buf) {
+    const int N = c->N, n = (int)nodes.size();
+    std::vector<int> depth(n, 0);
+    int maxd = 0;
+    for (int i = 0; i < n; ++i) {
+        const CNode &nd = nodes[i];
+        int d = 0;
+        if (nd.a >= 0) d = std::max(d, depth[nd.a] + 1);
+        if (nd.b >= 0) d = std::max(d, depth[nd.b] + 1);
+        for (int x : nd.ins) d = std::max(d, depth[x] + 1);
+        depth[i] = d;
+        maxd = std::max(maxd, d);
+    }
+    buf.assign(n, nullptr);
+    for (int i = 0; i < n; ++i)
+        if (nodes[i].op == C_INPUT) buf[i] = const_cast<u64 *>(in);
+    const KeyEntry *rk = K->find(0);
+    CHECK(rk, FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
+    auto lw = [&](int level) { return (size_t)(level + 1) * N; };
+    for (int d = 1; d <= maxd; ++d) {
+        // --- scalar family (adjust, scalar, leaf), grouped by output level
+        std::vector<std::vector<int>> by_level(FR_MAXLEVEL), mul_by_level(FR_MAXLEVEL);
+        for (int i = 0; i < n; ++i) {
+            if (depth[i] != d) continue;
+            const COp op = nodes[i].op;
+            if (op == C_ADJUST || op == C_SCALAR || op == C_LEAF) by_level[nodes[i].level].push_back(i);
+            if (op == C_MUL) mul_by_level[nodes[i].level + 1].push_back(i);
+        }
+        for (int lam = 0; lam < FR_MAXLEVEL; ++lam) {
+            const auto &L = by_level[lam];
+            if (L.empty()) continue;
+            const int B = (int)L.size();
+            const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
+            u64 *stage = scratch(c, (size_t)B * sw);
+            u64 *out = scratch(c, (size_t)B * ow);
+            u64 *tmp = scratch(c, sw);
+            for (int b = 0; b < B; ++b) {
+                const CNode &nd = nodes[L[b]];
+                u64 *st = stage + (size_t)b * sw;
+                if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
+                    const int la = nodes[nd.a].level;
+                    const long long k = nd.op == C_ADJUST
+                                            ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
+                                            : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
+                    mul_int_dev(c, buf[nd.a], lw(la), lam + 2, k, st, lw(lam + 1));
+                } else {
+                    for (size_t t = 0; t < nd.ins.size(); ++t) {
+                        const int src = nd.ins[t], ls = nodes[src].level;
+                        const long long k = rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls]);
+                        mul_int_dev(c, buf[src], lw(ls), lam + 2, k, t == 0 ? st : tmp, lw(lam + 1));
+                        if (t > 0) frk::add(c, st, st, tmp, lam + 2, 2, lw(lam + 1), lw(lam + 1), lw(lam + 1), false);
+                    }
+                }
+            }
+            rescale_dev(c, stage, lam + 1, out, B);
+            for (int b = 0; b < B; ++b) {
+                buf[L[b]] = out + (size_t)b * ow;
+                if (nodes[L[b]].op == C_LEAF) add_const_dev(c, buf[L[b]], lam, nodes[L[b]].cf[0], D[lam]);
+            }
+        }
+        // --- relinearised products, grouped by input level
+        for (int lv = 1; lv < FR_MAXLEVEL; ++lv) {
+            const auto &L = mul_by_level[lv];
+            if (L.empty()) continue;
+            const int B = (int)L.size(), nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
+            const size_t cw = 2 * lw(lv);
+            u64 *T01 = scratch(c, (size_t)B * cw);
+            u64 *T2 = scratch(c, (size_t)B * lw(lv));
+            u64 *Dg = scratch(c, (size_t)B * ndig * nE * N);
+            u64 *U = scratch(c, (size_t)B * 2 * nE * N);
+            u64 *V = scratch(c, (size_t)B * cw);
+            u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
+            for (int b = 0; b < B; ++b) {
+                const CNode &nd = nodes[L[b]];
+                const u64 *x = buf[nd.a], *y = buf[nd.b];
+                u64 *t01 = T01 + (size_t)b * cw;
+                frk::tensor(c, t01, t01 + lw(lv), T2 + (size_t)b * lw(lv), x, x + lw(lv), y, y + lw(lv), lv + 1);
+            }
+            ks_modup(c, T2, lv, Dg, B, lw(lv));
+            frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
+                          (size_t)2 * nE * N);
+            ks_moddown_prep(c, U, B, lv, V);
+            for (int b = 0; b < B; ++b)
+                frk::moddown_finish(c, T01 + (size_t)b * cw, U + (size_t)b * 2 * nE * N, V + (size_t)b * cw, lv, 2,
+                                    lw(lv), (size_t)nE * N, lw(lv), true);
+            rescale_dev(c, T01, lv, out, B);
+            for (int b = 0; b < B; ++b) buf[L[b]] = out + (size_t)b * 2 * lw(lv - 1);
+        }
+        // --- additions
+        for (int i = 0; i < n; ++i) {
+            if (depth[i] != d) continue;
+            const CNode &nd = nodes[i];
+            if (nd.op != C_ADD && nd.op != C_SUB && nd.op != C_TWICE_M1) continue;
+            const size_t w = lw(nd.level);
+            u64 *o = scratch(c, 2 * w);
+            const u64 *y = nd.op == C_TWICE_M1 ? buf[nd.a] : buf[nd.b];
+            frk::add(c, o, buf[nd.a], y, nd.level + 1, 2, w, w, w, nd.op == C_SUB);
+            if (nd.op == C_TWICE_M1) add_const_dev(c, o, nd.level, -1.0, D[nd.level]);
+            buf[i] = o;
+        }
+    }
+    return FR_OK;
+}
 
 }  // namespace
 
@@ -1327,32 +1414,38 @@ extern "C" int fr_chebyshev_eval(fr_ctx *c, const fr_keys *K, const fr_ct *in, c
     CHECK(c && K && cf && out, FR_EINVAL, "fr_chebyshev_eval: null argument");
     CHECK(degree >= 1 && d1 >= 2, FR_EINVAL, "fr_chebyshev_eval: need degree >= 1 and d1 >= 2");
     if (int e = check_ct(c, in, "fr_chebyshev_eval")) return e;
-    const int ol = fr_cheb_out_level(in->level, degree, d1);
-    CHECK(ol >= 0, FR_ELEVEL, "fr_chebyshev_eval: not enough levels for degree %d from level %d", degree, in->level);
+    ChebPlan plan(in->level, cf, degree, d1);
+    CHECK(plan.ok, FR_ELEVEL, "fr_chebyshev_eval: not enough levels for degree %d from level %d", degree, in->level);
+    const int ol = plan.rec.nodes[plan.out.id].level;
     if (int e = check_out(c, out, ol, "fr_chebyshev_eval")) return e;
     CHECK(K->find(0), FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
     c->arena.reset();
-    DevBackend be;
-    be.c = c;
-    be.K = K;
-    be.pool = &pool_of(c);
-    be.D[in->level] = in->scale;
-    for (int l = in->level; l >= 1; --l) be.D[l - 1] = (be.D[l] * be.D[l]) / (double)c->mod[l];
-    int res_level = -1;
-    {
-        Cheb<DevBackend> ch{be, d1, std::vector<DevBackend::H>(std::max(degree + 2, 2 * d1 + 2))};
-        ch.T[1] = DevBackend::H(new DevBackend::DCt{in->data, in->level, in->scale, nullptr});
-        std::vector<double> coef(cf, cf + degree + 1);
-        DevBackend::H y = ch.eval(coef, degree + 1);
-        if (!y) return be.err ? be.err : fr_fail(FR_ELEVEL, "fr_chebyshev_eval: evaluation failed");
-        res_level = y->level;
-        FR_HIP(hipMemcpyAsync(out->data, y->d, (size_t)2 * (y->level + 1) * c->N * 8, hipMemcpyDeviceToDevice,
-                              c->stream));
-    }
+    Scope sc(c->arena);
+    double D[FR_MAXLEVEL];
+    D[in->level] = in->scale;
+    for (int l = in->level; l >= 1; --l) D[l - 1] = (D[l] * D[l]) / (double)c->mod[l];
+    std::vector<u64 *> buf;
+    if (int e = cheb_execute(c, K, plan.rec.nodes, D, in->data, buf)) return e;
+    FR_HIP(hipMemcpyAsync(out->data, buf[plan.out.id], (size_t)2 * (ol + 1) * c->N * 8, hipMemcpyDeviceToDevice,
+                          c->stream));
     FR_HIP(hipGetLastError());
-    out->level = res_level;
-    out->scale = be.D[res_level];
+    out->level = ol;
+    out->scale = D[ol];
     return FR_OK;
+}
+
+extern "C" int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1) {
+    if (degree < 1 || d1 < 2 || in_level < 0) return -1;
+    std::vector<double> coef(degree + 1, 1.0);
+    ChebPlan plan(in_level, coef.data(), degree, d1);
+    return plan.ok ? plan.rec.nodes[plan.out.id].level : -1;
+}
+
+extern "C" int fr_cheb_mult_count(int32_t degree, int32_t d1) {
+    if (degree < 1 || d1 < 2) return -1;
+    std::vector<double> coef(degree + 1, 1.0);
+    ChebPlan plan(1 << 20, coef.data(), degree, d1);
+    return plan.rec.nmul;
 }
 
 // ---------------------------------------------------------------------------
@@ -1403,27 +1496,6 @@ extern "C" int fr_prof_end(fr_ctx *c, int32_t *launches, double *total_ms, doubl
 // ---------------------------------------------------------------------------
 // host-only planning helpers
 // ---------------------------------------------------------------------------
-extern "C" int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1) {
-    if (degree < 1 || d1 < 2 || in_level < 0) return -1;
-    LevelSim sim;
-    Cheb<LevelSim> ch{sim, d1, std::vector<LevelSim::H>(std::max(degree + 2, 2 * d1 + 2))};
-    ch.T[1] = sim.make(in_level);
-    std::vector<double> coef(degree + 1, 1.0);
-    auto y = ch.eval(coef, degree + 1);
-    if (!y || sim.fail) return -1;
-    return y->level;
-}
-
-extern "C" int fr_cheb_mult_count(int32_t degree, int32_t d1) {
-    if (degree < 1 || d1 < 2) return -1;
-    LevelSim sim;
-    Cheb<LevelSim> ch{sim, d1, std::vector<LevelSim::H>(std::max(degree + 2, 2 * d1 + 2))};
-    ch.T[1] = sim.make(1 << 20);
-    std::vector<double> coef(degree + 1, 1.0);
-    ch.eval(coef, degree + 1);
-    return sim.nmul;
-}
-
 extern "C" int fr_cheb_step_coeffs(int32_t degree, double delta, double *c) {
     if (degree < 1 || !c) return fr_fail(FR_EINVAL, "fr_cheb_step_coeffs: bad arguments");
     const int n = degree + 1;

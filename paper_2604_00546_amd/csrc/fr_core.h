@@ -226,9 +226,13 @@ int num_digits(const fr_ctx *c, int level);   // ceil((level+1)/alpha)
 // kernel launchers (kernels_*.hip)
 // ---------------------------------------------------------------------------
 namespace frk {
-// NTT over `nlimbs` limbs x `npoly` polynomials; poly_stride in words
-void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride);
-void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride);
+// NTT over `nlimbs` limbs x `npoly` polynomials; poly_stride in words.  With
+// src set the transform is out of place: it reads src (same limb map,
+// src_poly_stride between polynomials) and writes data.
+void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
+             const u64 *src = nullptr, size_t src_poly_stride = 0);
+void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
+             const u64 *src = nullptr, size_t src_poly_stride = 0);
 
 void add(const fr_ctx *c, u64 *out, const u64 *a, const u64 *b, int nlimbs, int npoly,
          size_t so, size_t sa, size_t sb, bool subtract);
@@ -251,13 +255,14 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
                 size_t poly_stride, bool to_mont);
 // fast base conversion of one digit: coefficient-form x[level+1][N] ->
 // D[nE][N] coefficient form on every extended limb outside the digit
-void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t);
+void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,
+                 size_t sx = 0);
 // U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p]
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
-              bool accumulate);
+              bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0);
 // ModDown of U (eval domain, P limbs already coefficient form in Upc):
 // v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
-void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level);
+void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly);
 // out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)
 void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int level, int npoly,
                     size_t so, size_t su, size_t sv, bool accumulate);

@@ -20,6 +20,8 @@ constexpr int kThreads = 256;
 struct NttLaunch {
     u64 *data;
     size_t poly_stride;
+    const u64 *src;          // first pass reads here when set (out-of-place)
+    size_t src_poly_stride;
     int N, logN, s1;
     LimbMap map;
     const u64 *tw, *tw_sh;
@@ -38,9 +40,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols(NttLaunch a) {
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
     const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
     const int c0 = blockIdx.x * COLS;
+    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * a.N : x;
     for (int idx = threadIdx.x; idx < total; idx += kThreads) {
         int r = idx >> lcols, c = idx & (COLS - 1);
-        tile[idx] = x[c0 + c + ((size_t)r << lc)];
+        tile[idx] = xs[c0 + c + ((size_t)r << lc)];
     }
     __syncthreads();
     for (int st = 0; st < lr; ++st) {
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows(NttLaunch a) {
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N + (size_t)blockIdx.x * total;
     const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
     const int b0 = blockIdx.x * BLKS;
-    for (int idx = threadIdx.x; idx < total; idx += kThreads) tile[idx] = x[idx];
+    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * a.N + (size_t)blockIdx.x * total : x;
+    for (int idx = threadIdx.x; idx < total; idx += kThreads) tile[idx] = xs[idx];
     __syncthreads();
     for (int lt = 0; lt < lc; ++lt) {  // t = 1, 2, .., C/2
         const int t = 1 << lt;
@@ -210,9 +214,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
     const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
     const int col = blockIdx.x * COLS + c;
+    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * a.N : x;
     u64 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = x[col + (size_t)(g + E * k) * R];
+    for (int k = 0; k < E; ++k) v[k] = xs[col + (size_t)(g + E * k) * R];
 #pragma unroll
     for (int st = 0; st < LE; ++st) {
         const int half = E >> (st + 1);
@@ -303,10 +308,11 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
     const int gb = blockIdx.x * BLKS + blk;
     u64 *xb = x + (size_t)gb * R;
+    const u64 *xsb = (a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * N : x) + (size_t)gb * R;
     u64 *tb = tile + blk * R;
     u64 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) tb[u0 + E * k] = xb[u0 + E * k];
+    for (int k = 0; k < E; ++k) tb[u0 + E * k] = xsb[u0 + E * k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = tb[E * u0 + k];
@@ -387,10 +393,13 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
     }
 }
 
-NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t poly_stride, bool inverse) {
+NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t poly_stride, bool inverse,
+                      const u64 *src, size_t src_poly_stride) {
     NttLaunch a;
     a.data = data;
     a.poly_stride = poly_stride;
+    a.src = src;
+    a.src_poly_stride = src_poly_stride;
     a.N = c->N;
     a.logN = c->logN;
     a.s1 = c->logN / 2;
@@ -405,10 +414,11 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
 
 namespace frk {
 
-void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride) {
+void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
+             const u64 *src, size_t src_poly_stride) {
     if (nlimbs <= 0 || npoly <= 0) return;
     ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
-    NttLaunch a = make_launch(c, data, map, poly_stride, false);
+    NttLaunch a = make_launch(c, data, map, poly_stride, false, src, src_poly_stride);
     if (c->logN == 16 || c->logN == 12) {
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
         dim3 g(R / (kThreads / E), nlimbs, npoly);
@@ -428,10 +438,11 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     hipLaunchKernelGGL(k_fwd_rows, g2, dim3(kThreads), 0, c->stream, a);
 }
 
-void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride) {
+void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
+             const u64 *src, size_t src_poly_stride) {
     if (nlimbs <= 0 || npoly <= 0) return;
     ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
-    NttLaunch a = make_launch(c, data, map, poly_stride, true);
+    NttLaunch a = make_launch(c, data, map, poly_stride, true, src, src_poly_stride);
     if (c->logN == 16 || c->logN == 12) {
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
         dim3 g(R / (kThreads / E), nlimbs, npoly);

@@ -82,8 +82,10 @@ __global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, 
 // y_d = [x_{lo+d} * Dhat_d^-1]_{q_{lo+d}} (canonical), then for every
 // extended position e outside the digit: D[e] = sum_d y_d * [Dhat_d]_{r_e} mod r_e.
 __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd, int nE, int level,
-                                              int pbase, const u64 *tab, const ModConst *mods) {
+                                              int pbase, const u64 *tab, const ModConst *mods, size_t sd, size_t sx) {
     const int k = blockIdx.x * kT + threadIdx.x;
+    D += blockIdx.z * sd;
+    x += blockIdx.z * sx;
     const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
     u64 y[kMaxDigit];
 #pragma unroll
@@ -106,8 +108,11 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
 // Montgomery-scaled so one reduction yields the canonical sum.
 __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
-                                                 const ModConst *mods, int accumulate) {
+                                                 const ModConst *mods, int accumulate, size_t sd, size_t su) {
     const int p = blockIdx.x * kT + threadIdx.x, e = blockIdx.y;
+    D += blockIdx.z * sd;
+    U0 += blockIdx.z * su;
+    U1 += blockIdx.z * su;
     const int gm = e <= level ? e : pbase + (e - level - 1);
     const ModConst m = mods[gm];
     const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
@@ -342,28 +347,31 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
                        c->d_mod, (int)to_mont);
 }
 
-void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t) {
-    ProfScope ps(c, K_MODUP, (double)(level + 1 + c->nP) * 8.0 * c->N);
+void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch, size_t sd, size_t sx) {
+    ProfScope ps(c, K_MODUP, (double)batch * (level + 1 + c->nP) * 8.0 * c->N);
     const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
     const int nE = level + 1 + c->nP;
     const int ntarget = nE - nd;
-    dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, 1);
+    dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, batch);
     hipLaunchKernelGGL(k_modup, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
-                       c->d_modup + c->modup_off[level][t], c->d_mod);
+                       c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx);
 }
 
-void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate) {
+void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate,
+              int batch, size_t sd, size_t su) {
     const int nE_ = level + 1 + c->nP, nd_ = (level + 1 + c->alpha - 1) / c->alpha;
-    ProfScope ps(c, K_KS, (3.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) * 8.0 * c->N);
+    // digits and outputs per batch item, the shared key once
+    ProfScope ps(c, K_KS,
+                 (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) + 2.0 * nd_ * nE_) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
-    hipLaunchKernelGGL(k_ks_inner, grid(c, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN, nE,
-                       level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate);
+    hipLaunchKernelGGL(k_ks_inner, grid(c, nE, batch), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN, nE,
+                       level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su);
 }
 
-void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level) {
-    ProfScope ps(c, K_MODDOWN, (2.0 * c->nP + 2.0 * (level + 1)) * 8.0 * c->N);
-    dim3 g(c->N / kT, (level + 1 + kTargetsPerThread - 1) / kTargetsPerThread, 2);
+void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
+    ProfScope ps(c, K_MODDOWN, npoly * (1.0 * c->nP + 1.0 * (level + 1)) * 8.0 * c->N);
+    dim3 g(c->N / kT, (level + 1 + kTargetsPerThread - 1) / kTargetsPerThread, npoly);
     hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
                        c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
 }
