@@ -33,10 +33,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "encrypted template scores/sec + p50/p99 query latency @2^15×512-d, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+# INT32 VALU peak from the unit counts: 256 CUs x 128 lanes (the FP32 vector
+# rate's lane count, 157.3 TFLOP/s / 2 per FMA) x 2.4 GHz
+INT32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# algorithmic 32-bit integer operations per radix-2 butterfly on 64-bit
+# residues: 10 multiplies for the 64x64-bit Shoup product and 20 adds,
+# subtracts, compares and selects for the lazy reductions and both outputs
+OPS_PER_BUTTERFLY = 30
 
-# algorithmic work per unit for the roofline object: bytes per launch are
-# accumulated by the library's timing hook (see include/fr.h)
-ROOFLINE_KERNEL = {"class": "ks_inner", "bound": "hbm"}
+# dominant kernel class (largest share of the step's kernel time in the trace)
+ROOFLINE_KERNEL = {"class": "ntt", "bound": "alu"}
+# HBM bytes per NTT launch (one forward or inverse transform of a batch of
+# limbs), from the FETCH_SIZE / WRITE_SIZE counter runs recorded in
+# profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
+# since those counters were taken
+NTT_TRAFFIC_BYTES_PER_LAUNCH = None
 
 
 def log(*a):
@@ -184,12 +195,25 @@ def main():
     }
     if n_launch:
         avg_ms = k_ms / n_launch
-        achieved = k_bytes / n_launch / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = {"bound": ROOFLINE_KERNEL["bound"], "kernel": ROOFLINE_KERNEL["class"],
-                           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "launches": n_launch, "avg_launch_ms": avg_ms,
-                           "bytes_per_launch": k_bytes / n_launch}
+        if ROOFLINE_KERNEL["bound"] == "alu":
+            # the hook counts 16 B per coefficient per transform; a transform
+            # of one limb is (N/2) log2 N butterflies
+            logn = int(np.log2(ctx.N))
+            bfly = k_bytes / n_launch / 16.0 / 2.0 * logn
+            achieved = bfly * OPS_PER_BUTTERFLY / (avg_ms * 1e-3) / 1e12
+            out["roofline"] = {"bound": "alu", "kernel": "ntt", "achieved": achieved, "peak": INT32_PEAK_TOPS,
+                               "unit": "TOPS (int32)", "frac": achieved / INT32_PEAK_TOPS,
+                               "traffic": NTT_TRAFFIC_BYTES_PER_LAUNCH, "launches": n_launch,
+                               "avg_launch_ms": avg_ms, "butterflies_per_launch": bfly,
+                               "ops_per_butterfly": OPS_PER_BUTTERFLY,
+                               "hbm_view_GBps": k_bytes / n_launch / (avg_ms * 1e-3) / 1e9}
+        else:
+            achieved = k_bytes / n_launch / (avg_ms * 1e-3) / 1e9
+            out["roofline"] = {"bound": ROOFLINE_KERNEL["bound"], "kernel": ROOFLINE_KERNEL["class"],
+                               "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                               "launches": n_launch, "avg_launch_ms": avg_ms,
+                               "bytes_per_launch": k_bytes / n_launch}
     if args.breakdown:
         ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev3[0].record(stream)
