@@ -349,6 +349,17 @@ static int ctx_build(fr_ctx *c) {
     if (int e = upload(&c->d_tw_sh, tws)) return e;
     if (int e = upload(&c->d_itw, itw)) return e;
     if (int e = upload(&c->d_itw_sh, itws)) return e;
+    {
+        std::vector<u64> t2((size_t)2 * nm * N), it2((size_t)2 * nm * N);
+        for (size_t o = 0; o < (size_t)nm * N; ++o) {
+            t2[2 * o] = tw[o];
+            t2[2 * o + 1] = tws[o];
+            it2[2 * o] = itw[o];
+            it2[2 * o + 1] = itws[o];
+        }
+        if (int e = upload(&c->d_tw2, t2)) return e;
+        if (int e = upload(&c->d_itw2, it2)) return e;
+    }
 
     // ModUp tables
     std::vector<u64> mu;
@@ -500,6 +511,7 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
     (void)hipDeviceSynchronize();
     drop_pool(c);
     for (void *p : {(void *)c->d_mod, (void *)c->d_tw, (void *)c->d_tw_sh, (void *)c->d_itw, (void *)c->d_itw_sh,
+                    (void *)c->d_tw2, (void *)c->d_itw2,
                     (void *)c->d_modup, (void *)c->d_moddown, (void *)c->d_rescale, (void *)c->d_crt,
                     (void *)c->d_fft_w, (void *)c->d_zeta, (void *)c->d_slot_pos, (void *)c->d_flag})
         if (p) (void)hipFree(p);
@@ -827,9 +839,7 @@ static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, con
         for (int i = 0; i < nl; ++i) {
             const int r = live[i];
             u64 *o = outs[r].data;
-            frk::moddown_finish(c, o, U + (size_t)i * 2 * nE * N, V + (size_t)i * 2 * lw, l, 2, lw, (size_t)nE * N,
-                                lw, false);
-            frk::automorph(c, o, in->data, gs[r], l + 1, 1, 0, 0, true);
+            frk::moddown_rot(c, o, U + (size_t)i * 2 * nE * N, V + (size_t)i * 2 * lw, in->data, gs[r], l);
         }
     }
     for (int r = 0; r < nrot; ++r) {

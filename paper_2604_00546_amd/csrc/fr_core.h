@@ -142,6 +142,7 @@ struct fr_ctx {
     ModConst *d_mod = nullptr;
     // twiddles [nmod][N]: psi^brv(k), Shoup companions, inverses
     u64 *d_tw = nullptr, *d_tw_sh = nullptr, *d_itw = nullptr, *d_itw_sh = nullptr;
+    u64 *d_tw2 = nullptr, *d_itw2 = nullptr;  // interleaved (twiddle, companion) pairs [nmod][N][2]
     // ModUp tables, per (level, digit): dinv[nd], dinv_sh[nd], dhat[nE][nd]
     u64 *d_modup = nullptr;
     size_t modup_off[FR_MAXLEVEL][8];
@@ -274,6 +275,20 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 // fused plaintext-diagonal multiply-accumulate of all giant steps
 void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell,
               int db_level, int level, int baby_level);
+// batched element-wise helpers (items addressed by pointer; kTerms = 8)
+// out[b] = sum_t k[b][t] * src[b][t] (first nl limbs of both polynomials),
+// out items contiguous [B][2][nl][N]; src/k/src_lp1 are [B][8] row-major
+void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const u64 *const *src, const long long *k,
+                  const int *src_lp1, const int *nterms);
+// c0 limbs of item b (items `item` words apart) += v[b]
+void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item);
+// out[b] = a[b] +/- b[b] (+ cst[b] on c0)
+void pair_batch(const fr_ctx *c, int nl, int B, const u64 *const *a, const u64 *const *b, u64 *const *out,
+                const long long *cst, const int *op);
+// tensor of B pairs: d0, d1 -> t01 + b * 2 lw, d2 -> t2 + b * lw
+void tensor_batch(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int B, const u64 *const *a, const u64 *const *b);
+// rotation output: out = ModDown-finish(U, V) + (sigma_g(in.c0), 0)
+void moddown_rot(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int level);
 // key generation / encryption / decryption combiners (eval domain)
 void key_combine(const fr_ctx *c, u64 *b, const u64 *a, const u64 *e, const u64 *s_mont, const u64 *sp, int dlo,
                  int dhi, int nlimbs);

@@ -25,6 +25,7 @@ struct NttLaunch {
     int N, logN, s1;
     LimbMap map;
     const u64 *tw, *tw_sh;
+    const ulonglong2 *tw2;   // (twiddle, Shoup companion) pairs, same indexing
     const ModConst *mods;
 };
 
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q2 = 2 * q;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
-    const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
     const int col = blockIdx.x * COLS + c;
     const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * a.N : x;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + (k >> (LE - st));
-                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + ((E * g + k) >> (LR - st));
-                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q2 = 2 * q;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
-    const u64 *tw = a.tw + (size_t)mi * a.N, *twsh = a.tw_sh + (size_t)mi * a.N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
     const int gb = blockIdx.x * BLKS + blk;
     u64 *xb = x + (size_t)gb * R;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + (k >> (LE - sl));
-                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + ((E * u0 + k) >> (LR - sl));
-                ct_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
     const u64 q = a.mods[mi].q, q2 = 2 * q;
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
-    const u64 *tw = a.tw + (size_t)mi * N, *twsh = a.tw_sh + (size_t)mi * N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
     const int gb = blockIdx.x * BLKS + blk;
     u64 *xb = x + (size_t)gb * R;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + ((E * u0 + k) >> (lt + 1));
-                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (k >> (lt + 1 - LE));
-                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
     const u64 q = mc.q, q2 = 2 * q;
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
-    const u64 *tw = a.tw + (size_t)mi * N, *twsh = a.tw_sh + (size_t)mi * N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
     const int col = blockIdx.x * COLS + c;
     u64 v[E];
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + ((E * g + k) >> (ltp + 1));
-                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + (k >> (ltp + 1 - LE));
-                gs_bfly(v[k], v[k + half], tw[ti], twsh[ti], q, q2);
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
             }
     }
 #pragma unroll
@@ -406,6 +407,7 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     a.map = map;
     a.tw = inverse ? c->d_itw : c->d_tw;
     a.tw_sh = inverse ? c->d_itw_sh : c->d_tw_sh;
+    a.tw2 = reinterpret_cast<const ulonglong2 *>(inverse ? c->d_itw2 : c->d_tw2);
     a.mods = c->d_mod;
     return a;
 }

@@ -205,53 +205,9 @@ __global__ __launch_bounds__(kT) void k_rescale_finish(u64 *out, const u64 *in, 
     out[p * so + w] = shoup(subq(in[p * si + w], Y[p * sy + w], q), qinv[i], qinv_sh[i], q);
 }
 
-// Fused multiply-accumulate of the BSGS inner sums (Eq. bsgs2):
-//   P_j[c][m][k] = sum_i baby_i[c][m][k] * diag_{j n1 + i}[m][k]
-// for a chunk of <= 32 baby steps and NJ giant steps per launch; each thread
-// keeps 2 NJ lazy 128-bit accumulators in registers, reads every diagonal
-// word once and every baby word once per launch.
 struct BabyPtrs {
     const u64 *p[32];
 };
-
-template <int NJ>
-__global__ __launch_bounds__(kT) void k_bsgs_mac(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
-                                                 int ell, const u64 *diag, int dbl, int bl, int lv, int N,
-                                                 const ModConst *mods, int accumulate) {
-    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y;
-    u64 a0l[NJ], a0h[NJ], a1l[NJ], a1h[NJ];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) a0l[jj] = a0h[jj] = a1l[jj] = a1h[jj] = 0;
-    for (int ii = 0; ii < nb; ++ii) {
-        const int i = i0 + ii;
-        const u64 b0 = bp.p[ii][(size_t)m * N + k];
-        const u64 b1 = bp.p[ii][(size_t)(bl + 1 + m) * N + k];
-#pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int d = (j0 + jj) * n1 + i;
-            if (jj < nj && d < ell) {
-                const u64 w = diag[((size_t)d * (dbl + 1) + m) * N + k];
-                mac128(a0l[jj], a0h[jj], b0, w);
-                mac128(a1l[jj], a1h[jj], b1, w);
-            }
-        }
-    }
-    const ModConst mc = mods[m];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        if (jj < nj) {
-            const size_t o0 = ((size_t)(j0 + jj) * 2 * (lv + 1) + m) * N + k;
-            const size_t o1 = o0 + (size_t)(lv + 1) * N;
-            u64 r0 = redc_any(a0l[jj], a0h[jj], mc), r1 = redc_any(a1l[jj], a1h[jj], mc);
-            if (accumulate) {
-                r0 = addq(r0, P[o0], mc.q);
-                r1 = addq(r1, P[o1], mc.q);
-            }
-            P[o0] = r0;
-            P[o1] = r1;
-        }
-    }
-}
 
 // b = e - a s + [limb in digit] (P mod q) s'   (key generation, eval domain;
 // limbs are global modulus indices; s_mont Montgomery-scaled)
@@ -287,6 +243,146 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
     const size_t w = (size_t)i * N + k;
     const u64 x = c1[w], s = s_mont[w];
     out[w] = addq(c0[w], redc(x * s, mulhi64(x, s), m), m.q);
+}
+
+
+// Fused multiply-accumulate of the BSGS inner sums (Eq. bsgs2):
+//   P_j[c][m][k] = sum_i baby_i[c][m][k] * diag_{j n1 + i}[m][k]
+// One coefficient per thread; every product is reduced on the spot with one
+// Montgomery reduction (the diagonals are Montgomery-scaled) and summed
+// canonically, so a thread keeps 2 NJ 64-bit sums.  Every diagonal word is
+// read once per launch.
+template <int NJ>
+__global__ __launch_bounds__(kT) void k_bsgs_mac2(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
+                                                  int ell, const u64 *diag, int dbl, int bl, int lv, int N,
+                                                  const ModConst *mods, int accumulate) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y;
+    const ModConst mc = mods[m];
+    u64 s0[NJ], s1[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) s0[jj] = s1[jj] = 0;
+    for (int ii = 0; ii < nb; ++ii) {
+        const int i = i0 + ii;
+        const u64 b0 = bp.p[ii][(size_t)m * N + k];
+        const u64 b1 = bp.p[ii][(size_t)(bl + 1 + m) * N + k];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int d = (j0 + jj) * n1 + i;
+            if (jj < nj && d < ell) {
+                const u64 w = diag[((size_t)d * (dbl + 1) + m) * N + k];
+                s0[jj] = addq(s0[jj], redc(b0 * w, mulhi64(b0, w), mc), mc.q);
+                s1[jj] = addq(s1[jj], redc(b1 * w, mulhi64(b1, w), mc), mc.q);
+            }
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        if (jj < nj) {
+            const size_t o0 = ((size_t)(j0 + jj) * 2 * (lv + 1) + m) * N + k;
+            const size_t o1 = o0 + (size_t)(lv + 1) * N;
+            u64 r0 = s0[jj], r1 = s1[jj];
+            if (accumulate) {
+                r0 = addq(r0, P[o0], mc.q);
+                r1 = addq(r1, P[o1], mc.q);
+            }
+            P[o0] = r0;
+            P[o1] = r1;
+        }
+    }
+}
+
+// out[i][p] = (U[i][p] - V[i][p]) P^-1 + in[i][auto_src(p, g)]: the ModDown
+// finish of a rotation fused with the automorphism of c0 (c1 part: no add)
+__global__ __launch_bounds__(kT) void k_moddown_rot(u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int N,
+                                                    int logN, int lp1, const u64 *pinv, const u64 *pinv_sh,
+                                                    const ModConst *mods, size_t su) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+    const u64 q = mods[i].q;
+    const size_t w = (size_t)i * N + k;
+    const size_t lw = (size_t)lp1 * N;
+    u64 r = shoup(subq(U[p * su + w], V[p * lw + w], q), pinv[i], pinv_sh[i], q);
+    if (p == 0) r = addq(r, in[(size_t)i * N + auto_src((u32)k, g, logN)], q);
+    out[p * lw + w] = r;
+}
+
+
+// ---------------------------------------------------------------------------
+// batched element-wise kernels of the Chebyshev waves: per-item pointers and
+// constants travel in the kernel arguments (up to kBatch items per launch)
+// ---------------------------------------------------------------------------
+constexpr int kBatch = 16, kTerms = 8;
+
+__device__ __forceinline__ u64 smod_dev(long long v, const ModConst &m) {
+    if (v >= 0) return reduce64((u64)v, m);
+    const u64 a = reduce64((u64)(-(v + 1)), m);  // -(v+1) >= 0 avoids overflow
+    const u64 b = a + 1 == m.q ? 0 : a + 1;
+    return b ? m.q - b : 0;
+}
+
+struct ScalarBatch {
+    const u64 *src[kBatch][kTerms];
+    long long k[kBatch][kTerms];
+    int src_lp1[kBatch][kTerms];  // (level + 1) of each source: its polynomial stride in limbs
+    int nterms[kBatch];
+};
+
+// out_b = sum_t k_{b,t} * src_{b,t} over the first nl limbs of both
+// polynomials; out items are contiguous [B][2][nl][N]
+__global__ __launch_bounds__(kT) void k_scalar_batch(u64 *out, ScalarBatch sb, int nl, int N, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y % nl, p = blockIdx.y / nl, b = blockIdx.z;
+    const ModConst m = mods[i];
+    u64 acc = 0;
+    for (int t = 0; t < sb.nterms[b]; ++t) {
+        const u64 x = sb.src[b][t][((size_t)p * sb.src_lp1[b][t] + i) * N + k];
+        acc = addq(acc, mulmod(x, smod_dev(sb.k[b][t], m), m), m.q);
+    }
+    out[(((size_t)b * 2 + p) * nl + i) * N + k] = acc;
+}
+
+// c0 of item b (items [B][2][nl][N]) gets the constant v_b on every word
+struct ConstBatch {
+    long long v[kBatch];
+};
+__global__ __launch_bounds__(kT) void k_add_const_batch(u64 *data, ConstBatch cb, int nl, int N, size_t item,
+                                                        const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
+    const ModConst m = mods[i];
+    u64 &x = data[b * item + (size_t)i * N + k];
+    x = addq(x, smod_dev(cb.v[b], m), m.q);
+}
+
+struct PairBatch {
+    const u64 *a[kBatch];
+    const u64 *b[kBatch];
+    u64 *out[kBatch];
+    long long cst[kBatch];  // added to c0 after the operation (0: none)
+    int op[kBatch];         // 0 add, 1 sub
+};
+// out_b = a_b (+/-) b_b  (+ cst_b on c0), ciphertexts of nl limbs per polynomial
+__global__ __launch_bounds__(kT) void k_pair_batch(PairBatch pb, int nl, int N, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y % nl, p = blockIdx.y / nl, b = blockIdx.z;
+    const ModConst m = mods[i];
+    const size_t w = ((size_t)p * nl + i) * N + k;
+    const u64 x = pb.a[b][w], y = pb.b[b][w];
+    u64 r = pb.op[b] ? subq(x, y, m.q) : addq(x, y, m.q);
+    if (p == 0 && pb.cst[b]) r = addq(r, smod_dev(pb.cst[b], m), m.q);
+    pb.out[b][w] = r;
+}
+
+struct TensorBatch {
+    const u64 *a[kBatch];
+    const u64 *b[kBatch];
+};
+// item b: d0, d1 into t01 + b * 2 lw, d2 into t2 + b * lw
+__global__ __launch_bounds__(kT) void k_tensor_batch(u64 *t01, u64 *t2, TensorBatch tb, int nl, int N,
+                                                     const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
+    const ModConst m = mods[i];
+    const size_t lw = (size_t)nl * N, w = (size_t)i * N + k;
+    const u64 x0 = tb.a[b][w], x1 = tb.a[b][lw + w], y0 = tb.b[b][w], y1 = tb.b[b][lw + w];
+    t01[b * 2 * lw + w] = mulmod(x0, y0, m);
+    t01[b * 2 * lw + lw + w] = addq(mulmod(x0, y1, m), mulmod(x1, y0, m), m.q);
+    t2[b * lw + w] = mulmod(x1, y1, m);
 }
 
 inline dim3 grid(const fr_ctx *c, int ny, int nz) { return dim3(c->N / kT, ny, nz); }
@@ -415,9 +511,84 @@ void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64
                 for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
             ProfScope ps(c, K_MAC,
                          8.0 * c->N * (level + 1) * (used + 2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj));
-            hipLaunchKernelGGL(k_bsgs_mac<NJ>, grid(c, level + 1, 1), dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0,
-                               nj, ell, diag, db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+            dim3 g(c->N / kT, level + 1, 1);
+            hipLaunchKernelGGL(k_bsgs_mac2<NJ>, g, dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0, nj, ell, diag,
+                               db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
         }
+    }
+}
+
+void moddown_rot(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int level) {
+    ProfScope ps(c, K_ELEM, 7.0 * (level + 1) * 8.0 * c->N);
+    const u64 *pinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;
+    const u64 *pinv_sh = pinv + (c->L + 1);
+    const int nE = level + 1 + c->nP;
+    hipLaunchKernelGGL(k_moddown_rot, grid(c, level + 1, 2), dim3(kT), 0, c->stream, out, U, V, in, g, c->N, c->logN,
+                       level + 1, pinv, pinv_sh, c->d_mod, (size_t)nE * c->N);
+}
+
+
+void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const u64 *const *src, const long long *k,
+                  const int *src_lp1, const int *nterms) {
+    for (int b0 = 0; b0 < B; b0 += kBatch) {
+        const int nb = std::min(kBatch, B - b0);
+        ScalarBatch sb{};
+        int terms = 0;
+        for (int b = 0; b < nb; ++b) {
+            sb.nterms[b] = nterms[b0 + b];
+            for (int t = 0; t < sb.nterms[b]; ++t) {
+                sb.src[b][t] = src[(b0 + b) * kTerms + t];
+                sb.k[b][t] = k[(b0 + b) * kTerms + t];
+                sb.src_lp1[b][t] = src_lp1[(b0 + b) * kTerms + t];
+            }
+            terms += sb.nterms[b];
+        }
+        ProfScope ps(c, K_ELEM, (terms + nb) * 2.0 * nl * 8.0 * c->N);
+        hipLaunchKernelGGL(k_scalar_batch, grid(c, 2 * nl, nb), dim3(kT), 0, c->stream,
+                           out + (size_t)b0 * 2 * nl * c->N, sb, nl, c->N, c->d_mod);
+    }
+}
+
+void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item) {
+    for (int b0 = 0; b0 < B; b0 += kBatch) {
+        const int nb = std::min(kBatch, B - b0);
+        ConstBatch cb{};
+        for (int b = 0; b < nb; ++b) cb.v[b] = v[b0 + b];
+        ProfScope ps(c, K_ELEM, nb * 2.0 * nl * 8.0 * c->N);
+        hipLaunchKernelGGL(k_add_const_batch, grid(c, nl, nb), dim3(kT), 0, c->stream, data + b0 * item, cb, nl,
+                           c->N, item, c->d_mod);
+    }
+}
+
+void pair_batch(const fr_ctx *c, int nl, int B, const u64 *const *a, const u64 *const *b, u64 *const *out,
+                const long long *cst, const int *op) {
+    for (int b0 = 0; b0 < B; b0 += kBatch) {
+        const int nb = std::min(kBatch, B - b0);
+        PairBatch pb{};
+        for (int t = 0; t < nb; ++t) {
+            pb.a[t] = a[b0 + t];
+            pb.b[t] = b[b0 + t];
+            pb.out[t] = out[b0 + t];
+            pb.cst[t] = cst[b0 + t];
+            pb.op[t] = op[b0 + t];
+        }
+        ProfScope ps(c, K_ELEM, nb * 6.0 * nl * 8.0 * c->N);
+        hipLaunchKernelGGL(k_pair_batch, grid(c, 2 * nl, nb), dim3(kT), 0, c->stream, pb, nl, c->N, c->d_mod);
+    }
+}
+
+void tensor_batch(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int B, const u64 *const *a, const u64 *const *b) {
+    for (int b0 = 0; b0 < B; b0 += kBatch) {
+        const int nb = std::min(kBatch, B - b0);
+        TensorBatch tb{};
+        for (int t = 0; t < nb; ++t) {
+            tb.a[t] = a[b0 + t];
+            tb.b[t] = b[b0 + t];
+        }
+        ProfScope ps(c, K_TENSOR, nb * 7.0 * nl * 8.0 * c->N);
+        const size_t lw = (size_t)nl * c->N;
+        hipLaunchKernelGGL(k_tensor_batch, grid(c, nl, nb), dim3(kT), 0, c->stream, t01 + (size_t)b0 * 2 * lw,
+                           t2 + (size_t)b0 * lw, tb, nl, c->N, c->d_mod);
     }
 }
 
