@@ -84,6 +84,12 @@ def step(s, d1):
     ctx.chebyshev_eval(s["keys"], s["score"], s["coeffs"], d1, out=s["cheb"])
 
 
+def fewest_products_d1(fr, degree):
+    """Baby-step degree with the fewest relinearised products (ties: smaller)."""
+    counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
+    return min(counts, key=lambda d1: (counts[d1], d1))
+
+
 def check(s):
     ctx, wl = s["ctx"], s["wl"]
     exact = wl.exact_scores()
@@ -126,7 +132,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--d1", type=int, default=2, help="Chebyshev baby-step degree")
+    ap.add_argument("--d1", type=int, default=None,
+                    help="Chebyshev baby-step degree (default: the one with the fewest relinearised products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -139,6 +146,8 @@ def main():
         sys.exit(2)
     import torch
     s = setup(args)
+    if args.d1 is None:
+        args.d1 = fewest_products_d1(s["fr"], len(s["coeffs"]) - 1)
     ctx = s["ctx"]
     for _ in range(args.warmup):
         step(s, args.d1)

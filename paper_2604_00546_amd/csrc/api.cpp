@@ -1348,30 +1348,35 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
             u64 *stage = scratch(c, (size_t)B * sw);
             u64 *out = scratch(c, (size_t)B * ow);
-            u64 *tmp = scratch(c, sw);
+            std::vector<ScalarItem> items(B);
+            std::vector<long long> cst(B, 0);
+            bool any_const = false;
             for (int b = 0; b < B; ++b) {
                 const CNode &nd = nodes[L[b]];
-                u64 *st = stage + (size_t)b * sw;
+                ScalarItem &it = items[b];
                 if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
                     const int la = nodes[nd.a].level;
                     const long long k = nd.op == C_ADJUST
                                             ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
                                             : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
-                    mul_int_dev(c, buf[nd.a], lw(la), lam + 2, k, st, lw(lam + 1));
+                    it.src.push_back(buf[nd.a]);
+                    it.k.push_back(k);
+                    it.lp1.push_back(la + 1);
                 } else {
                     for (size_t t = 0; t < nd.ins.size(); ++t) {
                         const int src = nd.ins[t], ls = nodes[src].level;
-                        const long long k = rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls]);
-                        mul_int_dev(c, buf[src], lw(ls), lam + 2, k, t == 0 ? st : tmp, lw(lam + 1));
-                        if (t > 0) frk::add(c, st, st, tmp, lam + 2, 2, lw(lam + 1), lw(lam + 1), lw(lam + 1), false);
+                        it.src.push_back(buf[src]);
+                        it.k.push_back(rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls]));
+                        it.lp1.push_back(ls + 1);
                     }
+                    cst[b] = rne_ll(nd.cf[0] * D[lam]);
+                    any_const = true;
                 }
             }
+            frk::scalar_batch(c, stage, lam + 2, B, items.data());
             rescale_dev(c, stage, lam + 1, out, B);
-            for (int b = 0; b < B; ++b) {
-                buf[L[b]] = out + (size_t)b * ow;
-                if (nodes[L[b]].op == C_LEAF) add_const_dev(c, buf[L[b]], lam, nodes[L[b]].cf[0], D[lam]);
-            }
+            if (any_const) frk::add_const_batch(c, out, lam + 1, B, cst.data(), ow);
+            for (int b = 0; b < B; ++b) buf[L[b]] = out + (size_t)b * ow;
         }
         // --- relinearised products, grouped by input level
         for (int lv = 1; lv < FR_MAXLEVEL; ++lv) {
@@ -1385,33 +1390,46 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             u64 *U = scratch(c, (size_t)B * 2 * nE * N);
             u64 *V = scratch(c, (size_t)B * cw);
             u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
+            std::vector<const u64 *> xa(B), yb(B);
             for (int b = 0; b < B; ++b) {
-                const CNode &nd = nodes[L[b]];
-                const u64 *x = buf[nd.a], *y = buf[nd.b];
-                u64 *t01 = T01 + (size_t)b * cw;
-                frk::tensor(c, t01, t01 + lw(lv), T2 + (size_t)b * lw(lv), x, x + lw(lv), y, y + lw(lv), lv + 1);
+                xa[b] = buf[nodes[L[b]].a];
+                yb[b] = buf[nodes[L[b]].b];
             }
+            frk::tensor_batch(c, T01, T2, lv + 1, B, xa.data(), yb.data());
             ks_modup(c, T2, lv, Dg, B, lw(lv));
             frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
                           (size_t)2 * nE * N);
             ks_moddown_prep(c, U, B, lv, V);
-            for (int b = 0; b < B; ++b)
-                frk::moddown_finish(c, T01 + (size_t)b * cw, U + (size_t)b * 2 * nE * N, V + (size_t)b * cw, lv, 2,
-                                    lw(lv), (size_t)nE * N, lw(lv), true);
+            frk::moddown_finish(c, T01, U, V, lv, 2 * B, lw(lv), (size_t)nE * N, lw(lv), true);
             rescale_dev(c, T01, lv, out, B);
             for (int b = 0; b < B; ++b) buf[L[b]] = out + (size_t)b * 2 * lw(lv - 1);
         }
-        // --- additions
-        for (int i = 0; i < n; ++i) {
-            if (depth[i] != d) continue;
-            const CNode &nd = nodes[i];
-            if (nd.op != C_ADD && nd.op != C_SUB && nd.op != C_TWICE_M1) continue;
-            const size_t w = lw(nd.level);
-            u64 *o = scratch(c, 2 * w);
-            const u64 *y = nd.op == C_TWICE_M1 ? buf[nd.a] : buf[nd.b];
-            frk::add(c, o, buf[nd.a], y, nd.level + 1, 2, w, w, w, nd.op == C_SUB);
-            if (nd.op == C_TWICE_M1) add_const_dev(c, o, nd.level, -1.0, D[nd.level]);
-            buf[i] = o;
+        // --- additions, grouped by level
+        for (int lv = 0; lv < FR_MAXLEVEL; ++lv) {
+            std::vector<int> L;
+            for (int i = 0; i < n; ++i) {
+                const COp op = nodes[i].op;
+                if (depth[i] == d && nodes[i].level == lv && (op == C_ADD || op == C_SUB || op == C_TWICE_M1))
+                    L.push_back(i);
+            }
+            if (L.empty()) continue;
+            const int B = (int)L.size();
+            const size_t w = lw(lv);
+            u64 *o = scratch(c, (size_t)B * 2 * w);
+            std::vector<const u64 *> xa(B), yb(B);
+            std::vector<u64 *> outs(B);
+            std::vector<long long> cst(B, 0);
+            std::vector<int> op(B, 0);
+            for (int b = 0; b < B; ++b) {
+                const CNode &nd = nodes[L[b]];
+                xa[b] = buf[nd.a];
+                yb[b] = nd.op == C_TWICE_M1 ? buf[nd.a] : buf[nd.b];
+                outs[b] = o + (size_t)b * 2 * w;
+                op[b] = nd.op == C_SUB;
+                if (nd.op == C_TWICE_M1) cst[b] = rne_ll(-1.0 * D[lv]);
+                buf[L[b]] = outs[b];
+            }
+            frk::pair_batch(c, lv + 1, B, xa.data(), yb.data(), outs.data(), cst.data(), op.data());
         }
     }
     return FR_OK;

@@ -226,6 +226,14 @@ int num_digits(const fr_ctx *c, int level);   // ceil((level+1)/alpha)
 // ---------------------------------------------------------------------------
 // kernel launchers (kernels_*.hip)
 // ---------------------------------------------------------------------------
+// one item of a batched integer linear combination: sources (ciphertexts
+// [2][lp1][N]) with their signed integer factors
+struct ScalarItem {
+    std::vector<const u64 *> src;
+    std::vector<long long> k;
+    std::vector<int> lp1;
+};
+
 namespace frk {
 // NTT over `nlimbs` limbs x `npoly` polynomials; poly_stride in words.  With
 // src set the transform is out of place: it reads src (same limb map,
@@ -275,11 +283,10 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 // fused plaintext-diagonal multiply-accumulate of all giant steps
 void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell,
               int db_level, int level, int baby_level);
-// batched element-wise helpers (items addressed by pointer; kTerms = 8)
-// out[b] = sum_t k[b][t] * src[b][t] (first nl limbs of both polynomials),
-// out items contiguous [B][2][nl][N]; src/k/src_lp1 are [B][8] row-major
-void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const u64 *const *src, const long long *k,
-                  const int *src_lp1, const int *nterms);
+// batched element-wise helpers (items addressed by pointer)
+// out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
+// polynomials of every source; out items contiguous [B][2][nl][N]
+void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const ScalarItem *items);
 // c0 limbs of item b (items `item` words apart) += v[b]
 void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item);
 // out[b] = a[b] +/- b[b] (+ cst[b] on c0)

@@ -248,45 +248,48 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 
 // Fused multiply-accumulate of the BSGS inner sums (Eq. bsgs2):
 //   P_j[c][m][k] = sum_i baby_i[c][m][k] * diag_{j n1 + i}[m][k]
-// One coefficient per thread; every product is reduced on the spot with one
-// Montgomery reduction (the diagonals are Montgomery-scaled) and summed
-// canonically, so a thread keeps 2 NJ 64-bit sums.  Every diagonal word is
-// read once per launch.
+// A wave covers 32 coefficients of one limb for both polynomials (lanes
+// 0..31: c0, lanes 32..63: c1), so each diagonal word is fetched once per
+// wave and shared by the two half-waves.  A thread keeps NJ 128-bit lazy sums
+// of full products (at most 32 products below 2^122 each) and reduces each
+// with one Montgomery reduction at the end (the diagonals are
+// Montgomery-scaled by 2^64).  All NJ diagonal words of a baby step are
+// loaded before the products that use them.  Positions past ell or nj read
+// diagonal 0 and contribute zero.
 template <int NJ>
-__global__ __launch_bounds__(kT) void k_bsgs_mac2(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
+__global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
                                                   int ell, const u64 *diag, int dbl, int bl, int lv, int N,
                                                   const ModConst *mods, int accumulate) {
-    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y;
-    const ModConst mc = mods[m];
-    u64 s0[NJ], s1[NJ];
+    const int lane = threadIdx.x & 63, p = lane >> 5;
+    const int k = blockIdx.x * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
+    const size_t pt = (size_t)(dbl + 1) * N;
+    const u64 *dg = diag + (size_t)m * N + k;
+    const size_t boff = ((size_t)p * (bl + 1) + m) * N + k;
+    unsigned __int128 acc[NJ];
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) s0[jj] = s1[jj] = 0;
+    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
     for (int ii = 0; ii < nb; ++ii) {
         const int i = i0 + ii;
-        const u64 b0 = bp.p[ii][(size_t)m * N + k];
-        const u64 b1 = bp.p[ii][(size_t)(bl + 1 + m) * N + k];
+        u64 w[NJ];
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
             const int d = (j0 + jj) * n1 + i;
-            if (jj < nj && d < ell) {
-                const u64 w = diag[((size_t)d * (dbl + 1) + m) * N + k];
-                s0[jj] = addq(s0[jj], redc(b0 * w, mulhi64(b0, w), mc), mc.q);
-                s1[jj] = addq(s1[jj], redc(b1 * w, mulhi64(b1, w), mc), mc.q);
-            }
+            const bool ok = jj < nj && d < ell;
+            w[jj] = dg[(ok ? (size_t)d : 0) * pt];
+            if (!ok) w[jj] = 0;
         }
+        const u64 b = bp.p[ii][boff];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
     }
+    const ModConst mc = mods[m];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
         if (jj < nj) {
-            const size_t o0 = ((size_t)(j0 + jj) * 2 * (lv + 1) + m) * N + k;
-            const size_t o1 = o0 + (size_t)(lv + 1) * N;
-            u64 r0 = s0[jj], r1 = s1[jj];
-            if (accumulate) {
-                r0 = addq(r0, P[o0], mc.q);
-                r1 = addq(r1, P[o1], mc.q);
-            }
-            P[o0] = r0;
-            P[o1] = r1;
+            const size_t o = (((size_t)(j0 + jj) * 2 + p) * (lv + 1) + m) * N + k;
+            u64 r = redc_any((u64)acc[jj], (u64)(acc[jj] >> 64), mc);
+            if (accumulate) r = addq(r, P[o], mc.q);
+            P[o] = r;
         }
     }
 }
@@ -324,19 +327,21 @@ struct ScalarBatch {
     long long k[kBatch][kTerms];
     int src_lp1[kBatch][kTerms];  // (level + 1) of each source: its polynomial stride in limbs
     int nterms[kBatch];
+    int accumulate;  // add to the current output instead of overwriting it
 };
 
-// out_b = sum_t k_{b,t} * src_{b,t} over the first nl limbs of both
+// out_b (+)= sum_t k_{b,t} * src_{b,t} over the first nl limbs of both
 // polynomials; out items are contiguous [B][2][nl][N]
 __global__ __launch_bounds__(kT) void k_scalar_batch(u64 *out, ScalarBatch sb, int nl, int N, const ModConst *mods) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y % nl, p = blockIdx.y / nl, b = blockIdx.z;
     const ModConst m = mods[i];
-    u64 acc = 0;
+    u64 *o = out + (((size_t)b * 2 + p) * nl + i) * N + k;
+    u64 acc = sb.accumulate ? *o : 0;
     for (int t = 0; t < sb.nterms[b]; ++t) {
         const u64 x = sb.src[b][t][((size_t)p * sb.src_lp1[b][t] + i) * N + k];
         acc = addq(acc, mulmod(x, smod_dev(sb.k[b][t], m), m), m.q);
     }
-    out[(((size_t)b * 2 + p) * nl + i) * N + k] = acc;
+    *o = acc;
 }
 
 // c0 of item b (items [B][2][nl][N]) gets the constant v_b on every word
@@ -346,6 +351,7 @@ struct ConstBatch {
 __global__ __launch_bounds__(kT) void k_add_const_batch(u64 *data, ConstBatch cb, int nl, int N, size_t item,
                                                         const ModConst *mods) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
+    if (cb.v[b] == 0) return;
     const ModConst m = mods[i];
     u64 &x = data[b * item + (size_t)i * N + k];
     x = addq(x, smod_dev(cb.v[b], m), m.q);
@@ -511,8 +517,8 @@ void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64
                 for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
             ProfScope ps(c, K_MAC,
                          8.0 * c->N * (level + 1) * (used + 2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj));
-            dim3 g(c->N / kT, level + 1, 1);
-            hipLaunchKernelGGL(k_bsgs_mac2<NJ>, g, dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0, nj, ell, diag,
+            dim3 g(c->N / (kT / 2), level + 1, 1);
+            hipLaunchKernelGGL(k_bsgs_mac3<NJ>, g, dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0, nj, ell, diag,
                                db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
         }
     }
@@ -528,24 +534,30 @@ void moddown_rot(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, const u6
 }
 
 
-void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const u64 *const *src, const long long *k,
-                  const int *src_lp1, const int *nterms) {
+void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const ScalarItem *items) {
     for (int b0 = 0; b0 < B; b0 += kBatch) {
         const int nb = std::min(kBatch, B - b0);
-        ScalarBatch sb{};
-        int terms = 0;
-        for (int b = 0; b < nb; ++b) {
-            sb.nterms[b] = nterms[b0 + b];
-            for (int t = 0; t < sb.nterms[b]; ++t) {
-                sb.src[b][t] = src[(b0 + b) * kTerms + t];
-                sb.k[b][t] = k[(b0 + b) * kTerms + t];
-                sb.src_lp1[b][t] = src_lp1[(b0 + b) * kTerms + t];
+        size_t most = 0;
+        for (int b = 0; b < nb; ++b) most = std::max(most, items[b0 + b].src.size());
+        for (size_t t0 = 0; t0 == 0 || t0 < most; t0 += kTerms) {
+            ScalarBatch sb{};
+            sb.accumulate = t0 > 0;
+            int terms = 0;
+            for (int b = 0; b < nb; ++b) {
+                const ScalarItem &it = items[b0 + b];
+                const int nt = (int)std::min<size_t>(kTerms, it.src.size() > t0 ? it.src.size() - t0 : 0);
+                sb.nterms[b] = nt;
+                for (int t = 0; t < nt; ++t) {
+                    sb.src[b][t] = it.src[t0 + t];
+                    sb.k[b][t] = it.k[t0 + t];
+                    sb.src_lp1[b][t] = it.lp1[t0 + t];
+                }
+                terms += nt;
             }
-            terms += sb.nterms[b];
+            ProfScope ps(c, K_ELEM, (terms + nb * (sb.accumulate ? 2.0 : 1.0)) * 2.0 * nl * 8.0 * c->N);
+            hipLaunchKernelGGL(k_scalar_batch, grid(c, 2 * nl, nb), dim3(kT), 0, c->stream,
+                               out + (size_t)b0 * 2 * nl * c->N, sb, nl, c->N, c->d_mod);
         }
-        ProfScope ps(c, K_ELEM, (terms + nb) * 2.0 * nl * 8.0 * c->N);
-        hipLaunchKernelGGL(k_scalar_batch, grid(c, 2 * nl, nb), dim3(kT), 0, c->stream,
-                           out + (size_t)b0 * 2 * nl * c->N, sb, nl, c->N, c->d_mod);
     }
 }
 
