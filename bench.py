@@ -84,6 +84,46 @@ def step(s, d1):
     ctx.chebyshev_eval(s["keys"], s["score"], s["coeffs"], d1, out=s["cheb"])
 
 
+def batched(s, nq, steps, warmup, d1):
+    """The same hot path for nq queries at once (rotation keys, giant-step
+    keys and diagonals read once per batch): throughput and batch latency."""
+    import torch
+    fr, ctx, wl = s["fr"], s["ctx"], s["wl"]
+    from paper_2604_00546_amd import synth
+    Q = np.vstack([wl.query[None, :], synth.query_batch(3, nq - 1, s["ell"])])
+    qs = [s["q"]] + [ctx.encrypt(s["keys"], ctx.encode(synth.replicate_query(Q[q], ctx.N // 2), ctx.L, 2.0 ** 40),
+                                 synth.int_seed(3, synth.SUB_ENC, q)) for q in range(1, nq)]
+    rows = [[ctx.new_ct(ctx.L) for _ in range(s["n1"] - 1)] for _ in range(nq)]
+    babies = [[qs[q]] + rows[q] for q in range(nq)]
+    scores = [ctx.new_ct(ctx.L - 1) for _ in range(nq)]
+    chebs = [ctx.new_ct(ctx.L - 1) for _ in range(nq)]
+
+    def bstep():
+        ctx.rotate_hoisted_batch(s["keys"], qs, range(1, s["n1"]), outs=rows)
+        ctx.bsgs_diag_matvec_batch(s["keys"], babies, s["db"], 0, outs=scores)
+        ctx.chebyshev_eval_batch(s["keys"], scores, s["coeffs"], d1, outs=chebs)
+
+    for _ in range(warmup):
+        bstep()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        bstep()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    # query 0 is the plain run's query: its result must be the plain run's words
+    same = bool(np.array_equal(ctx.ct_export(chebs[0]), ctx.ct_export(s["cheb"])))
+    return {"queries_per_batch": nq, "steps": steps, "value": s["K"] * nq * steps / wall, "unit": "scores/s",
+            "ms_per_batch": wall * 1e3 / steps, "ms_per_query": wall * 1e3 / steps / nq,
+            "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "query0_equals_plain": same}
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -135,6 +175,8 @@ def main():
     ap.add_argument("--d1", type=int, default=None,
                     help="Chebyshev baby-step degree (default: the one with the fewest relinearised products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, one device-to-device copy of this many MiB (the known-size "
@@ -243,6 +285,9 @@ def main():
             bd[cls] = {"launches": n, "ms_per_step": ms, "GB/s": (b / (ms * 1e-3) / 1e9) if ms else None}
         out["kernel_breakdown"] = bd
     out["checks"] = check(s)
+    if args.batch:
+        log(f"batched form: {args.batch} queries per batch ...")
+        out["batched"] = batched(s, args.batch, max(2, min(args.steps, 5)), 1, args.d1)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one query ...")
         out["cpu_baseline"] = cpu_baseline(s, args.d1)

@@ -136,6 +136,13 @@ int fr_ct_export(fr_ctx *ctx, const fr_ct *ct, uint64_t *coeff_host);
  * * ksk_{g,t}.  outs must not alias in.  FR_ENOKEY if a key is absent. */
 int fr_rotate_hoisted(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const int32_t *rots,
                       int32_t nrot, fr_ct *outs);
+/* Batched form (queries sharing the rotation keys, the served setting of
+ * §5.1.2 where many matrices and queries are in flight): in[0..nq-1] at one
+ * level, outs[q * nrot + r] = Rot_{rots[r]}(in[q]).  Each query's outputs are
+ * the words fr_rotate_hoisted returns for it alone; each key is read once
+ * per rotation for the whole batch.  No output may alias any input. */
+int fr_rotate_hoisted_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t nq,
+                            const int32_t *rots, int32_t nrot, fr_ct *outs);
 /* Rescale (§3.2): drop q_l with centered rounding; scale /= q_l. */
 int fr_rescale(fr_ctx *ctx, const fr_ct *in, fr_ct *out);
 int fr_add(fr_ctx *ctx, const fr_ct *a, const fr_ct *b, fr_ct *out);
@@ -176,6 +183,13 @@ void fr_db_destroy(fr_db *db);
  * template g B ell + s. */
 int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t n1,
                         const fr_db *db, int32_t group, fr_ct *out);
+/* Batched form: baby[q * n1 + i] is baby step i of query q (every query's
+ * steps at one level and scale), out[q] its score ciphertext; identical to
+ * nq calls of fr_bsgs_diag_matvec.  Queries are processed in chunks of up to
+ * 8: each chunk reads every diagonal of the group and every giant-step key
+ * once. */
+int fr_bsgs_diag_matvec_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t nq,
+                              int32_t n1, const fr_db *db, int32_t group, fr_ct *out);
 
 /* ---- Chebyshev threshold (§5.1.4, Eq. cheb-sign) ----
  * out = p(in) slot-wise, p = sum_{k <= degree} c[k] T_k (c[0] the full T_0
@@ -184,6 +198,11 @@ int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int
  * canonical per-level scales (reading documented in the design notes). */
 int fr_chebyshev_eval(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const double *c,
                       int32_t degree, int32_t d1, fr_ct *out);
+/* Batched form: out[q] = p(in[q]) for nq inputs of one level and scale,
+ * identical to nq calls of fr_chebyshev_eval; every wave of the evaluation
+ * runs for up to 8 queries at once. */
+int fr_chebyshev_eval_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t nq,
+                            const double *c, int32_t degree, int32_t d1, fr_ct *out);
 
 /* ---- kernel timing hook (for the benchmark's roofline figures) ----
  * While a class is selected, every launch of that kernel class is bracketed

@@ -247,56 +247,7 @@ void add_const_dev(fr_ctx *c, u64 *c0, int level, double cst, double scale) {
     frk::add_const(c, c0, c0, r, level + 1);
 }
 
-// ---------------------------------------------------------------------------
-// ciphertext pool for the Chebyshev ladder (buffers kept for reuse)
-// ---------------------------------------------------------------------------
-struct CtPool {
-    fr_ctx *c;
-    struct Buf { u64 *p; size_t words; bool used; };
-    std::vector<Buf> bufs;
-    u64 *get(size_t words) {
-        for (auto &b : bufs)
-            if (!b.used && b.words >= words) {
-                b.used = true;
-                return b.p;
-            }
-        u64 *p = nullptr;
-        if (hipMalloc(&p, words * 8) != hipSuccess) return nullptr;
-        bufs.push_back({p, words, true});
-        return p;
-    }
-    void put(u64 *p) {
-        for (auto &b : bufs)
-            if (b.p == p) b.used = false;
-    }
-    ~CtPool() {
-        for (auto &b : bufs) (void)hipFree(b.p);
-    }
-};
-
 }  // namespace
-
-// pools live per context (attached lazily)
-struct fr_ctx_pools {
-    CtPool pool;
-};
-static std::vector<std::pair<const fr_ctx *, fr_ctx_pools *>> g_pools;
-
-static CtPool &pool_of(fr_ctx *c) {
-    for (auto &pr : g_pools)
-        if (pr.first == c) return pr.second->pool;
-    auto *p = new fr_ctx_pools{CtPool{c, {}}};
-    g_pools.push_back({c, p});
-    return p->pool;
-}
-static void drop_pool(const fr_ctx *c) {
-    for (size_t i = 0; i < g_pools.size(); ++i)
-        if (g_pools[i].first == c) {
-            delete g_pools[i].second;
-            g_pools.erase(g_pools.begin() + i);
-            return;
-        }
-}
 
 // ---------------------------------------------------------------------------
 // context
@@ -509,7 +460,6 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
 extern "C" void fr_ctx_destroy(fr_ctx *c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    drop_pool(c);
     for (void *p : {(void *)c->d_mod, (void *)c->d_tw, (void *)c->d_tw_sh, (void *)c->d_itw, (void *)c->d_itw_sh,
                     (void *)c->d_tw2, (void *)c->d_itw2,
                     (void *)c->d_modup, (void *)c->d_moddown, (void *)c->d_rescale, (void *)c->d_crt,
@@ -810,53 +760,100 @@ extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) {
 // ---------------------------------------------------------------------------
 // homomorphic operations
 // ---------------------------------------------------------------------------
-static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots, int nrot,
+// scratch bytes one batched step may take before it is split into chunks
+static const size_t kChunkBytes = (size_t)2 << 30;
+
+// Hoisted rotations of nq ciphertexts (same level): outs[q * nrot + r] =
+// Rot_{rots[r]}(in[q]).  ModUp of every c1 once, then per rotation the key
+// inner product of all queries (one read of the key feeds every query), one
+// batched ModDown preparation per chunk of rotations, and the fused finish.
+static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const int32_t *rots, int nrot,
                                fr_ct *outs) {
-    const int N = c->N, l = in->level, nE = l + 1 + c->nP;
+    const int N = c->N, l = in[0].level, nE = l + 1 + c->nP;
     const size_t lw = (size_t)(l + 1) * N;
+    for (int q = 0; q < nq; ++q) {
+        if (int e = check_ct(c, &in[q], "fr_rotate_hoisted")) return e;
+        CHECK(in[q].level == l, FR_ELEVEL, "fr_rotate_hoisted_batch: inputs differ in level");
+    }
     std::vector<u64> gs(nrot);
     std::vector<int> live;  // rotations that need a key switch
     for (int r = 0; r < nrot; ++r) {
         gs[r] = galois_element(N, rots[r]);
         CHECK(gs[r] == 1 || K->find(gs[r]), FR_ENOKEY, "fr_rotate_hoisted: no key for rotation %d", rots[r]);
-        if (int e = check_out(c, &outs[r], l, "fr_rotate_hoisted")) return e;
-        CHECK(outs[r].data != in->data, FR_EINVAL, "fr_rotate_hoisted: output aliases input");
         if (gs[r] != 1) live.push_back(r);
     }
+    for (int q = 0; q < nq; ++q)
+        for (int r = 0; r < nrot; ++r) {
+            fr_ct &o = outs[(size_t)q * nrot + r];
+            if (int e = check_out(c, &o, l, "fr_rotate_hoisted")) return e;
+            for (int q2 = 0; q2 < nq; ++q2)
+                CHECK(o.data != in[q2].data, FR_EINVAL, "fr_rotate_hoisted: output aliases an input");
+        }
     Scope sc(c->arena);
     const int nl = (int)live.size();
     if (nl) {
-        u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
-        u64 *U = scratch(c, (size_t)nl * 2 * nE * N);
-        u64 *V = scratch(c, (size_t)nl * 2 * lw);
-        ks_modup(c, in->data + lw, l, D);
-        for (int i = 0; i < nl; ++i) {
-            const u64 g = gs[live[i]];
-            u64 *Ui = U + (size_t)i * 2 * nE * N;
-            frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false);
+        const int ndig = num_digits(c, l);
+        const size_t dstride = (size_t)ndig * nE * N;
+        const u64 *c1 = in[0].data + lw;
+        if (nq > 1) {  // stage the c1 parts contiguously for the batched ModUp
+            u64 *C1 = scratch(c, (size_t)nq * lw);
+            for (int q = 0; q < nq; ++q)
+                FR_HIP(hipMemcpyAsync(C1 + (size_t)q * lw, in[q].data + lw, lw * 8, hipMemcpyDeviceToDevice,
+                                      c->stream));
+            c1 = C1;
         }
-        ks_moddown_prep(c, U, nl, l, V);
-        for (int i = 0; i < nl; ++i) {
-            const int r = live[i];
-            u64 *o = outs[r].data;
-            frk::moddown_rot(c, o, U + (size_t)i * 2 * nE * N, V + (size_t)i * 2 * lw, in->data, gs[r], l);
+        u64 *D = scratch(c, (size_t)nq * dstride);
+        ks_modup(c, c1, l, D, nq, lw);
+        const size_t per_rot = (size_t)nq * (2 * nE * N + 2 * lw) * 8;
+        const int rc = (int)std::max<size_t>(1, std::min<size_t>(nl, kChunkBytes / per_rot));
+        std::vector<u64 *> op(nq);
+        std::vector<const u64 *> ip(nq);
+        for (int q = 0; q < nq; ++q) ip[q] = in[q].data;
+        for (int r0 = 0; r0 < nl; r0 += rc) {
+            Scope sc2(c->arena);
+            const int rn = std::min(rc, nl - r0);
+            const size_t ur = (size_t)nq * 2 * nE * N, vr = (size_t)nq * 2 * lw;
+            u64 *U = scratch(c, rn * ur);
+            u64 *V = scratch(c, rn * vr);
+            for (int i = 0; i < rn; ++i) {
+                const u64 g = gs[live[r0 + i]];
+                u64 *Ui = U + i * ur;
+                frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, nq, dstride,
+                              (size_t)2 * nE * N);
+            }
+            ks_moddown_prep(c, U, rn * nq, l, V);
+            for (int i = 0; i < rn; ++i) {
+                const int r = live[r0 + i];
+                for (int q = 0; q < nq; ++q) op[q] = outs[(size_t)q * nrot + r].data;
+                frk::moddown_rot(c, op.data(), U + i * ur, V + i * vr, ip.data(), gs[r], l, nq);
+            }
         }
     }
-    for (int r = 0; r < nrot; ++r) {
-        if (gs[r] == 1) FR_HIP(hipMemcpyAsync(outs[r].data, in->data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
-        outs[r].level = l;
-        outs[r].scale = in->scale;
-    }
+    for (int q = 0; q < nq; ++q)
+        for (int r = 0; r < nrot; ++r) {
+            fr_ct &o = outs[(size_t)q * nrot + r];
+            if (gs[r] == 1)
+                FR_HIP(hipMemcpyAsync(o.data, in[q].data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+            o.level = l;
+            o.scale = in[q].scale;
+        }
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
 extern "C" int fr_rotate_hoisted(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots, int32_t nrot,
                                  fr_ct *outs) {
-    CHECK(c && K && (nrot == 0 || (rots && outs)), FR_EINVAL, "fr_rotate_hoisted: null argument");
-    if (int e = check_ct(c, in, "fr_rotate_hoisted")) return e;
+    CHECK(c && K && in && (nrot == 0 || (rots && outs)), FR_EINVAL, "fr_rotate_hoisted: null argument");
     c->arena.reset();
-    return rotate_hoisted_impl(c, K, in, rots, nrot, outs);
+    return rotate_hoisted_impl(c, K, in, 1, rots, nrot, outs);
+}
+
+extern "C" int fr_rotate_hoisted_batch(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t nq, const int32_t *rots,
+                                       int32_t nrot, fr_ct *outs) {
+    CHECK(c && K && in && nq >= 1 && (nrot == 0 || (rots && outs)), FR_EINVAL,
+          "fr_rotate_hoisted_batch: null argument or nq < 1");
+    c->arena.reset();
+    return rotate_hoisted_impl(c, K, in, nq, rots, nrot, outs);
 }
 
 extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) {
@@ -1063,15 +1060,22 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
 // ---------------------------------------------------------------------------
 // the BSGS diagonal matrix-vector product
 // ---------------------------------------------------------------------------
-extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t n1, const fr_db *db,
-                                   int32_t group, fr_ct *out) {
-    CHECK(c && K && baby && db && out, FR_EINVAL, "fr_bsgs_diag_matvec: null argument");
+// BSGS-Diagonal products of nq queries against one group: baby[q * n1 + i]
+// is baby step i of query q, out[q] its score ciphertext.  Queries run in
+// chunks of up to kMatvecChunk: one read of every diagonal per chunk (the
+// MAC), the n2 rescales of every query in one batch, one ModUp batch of all
+// giant-step inputs, per giant step one key read for the whole chunk, and
+// one ModDown per query.
+static const int kMatvecChunk = 8;
+
+static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, int n1, const fr_db *db, int group,
+                       fr_ct *out) {
     CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
     CHECK(group >= 0 && group < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range", group);
     const int N = c->N, ell = db->ell, bl = baby[0].level;
-    for (int i = 0; i < n1; ++i) {
-        if (int e = check_ct(c, &baby[i], "fr_bsgs_diag_matvec")) return e;
-        CHECK(baby[i].level == bl && baby[i].scale == baby[0].scale, FR_ELEVEL,
+    for (int t = 0; t < nq * n1; ++t) {
+        if (int e = check_ct(c, &baby[t], "fr_bsgs_diag_matvec")) return e;
+        CHECK(baby[t].level == bl && baby[t].scale == baby[(t / n1) * n1].scale, FR_ELEVEL,
               "fr_bsgs_diag_matvec: baby steps differ in level or scale");
     }
     const int lv = std::min(bl, db->level);
@@ -1079,39 +1083,73 @@ extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *bab
     const int n2 = (ell + n1 - 1) / n1, l = lv - 1;
     for (int j = 1; j < n2; ++j)
         CHECK(K->find(galois_element(N, j * n1)), FR_ENOKEY, "fr_bsgs_diag_matvec: no key for giant step %d", j * n1);
-    if (int e = check_out(c, out, l, "fr_bsgs_diag_matvec")) return e;
-    for (int i = 0; i < n1; ++i) CHECK(out->data != baby[i].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases");
-    c->arena.reset();
-    Scope sc(c->arena);
-    const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N;
-    u64 *P = scratch(c, (size_t)n2 * pw);
-    u64 *R = scratch(c, (size_t)n2 * rw);
-    CHECK(P && R, FR_ENOMEM, "fr_bsgs_diag_matvec: scratch");
-    std::vector<const u64 *> bp(n1);
-    for (int i = 0; i < n1; ++i) bp[i] = baby[i].data;
+    for (int q = 0; q < nq; ++q) {
+        if (int e = check_out(c, &out[q], l, "fr_bsgs_diag_matvec")) return e;
+        for (int t = 0; t < nq * n1; ++t)
+            CHECK(out[q].data != baby[t].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases a baby step");
+    }
+    const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N, lwl = (size_t)(l + 1) * N;
     const u64 *diag = db->data + (size_t)group * ell * (db->level + 1) * N;
-    frk::bsgs_mac(c, P, bp.data(), n1, diag, ell, db->level, lv, bl);
-    rescale_dev(c, P, lv, R, n2);
-    FR_HIP(hipMemcpyAsync(out->data, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
-    if (n2 > 1) {
-        const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
-        const size_t dstride = (size_t)ndig * nE * N;
-        u64 *D = scratch(c, (size_t)(n2 - 1) * dstride);
-        u64 *U = scratch(c, (size_t)2 * nE * N);
-        CHECK(D && U, FR_ENOMEM, "fr_bsgs_diag_matvec: scratch");
-        // ModUp of every P_j.c1, j >= 1, in one batch
-        ks_modup(c, R + rw + (size_t)(l + 1) * N, l, D, n2 - 1, rw);
-        for (int j = 1; j < n2; ++j) {
-            const u64 g = galois_element(N, j * n1);
-            frk::ks_inner(c, U, U + (size_t)nE * N, D + (size_t)(j - 1) * dstride, K->find(g)->data, g, l, j > 1);
-            frk::automorph(c, out->data, R + j * rw, g, l + 1, 1, 0, 0, true);
+    const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
+    const size_t dstride = (size_t)ndig * nE * N;
+    for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
+        Scope sc(c->arena);
+        const int qn = std::min(kMatvecChunk, nq - q0);
+        u64 *P = scratch(c, (size_t)qn * n2 * pw);
+        u64 *R = scratch(c, (size_t)qn * n2 * rw);
+        std::vector<const u64 *> bp((size_t)qn * n1);
+        for (size_t t = 0; t < bp.size(); ++t) bp[t] = baby[(size_t)q0 * n1 + t].data;
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, diag, ell, db->level, lv, bl);
+        rescale_dev(c, P, lv, R, qn * n2);
+        // S_q = R_{q,0} + sum_j sigma_j(R_{q,j}.c0) + ModDown(sum_j KS_j); staged
+        // contiguously unless there is a single query
+        u64 *S = qn == 1 ? out[q0].data : scratch(c, (size_t)qn * rw);
+        if (qn == 1)
+            FR_HIP(hipMemcpyAsync(S, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
+        else
+            FR_HIP(hipMemcpy2DAsync(S, rw * 8, R, n2 * rw * 8, rw * 8, qn, hipMemcpyDeviceToDevice, c->stream));
+        if (n2 > 1) {
+            // ModUp of every R_{q,j}.c1 (flat item f = q n2 + j, f >= 1; the
+            // j = 0 items of later queries are converted and left unused)
+            u64 *D = scratch(c, ((size_t)qn * n2 - 1) * dstride);
+            u64 *U = scratch(c, (size_t)qn * 2 * nE * N);
+            ks_modup(c, R + rw + lwl, l, D, qn * n2 - 1, rw);
+            for (int j = 1; j < n2; ++j) {
+                const u64 g = galois_element(N, j * n1);
+                frk::ks_inner(c, U, U + (size_t)nE * N, D + (size_t)(j - 1) * dstride, K->find(g)->data, g, l, j > 1,
+                              qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
+                frk::automorph(c, S, R + j * rw, g, l + 1, qn, rw, (size_t)n2 * rw, true);
+            }
+            u64 *V = scratch(c, (size_t)qn * rw);
+            ks_moddown_prep(c, U, qn, l, V);
+            frk::moddown_finish(c, S, U, V, l, 2 * qn, lwl, (size_t)nE * N, lwl, true);
         }
-        ks_moddown(c, U, l, out->data, true);
+        if (qn > 1)
+            for (int q = 0; q < qn; ++q)
+                FR_HIP(hipMemcpyAsync(out[q0 + q].data, S + (size_t)q * rw, rw * 8, hipMemcpyDeviceToDevice,
+                                      c->stream));
     }
     FR_HIP(hipGetLastError());
-    out->level = l;
-    out->scale = (baby[0].scale * db->scale) / (double)c->mod[lv];
+    for (int q = 0; q < nq; ++q) {
+        out[q].level = l;
+        out[q].scale = (baby[(size_t)q * n1].scale * db->scale) / (double)c->mod[lv];
+    }
     return FR_OK;
+}
+
+extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t n1, const fr_db *db,
+                                   int32_t group, fr_ct *out) {
+    CHECK(c && K && baby && db && out && n1 >= 1, FR_EINVAL, "fr_bsgs_diag_matvec: null argument");
+    c->arena.reset();
+    return matvec_impl(c, K, baby, 1, n1, db, group, out);
+}
+
+extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t nq, int32_t n1,
+                                         const fr_db *db, int32_t group, fr_ct *out) {
+    CHECK(c && K && baby && db && out && n1 >= 1 && nq >= 1, FR_EINVAL,
+          "fr_bsgs_diag_matvec_batch: null argument or empty batch");
+    c->arena.reset();
+    return matvec_impl(c, K, baby, nq, n1, db, group, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1309,11 +1347,12 @@ struct ChebPlan {
 
 long long rne_ll(double x) { return (long long)std::nearbyint(x); }
 
-// Executes the recorded DAG in waves.  Node outputs live in the arena for the
-// duration of the call; every ciphertext of a wave that needs a rescale is
+// Executes the recorded DAG in waves for nq inputs at once (the same DAG for
+// every query).  Node outputs live in the arena for the duration of the call
+// (buf[node * nq + q]); every ciphertext of a wave that needs a rescale is
 // staged contiguously so that one batched rescale serves the wave.
-int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, const double *D, const u64 *in,
-                 std::vector<u64 *> &buf) {
+int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, const double *D,
+                 const u64 *const *in, int nq, std::vector<u64 *> &buf) {
     const int N = c->N, n = (int)nodes.size();
     std::vector<int> depth(n, 0);
     int maxd = 0;
@@ -1326,9 +1365,11 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         depth[i] = d;
         maxd = std::max(maxd, d);
     }
-    buf.assign(n, nullptr);
+    buf.assign((size_t)n * nq, nullptr);
+    auto B_ = [&](int node, int q) -> u64 *& { return buf[(size_t)node * nq + q]; };
     for (int i = 0; i < n; ++i)
-        if (nodes[i].op == C_INPUT) buf[i] = const_cast<u64 *>(in);
+        if (nodes[i].op == C_INPUT)
+            for (int q = 0; q < nq; ++q) B_(i, q) = const_cast<u64 *>(in[q]);
     const KeyEntry *rk = K->find(0);
     CHECK(rk, FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
     auto lw = [&](int level) { return (size_t)(level + 1) * N; };
@@ -1344,7 +1385,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         for (int lam = 0; lam < FR_MAXLEVEL; ++lam) {
             const auto &L = by_level[lam];
             if (L.empty()) continue;
-            const int B = (int)L.size();
+            const int B = (int)L.size() * nq;  // item b = node L[b / nq], query b % nq
             const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
             u64 *stage = scratch(c, (size_t)B * sw);
             u64 *out = scratch(c, (size_t)B * ow);
@@ -1352,20 +1393,21 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             std::vector<long long> cst(B, 0);
             bool any_const = false;
             for (int b = 0; b < B; ++b) {
-                const CNode &nd = nodes[L[b]];
+                const CNode &nd = nodes[L[b / nq]];
+                const int q = b % nq;
                 ScalarItem &it = items[b];
                 if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
                     const int la = nodes[nd.a].level;
                     const long long k = nd.op == C_ADJUST
                                             ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
                                             : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
-                    it.src.push_back(buf[nd.a]);
+                    it.src.push_back(B_(nd.a, q));
                     it.k.push_back(k);
                     it.lp1.push_back(la + 1);
                 } else {
                     for (size_t t = 0; t < nd.ins.size(); ++t) {
                         const int src = nd.ins[t], ls = nodes[src].level;
-                        it.src.push_back(buf[src]);
+                        it.src.push_back(B_(src, q));
                         it.k.push_back(rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls]));
                         it.lp1.push_back(ls + 1);
                     }
@@ -1376,13 +1418,13 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             frk::scalar_batch(c, stage, lam + 2, B, items.data());
             rescale_dev(c, stage, lam + 1, out, B);
             if (any_const) frk::add_const_batch(c, out, lam + 1, B, cst.data(), ow);
-            for (int b = 0; b < B; ++b) buf[L[b]] = out + (size_t)b * ow;
+            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * ow;
         }
         // --- relinearised products, grouped by input level
         for (int lv = 1; lv < FR_MAXLEVEL; ++lv) {
             const auto &L = mul_by_level[lv];
             if (L.empty()) continue;
-            const int B = (int)L.size(), nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
+            const int B = (int)L.size() * nq, nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
             const size_t cw = 2 * lw(lv);
             u64 *T01 = scratch(c, (size_t)B * cw);
             u64 *T2 = scratch(c, (size_t)B * lw(lv));
@@ -1392,8 +1434,8 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
             std::vector<const u64 *> xa(B), yb(B);
             for (int b = 0; b < B; ++b) {
-                xa[b] = buf[nodes[L[b]].a];
-                yb[b] = buf[nodes[L[b]].b];
+                xa[b] = B_(nodes[L[b / nq]].a, b % nq);
+                yb[b] = B_(nodes[L[b / nq]].b, b % nq);
             }
             frk::tensor_batch(c, T01, T2, lv + 1, B, xa.data(), yb.data());
             ks_modup(c, T2, lv, Dg, B, lw(lv));
@@ -1402,7 +1444,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             ks_moddown_prep(c, U, B, lv, V);
             frk::moddown_finish(c, T01, U, V, lv, 2 * B, lw(lv), (size_t)nE * N, lw(lv), true);
             rescale_dev(c, T01, lv, out, B);
-            for (int b = 0; b < B; ++b) buf[L[b]] = out + (size_t)b * 2 * lw(lv - 1);
+            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
         }
         // --- additions, grouped by level
         for (int lv = 0; lv < FR_MAXLEVEL; ++lv) {
@@ -1413,7 +1455,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                     L.push_back(i);
             }
             if (L.empty()) continue;
-            const int B = (int)L.size();
+            const int B = (int)L.size() * nq;
             const size_t w = lw(lv);
             u64 *o = scratch(c, (size_t)B * 2 * w);
             std::vector<const u64 *> xa(B), yb(B);
@@ -1421,16 +1463,60 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             std::vector<long long> cst(B, 0);
             std::vector<int> op(B, 0);
             for (int b = 0; b < B; ++b) {
-                const CNode &nd = nodes[L[b]];
-                xa[b] = buf[nd.a];
-                yb[b] = nd.op == C_TWICE_M1 ? buf[nd.a] : buf[nd.b];
+                const CNode &nd = nodes[L[b / nq]];
+                const int q = b % nq;
+                xa[b] = B_(nd.a, q);
+                yb[b] = nd.op == C_TWICE_M1 ? B_(nd.a, q) : B_(nd.b, q);
                 outs[b] = o + (size_t)b * 2 * w;
                 op[b] = nd.op == C_SUB;
                 if (nd.op == C_TWICE_M1) cst[b] = rne_ll(-1.0 * D[lv]);
-                buf[L[b]] = outs[b];
             }
             frk::pair_batch(c, lv + 1, B, xa.data(), yb.data(), outs.data(), cst.data(), op.data());
+            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = outs[b];
         }
+    }
+    return FR_OK;
+}
+
+// queries per Chebyshev pass (bounds the arena: every node output of the
+// pass stays live until the pass ends)
+static const int kChebChunk = 8;
+
+int chebyshev_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const double *cf, int degree, int d1,
+                   fr_ct *out) {
+    CHECK(degree >= 1 && d1 >= 2, FR_EINVAL, "fr_chebyshev_eval: need degree >= 1 and d1 >= 2");
+    for (int q = 0; q < nq; ++q) {
+        if (int e = check_ct(c, &in[q], "fr_chebyshev_eval")) return e;
+        CHECK(in[q].level == in[0].level && in[q].scale == in[0].scale, FR_ELEVEL,
+              "fr_chebyshev_eval_batch: inputs differ in level or scale");
+    }
+    ChebPlan plan(in[0].level, cf, degree, d1);
+    CHECK(plan.ok, FR_ELEVEL, "fr_chebyshev_eval: not enough levels for degree %d from level %d", degree,
+          in[0].level);
+    const int ol = plan.rec.nodes[plan.out.id].level;
+    for (int q = 0; q < nq; ++q)
+        if (int e = check_out(c, &out[q], ol, "fr_chebyshev_eval")) return e;
+    CHECK(K->find(0), FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
+    double D[FR_MAXLEVEL];
+    D[in[0].level] = in[0].scale;
+    for (int l = in[0].level; l >= 1; --l) D[l - 1] = (D[l] * D[l]) / (double)c->mod[l];
+    const size_t ow = (size_t)2 * (ol + 1) * c->N;
+    for (int q0 = 0; q0 < nq; q0 += kChebChunk) {
+        const int qn = std::min(kChebChunk, nq - q0);
+        c->arena.reset();
+        Scope sc(c->arena);
+        std::vector<const u64 *> ip(qn);
+        for (int q = 0; q < qn; ++q) ip[q] = in[q0 + q].data;
+        std::vector<u64 *> buf;
+        if (int e = cheb_execute(c, K, plan.rec.nodes, D, ip.data(), qn, buf)) return e;
+        for (int q = 0; q < qn; ++q)
+            FR_HIP(hipMemcpyAsync(out[q0 + q].data, buf[(size_t)plan.out.id * qn + q], ow * 8,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    }
+    FR_HIP(hipGetLastError());
+    for (int q = 0; q < nq; ++q) {
+        out[q].level = ol;
+        out[q].scale = D[ol];
     }
     return FR_OK;
 }
@@ -1439,27 +1525,14 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
 
 extern "C" int fr_chebyshev_eval(fr_ctx *c, const fr_keys *K, const fr_ct *in, const double *cf, int32_t degree,
                                  int32_t d1, fr_ct *out) {
-    CHECK(c && K && cf && out, FR_EINVAL, "fr_chebyshev_eval: null argument");
-    CHECK(degree >= 1 && d1 >= 2, FR_EINVAL, "fr_chebyshev_eval: need degree >= 1 and d1 >= 2");
-    if (int e = check_ct(c, in, "fr_chebyshev_eval")) return e;
-    ChebPlan plan(in->level, cf, degree, d1);
-    CHECK(plan.ok, FR_ELEVEL, "fr_chebyshev_eval: not enough levels for degree %d from level %d", degree, in->level);
-    const int ol = plan.rec.nodes[plan.out.id].level;
-    if (int e = check_out(c, out, ol, "fr_chebyshev_eval")) return e;
-    CHECK(K->find(0), FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
-    c->arena.reset();
-    Scope sc(c->arena);
-    double D[FR_MAXLEVEL];
-    D[in->level] = in->scale;
-    for (int l = in->level; l >= 1; --l) D[l - 1] = (D[l] * D[l]) / (double)c->mod[l];
-    std::vector<u64 *> buf;
-    if (int e = cheb_execute(c, K, plan.rec.nodes, D, in->data, buf)) return e;
-    FR_HIP(hipMemcpyAsync(out->data, buf[plan.out.id], (size_t)2 * (ol + 1) * c->N * 8, hipMemcpyDeviceToDevice,
-                          c->stream));
-    FR_HIP(hipGetLastError());
-    out->level = ol;
-    out->scale = D[ol];
-    return FR_OK;
+    CHECK(c && K && in && cf && out, FR_EINVAL, "fr_chebyshev_eval: null argument");
+    return chebyshev_impl(c, K, in, 1, cf, degree, d1, out);
+}
+
+extern "C" int fr_chebyshev_eval_batch(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t nq, const double *cf,
+                                       int32_t degree, int32_t d1, fr_ct *out) {
+    CHECK(c && K && in && cf && out && nq >= 1, FR_EINVAL, "fr_chebyshev_eval_batch: null argument or empty batch");
+    return chebyshev_impl(c, K, in, nq, cf, degree, d1, out);
 }
 
 extern "C" int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1) {

@@ -280,8 +280,10 @@ void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly
 // out[p][i] = (in[p][i] - Y[p][i]) q_level^-1
 void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly,
                     size_t so, size_t si, size_t sy);
-// fused plaintext-diagonal multiply-accumulate of all giant steps
-void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell,
+// fused plaintext-diagonal multiply-accumulate of all giant steps for nq
+// queries: baby[q * n1 + i] is baby step i of query q; the n2 outputs of
+// query q start at P + q * pq
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *diag, int ell,
               int db_level, int level, int baby_level);
 // batched element-wise helpers (items addressed by pointer)
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
@@ -294,8 +296,10 @@ void pair_batch(const fr_ctx *c, int nl, int B, const u64 *const *a, const u64 *
                 const long long *cst, const int *op);
 // tensor of B pairs: d0, d1 -> t01 + b * 2 lw, d2 -> t2 + b * lw
 void tensor_batch(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int B, const u64 *const *a, const u64 *const *b);
-// rotation output: out = ModDown-finish(U, V) + (sigma_g(in.c0), 0)
-void moddown_rot(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int level);
+// rotation outputs of nitems ciphertexts by one Galois element g (U, V:
+// consecutive items): out[b] = ModDown-finish(U_b, V_b) + (sigma_g(in[b].c0), 0)
+void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,
+                 int level, int nitems);
 // key generation / encryption / decryption combiners (eval domain)
 void key_combine(const fr_ctx *c, u64 *b, const u64 *a, const u64 *e, const u64 *s_mont, const u64 *sp, int dlo,
                  int dhi, int nlimbs);

@@ -108,11 +108,15 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
 // Montgomery-scaled so one reduction yields the canonical sum.
 __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
-                                                 const ModConst *mods, int accumulate, size_t sd, size_t su) {
-    const int p = blockIdx.x * kT + threadIdx.x, e = blockIdx.y;
-    D += blockIdx.z * sd;
-    U0 += blockIdx.z * su;
-    U1 += blockIdx.z * su;
+                                                 const ModConst *mods, int accumulate, size_t sd, size_t su,
+                                                 int batch) {
+    // batch items vary fastest along x, so the blocks that read one key
+    // tile for every item run back to back (one HBM read, cache hits after)
+    const int item = blockIdx.x % batch;
+    const int p = (blockIdx.x / batch) * kT + threadIdx.x, e = blockIdx.y;
+    D += item * sd;
+    U0 += item * su;
+    U1 += item * su;
     const int gm = e <= level ? e : pbase + (e - level - 1);
     const ModConst m = mods[gm];
     const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
@@ -205,8 +209,9 @@ __global__ __launch_bounds__(kT) void k_rescale_finish(u64 *out, const u64 *in, 
     out[p * so + w] = shoup(subq(in[p * si + w], Y[p * sy + w], q), qinv[i], qinv_sh[i], q);
 }
 
+constexpr int kMacQ = 8;  // queries per MAC launch (baby pointer table in the kernel arguments)
 struct BabyPtrs {
-    const u64 *p[32];
+    const u64 *p[kMacQ][32];
 };
 
 // b = e - a s + [limb in digit] (P mod q) s'   (key generation, eval domain;
@@ -257,14 +262,18 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 // loaded before the products that use them.  Positions past ell or nj read
 // diagonal 0 and contribute zero.
 template <int NJ>
-__global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, BabyPtrs bp, int nb, int i0, int n1, int j0, int nj,
-                                                  int ell, const u64 *diag, int dbl, int bl, int lv, int N,
+__global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
+                                                  int nj, int ell, const u64 *diag, int dbl, int bl, int lv, int N,
                                                   const ModConst *mods, int accumulate) {
+    // queries vary fastest along x: the nq blocks that read one diagonal
+    // tile run back to back (one HBM read, cache hits for the others)
+    const int q = blockIdx.x % nq, tile = blockIdx.x / nq;
     const int lane = threadIdx.x & 63, p = lane >> 5;
-    const int k = blockIdx.x * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
+    const int k = tile * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
     const size_t pt = (size_t)(dbl + 1) * N;
     const u64 *dg = diag + (size_t)m * N + k;
     const size_t boff = ((size_t)p * (bl + 1) + m) * N + k;
+    P += q * pq;
     unsigned __int128 acc[NJ];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, BabyPtrs bp, int nb, i
             w[jj] = dg[(ok ? (size_t)d : 0) * pt];
             if (!ok) w[jj] = 0;
         }
-        const u64 b = bp.p[ii][boff];
+        const u64 b = bp.p[q][ii][boff];
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
     }
@@ -294,26 +303,32 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, BabyPtrs bp, int nb, i
     }
 }
 
-// out[i][p] = (U[i][p] - V[i][p]) P^-1 + in[i][auto_src(p, g)]: the ModDown
-// finish of a rotation fused with the automorphism of c0 (c1 part: no add)
-__global__ __launch_bounds__(kT) void k_moddown_rot(u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int N,
-                                                    int logN, int lp1, const u64 *pinv, const u64 *pinv_sh,
-                                                    const ModConst *mods, size_t su) {
-    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z;
+// out_b[i][p] = (U_b[i][p] - V_b[i][p]) P^-1 + in_b[i][auto_src(p, g)]: the
+// ModDown finish of one rotation of several ciphertexts fused with the
+// automorphism of c0 (c1 part: no add).  U_b, V_b are consecutive items.
+constexpr int kRotItems = 16;
+struct RotItems {
+    u64 *out[kRotItems];
+    const u64 *in[kRotItems];
+};
+__global__ __launch_bounds__(kT) void k_moddown_rot(RotItems it, const u64 *U, const u64 *V, u64 g, int N, int logN,
+                                                    int lp1, const u64 *pinv, const u64 *pinv_sh, const ModConst *mods,
+                                                    size_t su) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z & 1, b = blockIdx.z >> 1;
     const u64 q = mods[i].q;
     const size_t w = (size_t)i * N + k;
     const size_t lw = (size_t)lp1 * N;
-    u64 r = shoup(subq(U[p * su + w], V[p * lw + w], q), pinv[i], pinv_sh[i], q);
-    if (p == 0) r = addq(r, in[(size_t)i * N + auto_src((u32)k, g, logN)], q);
-    out[p * lw + w] = r;
+    u64 r = shoup(subq(U[(2 * b + p) * su + w], V[(2 * b + p) * lw + w], q), pinv[i], pinv_sh[i], q);
+    if (p == 0) r = addq(r, it.in[b][(size_t)i * N + auto_src((u32)k, g, logN)], q);
+    it.out[b][p * lw + w] = r;
 }
-
 
 // ---------------------------------------------------------------------------
 // batched element-wise kernels of the Chebyshev waves: per-item pointers and
 // constants travel in the kernel arguments (up to kBatch items per launch)
 // ---------------------------------------------------------------------------
 constexpr int kBatch = 16, kTerms = 8;
+static_assert(kRotItems == kBatch, "one item limit for the pointer-table launches");
 
 __device__ __forceinline__ u64 smod_dev(long long v, const ModConst &m) {
     if (v >= 0) return reduce64((u64)v, m);
@@ -467,8 +482,8 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
                  (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) + 2.0 * nd_ * nE_) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
-    hipLaunchKernelGGL(k_ks_inner, grid(c, nE, batch), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN, nE,
-                       level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su);
+    hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
+                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
@@ -502,35 +517,50 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
                        qinv_sh, c->d_mod, so, si, sy);
 }
 
-void bsgs_mac(const fr_ctx *c, u64 *P, const u64 *const *baby, int n1, const u64 *diag, int ell, int db_level,
-              int level, int baby_level) {
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *diag, int ell,
+              int db_level, int level, int baby_level) {
     const int n2 = (ell + n1 - 1) / n1;
     constexpr int NJ = 16;
-    for (int j0 = 0; j0 < n2; j0 += NJ) {
-        const int nj = std::min(NJ, n2 - j0);
-        for (int i0 = 0; i0 < n1; i0 += 32) {
-            const int nb = std::min(32, n1 - i0);
-            BabyPtrs bp;
-            for (int ii = 0; ii < 32; ++ii) bp.p[ii] = ii < nb ? baby[i0 + ii] : nullptr;
-            long long used = 0;  // diagonal plaintexts this launch reads
-            for (int jj = 0; jj < nj; ++jj)
-                for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
-            ProfScope ps(c, K_MAC,
-                         8.0 * c->N * (level + 1) * (used + 2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj));
-            dim3 g(c->N / (kT / 2), level + 1, 1);
-            hipLaunchKernelGGL(k_bsgs_mac3<NJ>, g, dim3(kT), 0, c->stream, P, bp, nb, i0, n1, j0, nj, ell, diag,
-                               db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+    for (int q0 = 0; q0 < nq; q0 += kMacQ) {
+        const int qn = std::min(kMacQ, nq - q0);
+        for (int j0 = 0; j0 < n2; j0 += NJ) {
+            const int nj = std::min(NJ, n2 - j0);
+            for (int i0 = 0; i0 < n1; i0 += 32) {
+                const int nb = std::min(32, n1 - i0);
+                BabyPtrs bp{};
+                for (int qq = 0; qq < qn; ++qq)
+                    for (int ii = 0; ii < nb; ++ii) bp.p[qq][ii] = baby[(size_t)(q0 + qq) * n1 + i0 + ii];
+                long long used = 0;  // diagonal plaintexts this launch reads
+                for (int jj = 0; jj < nj; ++jj)
+                    for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
+                ProfScope ps(c, K_MAC,
+                             8.0 * c->N * (level + 1) * (used + qn * (2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj)));
+                dim3 g(c->N / (kT / 2) * qn, level + 1, 1);
+                hipLaunchKernelGGL(k_bsgs_mac3<NJ>, g, dim3(kT), 0, c->stream, P + q0 * pq, pq, bp, qn, nb, i0, n1,
+                                   j0, nj, ell, diag, db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+            }
         }
     }
 }
 
-void moddown_rot(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, const u64 *in, u64 g, int level) {
-    ProfScope ps(c, K_ELEM, 7.0 * (level + 1) * 8.0 * c->N);
+void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,
+                 int level, int nitems) {
     const u64 *pinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;
     const u64 *pinv_sh = pinv + (c->L + 1);
     const int nE = level + 1 + c->nP;
-    hipLaunchKernelGGL(k_moddown_rot, grid(c, level + 1, 2), dim3(kT), 0, c->stream, out, U, V, in, g, c->N, c->logN,
-                       level + 1, pinv, pinv_sh, c->d_mod, (size_t)nE * c->N);
+    const size_t lw = (size_t)(level + 1) * c->N;
+    for (int b0 = 0; b0 < nitems; b0 += kBatch) {
+        const int nb = std::min(kBatch, nitems - b0);
+        RotItems it{};
+        for (int b = 0; b < nb; ++b) {
+            it.out[b] = out[b0 + b];
+            it.in[b] = in[b0 + b];
+        }
+        ProfScope ps(c, K_ELEM, nb * 7.0 * (level + 1) * 8.0 * c->N);
+        hipLaunchKernelGGL(k_moddown_rot, grid(c, level + 1, 2 * nb), dim3(kT), 0, c->stream, it,
+                           U + (size_t)b0 * 2 * nE * c->N, V + (size_t)b0 * 2 * lw, g, c->N, c->logN, level + 1,
+                           pinv, pinv_sh, c->d_mod, (size_t)nE * c->N);
+    }
 }
 
 

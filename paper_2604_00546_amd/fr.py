@@ -83,6 +83,9 @@ SIGNATURES = {
     "fr_db_destroy": (None, [_P]),
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
+    "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
+    "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, C.c_int32, _CTP]),
+    "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
     "fr_prof_end": (C.c_int, [_P, _I32P, _DP, _DP]),
     "fr_cheb_step_coeffs": (C.c_int, [C.c_int32, C.c_double, _DP]),
@@ -356,6 +359,22 @@ class Context:
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs
 
+    def rotate_hoisted_batch(self, keys: Keys, cts: Sequence[Ct], rots: Sequence[int],
+                             outs: List[List[Ct]] | None = None) -> List[List[Ct]]:
+        """outs[q][r] = Rot_{rots[r]}(cts[q]); one key read per rotation for the whole batch."""
+        rots, cts = list(rots), list(cts)
+        if outs is None:
+            outs = [[self.new_ct(ct.level) for _ in rots] for ct in cts]
+        ins = (CtDesc * len(cts))(*[c.desc for c in cts])
+        flat = [o for row in outs for o in row]
+        arr = (CtDesc * max(len(flat), 1))(*[o.desc for o in flat])
+        r = np.ascontiguousarray(rots, dtype=np.int32)
+        _check(lib().fr_rotate_hoisted_batch(self.ptr, keys.ptr, ins, len(cts), r.ctypes.data_as(_I32P), len(r),
+                                             arr), "fr_rotate_hoisted_batch")
+        for o, d in zip(flat, arr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
+
     def rescale(self, ct: Ct) -> Ct:
         out = self.new_ct(max(ct.level - 1, 0))
         _check(lib().fr_rescale(self.ptr, ct.ref, out.ref), "fr_rescale")
@@ -417,6 +436,35 @@ class Context:
         _check(lib().fr_bsgs_diag_matvec(self.ptr, keys.ptr, arr, len(baby), db.ptr, group, out.ref),
                "fr_bsgs_diag_matvec")
         return out
+
+    def bsgs_diag_matvec_batch(self, keys: Keys, babies: Sequence[Sequence[Ct]], db: Db, group: int,
+                               outs: List[Ct] | None = None) -> List[Ct]:
+        """babies[q] = the n1 baby steps of query q; one score ciphertext per query."""
+        n1 = len(babies[0])
+        flat = [b for row in babies for b in row]
+        arr = (CtDesc * len(flat))(*[b.desc for b in flat])
+        if outs is None:
+            outs = [self.new_ct(max(min(row[0].level, db.level) - 1, 0)) for row in babies]
+        oarr = (CtDesc * len(outs))(*[o.desc for o in outs])
+        _check(lib().fr_bsgs_diag_matvec_batch(self.ptr, keys.ptr, arr, len(babies), n1, db.ptr, group, oarr),
+               "fr_bsgs_diag_matvec_batch")
+        for o, d in zip(outs, oarr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
+
+    def chebyshev_eval_batch(self, keys: Keys, cts: Sequence[Ct], coeffs, d1: int,
+                             outs: List[Ct] | None = None) -> List[Ct]:
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        cts = list(cts)
+        if outs is None:
+            outs = [self.new_ct(max(cheb_out_level(ct.level, len(c) - 1, d1), 0)) for ct in cts]
+        ins = (CtDesc * len(cts))(*[x.desc for x in cts])
+        oarr = (CtDesc * len(outs))(*[o.desc for o in outs])
+        _check(lib().fr_chebyshev_eval_batch(self.ptr, keys.ptr, ins, len(cts), c.ctypes.data_as(_DP), len(c) - 1,
+                                             d1, oarr), "fr_chebyshev_eval_batch")
+        for o, d in zip(outs, oarr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
 
     def chebyshev_eval(self, keys: Keys, ct: Ct, coeffs, d1: int, out: Ct | None = None) -> Ct:
         c = np.ascontiguousarray(coeffs, dtype=np.float64)

@@ -87,3 +87,8 @@ def replicate_query(x: np.ndarray, n_slots: int) -> np.ndarray:
     """Slot vector carrying n_slots / ell copies of the query (period ell)."""
     ell = len(x)
     return np.tile(x.astype(np.float64), n_slots // ell)
+
+
+def query_batch(config: int, nq: int, ell: int) -> np.ndarray:
+    """nq unit-norm queries (float32 rows), query q drawn from its own stream."""
+    return np.stack([unit_rows(rng(config, SUB_QUERY, 1 + q), 1, ell)[0] for q in range(nq)])

@@ -121,3 +121,36 @@ def test_identification_2p15(F, gctx):
         y = g.decrypt_decode(keys, Y)
         assert np.max(np.abs(y - np.polynomial.chebyshev.chebval(exact, coeffs))) <= 2 ** -12
         assert np.array_equal(np.nonzero(y >= 0.5)[0], wl.planted)
+
+
+@pytest.mark.timeout(600)
+def test_batched_path_equals_alone_2p15(F, gctx):
+    """Three queries through the batched hot path at N = 2^16 against the
+    2^15-template database: each query's baby steps, score and Chebyshev
+    ciphertexts are the words the one-query path gives for it."""
+    g = gctx
+    wl = synth.make_workload(3, 2 ** 15, ELL, planted_frac=0.01)
+    rots = F.bsgs_rotation_set(ELL, N1)
+    keys = g.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
+    db = g.db_load(wl.templates, ELL, g.N // 2 // ELL, N1, g.L, 2.0 ** 40)
+    Q = np.vstack([wl.query[None, :], synth.query_batch(3, 2, ELL)])
+    qs = [g.encrypt(keys, g.encode(synth.replicate_query(Q[q], g.N // 2), g.L, 2.0 ** 40),
+                    synth.int_seed(3, synth.SUB_ENC, q)) for q in range(3)]
+    coeffs = F.cheb_step_coeffs(63, 0.3)
+    rows = g.rotate_hoisted_batch(keys, qs, range(1, N1))
+    babies = [[qs[q]] + rows[q] for q in range(3)]
+    S = g.bsgs_diag_matvec_batch(keys, babies, db, 0)
+    Y = g.chebyshev_eval_batch(keys, S, coeffs, 8)
+    for q in range(3):
+        alone = [qs[q]] + g.rotate_hoisted(keys, qs[q], range(1, N1))
+        for i in (1, 16, 31):
+            assert np.array_equal(g.ct_export(alone[i]), g.ct_export(babies[q][i]))
+        s1 = g.bsgs_diag_matvec(keys, alone, db, 0)
+        assert np.array_equal(g.ct_export(s1), g.ct_export(S[q]))
+        y1 = g.chebyshev_eval(keys, s1, coeffs, 8)
+        assert (y1.level, y1.scale) == (Y[q].level, Y[q].scale)
+        assert np.array_equal(g.ct_export(y1), g.ct_export(Y[q]))
+        exact = wl.templates.astype(np.float64) @ Q[q].astype(np.float64)
+        assert np.max(np.abs(g.decrypt_decode(keys, S[q]) - exact)) <= 2 ** -20
+    y0 = g.decrypt_decode(keys, Y[0])
+    assert np.array_equal(np.nonzero(y0 >= 0.5)[0], wl.planted)
