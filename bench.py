@@ -124,6 +124,63 @@ def batched(s, nq, steps, warmup, d1):
             "query0_equals_plain": same}
 
 
+def mixed_batches(s, nbatch, d1):
+    """Batches of 1..64 queries (sizes drawn from the batch stream), each query
+    against its own database of 2^10..2^15 templates (sizes drawn per query),
+    run batched and as a plain one-query loop on the same queries."""
+    import torch
+    from paper_2604_00546_amd import synth
+    fr, ctx = s["fr"], s["ctx"]
+    ell, n1 = s["ell"], s["n1"]
+    r = synth.rng(4, synth.SUB_BATCH)
+    sizes = r.integers(1, 65, size=nbatch)
+    dbsz = [r.integers(10, 16, size=int(b)) for b in sizes]
+    dbs = {}
+    for e in range(10, 16):  # one resident database per size (prefixes of one template set)
+        dbs[e] = ctx.db_load(s["wl"].templates[: 1 << e], ell, s["B"], n1, ctx.L, 2.0 ** 40)
+    nmax = int(sizes.max())
+    Q = synth.query_batch(4, nmax, ell)
+    qs = [ctx.encrypt(s["keys"], ctx.encode(synth.replicate_query(Q[q], ctx.N // 2), ctx.L, 2.0 ** 40),
+                      synth.int_seed(4, synth.SUB_ENC, q)) for q in range(nmax)]
+    rows = [[ctx.new_ct(ctx.L) for _ in range(n1 - 1)] for _ in range(nmax)]
+    babies = [[qs[q]] + rows[q] for q in range(nmax)]
+    scores = [ctx.new_ct(ctx.L - 1) for _ in range(nmax)]
+    chebs = [ctx.new_ct(ctx.L - 1) for _ in range(nmax)]
+    torch.cuda.synchronize()
+
+    def run_batched(b, sz):
+        ctx.rotate_hoisted_batch(s["keys"], qs[:b], range(1, n1), outs=rows[:b])
+        ctx.bsgs_diag_matvec_batch(s["keys"], babies[:b], [dbs[int(e)] for e in sz], [0] * b, outs=scores[:b])
+        ctx.chebyshev_eval_batch(s["keys"], scores[:b], s["coeffs"], d1, outs=chebs[:b])
+
+    def run_plain(b, sz):
+        for q in range(b):
+            ctx.rotate_hoisted(s["keys"], qs[q], range(1, n1), outs=rows[q])
+            ctx.bsgs_diag_matvec(s["keys"], babies[q], dbs[int(sz[q])], 0, out=scores[q])
+            ctx.chebyshev_eval(s["keys"], scores[q], s["coeffs"], d1, out=chebs[q])
+
+    out = {}
+    for name, fn in (("batched", run_batched), ("plain_loop", run_plain)):
+        fn(int(sizes[0]), dbsz[0])  # warm the arena
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for b, sz in zip(sizes, dbsz):
+            t1 = time.perf_counter()
+            fn(int(b), sz)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t1) * 1e3)
+        wall = time.perf_counter() - t0
+        nq = int(sizes.sum())
+        scored = int(sum((1 << int(e)) for sz in dbsz for e in sz))
+        out[name] = {"queries": nq, "wall_s": wall, "queries_per_s": nq / wall, "scores_per_s": scored / wall,
+                     "batch_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+    out["batches"] = int(nbatch)
+    out["batch_sizes"] = [int(b) for b in sizes]
+    out["speedup"] = out["plain_loop"]["wall_s"] / out["batched"]["wall_s"]
+    return out
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -175,6 +232,9 @@ def main():
     ap.add_argument("--d1", type=int, default=None,
                     help="Chebyshev baby-step degree (default: the one with the fewest relinearised products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mix", type=int, default=0,
+                    help="also run this many batches of 1..64 queries against databases of 2^10..2^15 "
+                         "templates, batched and as a plain loop")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
@@ -288,6 +348,9 @@ def main():
     if args.batch:
         log(f"batched form: {args.batch} queries per batch ...")
         out["batched"] = batched(s, args.batch, max(2, min(args.steps, 5)), 1, args.d1)
+    if args.mix:
+        log(f"mixed batches: {args.mix} ...")
+        out["mixed_batches"] = mixed_batches(s, args.mix, args.d1)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one query ...")
         out["cpu_baseline"] = cpu_baseline(s, args.d1)

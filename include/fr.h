@@ -184,12 +184,13 @@ void fr_db_destroy(fr_db *db);
 int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t n1,
                         const fr_db *db, int32_t group, fr_ct *out);
 /* Batched form: baby[q * n1 + i] is baby step i of query q (every query's
- * steps at one level and scale), out[q] its score ciphertext; identical to
- * nq calls of fr_bsgs_diag_matvec.  Queries are processed in chunks of up to
- * 8: each chunk reads every diagonal of the group and every giant-step key
- * once. */
+ * steps at one level), scored against group groups[q] of dbs[q] (databases
+ * of one ell, n1 and level; sizes may differ); out[q] is its score
+ * ciphertext, identical to the one-query call.  Queries are ordered by
+ * diagonal group and processed in chunks of up to 8: each chunk reads every
+ * diagonal of each of its groups and every giant-step key once. */
 int fr_bsgs_diag_matvec_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t nq,
-                              int32_t n1, const fr_db *db, int32_t group, fr_ct *out);
+                              int32_t n1, const fr_db *const *dbs, const int32_t *groups, fr_ct *out);
 
 /* ---- Chebyshev threshold (§5.1.4, Eq. cheb-sign) ----
  * out = p(in) slot-wise, p = sum_{k <= degree} c[k] T_k (c[0] the full T_0

@@ -259,6 +259,10 @@ static int upload(T **dst, const std::vector<T> &src) {
     return FR_OK;
 }
 
+// x 2^64 mod q: table entries that multiply 128-bit lazy sums, so that one
+// Montgomery reduction of the sum yields the canonical residue
+static u64 to_mont(u64 x, u64 q) { return (u64)(((unsigned __int128)x << 64) % q); }
+
 static u64 prod_mod(const fr_ctx *c, const std::vector<int> &idx, int skip, u64 r) {
     u64 p = 1 % r;
     for (int i : idx)
@@ -329,7 +333,7 @@ static int ctx_build(fr_ctx *c) {
             for (int d = 0; d < nd; ++d) mu.push_back(shoup_companion(mu[c->modup_off[l][t] + d], c->mod[lo + d]));
             for (int e = 0; e < nE; ++e) {
                 const int gm = e <= l ? e : L + 1 + (e - l - 1);
-                for (int d = 0; d < nd; ++d) mu.push_back(prod_mod(c, dig, lo + d, c->mod[gm]));
+                for (int d = 0; d < nd; ++d) mu.push_back(to_mont(prod_mod(c, dig, lo + d, c->mod[gm]), c->mod[gm]));
             }
         }
     }
@@ -342,7 +346,7 @@ static int ctx_build(fr_ctx *c) {
     for (int j = 0; j < nP; ++j) md.push_back(invmod_h(prod_mod(c, pidx, L + 1 + j, c->mod[L + 1 + j]), c->mod[L + 1 + j]));
     for (int j = 0; j < nP; ++j) md.push_back(shoup_companion(md[j], c->mod[L + 1 + j]));
     for (int i = 0; i <= L; ++i)
-        for (int j = 0; j < nP; ++j) md.push_back(prod_mod(c, pidx, L + 1 + j, c->mod[i]));
+        for (int j = 0; j < nP; ++j) md.push_back(to_mont(prod_mod(c, pidx, L + 1 + j, c->mod[i]), c->mod[i]));
     std::vector<u64> pinv(L + 1), pinvs(L + 1);
     for (int i = 0; i <= L; ++i) {
         const u64 pm = prod_mod(c, pidx, -1, c->mod[i]);
@@ -1060,25 +1064,34 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
 // ---------------------------------------------------------------------------
 // the BSGS diagonal matrix-vector product
 // ---------------------------------------------------------------------------
-// BSGS-Diagonal products of nq queries against one group: baby[q * n1 + i]
-// is baby step i of query q, out[q] its score ciphertext.  Queries run in
-// chunks of up to kMatvecChunk: one read of every diagonal per chunk (the
-// MAC), the n2 rescales of every query in one batch, one ModUp batch of all
-// giant-step inputs, per giant step one key read for the whole chunk, and
-// one ModDown per query.
+// BSGS-Diagonal products of nq queries, query q against group groups[q] of
+// dbs[q] (every database with the same ell, n1 and level): baby[q * n1 + i]
+// is baby step i of query q, out[q] its score ciphertext.  Queries are
+// ordered by diagonal group and run in chunks of up to kMatvecChunk: one
+// read of every diagonal per chunk and group (the MAC), the n2 rescales of
+// every query in one batch, one ModUp batch of all giant-step inputs, per
+// giant step one key read for the whole chunk, and one ModDown per query.
 static const int kMatvecChunk = 8;
 
-static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, int n1, const fr_db *db, int group,
-                       fr_ct *out) {
-    CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
-    CHECK(group >= 0 && group < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range", group);
-    const int N = c->N, ell = db->ell, bl = baby[0].level;
+static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, int n1, const fr_db *const *dbs,
+                       const int32_t *groups, fr_ct *out) {
+    const fr_db *db0 = dbs[0];
+    for (int q = 0; q < nq; ++q) {
+        const fr_db *db = dbs[q];
+        CHECK(db, FR_EINVAL, "fr_bsgs_diag_matvec: null database");
+        CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
+        CHECK(groups[q] >= 0 && groups[q] < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range",
+              groups[q]);
+        CHECK(db->ell == db0->ell && db->level == db0->level, FR_EINVAL,
+              "fr_bsgs_diag_matvec_batch: databases differ in ell or level");
+    }
+    const int N = c->N, ell = db0->ell, bl = baby[0].level;
     for (int t = 0; t < nq * n1; ++t) {
         if (int e = check_ct(c, &baby[t], "fr_bsgs_diag_matvec")) return e;
         CHECK(baby[t].level == bl && baby[t].scale == baby[(t / n1) * n1].scale, FR_ELEVEL,
               "fr_bsgs_diag_matvec: baby steps differ in level or scale");
     }
-    const int lv = std::min(bl, db->level);
+    const int lv = std::min(bl, db0->level);
     CHECK(lv >= 1, FR_ELEVEL, "fr_bsgs_diag_matvec: no level left to rescale");
     const int n2 = (ell + n1 - 1) / n1, l = lv - 1;
     for (int j = 1; j < n2; ++j)
@@ -1089,7 +1102,12 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
             CHECK(out[q].data != baby[t].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases a baby step");
     }
     const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N, lwl = (size_t)(l + 1) * N;
-    const u64 *diag = db->data + (size_t)group * ell * (db->level + 1) * N;
+    auto diag_of = [&](int q) {
+        return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * (dbs[q]->level + 1) * N);
+    };
+    std::vector<int> order(nq);
+    for (int q = 0; q < nq; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
     const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
     const size_t dstride = (size_t)ndig * nE * N;
     for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
@@ -1097,13 +1115,17 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
         const int qn = std::min(kMatvecChunk, nq - q0);
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
         u64 *R = scratch(c, (size_t)qn * n2 * rw);
-        std::vector<const u64 *> bp((size_t)qn * n1);
-        for (size_t t = 0; t < bp.size(); ++t) bp[t] = baby[(size_t)q0 * n1 + t].data;
-        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, diag, ell, db->level, lv, bl);
+        std::vector<const u64 *> bp((size_t)qn * n1), dp(qn);
+        for (int qq = 0; qq < qn; ++qq) {
+            const int q = order[q0 + qq];
+            dp[qq] = diag_of(q);
+            for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = baby[(size_t)q * n1 + i].data;
+        }
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, db0->level, lv, bl);
         rescale_dev(c, P, lv, R, qn * n2);
         // S_q = R_{q,0} + sum_j sigma_j(R_{q,j}.c0) + ModDown(sum_j KS_j); staged
         // contiguously unless there is a single query
-        u64 *S = qn == 1 ? out[q0].data : scratch(c, (size_t)qn * rw);
+        u64 *S = qn == 1 ? out[order[q0]].data : scratch(c, (size_t)qn * rw);
         if (qn == 1)
             FR_HIP(hipMemcpyAsync(S, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
         else
@@ -1125,14 +1147,14 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
             frk::moddown_finish(c, S, U, V, l, 2 * qn, lwl, (size_t)nE * N, lwl, true);
         }
         if (qn > 1)
-            for (int q = 0; q < qn; ++q)
-                FR_HIP(hipMemcpyAsync(out[q0 + q].data, S + (size_t)q * rw, rw * 8, hipMemcpyDeviceToDevice,
+            for (int qq = 0; qq < qn; ++qq)
+                FR_HIP(hipMemcpyAsync(out[order[q0 + qq]].data, S + (size_t)qq * rw, rw * 8, hipMemcpyDeviceToDevice,
                                       c->stream));
     }
     FR_HIP(hipGetLastError());
     for (int q = 0; q < nq; ++q) {
         out[q].level = l;
-        out[q].scale = (baby[(size_t)q * n1].scale * db->scale) / (double)c->mod[lv];
+        out[q].scale = (baby[(size_t)q * n1].scale * dbs[q]->scale) / (double)c->mod[lv];
     }
     return FR_OK;
 }
@@ -1141,15 +1163,15 @@ extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *bab
                                    int32_t group, fr_ct *out) {
     CHECK(c && K && baby && db && out && n1 >= 1, FR_EINVAL, "fr_bsgs_diag_matvec: null argument");
     c->arena.reset();
-    return matvec_impl(c, K, baby, 1, n1, db, group, out);
+    return matvec_impl(c, K, baby, 1, n1, &db, &group, out);
 }
 
 extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t nq, int32_t n1,
-                                         const fr_db *db, int32_t group, fr_ct *out) {
-    CHECK(c && K && baby && db && out && n1 >= 1 && nq >= 1, FR_EINVAL,
+                                         const fr_db *const *dbs, const int32_t *groups, fr_ct *out) {
+    CHECK(c && K && baby && dbs && groups && out && n1 >= 1 && nq >= 1, FR_EINVAL,
           "fr_bsgs_diag_matvec_batch: null argument or empty batch");
     c->arena.reset();
-    return matvec_impl(c, K, baby, nq, n1, db, group, out);
+    return matvec_impl(c, K, baby, nq, n1, dbs, groups, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -144,9 +144,11 @@ struct fr_ctx {
     u64 *d_tw = nullptr, *d_tw_sh = nullptr, *d_itw = nullptr, *d_itw_sh = nullptr;
     u64 *d_tw2 = nullptr, *d_itw2 = nullptr;  // interleaved (twiddle, companion) pairs [nmod][N][2]
     // ModUp tables, per (level, digit): dinv[nd], dinv_sh[nd], dhat[nE][nd]
+    // (dhat Montgomery-scaled by 2^64 mod r_e)
     u64 *d_modup = nullptr;
     size_t modup_off[FR_MAXLEVEL][8];
-    // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP],
+    // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP]
+    // (Montgomery-scaled by 2^64 mod q_i),
     // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits)
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
@@ -281,10 +283,11 @@ void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly
 void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly,
                     size_t so, size_t si, size_t sy);
 // fused plaintext-diagonal multiply-accumulate of all giant steps for nq
-// queries: baby[q * n1 + i] is baby step i of query q; the n2 outputs of
-// query q start at P + q * pq
-void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *diag, int ell,
-              int db_level, int level, int baby_level);
+// queries: baby[q * n1 + i] is baby step i of query q, diag[q] the diagonal
+// group it is scored against (queries sharing a group should be adjacent);
+// the n2 outputs of query q start at P + q * pq
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
+              int ell, int db_level, int level, int baby_level);
 // batched element-wise helpers (items addressed by pointer)
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
 // polynomials of every source; out items contiguous [B][2][nl][N]

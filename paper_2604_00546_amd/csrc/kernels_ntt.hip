@@ -180,26 +180,56 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(NttLaunch a) {
 // Radix-2^LE register kernels for even logN = 4 LE (N = 2^12, 2^16): every
 // 2^(2 LE)-point sub-transform is done by E = 2^LE threads, E coefficients
 // each, in two register rounds of LE stages with one LDS transpose between
-// them.  Butterflies are Harvey's lazy forms (forward values in [0, 4q),
-// inverse in [0, 2q)); outputs are reduced to [0, q).  Round-1 twiddles of
+// them.  Butterflies are Harvey's lazy forms with a truncated Shoup quotient
+// (forward values in [0, 8q), inverse in [0, 4q); every prime is below 2^61
+// so 8q fits a word); outputs are reduced to [0, q).  Round-1 twiddles of
 // the column pass are uniform across the workgroup.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - mulhi64(a, wp) * q; }
 
-__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
-    u64 x = X >= q2 ? X - q2 : X;
-    const u64 t = shoup_lazy(Y, w, wp, q);
+// a * w - h q with h the high word of a * wp built from the three partial
+// products that reach it (the low 32x32 product and the carries out of the
+// middle products' low halves are dropped): h is at most 2 below the exact
+// quotient estimate, so the result lies in [0, 4q) for any 64-bit a.
+__device__ __forceinline__ u64 shoup_lazy4(u64 a, u64 w, u64 wp, u64 q) {
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), p0 = (u32)wp, p1 = (u32)(wp >> 32);
+    const u64 h = (u64)a1 * p1 + __umulhi(a0, p1) + __umulhi(a1, p0);
+    return a * w - h * q;
+}
+
+// inputs and outputs in [0, 8q)
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4) {
+    u64 x = X >= q4 ? X - q4 : X;
+    const u64 t = shoup_lazy4(Y, w, wp, q);
     X = x + t;
-    Y = x - t + q2;
+    Y = x - t + q4;
 }
-__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q2) {
+// inputs and outputs in [0, 4q)
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4) {
     u64 s = X + Y;
-    s = s >= q2 ? s - q2 : s;
-    const u64 d = X - Y + q2;
+    s = s >= q4 ? s - q4 : s;
+    const u64 d = X - Y + q4;
     X = s;
-    Y = shoup_lazy(d, w, wp, q);
+    Y = shoup_lazy4(d, w, wp, q);
 }
-__device__ __forceinline__ u64 red4(u64 x, u64 q) {
+// LDS layouts of the transposes.  A row tile of R = E^2 words is read both
+// as i = u + E k and as i = E u + k (u the lane's index); word i = E r + c of
+// the tile of sub-transform `blk` is stored at E (r ^ blk mod E) + (c ^ r),
+// which spreads both patterns of a wave evenly over the banks.  The column
+// tiles (COLS words per row) are read as rows g + E k and E g + k; row r is
+// stored at r ^ ((r >> LE) & 1) so that the second pattern uses both halves
+// of the banks.
+template <int LE>
+__device__ __forceinline__ int rsw(int i, int blk) {
+    constexpr int E = 1 << LE;
+    const int r = i >> LE, c = i & (E - 1);
+    return (((r ^ blk) & (E - 1)) << LE) | (c ^ r);
+}
+template <int LE>
+__device__ __forceinline__ int csw(int row) { return row ^ ((row >> LE) & 1); }
+
+__device__ __forceinline__ u64 red8(u64 x, u64 q) {
+    x = x >= 4 * q ? x - 4 * q : x;
     x = x >= 2 * q ? x - 2 * q : x;
     return x >= q ? x - q : x;
 }
@@ -210,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
     __shared__ u64 tile[R * COLS];
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
-    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
@@ -226,14 +256,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + (k >> (LE - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) tile[(g + E * k) * COLS + c] = v[k];
+    for (int k = 0; k < E; ++k) tile[csw<LE>(g + E * k) * COLS + c] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = tile[(E * g + k) * COLS + c];
+    for (int k = 0; k < E; ++k) v[k] = tile[csw<LE>(E * g + k) * COLS + c];
 #pragma unroll
     for (int st = LE; st < LR; ++st) {
         const int half = 1 << (LR - st - 1);
@@ -241,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + ((E * g + k) >> (LR - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -254,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
     __shared__ u64 tile[BLKS * R];
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
-    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
@@ -271,14 +301,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + (k >> (LE - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) tb[u0 + E * k] = v[k];
+    for (int k = 0; k < E; ++k) tb[rsw<LE>(u0 + E * k, blk)] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = tb[E * u0 + k];
+    for (int k = 0; k < E; ++k) v[k] = tb[rsw<LE>(E * u0 + k, blk)];
 #pragma unroll
     for (int sl = LE; sl < LR; ++sl) {
         const int half = 1 << (LR - sl - 1);
@@ -286,14 +316,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + ((E * u0 + k) >> (LR - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) tb[E * u0 + k] = v[k];
+    for (int k = 0; k < E; ++k) tb[rsw<LE>(E * u0 + k, blk)] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) xb[u0 + E * k] = red4(tb[u0 + E * k], q);
+    for (int k = 0; k < E; ++k) xb[u0 + E * k] = red8(tb[rsw<LE>(u0 + E * k, blk)], q);
 }
 
 template <int LE>
@@ -302,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
     __shared__ u64 tile[BLKS * R];
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
-    const u64 q = a.mods[mi].q, q2 = 2 * q;
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -313,10 +343,10 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
     u64 *tb = tile + blk * R;
     u64 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) tb[u0 + E * k] = xsb[u0 + E * k];
+    for (int k = 0; k < E; ++k) tb[rsw<LE>(u0 + E * k, blk)] = xsb[u0 + E * k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = tb[E * u0 + k];
+    for (int k = 0; k < E; ++k) v[k] = tb[rsw<LE>(E * u0 + k, blk)];
 #pragma unroll
     for (int lt = 0; lt < LE; ++lt) {
         const int half = 1 << lt;
@@ -324,14 +354,14 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + ((E * u0 + k) >> (lt + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) tb[E * u0 + k] = v[k];
+    for (int k = 0; k < E; ++k) tb[rsw<LE>(E * u0 + k, blk)] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = tb[u0 + E * k];
+    for (int k = 0; k < E; ++k) v[k] = tb[rsw<LE>(u0 + E * k, blk)];
 #pragma unroll
     for (int lt = LE; lt < LR; ++lt) {
         const int half = 1 << (lt - LE);
@@ -339,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (k >> (lt + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -353,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
     const ModConst mc = a.mods[mi];
-    const u64 q = mc.q, q2 = 2 * q;
+    const u64 q = mc.q, q4 = 4 * q;
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -369,14 +399,14 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + ((E * g + k) >> (ltp + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) tile[(E * g + k) * COLS + c] = v[k];
+    for (int k = 0; k < E; ++k) tile[csw<LE>(E * g + k) * COLS + c] = v[k];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = tile[(g + E * k) * COLS + c];
+    for (int k = 0; k < E; ++k) v[k] = tile[csw<LE>(g + E * k) * COLS + c];
 #pragma unroll
     for (int ltp = LE; ltp < LR; ++ltp) {
         const int half = 1 << (ltp - LE);
@@ -384,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + (k >> (ltp + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q2); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll

@@ -15,6 +15,22 @@ constexpr int kT = 256;
 constexpr int kMaxDigit = 8;  // alpha <= 8 (checked at context creation)
 constexpr int kTargetsPerThread = 4;
 
+// Batch item and tile of a block when every tile is processed for `batch`
+// items.  Workgroups are placed on the 8 XCDs round-robin by linear id, so
+// with ntiles a multiple of 8 the `batch` blocks of one tile are consecutive
+// on one XCD and share its L2 (one HBM read of the shared operand); other
+// shapes fall back to items varying fastest.
+__device__ __forceinline__ void item_tile(int b, int batch, int ntiles, int &item, int &tile) {
+    if ((ntiles & 7) == 0) {
+        const int s = b >> 3;
+        item = s % batch;
+        tile = (s / batch) * 8 + (b & 7);
+    } else {
+        item = b % batch;
+        tile = b / batch;
+    }
+}
+
 struct LimbConsts {
     u64 v[FR_MAXMOD];
     u64 sh[FR_MAXMOD];
@@ -80,7 +96,8 @@ __global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, 
 
 // ModUp of digit [lo, lo+nd): x coefficient form [level+1][N]; D[nE][N].
 // y_d = [x_{lo+d} * Dhat_d^-1]_{q_{lo+d}} (canonical), then for every
-// extended position e outside the digit: D[e] = sum_d y_d * [Dhat_d]_{r_e} mod r_e.
+// extended position e outside the digit: D[e] = sum_d y_d * [Dhat_d]_{r_e} mod r_e
+// (table entries Montgomery-scaled: one reduction of the 128-bit sum).
 __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd, int nE, int level,
                                               int pbase, const u64 *tab, const ModConst *mods, size_t sd, size_t sx) {
     const int k = blockIdx.x * kT + threadIdx.x;
@@ -100,7 +117,7 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
 #pragma unroll
         for (int d = 0; d < kMaxDigit; ++d)
             if (d < nd) mac128(al, ah, y[d], dhat[(size_t)e * nd + d]);
-        D[(size_t)e * N + k] = reduce128(al, ah, mods[gm]);
+        D[(size_t)e * N + k] = redc_any(al, ah, mods[gm]);
     }
 }
 
@@ -110,10 +127,9 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
                                                  const ModConst *mods, int accumulate, size_t sd, size_t su,
                                                  int batch) {
-    // batch items vary fastest along x, so the blocks that read one key
-    // tile for every item run back to back (one HBM read, cache hits after)
-    const int item = blockIdx.x % batch;
-    const int p = (blockIdx.x / batch) * kT + threadIdx.x, e = blockIdx.y;
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
     D += item * sd;
     U0 += item * su;
     U1 += item * su;
@@ -168,7 +184,7 @@ __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int 
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
             if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        V[poly * sv + (size_t)i * N + k] = subq(reduce128(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
+        V[poly * sv + (size_t)i * N + k] = subq(redc_any(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
     }
 }
 
@@ -212,6 +228,7 @@ __global__ __launch_bounds__(kT) void k_rescale_finish(u64 *out, const u64 *in, 
 constexpr int kMacQ = 8;  // queries per MAC launch (baby pointer table in the kernel arguments)
 struct BabyPtrs {
     const u64 *p[kMacQ][32];
+    const u64 *diag[kMacQ];  // diagonal group of each query
 };
 
 // b = e - a s + [limb in digit] (P mod q) s'   (key generation, eval domain;
@@ -260,18 +277,18 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 // with one Montgomery reduction at the end (the diagonals are
 // Montgomery-scaled by 2^64).  All NJ diagonal words of a baby step are
 // loaded before the products that use them.  Positions past ell or nj read
-// diagonal 0 and contribute zero.
-template <int NJ>
+// diagonal 0 and contribute zero (a launch whose tile lies inside the
+// matrix is compiled without those guards).
+template <int NJ, bool FULL>
 __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
-                                                  int nj, int ell, const u64 *diag, int dbl, int bl, int lv, int N,
+                                                  int nj, int ell, int dbl, int bl, int lv, int N,
                                                   const ModConst *mods, int accumulate) {
-    // queries vary fastest along x: the nq blocks that read one diagonal
-    // tile run back to back (one HBM read, cache hits for the others)
-    const int q = blockIdx.x % nq, tile = blockIdx.x / nq;
+    int q, tile;
+    item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
     const int lane = threadIdx.x & 63, p = lane >> 5;
     const int k = tile * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
     const size_t pt = (size_t)(dbl + 1) * N;
-    const u64 *dg = diag + (size_t)m * N + k;
+    const u64 *dg = bp.diag[q] + (size_t)m * N + k;
     const size_t boff = ((size_t)p * (bl + 1) + m) * N + k;
     P += q * pq;
     unsigned __int128 acc[NJ];
@@ -283,9 +300,13 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
             const int d = (j0 + jj) * n1 + i;
-            const bool ok = jj < nj && d < ell;
-            w[jj] = dg[(ok ? (size_t)d : 0) * pt];
-            if (!ok) w[jj] = 0;
+            if (FULL) {
+                w[jj] = dg[(size_t)d * pt];
+            } else {
+                const bool ok = jj < nj && d < ell;
+                w[jj] = dg[(ok ? (size_t)d : 0) * pt];
+                if (!ok) w[jj] = 0;
+            }
         }
         const u64 b = bp.p[q][ii][boff];
 #pragma unroll
@@ -517,27 +538,35 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
                        qinv_sh, c->d_mod, so, si, sy);
 }
 
-void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *diag, int ell,
-              int db_level, int level, int baby_level) {
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
+              int ell, int db_level, int level, int baby_level) {
     const int n2 = (ell + n1 - 1) / n1;
     constexpr int NJ = 16;
     for (int q0 = 0; q0 < nq; q0 += kMacQ) {
         const int qn = std::min(kMacQ, nq - q0);
+        int ngroups = 0;  // distinct diagonal groups read by this launch
+        for (int qq = 0; qq < qn; ++qq) ngroups += qq == 0 || diag[q0 + qq] != diag[q0 + qq - 1];
         for (int j0 = 0; j0 < n2; j0 += NJ) {
             const int nj = std::min(NJ, n2 - j0);
             for (int i0 = 0; i0 < n1; i0 += 32) {
                 const int nb = std::min(32, n1 - i0);
                 BabyPtrs bp{};
-                for (int qq = 0; qq < qn; ++qq)
+                for (int qq = 0; qq < qn; ++qq) {
+                    bp.diag[qq] = diag[q0 + qq];
                     for (int ii = 0; ii < nb; ++ii) bp.p[qq][ii] = baby[(size_t)(q0 + qq) * n1 + i0 + ii];
-                long long used = 0;  // diagonal plaintexts this launch reads
+                }
+                long long used = 0;  // diagonal plaintexts of one group this launch reads
                 for (int jj = 0; jj < nj; ++jj)
                     for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
                 ProfScope ps(c, K_MAC,
-                             8.0 * c->N * (level + 1) * (used + qn * (2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj)));
+                             8.0 * c->N * (level + 1) *
+                                 (ngroups * used + qn * (2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj)));
                 dim3 g(c->N / (kT / 2) * qn, level + 1, 1);
-                hipLaunchKernelGGL(k_bsgs_mac3<NJ>, g, dim3(kT), 0, c->stream, P + q0 * pq, pq, bp, qn, nb, i0, n1,
-                                   j0, nj, ell, diag, db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+                // every (j, i) of the tile inside the matrix: no per-term guards
+                const bool full = nj == NJ && (j0 + NJ - 1) * n1 + i0 + nb - 1 < ell;
+                auto kern = full ? k_bsgs_mac3<NJ, true> : k_bsgs_mac3<NJ, false>;
+                hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, P + q0 * pq, pq, bp, qn, nb, i0, n1, j0, nj, ell,
+                                   db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
             }
         }
     }

@@ -84,7 +84,7 @@ SIGNATURES = {
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
-    "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, C.c_int32, _CTP]),
+    "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
     "fr_prof_end": (C.c_int, [_P, _I32P, _DP, _DP]),
@@ -437,17 +437,23 @@ class Context:
                "fr_bsgs_diag_matvec")
         return out
 
-    def bsgs_diag_matvec_batch(self, keys: Keys, babies: Sequence[Sequence[Ct]], db: Db, group: int,
+    def bsgs_diag_matvec_batch(self, keys: Keys, babies: Sequence[Sequence[Ct]], db, group=0,
                                outs: List[Ct] | None = None) -> List[Ct]:
-        """babies[q] = the n1 baby steps of query q; one score ciphertext per query."""
-        n1 = len(babies[0])
+        """babies[q] = the n1 baby steps of query q; db / group: one database
+        and group for every query, or one per query.  One score ciphertext
+        per query."""
+        nq, n1 = len(babies), len(babies[0])
+        dbs = list(db) if isinstance(db, (list, tuple)) else [db] * nq
+        grp = np.ascontiguousarray(list(group) if isinstance(group, (list, tuple)) else [group] * nq,
+                                   dtype=np.int32)
         flat = [b for row in babies for b in row]
         arr = (CtDesc * len(flat))(*[b.desc for b in flat])
         if outs is None:
-            outs = [self.new_ct(max(min(row[0].level, db.level) - 1, 0)) for row in babies]
-        oarr = (CtDesc * len(outs))(*[o.desc for o in outs])
-        _check(lib().fr_bsgs_diag_matvec_batch(self.ptr, keys.ptr, arr, len(babies), n1, db.ptr, group, oarr),
-               "fr_bsgs_diag_matvec_batch")
+            outs = [self.new_ct(max(min(row[0].level, d.level) - 1, 0)) for row, d in zip(babies, dbs)]
+        oarr = (CtDesc * nq)(*[o.desc for o in outs])
+        dptr = (C.c_void_p * nq)(*[d.ptr for d in dbs])
+        _check(lib().fr_bsgs_diag_matvec_batch(self.ptr, keys.ptr, arr, nq, n1, dptr, grp.ctypes.data_as(_I32P),
+                                               oarr), "fr_bsgs_diag_matvec_batch")
         for o, d in zip(outs, oarr):
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs

@@ -34,7 +34,7 @@ def trace(path, steps, calib_mib):
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     # the copy kernel's grid covers M MiB; identify it as the last long copy
-    cand = [i for i, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+    cand = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"]
     dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     start = max(cand, key=lambda i: dur(rows[i]))
     timed = rows[start + 1:]
@@ -60,8 +60,10 @@ def counters(fpath, wpath, calib_mib):
     f, w = load(fpath, "FETCH_SIZE"), load(wpath, "WRITE_SIZE")
     ref_kib = calib_mib * 1024.0
     # calibration: the largest copy's counters against its known size
-    fc = max((r for r in f if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
-    wc = max((r for r in w if "copyBuffer" in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+    def is_copy(r):
+        return _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"
+    fc = max((r for r in f if is_copy(r)), key=lambda r: float(r["Counter_Value"]))
+    wc = max((r for r in w if is_copy(r)), key=lambda r: float(r["Counter_Value"]))
     kf, kw = ref_kib / float(fc["Counter_Value"]), ref_kib / float(wc["Counter_Value"])
     print(f"calibration copy of {calib_mib} MiB: FETCH_SIZE {float(fc['Counter_Value']):.1f} KiB -> factor {kf:.4f}; "
           f"WRITE_SIZE {float(wc['Counter_Value']):.1f} KiB -> factor {kw:.4f}")

@@ -109,6 +109,25 @@ def test_matvec_batch_equals_alone_and_oracle(B, babies, scores, oracle_scores):
         assert np.max(np.abs(dec[: wl.K] - exact)) <= 2 ** -20
 
 
+def test_matvec_batch_mixed_databases(B, babies, scores):
+    """Queries scored against two databases of different sizes in one batch
+    (interleaved, so the batch reorders them by group): each result is the
+    one-query result against its own database."""
+    g, o = B["g"], B["o"]
+    wl2 = synth.make_workload(4, 40, ELL, extra=1)
+    odb2 = o.db_build(wl2.templates, wl2.K, ELL, 16, N1, o.L, 2.0 ** 40)
+    gdb2 = g.db_import(odb2.export_all(), odb2.G, ELL, 16, N1, g.L, 2.0 ** 40)
+    dbs = [B["gdb"] if q % 2 == 0 else gdb2 for q in range(NQ)]
+    mixed = g.bsgs_diag_matvec_batch(B["kg"], babies, dbs, [0] * NQ)
+    for q in range(NQ):
+        if q % 2 == 0:
+            _same_ct(g, mixed[q], scores[q])
+        else:
+            _same_ct(g, mixed[q], g.bsgs_diag_matvec(B["kg"], babies[q], gdb2, 0))
+    ob = [B["oq"][9]] + o.rotate_hoisted(B["ko"], B["oq"][9], range(1, N1))
+    _same_oracle(g, mixed[9], o.bsgs_matvec(B["ko"], ob, odb2, 0))
+
+
 def test_matvec_batch_single_query(B, babies, scores):
     g = B["g"]
     one = g.bsgs_diag_matvec_batch(B["kg"], babies[3:4], B["gdb"], 0)
