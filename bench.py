@@ -181,6 +181,38 @@ def mixed_batches(s, nbatch, d1):
     return out
 
 
+def served(s, seconds, d1, rates=(10.0, 50.0, 200.0), pool=64):
+    """Poisson arrivals at each rate for `seconds`: half verification (one
+    512-template block), half identification (2^10..2^15 templates), served
+    with continuous batching and as a plain one-at-a-time loop on the same
+    trace.  Requests reuse a pool of encrypted queries."""
+    from paper_2604_00546_amd import serve, synth
+    ctx, ell, n1 = s["ctx"], s["ell"], s["n1"]
+    dbs = {e: ctx.db_load(s["wl"].templates[: 1 << e], ell, s["B"], n1, ctx.L, 2.0 ** 40) for e in range(9, 16)}
+    Q = synth.query_batch(5, pool, ell)
+    qs = [ctx.encrypt(s["keys"], ctx.encode(synth.replicate_query(Q[q], ctx.N // 2), ctx.L, 2.0 ** 40),
+                      synth.int_seed(5, synth.SUB_ENC, q)) for q in range(pool)]
+    slots = serve.slot_count(ctx)
+    srv = serve.Server(ctx, s["keys"], s["coeffs"], d1, n1, slots=slots)
+    out = {"slots": slots, "seconds": seconds, "query_pool": pool}
+    for rate in rates:
+        arr = serve.poisson_trace(rate, seconds, synth.rng(5, synth.SUB_ARRIVAL, int(rate)))
+        kr = synth.rng(5, synth.SUB_KIND, int(rate))
+        kinds = kr.integers(0, 2, size=len(arr))
+        sizes = kr.integers(10, 16, size=len(arr))
+
+        def trace():
+            return [serve.Request(i, float(t), "verify" if kinds[i] else "identify", qs[i % pool],
+                                  dbs[9] if kinds[i] else dbs[int(sizes[i])]) for i, t in enumerate(arr)]
+        srv.batches = []
+        b = srv.run(trace())
+        p = serve.plain(ctx, s["keys"], s["coeffs"], d1, n1, trace())
+        out[f"{rate:g}/s"] = {"batched": b, "plain": p}
+        log(f"served {rate:g}/s: batched p50 {b['latency_ms']['p50']:.1f} ms p99 {b['latency_ms']['p99']:.1f} ms; "
+            f"plain p50 {p['latency_ms']['p50']:.1f} ms p99 {p['latency_ms']['p99']:.1f} ms")
+    return out
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -235,6 +267,9 @@ def main():
     ap.add_argument("--mix", type=int, default=0,
                     help="also run this many batches of 1..64 queries against databases of 2^10..2^15 "
                          "templates, batched and as a plain loop")
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="also serve Poisson traces at 10, 50 and 200 requests/s for this many seconds each, "
+                         "with continuous batching and as a plain loop")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
@@ -348,6 +383,9 @@ def main():
     if args.batch:
         log(f"batched form: {args.batch} queries per batch ...")
         out["batched"] = batched(s, args.batch, max(2, min(args.steps, 5)), 1, args.d1)
+    if args.serve:
+        log(f"served form: {args.serve:g} s per arrival rate ...")
+        out["served"] = served(s, args.serve, args.d1)
     if args.mix:
         log(f"mixed batches: {args.mix} ...")
         out["mixed_batches"] = mixed_batches(s, args.mix, args.d1)

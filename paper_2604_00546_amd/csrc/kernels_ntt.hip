@@ -282,10 +282,10 @@ template <int LE>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     __shared__ u64 tile[BLKS * R];
-    const int s = a.map.storage(blockIdx.y);
+    const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
-    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
+    u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
     const int gb = blockIdx.x * BLKS + blk;
@@ -330,16 +330,16 @@ template <int LE>
 __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     __shared__ u64 tile[BLKS * R];
-    const int s = a.map.storage(blockIdx.y);
+    const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
     const int N = a.N;
-    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
+    u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
     const int gb = blockIdx.x * BLKS + blk;
     u64 *xb = x + (size_t)gb * R;
-    const u64 *xsb = (a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * N : x) + (size_t)gb * R;
+    const u64 *xsb = (a.src ? a.src + blockIdx.y * a.src_poly_stride + (size_t)s * N : x) + (size_t)gb * R;
     u64 *tb = tile + blk * R;
     u64 v[E];
 #pragma unroll
@@ -453,13 +453,15 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     NttLaunch a = make_launch(c, data, map, poly_stride, false, src, src_poly_stride);
     if (c->logN == 16 || c->logN == 12) {
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
-        dim3 g(R / (kThreads / E), nlimbs, npoly);
+        // the row passes walk every polynomial of one limb before the next
+        // limb, so the limb's large-stage twiddles stay in L2
+        dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
             hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-            hipLaunchKernelGGL(k_fwd_rows2<4>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
         } else {
             hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
-            hipLaunchKernelGGL(k_fwd_rows2<3>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
         }
         return;
     }
@@ -477,12 +479,12 @@ void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     NttLaunch a = make_launch(c, data, map, poly_stride, true, src, src_poly_stride);
     if (c->logN == 16 || c->logN == 12) {
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
-        dim3 g(R / (kThreads / E), nlimbs, npoly);
+        dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
-            hipLaunchKernelGGL(k_inv_rows2<4>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_inv_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
             hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
         } else {
-            hipLaunchKernelGGL(k_inv_rows2<3>, g, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(k_inv_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
             hipLaunchKernelGGL(k_inv_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
         }
         return;

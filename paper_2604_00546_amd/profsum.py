@@ -78,6 +78,14 @@ def counters(fpath, wpath, calib_mib):
     print(f"{'kernel':40s} {'dispatches':>10s} {'read MiB/disp':>14s} {'write MiB/disp':>15s}")
     for k, (n, rd, wr) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         print(f"{k[:40]:40s} {n:10d} {rd / n / 1024:14.3f} {wr / n / 1024:15.3f}")
+    # one NTT transform = one column kernel plus one row kernel
+    ntt = [k for k in agg if k.startswith(("k_fwd_", "k_inv_"))]
+    transforms = sum(agg[k][0] for k in ntt if "cols" in k)
+    if transforms:
+        rd = sum(agg[k][1] for k in ntt) * 1024.0
+        wr = sum(agg[k][2] for k in ntt) * 1024.0
+        print(f"NTT per transform (both passes): {transforms} transforms, read {rd / transforms / 2**20:.3f} MiB, "
+              f"write {wr / transforms / 2**20:.3f} MiB, total {(rd + wr) / transforms:.0f} B")
 
 
 def main():

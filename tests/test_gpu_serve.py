@@ -1,0 +1,81 @@
+"""The served form: a request loop with continuous batching over the batched
+calls.  Every request's result is bit-identical to the same request run
+alone through the one-query calls, whatever batch it landed in, and the
+plain one-at-a-time loop gives the same words.
+
+Ring N = 2^12 with the paper-scale modulus chain, 128-d templates, two
+databases (64 and 40 templates), n1 = 8, n2 = 16; eleven requests, half
+verification and half identification, arriving in two bursts into a pool
+of 4 slots (ragged batches).
+"""
+import numpy as np
+import pytest
+
+from paper_2604_00546_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ELL, N1, NR = 128, 8, 11
+ROTS = list(range(1, N1)) + [N1 * j for j in range(1, ELL // N1)]
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2604_00546_amd import fr, serve
+    g = fr.Context(**fr.deep_small_params())
+    keys = g.keygen(synth.int_seed(5, synth.SUB_KEYS), ROTS)
+    wl = synth.make_workload(5, 64, ELL)
+    db_id = g.db_load(wl.templates, ELL, 16, N1, g.L, 2.0 ** 40)
+    db_ver = g.db_load(wl.templates[:40], ELL, 16, N1, g.L, 2.0 ** 40)
+    Q = synth.query_batch(5, NR, ELL)
+    kinds = synth.rng(5, synth.SUB_KIND).integers(0, 2, size=NR)
+    reqs = []
+    for i in range(NR):
+        ct = g.encrypt(keys, g.encode(synth.replicate_query(Q[i], g.N // 2), g.L, 2.0 ** 40),
+                       synth.int_seed(5, synth.SUB_ENC, i))
+        verify = bool(kinds[i])
+        reqs.append(serve.Request(i, 0.0 if i < 7 else 0.05, "verify" if verify else "identify", ct,
+                                  db_ver if verify else db_id, 0))
+    coeffs = fr.cheb_step_coeffs(63, 0.3)
+    return dict(fr=fr, serve=serve, g=g, keys=keys, wl=wl, Q=Q, reqs=reqs, coeffs=coeffs)
+
+
+def _alone(S, r):
+    g, keys = S["g"], S["keys"]
+    baby = [r.query] + g.rotate_hoisted(keys, r.query, range(1, N1))
+    return g.chebyshev_eval(keys, g.bsgs_diag_matvec(keys, baby, r.db, r.group), S["coeffs"], 8)
+
+
+def test_served_results_equal_alone(S):
+    g, serve = S["g"], S["serve"]
+    srv = serve.Server(g, S["keys"], S["coeffs"], 8, N1, slots=4, keep_results=True)
+    stats = srv.run(S["reqs"])
+    assert stats["requests"] == NR
+    assert max(srv.batches) <= 4 and sum(srv.batches) == NR and len(srv.batches) >= 3
+    for r in S["reqs"]:
+        assert r.done >= r.admitted >= r.arrival
+        a = _alone(S, r)
+        assert (r.result.level, r.result.scale) == (a.level, a.scale)
+        assert np.array_equal(g.ct_export(r.result), g.ct_export(a)), f"request {r.rid}"
+    # the plain loop over the same trace
+    plain_res = {}
+    for r in S["reqs"]:
+        plain_res[r.rid] = r.result
+    serve.plain(g, S["keys"], S["coeffs"], 8, N1, S["reqs"], keep_results=True)
+    for r in S["reqs"]:
+        assert np.array_equal(g.ct_export(r.result), g.ct_export(plain_res[r.rid]))
+
+
+def test_served_thresholds(S):
+    g, wl = S["g"], S["wl"]
+    r = S["reqs"][0]
+    y = g.decrypt_decode(S["keys"], _alone(S, r))
+    K = 40 if r.kind == "verify" else 64
+    exact = wl.templates[:K].astype(np.float64) @ S["Q"][0].astype(np.float64)
+    want = np.polynomial.chebyshev.chebval(exact, S["coeffs"])
+    assert np.max(np.abs(y[:K] - want)) <= 2 ** -12
+
+
+def test_slot_count_rule(S):
+    n = S["serve"].slot_count(S["g"])
+    assert 2 <= n <= 64
