@@ -44,10 +44,10 @@ OPS_PER_BUTTERFLY = 30
 # dominant kernel class (largest share of the step's kernel time in the trace)
 ROOFLINE_KERNEL = {"class": "ntt", "bound": "alu"}
 # HBM bytes per NTT launch (one forward or inverse transform of a batch of
-# limbs), from the FETCH_SIZE / WRITE_SIZE counter runs recorded in
-# profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
+# limbs, both passes), from the FETCH_SIZE / WRITE_SIZE counter runs recorded
+# in profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
 # since those counters were taken
-NTT_TRAFFIC_BYTES_PER_LAUNCH = None
+NTT_TRAFFIC_BYTES_PER_LAUNCH = 104627195
 
 
 def log(*a):
