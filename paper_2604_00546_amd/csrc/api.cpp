@@ -145,11 +145,25 @@ int flag_check(fr_ctx *c, const char *what) {
 // D[b][t] (b < batch, t < ndig) = ModUp of digit t of c1[b] (eval domain,
 // c1 polynomials c1_stride words apart) over Q_level U P; D items are
 // ndig * nE * N words apart.
+// items x digits up to which ModUp runs as one conversion launch and one
+// transform over all extended limbs
+static const int kModupMerge = 12;
+
 void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t c1_stride = 0) {
     const int N = c->N, nE = level + 1 + c->nP, ndig = num_digits(c, level);
     const size_t lw = (size_t)(level + 1) * N, dstride = (size_t)ndig * nE * N;
     u64 *X = scratch(c, (size_t)batch * lw);
     frk::ntt_inv(c, X, level + 1, qmap(), batch, lw, c1, c1_stride);
+    if (batch * ndig <= kModupMerge) {
+        // small batches: every digit in one conversion launch and one
+        // transform (which also re-derives the digit's own limbs)
+        frk::modup_all(c, D, X, level, batch, dstride, lw);
+        LimbMap ext{0, INT_MAX, 0, level + 1, c->L + 1};
+        frk::ntt_fwd(c, D, nE, ext, ndig * batch, (size_t)nE * N);
+        return;
+    }
+    // large batches: per digit, transforming only the converted limbs and
+    // copying the digit's own evaluation-form limbs
     for (int t = 0; t < ndig; ++t) {
         u64 *Dt = D + (size_t)t * nE * N;
         const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
@@ -194,6 +208,7 @@ void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out, int ncts = 1) {
     u64 *xt = scratch(c, (size_t)np * N);
     frk::ntt_inv(c, xt, 1, single(l), np, (size_t)N, in + (size_t)l * N, (size_t)(l + 1) * N);
     u64 *Y = scratch(c, (size_t)np * l * N);
+    if (frk::ntt_fwd_rescale(c, Y, l, np, xt, in, (size_t)(l + 1) * N, out, (size_t)l * N)) return;
     frk::rescale_prep(c, Y, xt, l, np, (size_t)l * N, (size_t)N);
     frk::ntt_fwd(c, Y, l, qmap(), np, (size_t)l * N);
     frk::rescale_finish(c, out, in, Y, l, np, (size_t)l * N, (size_t)(l + 1) * N, (size_t)l * N);

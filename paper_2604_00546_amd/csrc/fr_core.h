@@ -242,6 +242,12 @@ namespace frk {
 // src_poly_stride between polynomials) and writes data.
 void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
              const u64 *src = nullptr, size_t src_poly_stride = 0);
+// rescale fused into one forward transform (radix-16 kernels; returns false
+// when the ring has no such kernels): out[p] = (in[p] - NTT(centered(xtop[p])
+// mod q_i)) q_l^-1 for limbs i < l; xtop[p] is the coefficient form of limb l
+// of polynomial p (N words each), tmp holds npoly * l limbs between passes
+bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xtop, const u64 *in, size_t in_stride,
+                     u64 *out, size_t out_stride);
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
              const u64 *src = nullptr, size_t src_poly_stride = 0);
 
@@ -266,6 +272,10 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
                 size_t poly_stride, bool to_mont);
 // fast base conversion of one digit: coefficient-form x[level+1][N] ->
 // D[nE][N] coefficient form on every extended limb outside the digit
+// every digit of `batch` items at once: D[b][t] = [ndig][nE][N] per item
+// (item stride sd), own limbs copied in coefficient form (one forward
+// transform over all nE limbs then completes every digit)
+void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx);
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,
                  size_t sx = 0);
 // U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p]

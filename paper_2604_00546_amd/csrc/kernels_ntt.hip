@@ -27,6 +27,16 @@ struct NttLaunch {
     const u64 *tw, *tw_sh;
     const ulonglong2 *tw2;   // (twiddle, Shoup companion) pairs, same indexing
     const ModConst *mods;
+    // rescale fused into a forward transform (radix-16 kernels only):
+    // pre_top >= 0: the first pass reads src as ONE limb per polynomial and
+    // maps x to the centered residue of x mod q_pre_top in the target limb;
+    // epi_out != nullptr: the last pass writes epi_out = (epi_in - y) qinv
+    // instead of y
+    int pre_top;
+    u64 *epi_out;
+    const u64 *epi_in;
+    size_t epi_out_stride, epi_in_stride;
+    const u64 *qinv, *qinv_sh;
 };
 
 __global__ __launch_bounds__(kThreads) void k_fwd_cols(NttLaunch a) {
@@ -245,10 +255,23 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
     const int col = blockIdx.x * COLS + c;
-    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (size_t)s * a.N : x;
+    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (a.pre_top >= 0 ? 0 : (size_t)s * a.N) : x;
     u64 v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = xs[col + (size_t)(g + E * k) * R];
+    if (a.pre_top >= 0) {  // centered residue of the top limb in this limb
+        const u64 qt = a.mods[a.pre_top].q;
+        const ModConst mc = a.mods[mi];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            if (v[k] > (qt >> 1)) {
+                const u64 neg = reduce64(qt - v[k], mc);
+                v[k] = neg ? mc.q - neg : 0;
+            } else {
+                v[k] = reduce64(v[k], mc);
+            }
+        }
+    }
 #pragma unroll
     for (int st = 0; st < LE; ++st) {
         const int half = E >> (st + 1);
@@ -322,6 +345,16 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
 #pragma unroll
     for (int k = 0; k < E; ++k) tb[rsw<LE>(E * u0 + k, blk)] = v[k];
     __syncthreads();
+    if (a.epi_out) {  // rescale finish: (in - y) q_top^-1
+        const size_t w = (size_t)s * a.N + (size_t)gb * R;
+        const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
+        u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
+        const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            out[u0 + E * k] = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < E; ++k) xb[u0 + E * k] = red8(tb[rsw<LE>(u0 + E * k, blk)], q);
 }
@@ -424,6 +457,8 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
     }
 }
 
+LimbMap qmap_all() { return LimbMap{0, INT_MAX, 0, INT_MAX, 0}; }
+
 NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t poly_stride, bool inverse,
                       const u64 *src, size_t src_poly_stride) {
     NttLaunch a;
@@ -439,6 +474,11 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     a.tw_sh = inverse ? c->d_itw_sh : c->d_tw_sh;
     a.tw2 = reinterpret_cast<const ulonglong2 *>(inverse ? c->d_itw2 : c->d_tw2);
     a.mods = c->d_mod;
+    a.pre_top = -1;
+    a.epi_out = nullptr;
+    a.epi_in = nullptr;
+    a.epi_out_stride = a.epi_in_stride = 0;
+    a.qinv = a.qinv_sh = nullptr;
     return a;
 }
 
@@ -470,6 +510,31 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
     dim3 g1(1 << (lc - lcols), nlimbs, npoly), g2(1 << (lr - lblks), nlimbs, npoly);
     hipLaunchKernelGGL(k_fwd_cols, g1, dim3(kThreads), 0, c->stream, a);
     hipLaunchKernelGGL(k_fwd_rows, g2, dim3(kThreads), 0, c->stream, a);
+}
+
+bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xtop, const u64 *in, size_t in_stride,
+                     u64 *out, size_t out_stride) {
+    if (c->logN != 16 && c->logN != 12) return false;
+    if (l <= 0 || npoly <= 0) return true;
+    ProfScope ps(c, K_NTT, 16.0 * l * npoly * c->N);
+    NttLaunch a = make_launch(c, tmp, qmap_all(), (size_t)l * c->N, false, xtop, (size_t)c->N);
+    a.pre_top = l;
+    a.epi_out = out;
+    a.epi_in = in;
+    a.epi_out_stride = out_stride;
+    a.epi_in_stride = in_stride;
+    a.qinv = c->d_rescale + (size_t)l * (c->L + 1) * 2;
+    a.qinv_sh = a.qinv + (c->L + 1);
+    const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
+    dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
+    if (LE == 4) {
+        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+    } else {
+        hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+    }
+    return true;
 }
 
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,

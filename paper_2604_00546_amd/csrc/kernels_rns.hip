@@ -121,6 +121,45 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
     }
 }
 
+// ModUp of every digit in one launch: grid.z = item * ndig + t.  Digit t of
+// item b fills D[b][t][e] for all e < nE: the converted value outside the
+// digit (as k_modup) and, inside it, the digit's own coefficients x_e, so
+// that one forward transform over all nE limbs gives the extended digit (the
+// transform of x_e is the input limb's evaluation form word for word).
+struct ModupTabs {
+    const u64 *tab[kMaxDigit];
+};
+__global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
+                                                  int level, int pbase, ModupTabs mt, const ModConst *mods, size_t sd,
+                                                  size_t sx) {
+    const int k = blockIdx.x * kT + threadIdx.x;
+    const int t = tfirst + blockIdx.z % nt, b = blockIdx.z / nt;
+    const int lo = t * alpha, nd = min(alpha, level + 1 - lo);
+    D += b * sd + (size_t)t * nE * N;
+    x += b * sx;
+    const u64 *tab = mt.tab[t - tfirst];
+    const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
+    u64 y[kMaxDigit];
+#pragma unroll
+    for (int d = 0; d < kMaxDigit; ++d)
+        if (d < nd) {
+            const u64 xv = x[(size_t)(lo + d) * N + k];
+            if (blockIdx.y == 0) D[(size_t)(lo + d) * N + k] = xv;
+            y[d] = shoup(xv, dinv[d], dinv_sh[d], mods[lo + d].q);
+        }
+    const int ntarget = nE - nd;
+    const int t0 = blockIdx.y * kTargetsPerThread, t1 = min(ntarget, t0 + kTargetsPerThread);
+    for (int te = t0; te < t1; ++te) {
+        const int e = te < lo ? te : te + nd;
+        const int gm = e <= level ? e : pbase + (e - level - 1);
+        u64 al = 0, ah = 0;
+#pragma unroll
+        for (int d = 0; d < kMaxDigit; ++d)
+            if (d < nd) mac128(al, ah, y[d], dhat[(size_t)e * nd + d]);
+        D[(size_t)e * N + k] = redc_any(al, ah, mods[gm]);
+    }
+}
+
 // U{0,1}[e][p] (+)= sum_t D_t[e][src(p)] * ksk_t{b,a}[gm(e)][p]; keys are
 // Montgomery-scaled so one reduction yields the canonical sum.
 __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
@@ -493,6 +532,23 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
     dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, batch);
     hipLaunchKernelGGL(k_modup, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
                        c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx);
+}
+
+void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx) {
+    const int nE = level + 1 + c->nP, ndig = (level + c->alpha) / c->alpha;
+    for (int t0 = 0; t0 < ndig; t0 += kMaxDigit) {
+        const int nt = std::min(kMaxDigit, ndig - t0);
+        ProfScope ps(c, K_MODUP, (double)batch * nt * (level + 1 + c->nP) * 8.0 * c->N);
+        ModupTabs mt{};
+        int maxt = 0;
+        for (int t = t0; t < t0 + nt; ++t) {
+            mt.tab[t - t0] = c->d_modup + c->modup_off[level][t];
+            maxt = std::max(maxt, nE - std::min(c->alpha, level + 1 - t * c->alpha));
+        }
+        dim3 g(c->N / kT, (maxt + kTargetsPerThread - 1) / kTargetsPerThread, nt * batch);
+        hipLaunchKernelGGL(k_modup_all, g, dim3(kT), 0, c->stream, D, x, c->N, t0, nt, c->alpha, nE, level, c->L + 1,
+                           mt, c->d_mod, sd, sx);
+    }
 }
 
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate,
