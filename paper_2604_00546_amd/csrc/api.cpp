@@ -190,14 +190,25 @@ void ks_moddown_prep(fr_ctx *c, const u64 *U, int nblk, int level, u64 *V) {
     frk::ntt_fwd(c, V, level + 1, qmap(), 2 * nblk, (size_t)(level + 1) * N);
 }
 
+// out[b] (ciphertexts [2][level+1][N], polynomials so words apart) (+)=
+// ModDown(U[b]) for b < nblk, U = [nblk][2][nE][N]; the finish runs inside
+// the last pass of the forward transform of the correction
+void ks_moddown_into(fr_ctx *c, const u64 *U, int nblk, int level, u64 *out, size_t so, bool accumulate) {
+    Scope sc(c->arena);
+    const int N = c->N, nE = level + 1 + c->nP, nP = c->nP;
+    const size_t lw = (size_t)(level + 1) * N;
+    u64 *Upc = scratch(c, (size_t)2 * nblk * nP * N);
+    frk::ntt_inv(c, Upc, nP, pmap(c), 2 * nblk, (size_t)nP * N, U + lw, (size_t)nE * N);
+    u64 *V = scratch(c, (size_t)2 * nblk * lw);
+    frk::moddown_fbc(c, V, Upc, level, 2 * nblk);
+    if (frk::ntt_fwd_moddown(c, V, level, 2 * nblk, U, (size_t)nE * N, out, so, accumulate)) return;
+    frk::ntt_fwd(c, V, level + 1, qmap(), 2 * nblk, lw);
+    frk::moddown_finish(c, out, U, V, level, 2 * nblk, so, (size_t)nE * N, lw, accumulate);
+}
+
 // out (ciphertext [2][level+1][N]) (+)= ModDown(U), U = [2][nE][N]
 void ks_moddown(fr_ctx *c, const u64 *U, int level, u64 *out, bool accumulate) {
-    Scope sc(c->arena);
-    const int N = c->N, nE = level + 1 + c->nP;
-    u64 *V = scratch(c, (size_t)2 * (level + 1) * N);
-    ks_moddown_prep(c, U, 1, level, V);
-    frk::moddown_finish(c, out, U, V, level, 2, (size_t)(level + 1) * N, (size_t)nE * N, (size_t)(level + 1) * N,
-                        accumulate);
+    ks_moddown_into(c, U, 1, level, out, (size_t)(level + 1) * c->N, accumulate);
 }
 
 // out = Rescale(in) for ncts consecutive ciphertexts at level l >= 1 (in:
@@ -1157,9 +1168,7 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
                               qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
                 frk::automorph(c, S, R + j * rw, g, l + 1, qn, rw, (size_t)n2 * rw, true);
             }
-            u64 *V = scratch(c, (size_t)qn * rw);
-            ks_moddown_prep(c, U, qn, l, V);
-            frk::moddown_finish(c, S, U, V, l, 2 * qn, lwl, (size_t)nE * N, lwl, true);
+            ks_moddown_into(c, U, qn, l, S, lwl, true);
         }
         if (qn > 1)
             for (int qq = 0; qq < qn; ++qq)
@@ -1467,7 +1476,6 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             u64 *T2 = scratch(c, (size_t)B * lw(lv));
             u64 *Dg = scratch(c, (size_t)B * ndig * nE * N);
             u64 *U = scratch(c, (size_t)B * 2 * nE * N);
-            u64 *V = scratch(c, (size_t)B * cw);
             u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
             std::vector<const u64 *> xa(B), yb(B);
             for (int b = 0; b < B; ++b) {
@@ -1478,8 +1486,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             ks_modup(c, T2, lv, Dg, B, lw(lv));
             frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
                           (size_t)2 * nE * N);
-            ks_moddown_prep(c, U, B, lv, V);
-            frk::moddown_finish(c, T01, U, V, lv, 2 * B, lw(lv), (size_t)nE * N, lw(lv), true);
+            ks_moddown_into(c, U, B, lv, T01, lw(lv), true);
             rescale_dev(c, T01, lv, out, B);
             for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
         }

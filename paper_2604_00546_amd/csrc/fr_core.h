@@ -248,6 +248,13 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
 // of polynomial p (N words each), tmp holds npoly * l limbs between passes
 bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xtop, const u64 *in, size_t in_stride,
                      u64 *out, size_t out_stride);
+// ModDown finish fused into the forward transform of V (the converted
+// correction, coefficient form, npoly polynomials of level+1 limbs):
+// out[p] (+)= (U[p] - NTT(V[p])) P^-1 on limbs 0..level; U and out strides
+// su / so per polynomial.  Returns false when the ring has no radix-16
+// kernels.
+bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U, size_t su, u64 *out, size_t so,
+                     bool accumulate);
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
              const u64 *src = nullptr, size_t src_poly_stride = 0);
 

@@ -31,8 +31,9 @@ struct NttLaunch {
     // pre_top >= 0: the first pass reads src as ONE limb per polynomial and
     // maps x to the centered residue of x mod q_pre_top in the target limb;
     // epi_out != nullptr: the last pass writes epi_out = (epi_in - y) qinv
-    // instead of y
+    // (+ epi_out if epi_acc) instead of y (rescale or ModDown finish)
     int pre_top;
+    int epi_acc;
     u64 *epi_out;
     const u64 *epi_in;
     size_t epi_out_stride, epi_in_stride;
@@ -345,14 +346,17 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
 #pragma unroll
     for (int k = 0; k < E; ++k) tb[rsw<LE>(E * u0 + k, blk)] = v[k];
     __syncthreads();
-    if (a.epi_out) {  // rescale finish: (in - y) q_top^-1
+    if (a.epi_out) {  // rescale / ModDown finish: (in - y) qinv (+ out)
         const size_t w = (size_t)s * a.N + (size_t)gb * R;
         const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
         u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
         const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
 #pragma unroll
-        for (int k = 0; k < E; ++k)
-            out[u0 + E * k] = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+        for (int k = 0; k < E; ++k) {
+            u64 r = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+            if (a.epi_acc) r = addq(r, out[u0 + E * k], q);
+            out[u0 + E * k] = r;
+        }
         return;
     }
 #pragma unroll
@@ -475,6 +479,7 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     a.tw2 = reinterpret_cast<const ulonglong2 *>(inverse ? c->d_itw2 : c->d_tw2);
     a.mods = c->d_mod;
     a.pre_top = -1;
+    a.epi_acc = 0;
     a.epi_out = nullptr;
     a.epi_in = nullptr;
     a.epi_out_stride = a.epi_in_stride = 0;
@@ -527,6 +532,31 @@ bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xto
     a.qinv_sh = a.qinv + (c->L + 1);
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
+    if (LE == 4) {
+        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+    } else {
+        hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+    }
+    return true;
+}
+
+bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U, size_t su, u64 *out, size_t so,
+                     bool accumulate) {
+    if (c->logN != 16 && c->logN != 12) return false;
+    const int nl = level + 1;
+    ProfScope ps(c, K_NTT, 16.0 * nl * npoly * c->N);
+    NttLaunch a = make_launch(c, V, qmap_all(), (size_t)nl * c->N, false, nullptr, 0);
+    a.epi_out = out;
+    a.epi_in = U;
+    a.epi_out_stride = so;
+    a.epi_in_stride = su;
+    a.epi_acc = accumulate;
+    a.qinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;  // P^-1 mod q_i, then its companions
+    a.qinv_sh = a.qinv + (c->L + 1);
+    const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
+    dim3 g(R / (kThreads / E), nl, npoly), gr(R / (kThreads / E), npoly, nl);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
         hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
