@@ -241,3 +241,38 @@ def test_relin_bitexact_deep(deep):
     orr = o.rotate_hoisted(keys[1], oa, [1, 3])
     for a, b in zip(gr, orr):
         _same(g, a, b)
+
+
+# --------------------------------------------------------------------------
+# ragged and degenerate matvec shapes at N = 2^12 (small modulus chain)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("K,ell,B,n1,group", [
+    (300, 100, 20, 8, 0),    # n2 = 13: partial giant-step tile, diagonals past ell
+    (1000, 128, 4, 40, 1),   # n1 > 32: baby steps in two MAC chunks; second of two groups
+    (64, 64, 32, 64, 0),     # the diagonal method: n2 = 1, no giant step
+    (20, 128, 1, 8, 0),      # B = 1: one block per plaintext
+])
+def test_matvec_ragged_shapes_bitexact(F, oracle_mod, K, ell, B, n1, group):
+    p = F.small_params()
+    g, o = F.Context(**p), oracle_mod.Context(**_oparams(p))
+    rots = F.bsgs_rotation_set(ell, n1)
+    seed = synth.int_seed(1, synth.SUB_KEYS, ell + n1)
+    kg, ko = g.keygen(seed, rots), o.keygen(seed, rots)
+    wl = synth.make_workload(1, K, ell, extra=ell + n1)
+    odb = o.db_build(wl.templates, wl.K, ell, B, n1, o.L, 2.0 ** 40)
+    gdb = g.db_import(odb.export_all(), odb.G, ell, B, n1, g.L, 2.0 ** 40)
+    assert gdb.G == odb.G and group < gdb.G
+    opt = o.encode(synth.replicate_query(wl.query, g.N // 2), o.L, 2.0 ** 40)
+    es = synth.int_seed(1, synth.SUB_ENC, ell + n1)
+    gq, oq = g.encrypt(kg, g.pt_import(opt.coeffs(), g.L, 2.0 ** 40), es), o.encrypt(ko, opt, es)
+    gb = [gq] + g.rotate_hoisted(kg, gq, range(1, n1))
+    ob = [oq] + o.rotate_hoisted(ko, oq, range(1, n1))
+    gs = g.bsgs_diag_matvec(kg, gb, gdb, group)
+    os_ = o.bsgs_matvec(ko, ob, odb, group)
+    _same(g, gs, os_)
+    dec = g.decrypt_decode(kg, gs)
+    exact = wl.exact_scores()
+    lo = group * B * ell
+    hi = min(K, lo + B * ell)
+    # slot s of group g holds template g B ell + s (B = 1: the block's ell slots, replicated)
+    assert np.max(np.abs(dec[: hi - lo] - exact[lo:hi])) <= 2 ** -20
