@@ -1162,12 +1162,20 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
             u64 *D = scratch(c, ((size_t)qn * n2 - 1) * dstride);
             u64 *U = scratch(c, (size_t)qn * 2 * nE * N);
             ks_modup(c, R + rw + lwl, l, D, qn * n2 - 1, rw);
+            std::vector<const u64 *> kp(n2 - 1);
+            std::vector<u64> gp(n2 - 1);
             for (int j = 1; j < n2; ++j) {
-                const u64 g = galois_element(N, j * n1);
-                frk::ks_inner(c, U, U + (size_t)nE * N, D + (size_t)(j - 1) * dstride, K->find(g)->data, g, l, j > 1,
-                              qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
-                frk::automorph(c, S, R + j * rw, g, l + 1, qn, rw, (size_t)n2 * rw, true);
+                gp[j - 1] = galois_element(N, j * n1);
+                kp[j - 1] = K->find(gp[j - 1])->data;
             }
+            // all giant-step key inner products summed in one pass per chunk
+            const int chunk = frk::ks_inner_sum_chunk(c, l);
+            for (int j0 = 0; j0 < n2 - 1; j0 += chunk) {
+                const int nj = std::min(chunk, n2 - 1 - j0);
+                frk::ks_inner_sum(c, U, U + (size_t)nE * N, D + (size_t)j0 * dstride, kp.data() + j0, gp.data() + j0,
+                                  nj, dstride, l, j0 > 0, qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
+            }
+            frk::automorph_sum(c, S, R + rw, gp.data(), n2 - 1, l + 1, qn, rw, rw, (size_t)n2 * rw);
             ks_moddown_into(c, U, qn, l, S, lwl, true);
         }
         if (qn > 1)

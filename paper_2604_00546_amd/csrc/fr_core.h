@@ -289,6 +289,16 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
               bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0);
 // ModDown of U (eval domain, P limbs already coefficient form in Upc):
+// giant steps of rotations per key-sum launch at this level (bounded so the
+// 128-bit lazy sums cannot overflow)
+int ks_inner_sum_chunk(const fr_ctx *c, int level);
+// U{0,1} (+)= sum over nj rotations (keys ksk[j], Galois elements g[j]; their
+// digits D + j sdj) of the key inner products, for `batch` items
+void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *const *ksk, const u64 *g, int nj,
+                  size_t sdj, int level, bool accumulate, int batch, size_t sd, size_t su);
+// out[b] += sum_j sigma_{g_j}(in[b][j]) on nlimbs limbs of one polynomial
+void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
+                   size_t sij, size_t sib);
 // v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly);
 // out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)

@@ -193,6 +193,62 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     U1[w] = u1;
 }
 
+// Sum of the key inner products of several rotations (the giant steps of
+// one BSGS product, accumulated in the extended basis before one ModDown):
+// U{0,1}[e][p] (+)= sum_j sum_t D_{j,t}[e][auto_src(p, g_j)] * ksk_{j,t}[gm(e)][p].
+// The 128-bit lazy sum holds nj * ndig <= 64 products below 2^122.
+constexpr int kGiant = 16;
+struct GiantKeys {
+    const u64 *ksk[kGiant];
+    u64 g[kGiant];
+};
+__global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64 *D, GiantKeys gk, int nj, size_t sdj,
+                                                     int N, int logN, int nE, int level, int pbase, int ndig, int nmod,
+                                                     const ModConst *mods, int accumulate, size_t sd, size_t su,
+                                                     int batch) {
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
+    D += item * sd;
+    U0 += item * su;
+    U1 += item * su;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    u64 l0 = 0, h0 = 0, l1 = 0, h1 = 0;
+    for (int jj = 0; jj < nj; ++jj) {
+        const u32 src = auto_src((u32)p, gk.g[jj], logN);
+        const u64 *Dj = D + jj * sdj;
+        const u64 *kj = gk.ksk[jj];
+        for (int t = 0; t < ndig; ++t) {
+            const u64 d = Dj[((size_t)t * nE + e) * N + src];
+            const u64 kb = kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
+            const u64 ka = kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+            mac128(l0, h0, d, kb);
+            mac128(l1, h1, d, ka);
+        }
+    }
+    u64 u0 = redc_any(l0, h0, m), u1 = redc_any(l1, h1, m);
+    const size_t w = (size_t)e * N + p;
+    if (accumulate) {
+        u0 = addq(u0, U0[w], m.q);
+        u1 = addq(u1, U1[w], m.q);
+    }
+    U0[w] = u0;
+    U1[w] = u1;
+}
+
+// out[b][i][k] += sum_j in[b][j][i][auto_src(k, g_j)] (c0 parts of the giant
+// steps; in items sij words apart per j and sib per b, out sob per b)
+__global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, GiantKeys gk, int nj, int N, int logN,
+                                                      size_t sob, size_t sij, size_t sib, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
+    const u64 q = mods[i].q;
+    const u64 *ib = in + b * sib + (size_t)i * N;
+    u64 acc = out[b * sob + (size_t)i * N + k];
+    for (int jj = 0; jj < nj; ++jj) acc = addq(acc, ib[jj * sij + auto_src((u32)k, gk.g[jj], logN)], q);
+    out[b * sob + (size_t)i * N + k] = acc;
+}
+
 // ModDown base conversion P -> Q_level of the P limbs in coefficient form,
 // to the CENTERED residue of u mod P: y_j = [u_j * Phat_j^-1]_{p_j},
 // X = sum_j y_j Phat_j in [0, nP P), e = round(X / P) estimated in FP64 as
@@ -561,6 +617,37 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
     hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
                        c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+}
+
+int ks_inner_sum_chunk(const fr_ctx *c, int level) {
+    const int ndig = (level + c->alpha) / c->alpha;
+    return std::max(1, std::min(kGiant, 64 / ndig));
+}
+
+void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *const *ksk, const u64 *g, int nj,
+                  size_t sdj, int level, bool accumulate, int batch, size_t sd, size_t su) {
+    const int nE = level + 1 + c->nP, ndig = (level + c->alpha) / c->alpha;
+    GiantKeys gk{};
+    for (int j = 0; j < nj; ++j) {
+        gk.ksk[j] = ksk[j];
+        gk.g[j] = g[j];
+    }
+    ProfScope ps(c, K_KS, (batch * ((double)nj * ndig * nE + (accumulate ? 4.0 : 2.0) * nE) + 2.0 * nj * ndig * nE) *
+                              8.0 * c->N);
+    hipLaunchKernelGGL(k_ks_inner_sum, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, nj, sdj,
+                       c->N, c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+}
+
+void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
+                   size_t sij, size_t sib) {
+    for (int j0 = 0; j0 < nj; j0 += kGiant) {
+        const int n = std::min(kGiant, nj - j0);
+        GiantKeys gk{};
+        for (int j = 0; j < n; ++j) gk.g[j] = g[j0 + j];
+        ProfScope ps(c, K_ELEM, (n + 2.0) * nlimbs * nb * 8.0 * c->N);
+        hipLaunchKernelGGL(k_automorph_sum, grid(c, nlimbs, nb), dim3(kT), 0, c->stream, out, in + j0 * sij, gk, n,
+                           c->N, c->logN, sob, sij, sib, c->d_mod);
+    }
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
