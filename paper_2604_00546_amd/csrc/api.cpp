@@ -225,6 +225,30 @@ void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out, int ncts = 1) {
     frk::rescale_finish(c, out, in, Y, l, np, (size_t)l * N, (size_t)(l + 1) * N, (size_t)l * N);
 }
 
+// out (B items [2][l][N]) = Rescale(d + ModDown(U)) for relinearised
+// products at level l >= 1 (d = the tensor's first two polynomials, B items
+// [2][l+1][N]; U = [B][2][nE][N]).  On the radix-16 rings the ModDown and
+// the rescale share one forward transform of l limbs; otherwise they run in
+// sequence (d is then overwritten).
+void relin_rescale_into(fr_ctx *c, u64 *d, const u64 *U, int B, int l, u64 *out) {
+    Scope sc(c->arena);
+    const int N = c->N, nE = l + 1 + c->nP, np = 2 * B;
+    const size_t lw = (size_t)(l + 1) * N;
+    if (c->logN == 16 || c->logN == 12) {
+        u64 *Xu = scratch(c, (size_t)np * nE * N);
+        LimbMap top_and_p{l, INT_MAX, 0, l + 1, c->L + 1};
+        frk::ntt_inv(c, Xu, c->nP + 1, top_and_p, np, (size_t)nE * N, U, (size_t)nE * N);
+        u64 *Xd = scratch(c, (size_t)np * N);
+        frk::ntt_inv(c, Xd, 1, single(l), np, (size_t)N, d + (size_t)l * N, lw);
+        u64 *Z = scratch(c, (size_t)np * l * N);
+        frk::relin_rescale_prep(c, Z, Xu, Xd, l, np, (size_t)l * N, (size_t)nE * N, (size_t)N);
+        frk::ntt_fwd_relin_rescale(c, Z, l, np, U, (size_t)nE * N, d, lw, out, (size_t)l * N);
+        return;
+    }
+    ks_moddown_into(c, U, B, l, d, lw, true);
+    rescale_dev(c, d, l, out, B);
+}
+
 // d = relinearise + rescale of a x b (both at level l) into out at l - 1
 int mul_relin_rescale_dev(fr_ctx *c, const fr_keys *K, const Ct &a, const Ct &b, u64 *out) {
     const KeyEntry *rk = K->find(0);
@@ -238,8 +262,7 @@ int mul_relin_rescale_dev(fr_ctx *c, const fr_keys *K, const Ct &a, const Ct &b,
     ks_modup(c, T3 + 2 * lw, l, D);
     u64 *U = scratch(c, (size_t)2 * nE * N);
     frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false);
-    ks_moddown(c, U, l, T3, true);
-    rescale_dev(c, T3, l, out);
+    relin_rescale_into(c, T3, U, 1, l, out);
     return FR_OK;
 }
 
@@ -1494,8 +1517,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             ks_modup(c, T2, lv, Dg, B, lw(lv));
             frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
                           (size_t)2 * nE * N);
-            ks_moddown_into(c, U, B, lv, T01, lw(lv), true);
-            rescale_dev(c, T01, lv, out, B);
+            relin_rescale_into(c, T01, U, B, lv, out);
             for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
         }
         // --- additions, grouped by level

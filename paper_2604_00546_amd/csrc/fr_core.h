@@ -255,6 +255,11 @@ bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xto
 // kernels.
 bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U, size_t su, u64 *out, size_t so,
                      bool accumulate);
+// last step of a relinearised product merged with its rescale: out[p] =
+// (d[p] + (U[p] - NTT(Z[p])) P^-1) q_l^-1 on limbs 0..l-1 (Z from
+// relin_rescale_prep); false when the ring has no radix-16 kernels
+bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 *U, size_t su, const u64 *d,
+                           size_t sd, u64 *out, size_t so);
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
              const u64 *src = nullptr, size_t src_poly_stride = 0);
 
@@ -299,6 +304,11 @@ void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *co
 // out[b] += sum_j sigma_{g_j}(in[b][j]) on nlimbs limbs of one polynomial
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
                    size_t sij, size_t sib);
+// Z[p][i] (i < level) for the merged ModDown + rescale of relinearised
+// products: Xu holds the coefficient forms of U's limbs level..level+nP at
+// their storage positions, Xd that of d's limb level
+void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, int level, int npoly, size_t sz,
+                        size_t sxu, size_t sxd);
 // v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly);
 // out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)

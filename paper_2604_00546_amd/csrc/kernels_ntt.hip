@@ -34,6 +34,11 @@ struct NttLaunch {
     // (+ epi_out if epi_acc) instead of y (rescale or ModDown finish)
     int pre_top;
     int epi_acc;
+    // epi_in2 != nullptr: epi_out = (epi_in2 + (epi_in - y) qinv) qinv2
+    // (ModDown merged with the rescale of a relinearised product)
+    const u64 *epi_in2;
+    size_t epi_in2_stride;
+    const u64 *qinv2, *qinv2_sh;
     u64 *epi_out;
     const u64 *epi_in;
     size_t epi_out_stride, epi_in_stride;
@@ -351,6 +356,16 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
         u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
         const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
+        if (a.epi_in2) {
+            const u64 *in2 = a.epi_in2 + blockIdx.y * a.epi_in2_stride + w;
+            const u64 q2i = a.qinv2[mi], q2s = a.qinv2_sh[mi];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const u64 r = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+                out[u0 + E * k] = shoup(addq(in2[u0 + E * k], r, q), q2i, q2s, q);
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             u64 r = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
@@ -480,6 +495,9 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     a.mods = c->d_mod;
     a.pre_top = -1;
     a.epi_acc = 0;
+    a.epi_in2 = nullptr;
+    a.epi_in2_stride = 0;
+    a.qinv2 = a.qinv2_sh = nullptr;
     a.epi_out = nullptr;
     a.epi_in = nullptr;
     a.epi_out_stride = a.epi_in_stride = 0;
@@ -557,6 +575,33 @@ bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U
     a.qinv_sh = a.qinv + (c->L + 1);
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), nl, npoly), gr(R / (kThreads / E), npoly, nl);
+    if (LE == 4) {
+        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+    } else {
+        hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+    }
+    return true;
+}
+
+bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 *U, size_t su, const u64 *d,
+                           size_t sd, u64 *out, size_t so) {
+    if (c->logN != 16 && c->logN != 12) return false;
+    ProfScope ps(c, K_NTT, 16.0 * l * npoly * c->N);
+    NttLaunch a = make_launch(c, Z, qmap_all(), (size_t)l * c->N, false, nullptr, 0);
+    a.epi_out = out;
+    a.epi_in = U;
+    a.epi_out_stride = so;
+    a.epi_in_stride = su;
+    a.epi_in2 = d;
+    a.epi_in2_stride = sd;
+    a.qinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;  // P^-1 mod q_i and companions
+    a.qinv_sh = a.qinv + (c->L + 1);
+    a.qinv2 = c->d_rescale + (size_t)l * (c->L + 1) * 2;  // q_l^-1 mod q_i and companions
+    a.qinv2_sh = a.qinv2 + (c->L + 1);
+    const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
+    dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
         hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);

@@ -249,6 +249,53 @@ __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, G
     out[b * sob + (size_t)i * N + k] = acc;
 }
 
+// ModDown merged with the rescale that follows it (relinearised products at
+// level l >= 1).  With FBC_i the ModDown base conversion of the P limbs (as
+// k_moddown_fbc), x = [d_l + P^-1 (U_l - FBC_l)]_{q_l} the coefficient form of
+// the top limb of d + ModDown(U), and c its centered residue, it writes
+// Z_i = FBC_i + [P]_{q_i} [c]_{q_i} for i < l; then
+// (d + ModDown(U) - NTT(c)) q_l^-1 = (d + (U - NTT(Z)) P^-1) q_l^-1 limb by limb.
+// Xu: coefficient forms of U's limbs at storage index (level .. level+nP)
+// in a [nE][N] layout per polynomial; Xd: coefficient form of d's limb l.
+__global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu, const u64 *Xd, int N, int level,
+                                                           int nP, int pbase, int L1, const u64 *tab,
+                                                           const ModConst *mods, size_t sz, size_t sxu, size_t sxd) {
+    const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
+    const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
+    const u64 *pinv = tab + 2 * nP + (size_t)L1 * nP, *pinv_sh = pinv + L1;
+    const u64 *pmod = pinv + 2 * L1;
+    const double *invp = reinterpret_cast<const double *>(pmod + L1);
+    const u64 *xu = Xu + poly * sxu + (size_t)level * N + k;
+    u64 y[kMaxDigit];
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; ++j)
+        if (j < nP) {
+            y[j] = shoup(xu[(size_t)(1 + j) * N], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
+            s = s + (double)y[j] * invp[j];
+        }
+    const u64 e = (u64)rint(s);
+    auto fbc = [&](int i, const ModConst &mi) {
+        u64 al = 0, ah = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; ++j)
+            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
+        return subq(redc_any(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
+    };
+    const ModConst mt = mods[level];
+    const u64 qt = mt.q;
+    const u64 x = addq(Xd[poly * sxd + k], shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt), qt);
+    const bool neg = x > (qt >> 1);
+    const u64 mag = neg ? qt - x : x;
+    const int i0 = blockIdx.y * kTargetsPerThread, i1 = min(level, i0 + kTargetsPerThread);
+    for (int i = i0; i < i1; ++i) {
+        const ModConst mi = mods[i];
+        const u64 r = reduce64(mag, mi);
+        const u64 ci = neg ? (r ? mi.q - r : 0) : r;
+        Z[poly * sz + (size_t)i * N + k] = addq(fbc(i, mi), mulmod(ci, pmod[i], mi), mi.q);
+    }
+}
+
 // ModDown base conversion P -> Q_level of the P limbs in coefficient form,
 // to the CENTERED residue of u mod P: y_j = [u_j * Phat_j^-1]_{p_j},
 // X = sum_j y_j Phat_j in [0, nP P), e = round(X / P) estimated in FP64 as
@@ -648,6 +695,14 @@ void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int n
         hipLaunchKernelGGL(k_automorph_sum, grid(c, nlimbs, nb), dim3(kT), 0, c->stream, out, in + j0 * sij, gk, n,
                            c->N, c->logN, sob, sij, sib, c->d_mod);
     }
+}
+
+void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, int level, int npoly, size_t sz,
+                        size_t sxu, size_t sxd) {
+    ProfScope ps(c, K_MODDOWN, npoly * (2.0 + c->nP + 1.0 * level) * 8.0 * c->N);
+    dim3 g(c->N / kT, (level + kTargetsPerThread - 1) / kTargetsPerThread, npoly);
+    hipLaunchKernelGGL(k_relin_rescale_prep, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
+                       c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd);
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
