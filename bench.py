@@ -213,6 +213,41 @@ def served(s, seconds, d1, rates=(10.0, 50.0, 200.0), pool=64):
     return out
 
 
+def layout_b1(s, K, d1, steps=2):
+    """The same identification with one 512 x 512 block per plaintext (B = 1):
+    K / 512 groups of 512 diagonals, every group scored from the one set of
+    baby steps (the group matvecs run batched), then the Chebyshev threshold
+    on every score ciphertext.  Returns per-query time and scores/s."""
+    import torch
+    ctx, ell, n1 = s["ctx"], s["ell"], s["n1"]
+    db = ctx.db_load(s["wl"].templates[:K], ell, 1, n1, ctx.L, 2.0 ** 40)
+    G = db.G
+    babies = [s["baby"]] * G
+    scores = [ctx.new_ct(ctx.L - 1) for _ in range(G)]
+    chebs = [ctx.new_ct(ctx.L - 1) for _ in range(G)]
+
+    def run():
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, n1), outs=s["baby"][1:])
+        ctx.bsgs_diag_matvec_batch(s["keys"], babies, db, list(range(G)), outs=scores)
+        ctx.chebyshev_eval_batch(s["keys"], scores, s["coeffs"], d1, outs=chebs)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # check: the scores of group 0 and of the last group
+    exact = s["wl"].exact_scores()[:K]
+    err = 0.0
+    for g in (0, G - 1):
+        dec = ctx.decrypt_decode(s["keys"], scores[g])[:ell]
+        err = max(err, float(np.max(np.abs(dec - exact[g * ell:(g + 1) * ell]))))
+    return {"templates": K, "groups": G, "ms_per_query": dt * 1e3, "scores_per_s": K / dt,
+            "diagonal_bytes": G * ell * (ctx.L + 1) * ctx.N * 8, "score_max_abs_err": err}
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -270,6 +305,9 @@ def main():
     ap.add_argument("--serve", type=float, default=0.0,
                     help="also serve Poisson traces at 10, 50 and 200 requests/s for this many seconds each, "
                          "with continuous batching and as a plain loop")
+    ap.add_argument("--b1", type=int, default=0,
+                    help="also run the identification with one block per plaintext (B = 1) for this many "
+                         "templates (a multiple of 512)")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
@@ -386,6 +424,9 @@ def main():
     if args.serve:
         log(f"served form: {args.serve:g} s per arrival rate ...")
         out["served"] = served(s, args.serve, args.d1)
+    if args.b1:
+        log(f"B = 1 layout: {args.b1} templates ...")
+        out["layout_b1"] = layout_b1(s, args.b1, args.d1)
     if args.mix:
         log(f"mixed batches: {args.mix} ...")
         out["mixed_batches"] = mixed_batches(s, args.mix, args.d1)
