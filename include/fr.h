@@ -205,6 +205,16 @@ int fr_chebyshev_eval(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const d
 int fr_chebyshev_eval_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t nq,
                             const double *c, int32_t degree, int32_t d1, fr_ct *out);
 
+/* ---- membership aggregation (Alg. gpu-bsgs-membership, aggregation step;
+ * Alg. membership of the appendix: EvalAddMany then EvalSum over all slots) ----
+ * out = EvalSum(in[0] + ... + in[n-1]): the n inputs (one level and scale,
+ * typically the Chebyshev outputs of every group) are added, then log2(N/2)
+ * doublings x <- x + Rot_{2^i}(x) put the sum of all N/2 slots in every slot
+ * (slot 0 = the number of templates over the threshold).  Needs the rotation
+ * keys 2^i, i < log2(N/2) (FR_ENOKEY otherwise).  out must not alias any
+ * input; out->level = in[0].level. */
+int fr_membership_aggregate(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t n, fr_ct *out);
+
 /* ---- kernel timing hook (for the benchmark's roofline figures) ----
  * While a class is selected, every launch of that kernel class is bracketed
  * by HIP events on the context's stream and its algorithmic HBM bytes (the

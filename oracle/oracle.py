@@ -396,6 +396,18 @@ class Context:
     def rescale(self, ct: Ct) -> Ct:
         return Ct(self, lib().or_rescale(self.ptr, ct.ptr))
 
+    def membership_aggregate(self, keys: Keys, cts) -> Ct:
+        """Aggregation step of Alg. gpu-bsgs-membership (Alg. membership of the
+        appendix: EvalAddMany, then EvalSum over all slots): the group
+        ciphertexts are added in order, then x <- x + Rot_{2^i}(x) for
+        i < log2(N/2), after which every slot holds the sum of all slots."""
+        x = cts[0]
+        for c in cts[1:]:
+            x = self.add(x, c)
+        for i in range(self.logN - 1):
+            x = self.add(x, self.rotate_hoisted(keys, x, [1 << i])[0])
+        return x
+
     def add(self, a: Ct, b: Ct) -> Ct:
         return Ct(self, lib().or_add(self.ptr, a.ptr, b.ptr))
 

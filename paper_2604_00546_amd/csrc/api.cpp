@@ -939,6 +939,43 @@ static int addsub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out, bool su
 extern "C" int fr_add(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, false); }
 extern "C" int fr_sub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, true); }
 
+// Membership aggregation: the group ciphertexts are added, then every slot
+// receives the sum of all N/2 slots through log2(N/2) doublings
+// x <- x + Rot_{2^i}(x), each one key switch.
+extern "C" int fr_membership_aggregate(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t n, fr_ct *out) {
+    CHECK(c && K && in && out && n >= 1, FR_EINVAL, "fr_membership_aggregate: null argument or no input");
+    const int l = in[0].level;
+    for (int i = 0; i < n; ++i) {
+        if (int e = check_ct(c, &in[i], "fr_membership_aggregate")) return e;
+        CHECK(in[i].level == l && in[i].scale == in[0].scale, FR_ELEVEL,
+              "fr_membership_aggregate: inputs differ in level or scale");
+        CHECK(in[i].data != out->data, FR_EINVAL, "fr_membership_aggregate: output aliases an input");
+    }
+    if (int e = check_out(c, out, l, "fr_membership_aggregate")) return e;
+    const int slots_log = c->logN - 1;
+    for (int i = 0; i < slots_log; ++i)
+        CHECK(K->find(galois_element(c->N, 1 << i)), FR_ENOKEY, "fr_membership_aggregate: no key for rotation %d",
+              1 << i);
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t lw = (size_t)(l + 1) * c->N;
+    if (n == 1)
+        FR_HIP(hipMemcpyAsync(out->data, in[0].data, 2 * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+    else
+        frk::add(c, out->data, in[0].data, in[1].data, l + 1, 2, lw, lw, lw, false);
+    for (int i = 2; i < n; ++i) frk::add(c, out->data, out->data, in[i].data, l + 1, 2, lw, lw, lw, false);
+    out->level = l;
+    out->scale = in[0].scale;
+    fr_ct tmp{scratch(c, 2 * lw), l, l, 0.0};
+    for (int i = 0; i < slots_log; ++i) {
+        const int32_t r = 1 << i;
+        if (int e = rotate_hoisted_impl(c, K, out, 1, &r, 1, &tmp)) return e;
+        frk::add(c, out->data, out->data, tmp.data, l + 1, 2, lw, lw, lw, false);
+    }
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
 extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *out) {
     CHECK(c && p && p->data, FR_EINVAL, "fr_mul_plain: null argument");
     if (int e = check_ct(c, a, "fr_mul_plain")) return e;

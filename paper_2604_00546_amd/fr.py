@@ -84,6 +84,7 @@ SIGNATURES = {
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
+    "fr_membership_aggregate": (C.c_int, [_P, _P, _CTP, C.c_int32, _CTP]),
     "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
@@ -146,6 +147,11 @@ def cheb_mult_count(degree: int, d1: int) -> int:
 
 def stream_pool_size(compute_units: int, free_bytes: float, ct_bytes: float) -> int:
     return lib().fr_stream_pool_size(compute_units, free_bytes, ct_bytes)
+
+
+def power_of_two_rotations(N: int) -> List[int]:
+    """Rotation indices 2^i, i < log2(N/2): the keys of the slot-sum doublings."""
+    return [1 << i for i in range(int(N).bit_length() - 2)]
 
 
 def bsgs_rotation_set(ell: int, n1: int) -> List[int]:
@@ -471,6 +477,15 @@ class Context:
         for o, d in zip(outs, oarr):
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs
+
+    def membership_aggregate(self, keys: Keys, cts: Sequence[Ct], out: Ct | None = None) -> Ct:
+        """Sum of the inputs, then the sum of all slots in every slot."""
+        cts = list(cts)
+        if out is None:
+            out = self.new_ct(cts[0].level)
+        ins = (CtDesc * len(cts))(*[x.desc for x in cts])
+        _check(lib().fr_membership_aggregate(self.ptr, keys.ptr, ins, len(cts), out.ref), "fr_membership_aggregate")
+        return out
 
     def chebyshev_eval(self, keys: Keys, ct: Ct, coeffs, d1: int, out: Ct | None = None) -> Ct:
         c = np.ascontiguousarray(coeffs, dtype=np.float64)

@@ -103,7 +103,7 @@ def test_full_size_encoder_within_one(F, gctx, config2):
 def test_identification_2p15(F, gctx):
     g = gctx
     wl = synth.make_workload(3, 2 ** 15, ELL, planted_frac=0.01)
-    rots = F.bsgs_rotation_set(ELL, N1)
+    rots = sorted(set(F.bsgs_rotation_set(ELL, N1)) | set(F.power_of_two_rotations(g.N)))
     keys = g.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
     B = g.N // 2 // ELL
     db = g.db_load(wl.templates, ELL, B, N1, g.L, 2.0 ** 40)
@@ -121,6 +121,11 @@ def test_identification_2p15(F, gctx):
         y = g.decrypt_decode(keys, Y)
         assert np.max(np.abs(y - np.polynomial.chebyshev.chebval(exact, coeffs))) <= 2 ** -12
         assert np.array_equal(np.nonzero(y >= 0.5)[0], wl.planted)
+    # membership: the sum of the polynomial over all 2^15 slots in every slot
+    # (328 planted matches plus the ripple of the degree-63 step elsewhere)
+    count = g.decrypt_decode(keys, g.membership_aggregate(keys, [Y]))
+    want = np.polynomial.chebyshev.chebval(exact, coeffs).sum()
+    assert np.max(np.abs(count - want)) < 0.5
 
 
 @pytest.mark.timeout(600)

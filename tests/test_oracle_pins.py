@@ -528,3 +528,21 @@ def test_homomorphic_chebyshev_within_2m12(deep_ctx, deep_keys, oracle_mod):
         want = np.polynomial.chebyshev.chebval(x, c)
         assert np.max(np.abs(ctx.decrypt_decode(deep_keys, y) - want)) <= 2 ** -12
     assert y.level >= 0
+
+
+def test_membership_aggregate_sums_every_slot(small_ctx):
+    """EvalAddMany + EvalSum (Alg. membership): after the doublings every slot
+    holds the sum over all slots of the summed inputs."""
+    ctx = small_ctx
+    rots = [1 << i for i in range(ctx.logN - 1)]
+    K = ctx.keygen(synth.int_seed(1, synth.SUB_KEYS, 77), rots)
+    rnd = np.random.default_rng(77)
+    h = ctx.N // 2
+    xs = [rnd.uniform(0.0, 1.0 / h, h) for _ in range(3)]
+    cts = [ctx.encrypt(K, ctx.encode(x, ctx.L, 2.0 ** 40), 700 + i) for i, x in enumerate(xs)]
+    y = ctx.decrypt_decode(K, ctx.membership_aggregate(K, cts))
+    want = float(sum(x.sum() for x in xs))
+    assert np.max(np.abs(y - want)) < 2 ** -16
+    # one input, and the slot sum is what a rotation by any amount leaves unchanged
+    y1 = ctx.decrypt_decode(K, ctx.membership_aggregate(K, cts[:1]))
+    assert np.max(np.abs(y1 - xs[0].sum())) < 2 ** -16
