@@ -248,6 +248,88 @@ def layout_b1(s, K, d1, steps=2):
             "diagonal_bytes": G * ell * (ctx.L + 1) * ctx.N * 8, "score_max_abs_err": err}
 
 
+def rotq_vs_bsgs(s, K, d1, steps=2):
+    """Alg. bsgs-precomp's route against BSGS for K templates (G groups at
+    B = 64): the full table of ell query rotations (every baby step rotated
+    by every giant amount, batched), then per group a pure diagonal MAC over
+    plain diagonals; BSGS: the giant-step key switches per group.  Both end
+    with the Chebyshev threshold on every score ciphertext."""
+    import torch
+    from paper_2604_00546_amd import synth
+    ctx, ell, n1, B = s["ctx"], s["ell"], s["n1"], s["B"]
+    wl = synth.make_workload(3, K, ell, planted_frac=0.01)  # the same query as the bench's workload
+    T = wl.templates
+    db_bsgs = ctx.db_load(T, ell, B, n1, ctx.L, 2.0 ** 40)
+    db_plain = ctx.db_load(T, ell, B, ell, ctx.L, 2.0 ** 40)
+    G = db_bsgs.G
+    giant = [n1 * j for j in range(1, ell // n1)]
+    rows = [[ctx.new_ct(ctx.L) for _ in giant] for _ in range(n1)]
+    table = [s["baby"][i] if j == 0 else rows[i][j - 1] for j in range(ell // n1) for i in range(n1)]
+    scores = [ctx.new_ct(ctx.L - 1) for _ in range(G)]
+    chebs = [ctx.new_ct(ctx.L - 1) for _ in range(G)]
+
+    def bsgs():
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, n1), outs=s["baby"][1:])
+        ctx.bsgs_diag_matvec_batch(s["keys"], [s["baby"]] * G, db_bsgs, list(range(G)), outs=scores)
+        ctx.chebyshev_eval_batch(s["keys"], scores, s["coeffs"], d1, outs=chebs)
+
+    def rotq():
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, n1), outs=s["baby"][1:])
+        ctx.rotate_hoisted_batch(s["keys"], s["baby"], giant, outs=rows)
+        ctx.bsgs_diag_matvec_batch(s["keys"], [table] * G, db_plain, list(range(G)), outs=scores)
+        ctx.chebyshev_eval_batch(s["keys"], scores, s["coeffs"], d1, outs=chebs)
+
+    out = {"templates": K, "groups": G}
+    for name, fn in (("bsgs", bsgs), ("rotq_table", rotq)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        dec = ctx.decrypt_decode(s["keys"], scores[G - 1])
+        exact = wl.exact_scores()[(G - 1) * B * ell: K]
+        out[name] = {"ms_per_query": dt * 1e3, "scores_per_s": K / dt,
+                     "score_max_abs_err": float(np.max(np.abs(dec[: len(exact)] - exact)))}
+    return out
+
+
+def diagonal_method(s, d1, steps=2):
+    """HyDia-style diagonal method (n1 = ell, n2 = 1): 511 hoisted rotations
+    of the query and one MAC over the 512 plain diagonals, for the bench's
+    2^15-template database; needs 511 rotation keys (about 29 GB)."""
+    import torch
+    ctx, ell = s["ctx"], s["ell"]
+    fr = s["fr"]
+    from paper_2604_00546_amd import synth
+    t = time.time()
+    keys = ctx.keygen(synth.int_seed(3, synth.SUB_KEYS), list(range(1, ell)))
+    db = ctx.db_load(s["wl"].templates, ell, s["B"], ell, ctx.L, 2.0 ** 40)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t
+    baby = [s["q"]] + [ctx.new_ct(ctx.L) for _ in range(ell - 1)]
+    score, cheb = ctx.new_ct(ctx.L - 1), ctx.new_ct(ctx.L - 1)
+
+    def run():
+        ctx.rotate_hoisted(keys, s["q"], range(1, ell), outs=baby[1:])
+        ctx.bsgs_diag_matvec(keys, baby, db, 0, out=score)
+        ctx.chebyshev_eval(keys, score, s["coeffs"], d1, out=cheb)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    dec = ctx.decrypt_decode(keys, score)
+    err = float(np.max(np.abs(dec - s["wl"].exact_scores())))
+    del keys
+    return {"rotation_keys": ell - 1, "setup_s": setup_s, "ms_per_query": dt * 1e3, "scores_per_s": s["K"] / dt,
+            "score_max_abs_err": err}
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -308,6 +390,9 @@ def main():
     ap.add_argument("--b1", type=int, default=0,
                     help="also run the identification with one block per plaintext (B = 1) for this many "
                          "templates (a multiple of 512)")
+    ap.add_argument("--rotq", type=int, default=0,
+                    help="also compare the full rotation-table route with BSGS for this many templates")
+    ap.add_argument("--dg", action="store_true", help="also time the diagonal method (511 rotation keys)")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
@@ -424,6 +509,12 @@ def main():
     if args.serve:
         log(f"served form: {args.serve:g} s per arrival rate ...")
         out["served"] = served(s, args.serve, args.d1)
+    if args.rotq:
+        log(f"rotation-table route vs BSGS: {args.rotq} templates ...")
+        out["rotq_vs_bsgs"] = rotq_vs_bsgs(s, args.rotq, args.d1)
+    if args.dg:
+        log("diagonal method ...")
+        out["diagonal_method"] = diagonal_method(s, args.d1)
     if args.b1:
         log(f"B = 1 layout: {args.b1} templates ...")
         out["layout_b1"] = layout_b1(s, args.b1, args.d1)

@@ -736,10 +736,10 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
                        qinv_sh, c->d_mod, so, si, sy);
 }
 
-void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
-              int ell, int db_level, int level, int baby_level) {
+template <int NJ>
+static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1,
+                        const u64 *const *diag, int ell, int db_level, int level, int baby_level) {
     const int n2 = (ell + n1 - 1) / n1;
-    constexpr int NJ = 16;
     for (int q0 = 0; q0 < nq; q0 += kMacQ) {
         const int qn = std::min(kMacQ, nq - q0);
         int ngroups = 0;  // distinct diagonal groups read by this launch
@@ -768,6 +768,22 @@ void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq
             }
         }
     }
+}
+
+// giant steps per thread: 16, or the smallest power of two covering n2
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
+              int ell, int db_level, int level, int baby_level) {
+    const int n2 = (ell + n1 - 1) / n1;
+    if (n2 > 8)
+        bsgs_mac_nj<16>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+    else if (n2 > 4)
+        bsgs_mac_nj<8>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+    else if (n2 > 2)
+        bsgs_mac_nj<4>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+    else if (n2 > 1)
+        bsgs_mac_nj<2>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+    else
+        bsgs_mac_nj<1>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
 }
 
 void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,

@@ -154,3 +154,24 @@ def test_batch_rejects_mixed_levels(B, scores):
     low = g.rescale(scores[0])
     with pytest.raises(B["fr"].FrError):
         g.chebyshev_eval_batch(B["kg"], [scores[1], low], B["fr"].cheb_step_coeffs(63, 0.3), 8)
+
+
+def test_rotq_table_route(B, babies):
+    """The full rotation table of Alg. bsgs-precomp: every baby step rotated
+    by every giant amount (one batched hoisted call), then each group is a
+    pure diagonal MAC over ell rotations and plain (not pre-rotated)
+    diagonals.  Bit-exact against the oracle's same composition, scores
+    within 2^-20."""
+    g, o, wl = B["g"], B["o"], B["wl"]
+    giant = [N1 * j for j in range(1, ELL // N1)]
+    rows = g.rotate_hoisted_batch(B["kg"], babies[0], giant)   # rows[i][j-1] = Rot_{j n1}(baby_i)
+    table = [babies[0][i] if j == 0 else rows[i][j - 1] for j in range(ELL // N1) for i in range(N1)]
+    odm = o.db_build(wl.templates, wl.K, ELL, 16, ELL, o.L, 2.0 ** 40)
+    gdm = g.db_import(odm.export_all(), odm.G, ELL, 16, ELL, g.L, 2.0 ** 40)
+    gs = g.bsgs_diag_matvec(B["kg"], table, gdm, 0)
+    ob = [B["oq"][0]] + o.rotate_hoisted(B["ko"], B["oq"][0], range(1, N1))
+    orows = [o.rotate_hoisted(B["ko"], ob[i], giant) for i in range(N1)]
+    otable = [ob[i] if j == 0 else orows[i][j - 1] for j in range(ELL // N1) for i in range(N1)]
+    _same_oracle(g, gs, o.bsgs_matvec(B["ko"], otable, odm, 0))
+    exact = wl.templates.astype(np.float64) @ B["Q"][0].astype(np.float64)
+    assert np.max(np.abs(g.decrypt_decode(B["kg"], gs)[: wl.K] - exact)) <= 2 ** -20
