@@ -1084,6 +1084,47 @@ or_ct *or_drop_to(const or_ctx *c, const or_ct *a, int level) {
 
 /* ct x ct (§3.2 multiplication): tensor (a0b0, a0b1 + a1b0, a1b1), then
  * relinearise d2 with the key for s^2, then rescale.  Scale a.s * b.s / q_l. */
+/* Encrypted-database product (§3.3.1 encrypts the diagonal rows; §3.4.1's
+ * deferred relinearisation): the tensor products (a0 b0, a0 b1 + a1 b0,
+ * a1 b1) of n ciphertext pairs are summed as a degree-2 ciphertext, which is
+ * relinearised once with the s^2 key and rescaled. */
+or_ct *or_tensor_sum_relin_rescale(const or_ctx *c, const or_keys *K, const or_ct *const *a, const or_ct *const *b,
+                                   int n) {
+    if (n < 1) { set_err("or_tensor_sum: no pairs"); return NULL; }
+    for (int t = 0; t < n; t++)
+        if (!same_shape(a[t], a[0]) || !same_shape(b[t], a[0])) { set_err("or_tensor_sum: level mismatch"); return NULL; }
+    const or_ksk *rk = find_ksk(K, 0);
+    if (!rk) { set_err("or_tensor_sum: missing relinearisation key"); return NULL; }
+    int N = c->N, l = a[0]->level, nE = l + 1 + c->nP;
+    or_ct *y = ct_alloc(c, l, a[0]->scale * b[0]->scale);
+    uint64_t *d2 = calloc((size_t)(l + 1) * N, 8);
+    #pragma omp parallel for
+    for (int i = 0; i <= l; i++) {
+        uint64_t q = c->mod[i];
+        uint64_t *t = malloc(8 * (size_t)N);
+        uint64_t *y0 = CT0(c, y, i), *y1 = CT1(c, y, i), *z2 = d2 + (size_t)i * N;
+        for (int k = 0; k < N; k++) y0[k] = y1[k] = 0;
+        for (int p = 0; p < n; p++) {
+            or_polymul(c, i, CT0(c, a[p], i), CT0(c, b[p], i), t);
+            for (int k = 0; k < N; k++) y0[k] = addmod(y0[k], t[k], q);
+            or_polymul(c, i, CT0(c, a[p], i), CT1(c, b[p], i), t);
+            for (int k = 0; k < N; k++) y1[k] = addmod(y1[k], t[k], q);
+            or_polymul(c, i, CT1(c, a[p], i), CT0(c, b[p], i), t);
+            for (int k = 0; k < N; k++) y1[k] = addmod(y1[k], t[k], q);
+            or_polymul(c, i, CT1(c, a[p], i), CT1(c, b[p], i), t);
+            for (int k = 0; k < N; k++) z2[k] = addmod(z2[k], t[k], q);
+        }
+        free(t);
+    }
+    uint64_t *U0 = calloc((size_t)nE * N, 8), *U1 = calloc((size_t)nE * N, 8);
+    ks_accumulate(c, l, d2, 1, rk, U0, U1);
+    ks_finish(c, l, U0, U1, CT0(c, y, 0), CT1(c, y, 0));
+    free(U0); free(U1); free(d2);
+    or_ct *z = or_rescale(c, y);
+    or_ct_free(y);
+    return z;
+}
+
 or_ct *or_mul_relin_rescale(const or_ctx *c, const or_keys *K, const or_ct *a, const or_ct *b) {
     if (!same_shape(a, b)) { set_err("or_mul_relin: level mismatch"); return NULL; }
     const or_ksk *rk = find_ksk(K, 0);

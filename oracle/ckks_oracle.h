@@ -110,6 +110,9 @@ or_ct *or_sub(const or_ctx *ctx, const or_ct *a, const or_ct *b);
 or_ct *or_mul_plain(const or_ctx *ctx, const or_ct *a, const or_pt *p);
 /* tensor, relinearise with the s^2 key, then rescale */
 or_ct *or_mul_relin_rescale(const or_ctx *ctx, const or_keys *k, const or_ct *a, const or_ct *b);
+/* sum of the tensor products of n pairs, relinearised once, rescaled */
+or_ct *or_tensor_sum_relin_rescale(const or_ctx *ctx, const or_keys *k, const or_ct *const *a,
+                                   const or_ct *const *b, int n);
 /* multiply every limb by the signed integer kc (no rescale, scale *= kc) */
 or_ct *or_mul_int(const or_ctx *ctx, const or_ct *a, int64_t kc);
 /* add round(c * a->scale) to the constant coefficient of c0 */

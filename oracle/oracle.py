@@ -86,6 +86,7 @@ def lib():
         "or_sub": (_CT, [_P, _CT, _CT]),
         "or_mul_plain": (_CT, [_P, _CT, _PT]),
         "or_mul_relin_rescale": (_CT, [_P, _P, _CT, _CT]),
+        "or_tensor_sum_relin_rescale": (_CT, [_P, _P, C.POINTER(_CT), C.POINTER(_CT), C.c_int]),
         "or_mul_int": (_CT, [_P, _CT, C.c_int64]),
         "or_add_const": (_CT, [_P, _CT, C.c_double]),
         "or_drop_to": (_CT, [_P, _CT, C.c_int]),
@@ -419,6 +420,17 @@ class Context:
 
     def mul_relin_rescale(self, keys: Keys, a: Ct, b: Ct) -> Ct:
         return Ct(self, lib().or_mul_relin_rescale(self.ptr, keys.ptr, a.ptr, b.ptr))
+
+    def tensor_sum_relin_rescale(self, keys: Keys, a, b) -> Ct:
+        """Sum of the tensor products of the pairs (a[k], b[k]), one
+        relinearisation, rescale (the encrypted-database product)."""
+        n = len(a)
+        pa = (_CT * n)(*[x.ptr for x in a])
+        pb = (_CT * n)(*[x.ptr for x in b])
+        r = lib().or_tensor_sum_relin_rescale(self.ptr, keys.ptr, pa, pb, n)
+        if not r:
+            _err("tensor_sum_relin_rescale")
+        return Ct(self, r)
 
     def mul_int(self, a: Ct, k: int) -> Ct:
         return Ct(self, lib().or_mul_int(self.ptr, a.ptr, k))

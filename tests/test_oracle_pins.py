@@ -546,3 +546,22 @@ def test_membership_aggregate_sums_every_slot(small_ctx):
     # one input, and the slot sum is what a rotation by any amount leaves unchanged
     y1 = ctx.decrypt_decode(K, ctx.membership_aggregate(K, cts[:1]))
     assert np.max(np.abs(y1 - xs[0].sum())) < 2 ** -16
+
+
+def test_tensor_sum_relin_rescale(deep_ctx, deep_keys):
+    """Encrypted-database product: one pair gives the relinearised product's
+    words exactly; several pairs decrypt to the slot-wise sum of products."""
+    ctx, K = deep_ctx, deep_keys
+    rnd = np.random.default_rng(91)
+    h = ctx.N // 2
+    xs = [rnd.uniform(-1, 1, h) for _ in range(3)]
+    ys = [rnd.uniform(-1, 1, h) for _ in range(3)]
+    a = [ctx.encrypt(K, ctx.encode(x, 5, 2.0 ** 40), 910 + i) for i, x in enumerate(xs)]
+    b = [ctx.encrypt(K, ctx.encode(y, 5, 2.0 ** 40), 920 + i) for i, y in enumerate(ys)]
+    one = ctx.tensor_sum_relin_rescale(K, a[:1], b[:1])
+    ref = ctx.mul_relin_rescale(K, a[0], b[0])
+    assert (one.level, one.scale) == (ref.level, ref.scale)
+    assert np.array_equal(one.coeffs(), ref.coeffs())
+    z = ctx.decrypt_decode(K, ctx.tensor_sum_relin_rescale(K, a, b))
+    want = sum(x * y for x, y in zip(xs, ys))
+    assert np.max(np.abs(z - want)) < 2 ** -20
