@@ -295,6 +295,44 @@ def rotq_vs_bsgs(s, K, d1, steps=2):
     return out
 
 
+def encrypted_db(s, d1, steps=2):
+    """The paper's setting: the 512 diagonals of the 2^15-template database
+    encrypted, the group score Rescale(Relin(sum_d rot_d(q) (x) Enc(diag_d)))
+    over the full rotation table (one relinearisation per group), then the
+    Chebyshev threshold."""
+    import torch
+    from paper_2604_00546_amd import synth
+    ctx, ell, n1 = s["ctx"], s["ell"], s["n1"]
+    t = time.time()
+    plain = ctx.db_load(s["wl"].templates, ell, s["B"], ell, ctx.L, 2.0 ** 40)
+    ediag = [ctx.encrypt(s["keys"], ctx.pt_import(plain.export(0, d), ctx.L, 2.0 ** 40),
+                         synth.int_seed(3, synth.SUB_ENC, 1000 + d)) for d in range(ell)]
+    del plain
+    torch.cuda.synchronize()
+    setup_s = time.time() - t
+    giant = [n1 * j for j in range(1, ell // n1)]
+    rows = [[ctx.new_ct(ctx.L) for _ in giant] for _ in range(n1)]
+    table = [s["baby"][i] if j == 0 else rows[i][j - 1] for j in range(ell // n1) for i in range(n1)]
+    score, cheb = ctx.new_ct(ctx.L - 1), ctx.new_ct(ctx.L - 1)
+
+    def run():
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, n1), outs=s["baby"][1:])
+        ctx.rotate_hoisted_batch(s["keys"], s["baby"], giant, outs=rows)
+        ctx.tensor_sum_relin_rescale(s["keys"], table, ediag, out=score)
+        ctx.chebyshev_eval(s["keys"], score, s["coeffs"], d1, out=cheb)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    err = float(np.max(np.abs(ctx.decrypt_decode(s["keys"], score) - s["wl"].exact_scores())))
+    return {"encrypted_diagonals": ell, "setup_s": setup_s, "ms_per_query": dt * 1e3, "scores_per_s": s["K"] / dt,
+            "score_max_abs_err": err}
+
+
 def diagonal_method(s, d1, steps=2):
     """HyDia-style diagonal method (n1 = ell, n2 = 1): 511 hoisted rotations
     of the query and one MAC over the 512 plain diagonals, for the bench's
@@ -393,6 +431,7 @@ def main():
     ap.add_argument("--rotq", type=int, default=0,
                     help="also compare the full rotation-table route with BSGS for this many templates")
     ap.add_argument("--dg", action="store_true", help="also time the diagonal method (511 rotation keys)")
+    ap.add_argument("--edb", action="store_true", help="also time the encrypted-database route")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
@@ -512,6 +551,9 @@ def main():
     if args.rotq:
         log(f"rotation-table route vs BSGS: {args.rotq} templates ...")
         out["rotq_vs_bsgs"] = rotq_vs_bsgs(s, args.rotq, args.d1)
+    if args.edb:
+        log("encrypted database ...")
+        out["encrypted_db"] = encrypted_db(s, args.d1)
     if args.dg:
         log("diagonal method ...")
         out["diagonal_method"] = diagonal_method(s, args.d1)

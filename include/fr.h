@@ -205,6 +205,18 @@ int fr_chebyshev_eval(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const d
 int fr_chebyshev_eval_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t nq,
                             const double *c, int32_t degree, int32_t d1, fr_ct *out);
 
+/* ---- encrypted-database product (§3.3.1 encrypts the diagonal rows; the
+ * relinearisation is deferred to one per sum, §3.4.1) ----
+ * out = Rescale(Relin(sum_k a[k] (x) b[k])): the tensor products (a0 b0,
+ * a0 b1 + a1 b0, a1 b1) of the n pairs are summed as one degree-2
+ * ciphertext, relinearised once with the s^2 key and rescaled.  With a[k] the
+ * query rotations and b[k] the encrypted diagonals of a group this is the
+ * group's score ciphertext.  All 2n inputs at one level >= 1 and every
+ * product at one scale; out->level = level - 1.  FR_ENOKEY without the
+ * relinearisation key. */
+int fr_tensor_sum_relin_rescale(fr_ctx *ctx, const fr_keys *keys, const fr_ct *a, const fr_ct *b, int32_t n,
+                                fr_ct *out);
+
 /* ---- membership aggregation (Alg. gpu-bsgs-membership, aggregation step;
  * Alg. membership of the appendix: EvalAddMany then EvalSum over all slots) ----
  * out = EvalSum(in[0] + ... + in[n-1]): the n inputs (one level and scale,

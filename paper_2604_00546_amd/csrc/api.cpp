@@ -939,6 +939,45 @@ static int addsub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out, bool su
 extern "C" int fr_add(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, false); }
 extern "C" int fr_sub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { return addsub(c, a, b, out, true); }
 
+// Encrypted-database product: Rescale(Relin(sum_k a[k] (x) b[k])), the
+// degree-2 sum relinearised once.
+extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, int32_t n,
+                                           fr_ct *out) {
+    CHECK(c && K && a && b && out && n >= 1, FR_EINVAL, "fr_tensor_sum_relin_rescale: null argument or no pair");
+    const int l = a[0].level;
+    for (int k = 0; k < n; ++k) {
+        if (int e = check_ct(c, &a[k], "fr_tensor_sum_relin_rescale")) return e;
+        if (int e = check_ct(c, &b[k], "fr_tensor_sum_relin_rescale")) return e;
+        CHECK(a[k].level == l && b[k].level == l, FR_ELEVEL, "fr_tensor_sum_relin_rescale: level mismatch");
+        CHECK(a[k].scale * b[k].scale == a[0].scale * b[0].scale, FR_ELEVEL,
+              "fr_tensor_sum_relin_rescale: the products differ in scale");
+    }
+    CHECK(l >= 1, FR_ELEVEL, "fr_tensor_sum_relin_rescale: no level left");
+    if (int e = check_out(c, out, l - 1, "fr_tensor_sum_relin_rescale")) return e;
+    const KeyEntry *rk = K->find(0);
+    CHECK(rk, FR_ENOKEY, "fr_tensor_sum_relin_rescale: relinearisation key missing");
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int N = c->N, nE = l + 1 + c->nP;
+    const size_t lw = (size_t)(l + 1) * N;
+    std::vector<const u64 *> pa(n), pb(n);
+    for (int k = 0; k < n; ++k) {
+        pa[k] = a[k].data;
+        pb[k] = b[k].data;
+    }
+    u64 *T01 = scratch(c, 2 * lw), *T2 = scratch(c, lw);
+    frk::tensor_sum(c, T01, T2, l + 1, n, pa.data(), pb.data());
+    u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
+    ks_modup(c, T2, l, D);
+    u64 *U = scratch(c, (size_t)2 * nE * N);
+    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false);
+    relin_rescale_into(c, T01, U, 1, l, out->data);
+    FR_HIP(hipGetLastError());
+    out->level = l - 1;
+    out->scale = (a[0].scale * b[0].scale) / (double)c->mod[l];
+    return FR_OK;
+}
+
 // Membership aggregation: the group ciphertexts are added, then every slot
 // receives the sum of all N/2 slots through log2(N/2) doublings
 // x <- x + Rot_{2^i}(x), each one key switch.

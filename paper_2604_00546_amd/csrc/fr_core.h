@@ -295,6 +295,9 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
               bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0);
 // ModDown of U (eval domain, P limbs already coefficient form in Upc):
 // giant steps of rotations per key-sum launch at this level (bounded so the
+// t01 = (sum a0 b0, sum a0 b1 + a1 b0), t2 = sum a1 b1 over n ciphertext
+// pairs (nl limbs per polynomial; t01 = [2][nl][N], t2 = [nl][N])
+void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *const *a, const u64 *const *b);
 // 128-bit lazy sums cannot overflow)
 int ks_inner_sum_chunk(const fr_ctx *c, int level);
 // U{0,1} (+)= sum over nj rotations (keys ksk[j], Galois elements g[j]; their

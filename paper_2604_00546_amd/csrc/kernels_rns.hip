@@ -193,6 +193,39 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     U1[w] = u1;
 }
 
+// Summed tensor products of ciphertext pairs (encrypted-database product):
+// t01 (+)= (sum a0 b0, sum a0 b1 + a1 b0), t2 (+)= sum a1 b1 over up to
+// kPairs pairs per launch, each sum a 128-bit lazy accumulation of at most
+// 2 kPairs = 64 products below 2^122, reduced once.
+constexpr int kPairs = 32;
+struct PairPtrs {
+    const u64 *a[kPairs];
+    const u64 *b[kPairs];
+};
+__global__ __launch_bounds__(kT) void k_tensor_sum(u64 *t01, u64 *t2, PairPtrs pp, int np, int nl, int N,
+                                                   const ModConst *mods, int accumulate) {
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y;
+    const ModConst m = mods[i];
+    const size_t lw = (size_t)nl * N, w = (size_t)i * N + k;
+    u64 l0 = 0, h0 = 0, l1 = 0, h1 = 0, l2 = 0, h2 = 0;
+    for (int p = 0; p < np; ++p) {
+        const u64 x0 = pp.a[p][w], x1 = pp.a[p][lw + w], y0 = pp.b[p][w], y1 = pp.b[p][lw + w];
+        mac128(l0, h0, x0, y0);
+        mac128(l1, h1, x0, y1);
+        mac128(l1, h1, x1, y0);
+        mac128(l2, h2, x1, y1);
+    }
+    u64 r0 = reduce128(l0, h0, m), r1 = reduce128(l1, h1, m), r2 = reduce128(l2, h2, m);
+    if (accumulate) {
+        r0 = addq(r0, t01[w], m.q);
+        r1 = addq(r1, t01[lw + w], m.q);
+        r2 = addq(r2, t2[w], m.q);
+    }
+    t01[w] = r0;
+    t01[lw + w] = r1;
+    t2[w] = r2;
+}
+
 // Sum of the key inner products of several rotations (the giant steps of
 // one BSGS product, accumulated in the extended basis before one ModDown):
 // U{0,1}[e][p] (+)= sum_j sum_t D_{j,t}[e][auto_src(p, g_j)] * ksk_{j,t}[gm(e)][p].
@@ -664,6 +697,20 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
     hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
                        c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+}
+
+void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *const *a, const u64 *const *b) {
+    for (int p0 = 0; p0 < n; p0 += kPairs) {
+        const int np = std::min(kPairs, n - p0);
+        PairPtrs pp{};
+        for (int p = 0; p < np; ++p) {
+            pp.a[p] = a[p0 + p];
+            pp.b[p] = b[p0 + p];
+        }
+        ProfScope ps(c, K_TENSOR, (4.0 * np + (p0 > 0 ? 6.0 : 3.0)) * nl * 8.0 * c->N);
+        hipLaunchKernelGGL(k_tensor_sum, grid(c, nl, 1), dim3(kT), 0, c->stream, t01, t2, pp, np, nl, c->N, c->d_mod,
+                           (int)(p0 > 0));
+    }
 }
 
 int ks_inner_sum_chunk(const fr_ctx *c, int level) {

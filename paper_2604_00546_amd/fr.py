@@ -85,6 +85,7 @@ SIGNATURES = {
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
     "fr_membership_aggregate": (C.c_int, [_P, _P, _CTP, C.c_int32, _CTP]),
+    "fr_tensor_sum_relin_rescale": (C.c_int, [_P, _P, _CTP, _CTP, C.c_int32, _CTP]),
     "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
@@ -477,6 +478,17 @@ class Context:
         for o, d in zip(outs, oarr):
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs
+
+    def tensor_sum_relin_rescale(self, keys: Keys, a: Sequence[Ct], b: Sequence[Ct], out: Ct | None = None) -> Ct:
+        """Rescale(Relin(sum_k a[k] (x) b[k])): the encrypted-database product."""
+        a, b = list(a), list(b)
+        if out is None:
+            out = self.new_ct(max(a[0].level - 1, 0))
+        pa = (CtDesc * len(a))(*[x.desc for x in a])
+        pb = (CtDesc * len(b))(*[x.desc for x in b])
+        _check(lib().fr_tensor_sum_relin_rescale(self.ptr, keys.ptr, pa, pb, len(a), out.ref),
+               "fr_tensor_sum_relin_rescale")
+        return out
 
     def membership_aggregate(self, keys: Keys, cts: Sequence[Ct], out: Ct | None = None) -> Ct:
         """Sum of the inputs, then the sum of all slots in every slot."""

@@ -175,3 +175,28 @@ def test_rotq_table_route(B, babies):
     _same_oracle(g, gs, o.bsgs_matvec(B["ko"], otable, odm, 0))
     exact = wl.templates.astype(np.float64) @ B["Q"][0].astype(np.float64)
     assert np.max(np.abs(g.decrypt_decode(B["kg"], gs)[: wl.K] - exact)) <= 2 ** -20
+
+
+def test_encrypted_database_route(B, babies):
+    """Encrypted diagonals (the paper's setting): the group score is
+    Rescale(Relin(sum_d rot_d(q) (x) Enc(diag_d))) with one relinearisation
+    per group, over the full rotation table.  Bit-exact against the oracle,
+    scores within 2^-20."""
+    g, o, wl = B["g"], B["o"], B["wl"]
+    giant = [N1 * j for j in range(1, ELL // N1)]
+    rows = g.rotate_hoisted_batch(B["kg"], babies[0], giant)
+    table = [babies[0][i] if j == 0 else rows[i][j - 1] for j in range(ELL // N1) for i in range(N1)]
+    odm = o.db_build(wl.templates, wl.K, ELL, 16, ELL, o.L, 2.0 ** 40)
+    gdiag, odiag = [], []
+    for d in range(ELL):
+        coeffs = odm.export(0, d)
+        es = synth.int_seed(4, synth.SUB_ENC, 1000 + d)
+        gdiag.append(g.encrypt(B["kg"], g.pt_import(coeffs, g.L, 2.0 ** 40), es))
+        odiag.append(o.encrypt(B["ko"], o.pt_import(coeffs, o.L, 2.0 ** 40), es))
+    gs = g.tensor_sum_relin_rescale(B["kg"], table, gdiag)
+    ob = [B["oq"][0]] + o.rotate_hoisted(B["ko"], B["oq"][0], range(1, N1))
+    orows = [o.rotate_hoisted(B["ko"], ob[i], giant) for i in range(N1)]
+    otable = [ob[i] if j == 0 else orows[i][j - 1] for j in range(ELL // N1) for i in range(N1)]
+    _same_oracle(g, gs, o.tensor_sum_relin_rescale(B["ko"], otable, odiag))
+    exact = wl.templates.astype(np.float64) @ B["Q"][0].astype(np.float64)
+    assert np.max(np.abs(g.decrypt_decode(B["kg"], gs)[: wl.K] - exact)) <= 2 ** -20
