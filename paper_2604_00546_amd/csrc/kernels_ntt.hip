@@ -213,21 +213,32 @@ __device__ __forceinline__ u64 shoup_lazy4(u64 a, u64 w, u64 wp, u64 q) {
     return a * w - h * q;
 }
 
-// inputs and outputs in [0, 8q)
+// Forward butterfly.  Large primes: inputs and outputs in [0, 8q), x
+// reduced below 4q first.  Small primes (q < 2^46, SMALL): no reduction at
+// all, the bound grows by 4q per stage (at most 65q after 16 stages).
+template <bool SMALL>
 __device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4) {
-    u64 x = X >= q4 ? X - q4 : X;
+    u64 x = X;
+    if (!SMALL) x = X >= q4 ? X - q4 : X;
     const u64 t = shoup_lazy4(Y, w, wp, q);
     X = x + t;
     Y = x - t + q4;
 }
-// inputs and outputs in [0, 4q)
-__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4) {
+// Inverse butterfly.  Large primes: inputs and outputs in [0, 4q).  Small
+// primes: the sum is not reduced and M (a multiple of q at least the input
+// bound) keeps the difference positive; the bound doubles per stage (below
+// q 2^17 after 16 stages).
+template <bool SMALL>
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4, u64 M) {
     u64 s = X + Y;
-    s = s >= q4 ? s - q4 : s;
-    const u64 d = X - Y + q4;
+    if (!SMALL) s = s >= q4 ? s - q4 : s;
+    const u64 d = X - Y + (SMALL ? M : q4);
     X = s;
     Y = shoup_lazy4(d, w, wp, q);
 }
+// primes below this take the reduction-free butterflies
+constexpr u64 kSmallQ = 1ull << 46;
+
 // LDS layouts of the transposes.  A row tile of R = E^2 words is read both
 // as i = u + E k and as i = E u + k (u the lane's index); word i = E r + c of
 // the tile of sub-transform `blk` is stored at E (r ^ blk mod E) + (c ^ r),
@@ -249,11 +260,15 @@ __device__ __forceinline__ u64 red8(u64 x, u64 q) {
     x = x >= 2 * q ? x - 2 * q : x;
     return x >= q ? x - q : x;
 }
+// canonical forward output: [0, 8q) (large) or [0, 65q) (small)
+template <bool SMALL>
+__device__ __forceinline__ u64 fwd_final(u64 x, const ModConst &m) {
+    return SMALL ? reduce64(x, m) : red8(x, m.q);
+}
 
-template <int LE>
-__global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
+template <int LE, bool SMALL>
+__device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
-    __shared__ u64 tile[R * COLS];
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + (k >> (LE - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -300,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << st) + ((E * g + k) >> (LR - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -308,12 +323,23 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
 }
 
 template <int LE>
-__global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
+__global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
+    __shared__ u64 tile[R * COLS];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.y))].q;
+    if (qb < kSmallQ)
+        k_fwd_cols2_body<LE, true>(a, tile);
+    else
+        k_fwd_cols2_body<LE, false>(a, tile);
+}
+
+template <int LE, bool SMALL>
+__device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
-    __shared__ u64 tile[BLKS * R];
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const ModConst mcq = a.mods[mi];
     u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int blk = threadIdx.x / E, u0 = threadIdx.x % E;
@@ -330,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + (k >> (LE - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -345,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (1 << (LR + sl)) + (gb << sl) + ((E * u0 + k) >> (LR - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
             }
     }
 #pragma unroll
@@ -361,27 +387,37 @@ __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
             const u64 q2i = a.qinv2[mi], q2s = a.qinv2_sh[mi];
 #pragma unroll
             for (int k = 0; k < E; ++k) {
-                const u64 r = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+                const u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
                 out[u0 + E * k] = shoup(addq(in2[u0 + E * k], r, q), q2i, q2s, q);
             }
             return;
         }
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            u64 r = shoup(subq(in[u0 + E * k], red8(tb[rsw<LE>(u0 + E * k, blk)], q), q), qi, qs, q);
+            u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
             if (a.epi_acc) r = addq(r, out[u0 + E * k], q);
             out[u0 + E * k] = r;
         }
         return;
     }
 #pragma unroll
-    for (int k = 0; k < E; ++k) xb[u0 + E * k] = red8(tb[rsw<LE>(u0 + E * k, blk)], q);
+    for (int k = 0; k < E; ++k) xb[u0 + E * k] = fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq);
 }
 
 template <int LE>
-__global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
+__global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     __shared__ u64 tile[BLKS * R];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.z))].q;
+    if (qb < kSmallQ)
+        k_fwd_rows2_body<LE, true>(a, tile);
+    else
+        k_fwd_rows2_body<LE, false>(a, tile);
+}
+
+template <int LE, bool SMALL>
+__device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
@@ -406,7 +442,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + ((E * u0 + k) >> (lt + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1)); }
             }
     }
 #pragma unroll
@@ -421,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (k >> (lt + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1)); }
             }
     }
 #pragma unroll
@@ -429,9 +465,19 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
 }
 
 template <int LE>
-__global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
+__global__ __launch_bounds__(kThreads) void k_inv_rows2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
+    __shared__ u64 tile[BLKS * R];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.z))].q;
+    if (qb < kSmallQ)
+        k_inv_rows2_body<LE, true>(a, tile);
+    else
+        k_inv_rows2_body<LE, false>(a, tile);
+}
+
+template <int LE, bool SMALL>
+__device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
-    __shared__ u64 tile[R * COLS];
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
     const ModConst mc = a.mods[mi];
@@ -451,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + ((E * g + k) >> (ltp + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1)); }
             }
     }
 #pragma unroll
@@ -466,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const int ti = (N >> (LR + ltp + 1)) + (k >> (ltp + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1)); }
             }
     }
 #pragma unroll
@@ -474,6 +520,17 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
         u64 r = shoup_lazy(v[k], mc.ninv, mc.ninv_sh, q);
         x[col + (size_t)(g + E * k) * R] = r >= q ? r - q : r;
     }
+}
+
+template <int LE>
+__global__ __launch_bounds__(kThreads) void k_inv_cols2(NttLaunch a) {
+    constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
+    __shared__ u64 tile[R * COLS];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.y))].q;
+    if (qb < kSmallQ)
+        k_inv_cols2_body<LE, true>(a, tile);
+    else
+        k_inv_cols2_body<LE, false>(a, tile);
 }
 
 LimbMap qmap_all() { return LimbMap{0, INT_MAX, 0, INT_MAX, 0}; }
