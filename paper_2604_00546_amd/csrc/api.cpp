@@ -413,6 +413,14 @@ static int ctx_build(fr_ctx *c) {
         std::memcpy(&bits, &inv, 8);
         md.push_back(bits);
     }
+    // [i][e] = -e P 2^64 mod q_i, e = 0..nP: the overflow correction in the
+    // Montgomery domain of the conversion's 128-bit sums
+    for (int i = 0; i <= L; ++i)
+        for (int e = 0; e <= nP; ++e) {
+            const u64 qi = c->mod[i];
+            const u64 eP = mulmod_h((u64)e, c->P_mod_q[i], qi);
+            md.push_back(to_mont(eP ? qi - eP : 0, qi));
+        }
     if (int e = upload(&c->d_moddown, md)) return e;
 
     // rescale tables

@@ -149,7 +149,8 @@ struct fr_ctx {
     size_t modup_off[FR_MAXLEVEL][8];
     // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP]
     // (Montgomery-scaled by 2^64 mod q_i),
-    // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits)
+    // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits),
+    // -e P 2^64 mod q_i [L+1][nP+1] (e = 0..nP)
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
     // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each

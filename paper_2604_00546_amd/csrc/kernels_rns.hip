@@ -13,7 +13,8 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kMaxDigit = 8;  // alpha <= 8 (checked at context creation)
-constexpr int kTargetsPerThread = 4;
+constexpr int kTargetsPerThread = 8;  // ModUp conversions: target limbs per thread
+constexpr int kFbcTargets = 8;  // ModDown conversions: target limbs per thread
 
 // Batch item and tile of a block when every tile is processed for `batch`
 // items.  Workgroups are placed on the 8 XCDs round-robin by linear id, so
@@ -308,19 +309,20 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
             s = s + (double)y[j] * invp[j];
         }
     const u64 e = (u64)rint(s);
+    const u64 *epm = reinterpret_cast<const u64 *>(invp + nP);  // [L1][nP+1]: -e P 2^64 mod q_i
     auto fbc = [&](int i, const ModConst &mi) {
-        u64 al = 0, ah = 0;
+        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
             if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        return subq(redc_any(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
+        return redc_any(al, ah, mi);
     };
     const ModConst mt = mods[level];
     const u64 qt = mt.q;
     const u64 x = addq(Xd[poly * sxd + k], shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt), qt);
     const bool neg = x > (qt >> 1);
     const u64 mag = neg ? qt - x : x;
-    const int i0 = blockIdx.y * kTargetsPerThread, i1 = min(level, i0 + kTargetsPerThread);
+    const int i0 = blockIdx.y * kFbcTargets, i1 = min(level, i0 + kFbcTargets);
     for (int i = i0; i < i1; ++i) {
         const ModConst mi = mods[i];
         const u64 r = reduce64(mag, mi);
@@ -352,14 +354,15 @@ __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int 
             s = s + (double)y[j] * invp[j];
         }
     const u64 e = (u64)rint(s);
-    const int i0 = blockIdx.y * kTargetsPerThread, i1 = min(level + 1, i0 + kTargetsPerThread);
+    const u64 *epm = reinterpret_cast<const u64 *>(invp + nP);  // [L1][nP+1]: -e P 2^64 mod q_i
+    const int i0 = blockIdx.y * kFbcTargets, i1 = min(level + 1, i0 + kFbcTargets);
     for (int i = i0; i < i1; ++i) {
         const ModConst mi = mods[i];
-        u64 al = 0, ah = 0;
+        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
             if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        V[poly * sv + (size_t)i * N + k] = subq(redc_any(al, ah, mi), reduce64(e * pmod[i], mi), mi.q);
+        V[poly * sv + (size_t)i * N + k] = redc_any(al, ah, mi);
     }
 }
 
@@ -747,14 +750,14 @@ void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int n
 void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, int level, int npoly, size_t sz,
                         size_t sxu, size_t sxd) {
     ProfScope ps(c, K_MODDOWN, npoly * (2.0 + c->nP + 1.0 * level) * 8.0 * c->N);
-    dim3 g(c->N / kT, (level + kTargetsPerThread - 1) / kTargetsPerThread, npoly);
+    dim3 g(c->N / kT, (level + kFbcTargets - 1) / kFbcTargets, npoly);
     hipLaunchKernelGGL(k_relin_rescale_prep, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
                        c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd);
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
     ProfScope ps(c, K_MODDOWN, npoly * (1.0 * c->nP + 1.0 * (level + 1)) * 8.0 * c->N);
-    dim3 g(c->N / kT, (level + 1 + kTargetsPerThread - 1) / kTargetsPerThread, npoly);
+    dim3 g(c->N / kT, (level + 1 + kFbcTargets - 1) / kFbcTargets, npoly);
     hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
                        c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
 }
