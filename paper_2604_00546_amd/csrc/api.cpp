@@ -230,25 +230,27 @@ void rescale_dev(fr_ctx *c, const u64 *in, int l, u64 *out, int ncts = 1) {
 // [2][l+1][N]; U = [B][2][nE][N]).  On the radix-16 rings the ModDown and
 // the rescale share one forward transform of l limbs; otherwise they run in
 // sequence (d is then overwritten).
+// true when relin_rescale_into takes U with its top limb folded by ks_inner
+bool relin_folds(const fr_ctx *c) { return c->logN == 16 || c->logN == 12; }
+
 void relin_rescale_into(fr_ctx *c, u64 *d, const u64 *U, int B, int l, u64 *out) {
     Scope sc(c->arena);
     const int N = c->N, nE = l + 1 + c->nP, np = 2 * B;
     const size_t lw = (size_t)(l + 1) * N;
-    if (c->logN == 16 || c->logN == 12) {
+    if (relin_folds(c)) {
+        // U's limb l holds d_l + P^-1 U_l: one inverse transform of it and
+        // the P limbs gives everything the merged step needs
         u64 *Xu = scratch(c, (size_t)np * nE * N);
         LimbMap top_and_p{l, INT_MAX, 0, l + 1, c->L + 1};
         frk::ntt_inv(c, Xu, c->nP + 1, top_and_p, np, (size_t)nE * N, U, (size_t)nE * N);
-        u64 *Xd = scratch(c, (size_t)np * N);
-        frk::ntt_inv(c, Xd, 1, single(l), np, (size_t)N, d + (size_t)l * N, lw);
         u64 *Z = scratch(c, (size_t)np * l * N);
-        frk::relin_rescale_prep(c, Z, Xu, Xd, l, np, (size_t)l * N, (size_t)nE * N, (size_t)N);
+        frk::relin_rescale_prep(c, Z, Xu, nullptr, l, np, (size_t)l * N, (size_t)nE * N, 0);
         frk::ntt_fwd_relin_rescale(c, Z, l, np, U, (size_t)nE * N, d, lw, out, (size_t)l * N);
         return;
     }
     ks_moddown_into(c, U, B, l, d, lw, true);
     rescale_dev(c, d, l, out, B);
 }
-
 // d = relinearise + rescale of a x b (both at level l) into out at l - 1
 int mul_relin_rescale_dev(fr_ctx *c, const fr_keys *K, const Ct &a, const Ct &b, u64 *out) {
     const KeyEntry *rk = K->find(0);
@@ -261,7 +263,7 @@ int mul_relin_rescale_dev(fr_ctx *c, const fr_keys *K, const Ct &a, const Ct &b,
     u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
     ks_modup(c, T3 + 2 * lw, l, D);
     u64 *U = scratch(c, (size_t)2 * nE * N);
-    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false);
+    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false, 1, 0, 0, relin_folds(c) ? T3 : nullptr, 0);
     relin_rescale_into(c, T3, U, 1, l, out);
     return FR_OK;
 }
@@ -403,6 +405,8 @@ static int ctx_build(fr_ctx *c) {
         c->P_mod_q_sh[i] = shoup_companion(pm, c->mod[i]);
         pinv[i] = invmod_h(pm, c->mod[i]);
         pinvs[i] = shoup_companion(pinv[i], c->mod[i]);
+        c->P_inv_q[i] = pinv[i];
+        c->P_inv_q_sh[i] = pinvs[i];
     }
     md.insert(md.end(), pinv.begin(), pinv.end());
     md.insert(md.end(), pinvs.begin(), pinvs.end());
@@ -978,7 +982,7 @@ extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr
     u64 *D = scratch(c, (size_t)num_digits(c, l) * nE * N);
     ks_modup(c, T2, l, D);
     u64 *U = scratch(c, (size_t)2 * nE * N);
-    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false);
+    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false, 1, 0, 0, relin_folds(c) ? T01 : nullptr, 0);
     relin_rescale_into(c, T01, U, 1, l, out->data);
     FR_HIP(hipGetLastError());
     out->level = l - 1;
@@ -1600,7 +1604,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             frk::tensor_batch(c, T01, T2, lv + 1, B, xa.data(), yb.data());
             ks_modup(c, T2, lv, Dg, B, lw(lv));
             frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
-                          (size_t)2 * nE * N);
+                          (size_t)2 * nE * N, relin_folds(c) ? T01 : nullptr, cw);
             relin_rescale_into(c, T01, U, B, lv, out);
             for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
         }

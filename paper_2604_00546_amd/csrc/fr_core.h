@@ -153,6 +153,7 @@ struct fr_ctx {
     // -e P 2^64 mod q_i [L+1][nP+1] (e = 0..nP)
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
+    u64 P_inv_q[FR_MAXMOD], P_inv_q_sh[FR_MAXMOD];  // P^-1 mod q_i and Shoup companions
     // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each
     u64 *d_rescale = nullptr;
     // CRT lift per level: qhat_inv[i], qhat_inv_sh[i], qhat_mod64[i], Q_mod64,
@@ -291,9 +292,12 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
 void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx);
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,
                  size_t sx = 0);
-// U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p]
+// U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p];
+// with fold_d (relinearisation, items fold_sd words apart) the top limb e =
+// level is replaced by d_l + P^-1 U_l (its only later use)
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
-              bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0);
+              bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0, const u64 *fold_d = nullptr,
+              size_t fold_sd = 0);
 // ModDown of U (eval domain, P limbs already coefficient form in Upc):
 // giant steps of rotations per key-sum launch at this level (bounded so the
 // t01 = (sum a0 b0, sum a0 b1 + a1 b0), t2 = sum a1 b1 over n ciphertext

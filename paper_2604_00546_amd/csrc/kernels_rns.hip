@@ -163,10 +163,13 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
 
 // U{0,1}[e][p] (+)= sum_t D_t[e][src(p)] * ksk_t{b,a}[gm(e)][p]; keys are
 // Montgomery-scaled so one reduction yields the canonical sum.
+// fold (relinearisation): the top limb of U becomes d_l + P^-1 U_l (d an item
+// of fold_sd words, [2][level+1][N]); U_l is read by nothing else afterwards
 __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
                                                  const ModConst *mods, int accumulate, size_t sd, size_t su,
-                                                 int batch) {
+                                                 int batch, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
+                                                 u64 pinv_top_sh) {
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
     const int p = tile * kT + threadIdx.x, e = blockIdx.y;
@@ -189,6 +192,11 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     if (accumulate) {
         u0 = addq(u0, U0[w], m.q);
         u1 = addq(u1, U1[w], m.q);
+    }
+    if (fold_d && e == level) {
+        const u64 *d = fold_d + item * fold_sd + w;
+        u0 = addq(d[0], shoup(u0, pinv_top, pinv_top_sh, m.q), m.q);
+        u1 = addq(d[(size_t)(level + 1) * N], shoup(u1, pinv_top, pinv_top_sh, m.q), m.q);
     }
     U0[w] = u0;
     U1[w] = u1;
@@ -319,7 +327,10 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
     };
     const ModConst mt = mods[level];
     const u64 qt = mt.q;
-    const u64 x = addq(Xd[poly * sxd + k], shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt), qt);
+    // folded (Xd null): limb `level` of U already holds d_l + P^-1 U_l
+    const u64 x = Xd ? addq(Xd[poly * sxd + k], shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt),
+                            qt)
+                     : subq(xu[0], shoup(fbc(level, mt), pinv[level], pinv_sh[level], qt), qt);
     const bool neg = x > (qt >> 1);
     const u64 mag = neg ? qt - x : x;
     const int i0 = blockIdx.y * kFbcTargets, i1 = min(level, i0 + kFbcTargets);
@@ -691,15 +702,21 @@ void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size
 }
 
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate,
-              int batch, size_t sd, size_t su) {
+              int batch, size_t sd, size_t su, const u64 *fold_d, size_t fold_sd) {
     const int nE_ = level + 1 + c->nP, nd_ = (level + 1 + c->alpha - 1) / c->alpha;
     // digits and outputs per batch item, the shared key once
     ProfScope ps(c, K_KS,
                  (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) + 2.0 * nd_ * nE_) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
+    u64 pinv = 0, pinv_sh = 0;
+    if (fold_d) {
+        pinv = c->P_inv_q[level];
+        pinv_sh = c->P_inv_q_sh[level];
+    }
     hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
-                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch, fold_d,
+                       fold_sd, pinv, pinv_sh);
 }
 
 void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *const *a, const u64 *const *b) {
