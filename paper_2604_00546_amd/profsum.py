@@ -8,6 +8,7 @@ those dispatches and prints per-kernel figures per step.
 usage:
   python -m paper_2604_00546_amd.profsum trace <run_kernel_trace.csv> --steps S --calib-mib M
   python -m paper_2604_00546_amd.profsum counters <fetch.csv> <write.csv> --calib-mib M
+  python -m paper_2604_00546_amd.profsum sq <sq_counter_collection.csv>
 """
 import argparse
 import collections
@@ -88,6 +89,28 @@ def counters(fpath, wpath, calib_mib):
               f"write {wr / transforms / 2**20:.3f} MiB, total {(rd + wr) / transforms:.0f} B")
 
 
+def sq(path):
+    """Per-wave SQ counters of every dispatch in the run, by kernel."""
+    per = collections.defaultdict(dict)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        per[r["Dispatch_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
+        names[r["Dispatch_Id"]] = _short(r["Kernel_Name"])
+    agg = collections.defaultdict(lambda: collections.Counter())
+    disp = collections.Counter()
+    for d, cs in per.items():
+        agg[names[d]].update(cs)
+        disp[names[d]] += 1
+    cols = [("VALU/wave", "SQ_INSTS_VALU"), ("SALU/wave", "SQ_INSTS_SALU"), ("LDS/wave", "SQ_INSTS_LDS"),
+            ("wave_cyc/wave", "SQ_WAVE_CYCLES"), ("wait_any/wave", "SQ_WAIT_INST_ANY")]
+    print(f"{'kernel':28s} {'disp':>5s} " + " ".join(f"{h:>{max(9, len(h))}s}" for h, _ in cols))
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["SQ_WAVE_CYCLES"]):
+        w = max(a["SQ_WAVES"], 1.0)
+        print(f"{k[:28]:28s} {disp[k]:5d} " + " ".join(f"{a[c] / w:{max(9, len(h))}.0f}" for h, c in cols))
+    same = all(abs(a["SQ_ACTIVE_INST_VALU"] - a["SQ_INSTS_VALU"]) <= 0.01 * a["SQ_INSTS_VALU"] for a in agg.values())
+    print(f"SQ_ACTIVE_INST_VALU within 1% of SQ_INSTS_VALU for every kernel: {same}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -99,11 +122,15 @@ def main():
     c.add_argument("fetch")
     c.add_argument("write")
     c.add_argument("--calib-mib", type=int, required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("path")
     a = ap.parse_args()
     if a.cmd == "trace":
         trace(a.path, a.steps, a.calib_mib)
-    else:
+    elif a.cmd == "counters":
         counters(a.fetch, a.write, a.calib_mib)
+    else:
+        sq(a.path)
 
 
 if __name__ == "__main__":
