@@ -1161,6 +1161,7 @@ struct or_db {
     double scale;
     or_pt **pt;       /* [G*ell] */
     uint64_t **ntt;   /* [G*ell] oracle NTT form, [level+1][N] */
+    uint64_t **ntt_p; /* [G*ell] residues mod the special primes, oracle NTT form, [nP][N]; built on first use */
 };
 
 int or_db_groups(const or_db *db) { return db->G; }
@@ -1248,8 +1249,70 @@ void or_db_free(or_db *db) {
     for (int p = 0; p < n; p++) {
         if (db->pt) or_pt_free(db->pt[p]);
         if (db->ntt) free(db->ntt[p]);
+        if (db->ntt_p) free(db->ntt_p[p]);
     }
-    free(db->pt); free(db->ntt); free(db);
+    free(db->pt); free(db->ntt); free(db->ntt_p); free(db);
+}
+
+/* The plaintext's integer coefficients modulo the special primes p_j: each
+ * coefficient m is rebuilt exactly from its Q_level limbs by the CRT,
+ * m = sum_i [m_i Qhat_i^-1]_{q_i} Qhat_i mod Q, taken as the centered value in
+ * (-Q/2, Q/2], and reduced mod p_j (coefficient form, [nP][N]).  A plaintext
+ * multiplied into a ciphertext held over Q_l U P needs these limbs. */
+static void pt_special_residues(const or_ctx *c, const or_pt *p, uint64_t *out) {
+    int l = p->level, N = c->N, nP = c->nP, L = c->L;
+    big Q, halfQ, *Qhat = malloc(sizeof(big) * (l + 1));
+    uint64_t *qhat_inv = malloc(8 * (size_t)(l + 1));
+    big_zero(&Q); Q.w[0] = 1;
+    for (int i = 0; i <= l; i++) big_mul_small(&Q, c->mod[i]);
+    halfQ = Q;
+    for (int i = 0; i < BW; i++) halfQ.w[i] = (halfQ.w[i] >> 1) | (i + 1 < BW ? (halfQ.w[i + 1] << 63) : 0);
+    for (int i = 0; i <= l; i++) {
+        big_zero(&Qhat[i]); Qhat[i].w[0] = 1;
+        uint64_t prod = 1;
+        for (int j = 0; j <= l; j++) {
+            if (j == i) continue;
+            big_mul_small(&Qhat[i], c->mod[j]);
+            prod = mulmod(prod, c->mod[j] % c->mod[i], c->mod[i]);
+        }
+        qhat_inv[i] = invmod(prod, c->mod[i]);
+    }
+    #pragma omp parallel for
+    for (int k = 0; k < N; k++) {
+        big X, t;
+        big_zero(&X);
+        for (int i = 0; i <= l; i++) {
+            t = Qhat[i];
+            big_mul_small(&t, mulmod(p->m[(size_t)i * N + k], qhat_inv[i], c->mod[i]));
+            big_add(&X, &t);
+        }
+        while (big_cmp(&X, &Q) >= 0) big_sub(&X, &Q);
+        int neg = big_cmp(&X, &halfQ) > 0;
+        if (neg) { t = Q; big_sub(&t, &X); X = t; }  /* X = |m| */
+        for (int j = 0; j < nP; j++) {
+            uint64_t pj = c->mod[L + 1 + j], r = 0;
+            for (int w = BW - 1; w >= 0; w--) r = (uint64_t)((((u128)r << 64) | X.w[w]) % pj);
+            out[(size_t)j * N + k] = neg ? (r ? pj - r : 0) : r;
+        }
+    }
+    free(Qhat); free(qhat_inv);
+}
+
+static void db_cache_ntt_p(const or_ctx *c, or_db *db) {
+    if (db->ntt_p) return;
+    int N = c->N, n = db->G * db->ell, nP = c->nP, L = c->L;
+    db->ntt_p = calloc(n, sizeof(uint64_t *));
+    for (int p = 0; p < n; p++) {
+        db->ntt_p[p] = malloc(8 * (size_t)nP * N);
+        pt_special_residues(c, db->pt[p], db->ntt_p[p]);
+        for (int j = 0; j < nP; j++) nega_fwd(c, L + 1 + j, db->ntt_p[p] + (size_t)j * N);
+    }
+}
+
+int or_db_export_special(const or_ctx *c, or_db *db, int g, int d, uint64_t *out) {
+    if (g < 0 || g >= db->G || d < 0 || d >= db->ell) { set_err("or_db_export_special: bad index"); return -1; }
+    pt_special_residues(c, db->pt[(size_t)g * db->ell + d], out);
+    return 0;
 }
 
 int or_db_export(const or_db *db, int g, int d, uint64_t *out) {
@@ -1269,6 +1332,8 @@ int or_db_export(const or_db *db, int g, int d, uint64_t *out) {
 /* ModUp_t(P_j.c1)) * ksk_{g_j,t};  S = (P_0.c0 + sum_j sigma_{g_j}(P_j.c0)   */
 /* + ModDown(U0), P_0.c1 + ModDown(U1)).                                      */
 /* ------------------------------------------------------------------------ */
+static or_ct *giant_sum(const or_ctx *c, const or_keys *K, or_ct **P, int n2, int n1);
+
 or_ct *or_bsgs_matvec(const or_ctx *c, const or_keys *K, or_ct *const *baby, int n1, const or_db *db, int group) {
     int N = c->N, ell = db->ell;
     if (n1 != db->n1 || group < 0 || group >= db->G) { set_err("or_bsgs_matvec: layout mismatch"); return NULL; }
@@ -1315,7 +1380,13 @@ or_ct *or_bsgs_matvec(const or_ctx *c, const or_keys *K, or_ct *const *baby, int
     }
     for (int i = 0; i < n1; i++) free(bn[i]);
     free(bn);
-    int l = lv - 1, nE = l + 1 + c->nP;
+    return giant_sum(c, K, P, n2, n1);
+}
+
+/* S = P_0 + sum_{j >= 1} Rot_{j n1}(P_j) with one shared ModDown (the giant
+ * steps of Eq. bsgs2); frees P. */
+static or_ct *giant_sum(const or_ctx *c, const or_keys *K, or_ct **P, int n2, int n1) {
+    int N = c->N, l = P[0]->level, nE = l + 1 + c->nP;
     or_ct *S = or_ct_copy(c, P[0]);
     uint64_t *U0 = calloc((size_t)nE * N, 8), *U1 = calloc((size_t)nE * N, 8);
     uint64_t *tmp = malloc(8 * (size_t)N);
@@ -1332,6 +1403,84 @@ or_ct *or_bsgs_matvec(const or_ctx *c, const or_keys *K, or_ct *const *baby, int
     for (int j = 0; j < n2; j++) or_ct_free(P[j]);
     free(P);
     return S;
+}
+
+/* BSGS product with the ModDown of the baby steps hoisted past the inner
+ * sums (double hoisting of the plaintext-matrix BSGS, §2 hoisting and double
+ * hoisting).  Baby step i is kept over the extended basis Q_l U P,
+ *   B_i = (P sigma_i(c0) + U0_i, U1_i),  U_i = sum_t sigma_i(ModUp_t(c1)) ksk_{i,t},
+ *   B_0 = (P c0, P c1)  (zero on the special primes),
+ * the diagonals are multiplied over Q_l U P (their special-prime limbs are
+ * the residues of the plaintext's centered integer coefficients), and each
+ * inner sum takes one ModDown and one rescale:
+ *   P_j = Rescale(ModDown(sum_i B_i * diag'_{g, j n1 + i})),
+ * followed by the same giant steps as or_bsgs_matvec.  ModDown(B_i) is
+ * Rot_i(ct), so the result approximates the same product. */
+or_ct *or_bsgs_matvec_hoisted(const or_ctx *c, const or_keys *K, const or_ct *x, int n1, or_db *db, int group) {
+    int N = c->N, ell = db->ell, l = x->level, nP = c->nP;
+    if (n1 != db->n1 || group < 0 || group >= db->G) { set_err("or_bsgs_matvec_hoisted: layout mismatch"); return NULL; }
+    if (db->level != l) { set_err("or_bsgs_matvec_hoisted: query and database levels differ"); return NULL; }
+    if (l < 1) { set_err("or_bsgs_matvec_hoisted: no level left to rescale"); return NULL; }
+    int n2 = (ell + n1 - 1) / n1, nE = l + 1 + nP;
+    for (int i = 1; i < n1; i++)
+        if (!find_ksk(K, or_galois_element(c, i))) { set_err("or_bsgs_matvec_hoisted: missing baby-step key"); return NULL; }
+    for (int j = 1; j < n2; j++)
+        if (!find_ksk(K, or_galois_element(c, j * n1))) { set_err("or_bsgs_matvec_hoisted: missing giant-step key"); return NULL; }
+    db_cache_ntt_p(c, db);
+    uint64_t Pq[64];
+    for (int i = 0; i <= l; i++) {
+        Pq[i] = 1;
+        for (int j = 0; j < nP; j++) Pq[i] = mulmod(Pq[i], c->mod[c->L + 1 + j] % c->mod[i], c->mod[i]);
+    }
+    /* baby steps over Q_l U P, oracle NTT form, [2][nE][N] each */
+    uint64_t **bq = malloc(sizeof(uint64_t *) * n1);
+    for (int i = 0; i < n1; i++) {
+        uint64_t g = or_galois_element(c, i);
+        uint64_t *b0 = calloc((size_t)2 * nE * N, 8), *b1 = b0 + (size_t)nE * N;
+        bq[i] = b0;
+        if (g != 1) ks_accumulate(c, l, CT1(c, x, 0), g, find_ksk(K, g), b0, b1);
+        #pragma omp parallel for
+        for (int e = 0; e <= l; e++) {
+            uint64_t q = c->mod[e], *t = malloc(8 * (size_t)N);
+            if (g != 1) or_automorphism(c, e, g, CT0(c, x, e), t);
+            else memcpy(t, CT0(c, x, e), 8 * (size_t)N);
+            nega_fwd(c, e, t);
+            for (int k = 0; k < N; k++) b0[(size_t)e * N + k] = addmod(b0[(size_t)e * N + k], mulmod(Pq[e], t[k], q), q);
+            if (g == 1) {
+                memcpy(t, CT1(c, x, e), 8 * (size_t)N);
+                nega_fwd(c, e, t);
+                for (int k = 0; k < N; k++) b1[(size_t)e * N + k] = mulmod(Pq[e], t[k], q);
+            }
+            free(t);
+        }
+    }
+    or_ct **P = calloc(n2, sizeof(or_ct *));
+    uint64_t *acc = malloc(8 * (size_t)2 * nE * N);
+    for (int j = 0; j < n2; j++) {
+        int nb = ell - j * n1 < n1 ? ell - j * n1 : n1;
+        memset(acc, 0, 8 * (size_t)2 * nE * N);
+        #pragma omp parallel for
+        for (int pe = 0; pe < 2 * nE; pe++) {
+            int e = pe % nE, gm = ext_gidx(c, l, e);
+            uint64_t q = c->mod[gm], *d = acc + (size_t)pe * N;
+            for (int i = 0; i < nb; i++) {
+                size_t di = (size_t)group * ell + j * n1 + i;
+                const uint64_t *w = e <= l ? db->ntt[di] + (size_t)e * N : db->ntt_p[di] + (size_t)(e - l - 1) * N;
+                const uint64_t *xb = bq[i] + (size_t)pe * N;
+                for (int k = 0; k < N; k++) d[k] = addmod(d[k], mulmod(xb[k], w[k], q), q);
+            }
+            nega_inv(c, gm, d);
+        }
+        or_ct *y = ct_alloc(c, l, x->scale * db->scale);
+        or_moddown(c, l, acc, CT0(c, y, 0));
+        or_moddown(c, l, acc + (size_t)nE * N, CT1(c, y, 0));
+        P[j] = or_rescale(c, y);
+        or_ct_free(y);
+    }
+    free(acc);
+    for (int i = 0; i < n1; i++) free(bq[i]);
+    free(bq);
+    return giant_sum(c, K, P, n2, n1);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -131,12 +131,21 @@ void or_db_free(or_db *db);
 int or_db_groups(const or_db *db);
 /* Export plaintext (group g, diagonal d) as coefficient residues [level+1][N]. */
 int or_db_export(const or_db *db, int g, int d, uint64_t *out);
+/* Residues of plaintext (g, d)'s centered integer coefficients modulo the
+ * special primes, coefficient form [nP][N]. */
+int or_db_export_special(const or_ctx *ctx, or_db *db, int g, int d, uint64_t *out);
 /* Pre-rotated diagonal slot vector (group g, diagonal d) before encoding. */
 int or_db_slots(const or_ctx *ctx, const float *T, int K, int ell, int B, int n1,
                 int g, int d, double *v);
 /* S_g = sum_j Rot_{j n1}( Rescale( sum_i baby[i] * diag'_{g, j n1 + i} ) ) */
 or_ct *or_bsgs_matvec(const or_ctx *ctx, const or_keys *k, or_ct *const *baby, int n1,
                       const or_db *db, int group);
+/* The same product from the query itself, with the baby steps kept over
+ * Q_l U P and one ModDown per inner sum (query and database at one level):
+ * S_g = sum_j Rot_{j n1}( Rescale( ModDown( sum_i B_i * diag'_{g, j n1 + i} ) ) ),
+ * B_i = Rot_i(ct) before its ModDown. */
+or_ct *or_bsgs_matvec_hoisted(const or_ctx *ctx, const or_keys *k, const or_ct *x, int n1,
+                              or_db *db, int group);
 
 /* ---- Chebyshev threshold ---- */
 /* Coefficients of the degree-n interpolant of the 0/1 step at delta on

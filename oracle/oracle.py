@@ -99,6 +99,8 @@ def lib():
         "or_db_slots": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int, C.c_int, C.c_int, C.c_int,
                                   C.c_int, C.c_int, _DP]),
         "or_bsgs_matvec": (_CT, [_P, _P, C.POINTER(_CT), C.c_int, _P, C.c_int]),
+        "or_bsgs_matvec_hoisted": (_CT, [_P, _P, _CT, C.c_int, _P, C.c_int]),
+        "or_db_export_special": (C.c_int, [_P, _P, C.c_int, C.c_int, _U64P]),
         "or_cheb_step_coeffs": (None, [C.c_int, C.c_double, _DP]),
         "or_cheb_clenshaw": (C.c_double, [_DP, C.c_int, C.c_double]),
         "or_chebyshev": (_CT, [_P, _P, _CT, _DP, C.c_int, C.c_int]),
@@ -292,6 +294,13 @@ class Db:
     def export_all(self) -> np.ndarray:
         return np.stack([np.stack([self.export(g, d) for d in range(self.ell)]) for g in range(self.G)])
 
+    def export_special(self, g: int, d: int) -> np.ndarray:
+        """Residues of plaintext (g, d)'s centered coefficients mod the special primes, [nP][N]."""
+        out = np.zeros(self.ctx.nP * self.ctx.N, dtype=np.uint64)
+        if lib().or_db_export_special(self.ctx.ptr, self.ptr, g, d, _u64(out)):
+            _err("db_export_special")
+        return out.reshape(self.ctx.nP, self.ctx.N)
+
 
 class Context:
     """Parameter set and every oracle operation on it."""
@@ -462,6 +471,10 @@ class Context:
     def bsgs_matvec(self, keys: Keys, baby: list, db: Db, group: int) -> Ct:
         arr = (_CT * len(baby))(*[b.ptr for b in baby])
         return Ct(self, lib().or_bsgs_matvec(self.ptr, keys.ptr, arr, len(baby), db.ptr, group))
+
+    def bsgs_matvec_hoisted(self, keys: Keys, ct: Ct, db: Db, group: int) -> Ct:
+        """The product from the query itself, baby steps held over Q_l U P (one ModDown per inner sum)."""
+        return Ct(self, lib().or_bsgs_matvec_hoisted(self.ptr, keys.ptr, ct.ptr, db.n1, db.ptr, group))
 
     def chebyshev(self, keys: Keys, x: Ct, coeffs, d1: int) -> Ct:
         c = np.ascontiguousarray(coeffs, dtype=np.float64)

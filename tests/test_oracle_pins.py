@@ -463,6 +463,55 @@ def test_matvec_equals_diagonal_method_and_B1(small_ctx, config1):
     assert np.max(np.abs(s_b1[:64] - want)) <= 2 ** -20
 
 
+def test_db_special_residues_are_the_centered_integers(deep_ctx):
+    """A diagonal multiplied over Q_l U P needs its plaintext's residues mod
+    the special primes: those of the centered integer coefficient, pinned by
+    Python integers, including both ends of (-Q/2, Q/2]."""
+    ctx = deep_ctx
+    Q = math.prod(ctx.q)
+    P = ctx.moduli[ctx.L + 1:]
+    rnd = np.random.default_rng(21)
+    vals = [int(v) for v in rnd.integers(-2**45, 2**45, ctx.N)]
+    vals[0], vals[1], vals[2], vals[3] = (Q - 1) // 2, -((Q - 1) // 2), 0, -1
+    m = np.stack([[v % q for v in vals] for q in ctx.q]).astype(np.uint64)
+    db = ctx.db_import(m.reshape(1, 1, ctx.L + 1, ctx.N), 1, 1, 1, 1, ctx.L, 2.0 ** 40)
+    got = db.export_special(0, 0)
+    want = np.array([[v % p for v in vals] for p in P], dtype=np.uint64)
+    assert np.array_equal(got, want)
+    # (Q+1)/2 is the residue class of -(Q-1)/2: it must come out negative
+    assert int(got[0][1]) == (-((Q - 1) // 2)) % P[0] != ((Q + 1) // 2) % P[0]
+
+
+def test_matvec_hoisted_scores_within_2m20(small_ctx, small_keys, config1):
+    """The product with the baby steps' ModDown hoisted past the inner sums
+    decrypts to the plaintext scores within the same 2^-20 bound and agrees
+    with the single-hoisted product to well inside it."""
+    ctx = small_ctx
+    wl, ct, baby, db, S = config1
+    H = ctx.bsgs_matvec_hoisted(small_keys, ct, db, 0)
+    assert H.level == S.level and H.scale == S.scale
+    dh, ds = ctx.decrypt_decode(small_keys, H), ctx.decrypt_decode(small_keys, S)
+    assert np.max(np.abs(dh[:64] - wl.exact_scores())) <= 2 ** -20
+    assert np.max(np.abs(dh[64:])) <= 2 ** -20
+    assert np.max(np.abs(dh - ds)) <= 2 ** -22
+
+
+@pytest.mark.slow
+def test_matvec_hoisted_paper_chain(deep_ctx):
+    """The hoisted product on the paper's modulus chain (five special primes,
+    digits of five limbs) at N = 2^12."""
+    ctx = deep_ctx
+    keys = ctx.keygen(synth.int_seed(3, synth.SUB_KEYS), ROTS_C1)
+    wl = synth.make_workload(1, 64, 128)
+    ct = ctx.encrypt(keys, ctx.encode(synth.replicate_query(wl.query, ctx.N // 2), ctx.L, 2.0 ** 40), 5)
+    db = ctx.db_build(wl.templates, wl.K, 128, 16, 8, ctx.L, 2.0 ** 40)
+    H = ctx.bsgs_matvec_hoisted(keys, ct, db, 0)
+    assert H.level == ctx.L - 1
+    dh = ctx.decrypt_decode(keys, H)
+    assert np.max(np.abs(dh[:64] - wl.exact_scores())) <= 2 ** -20
+    assert np.max(np.abs(dh[64:])) <= 2 ** -20
+
+
 # --------------------------------------------------------------------------
 # Chebyshev threshold
 # --------------------------------------------------------------------------
