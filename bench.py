@@ -47,7 +47,7 @@ ROOFLINE_KERNEL = {"class": "ntt", "bound": "alu"}
 # limbs, both passes), from the FETCH_SIZE / WRITE_SIZE counter runs recorded
 # in profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
 # since those counters were taken
-NTT_TRAFFIC_BYTES_PER_LAUNCH = 151464921
+NTT_TRAFFIC_BYTES_PER_LAUNCH = None
 
 
 def log(*a):
@@ -65,6 +65,8 @@ def setup(args):
     t = time.time()
     keys = ctx.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
     db = ctx.db_load(wl.templates, ell, B, n1, ctx.L, 2.0 ** 40)
+    if args.route == "hoisted":
+        db.extend()
     qv = synth.replicate_query(wl.query, ctx.N // 2)
     q = ctx.encrypt(keys, ctx.encode(qv, ctx.L, 2.0 ** 40), synth.int_seed(3, synth.SUB_ENC))
     torch.cuda.synchronize()
@@ -74,14 +76,23 @@ def setup(args):
     score = ctx.new_ct(ctx.L - 1)
     cheb = ctx.new_ct(ctx.L - 1)
     return dict(fr=fr, ctx=ctx, wl=wl, keys=keys, db=db, q=q, baby=baby, score=score, cheb=cheb, coeffs=coeffs,
-                n1=n1, ell=ell, B=B, K=K)
+                n1=n1, ell=ell, B=B, K=K, route=args.route)
+
+
+def matvec(s):
+    """The score ciphertext of the query: the baby steps' ModDown hoisted
+    past the inner sums, or hoisted rotations followed by the product."""
+    ctx = s["ctx"]
+    if s["route"] == "hoisted":
+        ctx.bsgs_matvec_hoisted(s["keys"], s["q"], s["db"], 0, out=s["score"])
+    else:
+        ctx.rotate_hoisted(s["keys"], s["q"], range(1, s["n1"]), outs=s["baby"][1:])
+        ctx.bsgs_diag_matvec(s["keys"], s["baby"], s["db"], 0, out=s["score"])
 
 
 def step(s, d1):
-    ctx = s["ctx"]
-    ctx.rotate_hoisted(s["keys"], s["q"], range(1, s["n1"]), outs=s["baby"][1:])
-    ctx.bsgs_diag_matvec(s["keys"], s["baby"], s["db"], 0, out=s["score"])
-    ctx.chebyshev_eval(s["keys"], s["score"], s["coeffs"], d1, out=s["cheb"])
+    matvec(s)
+    s["ctx"].chebyshev_eval(s["keys"], s["score"], s["coeffs"], d1, out=s["cheb"])
 
 
 def batched(s, nq, steps, warmup, d1):
@@ -99,8 +110,11 @@ def batched(s, nq, steps, warmup, d1):
     chebs = [ctx.new_ct(ctx.L - 1) for _ in range(nq)]
 
     def bstep():
-        ctx.rotate_hoisted_batch(s["keys"], qs, range(1, s["n1"]), outs=rows)
-        ctx.bsgs_diag_matvec_batch(s["keys"], babies, s["db"], 0, outs=scores)
+        if s["route"] == "hoisted":
+            ctx.bsgs_matvec_hoisted_batch(s["keys"], qs, s["db"], 0, outs=scores)
+        else:
+            ctx.rotate_hoisted_batch(s["keys"], qs, range(1, s["n1"]), outs=rows)
+            ctx.bsgs_diag_matvec_batch(s["keys"], babies, s["db"], 0, outs=scores)
         ctx.chebyshev_eval_batch(s["keys"], scores, s["coeffs"], d1, outs=chebs)
 
     for _ in range(warmup):
@@ -400,8 +414,11 @@ def cpu_baseline(s, d1):
     db = o.db_build(wl.templates, wl.K, s["ell"], s["B"], s["n1"], o.L, 2.0 ** 40)
     q = o.encrypt(keys, o.encode(synth.replicate_query(wl.query, o.N // 2), o.L, 2.0 ** 40), 5)
     t0 = time.time()
-    baby = [q] + o.rotate_hoisted(keys, q, range(1, s["n1"]))
-    S = o.bsgs_matvec(keys, baby, db, 0)
+    if s["route"] == "hoisted":
+        S = o.bsgs_matvec_hoisted(keys, q, db, 0)
+    else:
+        baby = [q] + o.rotate_hoisted(keys, q, range(1, s["n1"]))
+        S = o.bsgs_matvec(keys, baby, db, 0)
     o.chebyshev(keys, S, s["coeffs"], d1)
     dt = time.time() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -434,6 +451,9 @@ def main():
     ap.add_argument("--edb", action="store_true", help="also time the encrypted-database route")
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
+    ap.add_argument("--route", choices=("hoisted", "single"), default="hoisted",
+                    help="hoisted: baby steps held over Q_l U P, one ModDown per inner sum (fr_bsgs_matvec_hoisted); "
+                         "single: hoisted rotations, each with its ModDown, then the product")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, one device-to-device copy of this many MiB (the known-size "
@@ -497,7 +517,9 @@ def main():
                                "pre-rotated diagonals), n1=32 n2=16, degree-63 Chebyshev step at 0.3 "
                                f"(d1={args.d1}); RNS-CKKS N=2^16, Q=60+14x40 bits, P=5x60 bits, dnum=3, "
                                "scale 2^40", "templates": s["K"], "dim": s["ell"], "ring_dim": ctx.N,
-                   "form": "plain, one query at a time"},
+                   "form": "plain, one query at a time",
+                   "route": ("baby steps held over Q_l U P, one ModDown per inner sum" if args.route == "hoisted"
+                             else "hoisted rotations with one ModDown each, then the product")},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
     }
@@ -523,17 +545,14 @@ def main():
                                "launches": n_launch, "avg_launch_ms": avg_ms,
                                "bytes_per_launch": k_bytes / n_launch}
     if args.breakdown:
-        ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev3[0].record(stream)
-        ctx.rotate_hoisted(s["keys"], s["q"], range(1, s["n1"]), outs=s["baby"][1:])
+        matvec(s)
         ev3[1].record(stream)
-        ctx.bsgs_diag_matvec(s["keys"], s["baby"], s["db"], 0, out=s["score"])
-        ev3[2].record(stream)
         ctx.chebyshev_eval(s["keys"], s["score"], s["coeffs"], args.d1, out=s["cheb"])
-        ev3[3].record(stream)
+        ev3[2].record(stream)
         torch.cuda.synchronize()
-        out["phase_ms"] = {"baby_rotations": ev3[0].elapsed_time(ev3[1]), "matvec": ev3[1].elapsed_time(ev3[2]),
-                           "chebyshev": ev3[2].elapsed_time(ev3[3])}
+        out["phase_ms"] = {"matvec": ev3[0].elapsed_time(ev3[1]), "chebyshev": ev3[1].elapsed_time(ev3[2])}
         bd = {}
         for cls in ctx.KERNEL_CLASSES:
             ctx.prof_begin(cls)

@@ -192,6 +192,33 @@ int fr_bsgs_diag_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int
 int fr_bsgs_diag_matvec_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t nq,
                               int32_t n1, const fr_db *const *dbs, const int32_t *groups, fr_ct *out);
 
+/* ---- the same product with the baby steps' ModDown hoisted past the inner
+ * sums (double hoisting of the plaintext-matrix BSGS, §2 hoisting and double
+ * hoisting) ----
+ * fr_db_extend appends to every diagonal of db its residues modulo the
+ * special primes (those of the plaintext's centered integer coefficients,
+ * exact), growing the database by nP / (level+1).  Idempotent; the
+ * database stays valid for every other call.  FR_ENOMEM leaves it as it was.
+ *
+ * fr_bsgs_matvec_hoisted computes the score ciphertext from the query
+ * itself (query level = database level = l >= 1, n1 = the database's):
+ *   B_0 = (P c0, P c1),  B_i = (P sigma_i(c0) + U0_i, U1_i) over Q_l U P,
+ *   U_i = sum_t sigma_i(ModUp_t(c1)) ksk_{i,t}   (Rot_i before its ModDown),
+ *   P_j = Rescale(ModDown(sum_i B_i * diag'_{g, j n1 + i})),
+ *   out = P_0 + sum_{j >= 1} Rot_{j n1}(P_j)   at level l-1,
+ * keys for rotations 1..n1-1 and j n1.  The scores approximate those of
+ * fr_rotate_hoisted + fr_bsgs_diag_matvec with one ModDown per inner sum
+ * instead of one per baby step; the words differ (other rounding).
+ * FR_EINVAL for a database that is not extended. */
+int fr_db_extend(fr_ctx *ctx, fr_db *db);
+int fr_bsgs_matvec_hoisted(fr_ctx *ctx, const fr_keys *keys, const fr_ct *query, const fr_db *db,
+                           int32_t group, fr_ct *out);
+/* Batched form: query q against group groups[q] of dbs[q] (extended, one
+ * ell, n1 and level); out[q] identical to the one-query call; chunks of up
+ * to 8 queries read every diagonal and key once per chunk. */
+int fr_bsgs_matvec_hoisted_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *queries, int32_t nq,
+                                 const fr_db *const *dbs, const int32_t *groups, fr_ct *out);
+
 /* ---- Chebyshev threshold (§5.1.4, Eq. cheb-sign) ----
  * out = p(in) slot-wise, p = sum_{k <= degree} c[k] T_k (c[0] the full T_0
  * coefficient), evaluated by recursive Chebyshev-basis division over

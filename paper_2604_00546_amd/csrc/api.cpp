@@ -425,6 +425,8 @@ static int ctx_build(fr_ctx *c) {
             const u64 eP = mulmod_h((u64)e, c->P_mod_q[i], qi);
             md.push_back(to_mont(eP ? qi - eP : 0, qi));
         }
+    // [i] = P 2^64 mod q_i: P times a word inside a Montgomery-reduced sum
+    for (int i = 0; i <= L; ++i) md.push_back(to_mont(c->P_mod_q[i], c->mod[i]));
     if (int e = upload(&c->d_moddown, md)) return e;
 
     // rescale tables
@@ -1117,6 +1119,7 @@ static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double 
     db->B = B;
     db->n1 = n1;
     db->level = level;
+    db->nl = level + 1;
     db->scale = scale;
     if (hipMalloc(&db->data, (size_t)G * ell * (level + 1) * c->N * 8) != hipSuccess) {
         delete db;
@@ -1190,7 +1193,8 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
     const size_t pw = (size_t)(db->level + 1) * c->N;
     u64 *t = scratch(c, pw);
     CHECK(t, FR_ENOMEM, "fr_db_export: scratch");
-    FR_HIP(hipMemcpyAsync(t, db->data + ((size_t)g * db->ell + d) * pw, pw * 8, hipMemcpyDeviceToDevice, c->stream));
+    FR_HIP(hipMemcpyAsync(t, db->data + ((size_t)g * db->ell + d) * db->nl * c->N, pw * 8, hipMemcpyDeviceToDevice,
+                          c->stream));
     frk::mont_scale(c, t, db->level + 1, qmap(), 1, 0, false);
     frk::ntt_inv(c, t, db->level + 1, qmap(), 1, 0);
     FR_HIP(hipMemcpyAsync(host, t, pw * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1210,6 +1214,51 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
 // giant step one key read for the whole chunk, and one ModDown per query.
 static const int kMatvecChunk = 8;
 
+// Giant steps of qn queries from their rescaled inner sums R =
+// [qn][n2][2][l+1][N]: out[q] = R_{q,0} + sum_j Rot_{j n1}(R_{q,j}), every
+// rotation's key inner product summed over Q_l U P before one ModDown per
+// query (Eq. bsgs2).
+static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2, int n1, int l, u64 *const *outp) {
+    Scope sc(c->arena);
+    const int N = c->N, nE = l + 1 + c->nP, ndig = num_digits(c, l);
+    const size_t rw = (size_t)2 * (l + 1) * N, lwl = (size_t)(l + 1) * N, dstride = (size_t)ndig * nE * N;
+    // S_q = R_{q,0} + sum_j sigma_j(R_{q,j}.c0) + ModDown(sum_j KS_j); staged
+    // contiguously unless there is a single query
+    u64 *S = qn == 1 ? outp[0] : scratch(c, (size_t)qn * rw);
+    CHECK(S, FR_ENOMEM, "giant steps: scratch");
+    if (qn == 1)
+        FR_HIP(hipMemcpyAsync(S, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
+    else
+        FR_HIP(hipMemcpy2DAsync(S, rw * 8, R, n2 * rw * 8, rw * 8, qn, hipMemcpyDeviceToDevice, c->stream));
+    if (n2 > 1) {
+        // ModUp of every R_{q,j}.c1 (flat item f = q n2 + j, f >= 1; the
+        // j = 0 items of later queries are converted and left unused)
+        u64 *D = scratch(c, ((size_t)qn * n2 - 1) * dstride);
+        u64 *U = scratch(c, (size_t)qn * 2 * nE * N);
+        CHECK(D && U, FR_ENOMEM, "giant steps: scratch");
+        ks_modup(c, R + rw + lwl, l, D, qn * n2 - 1, rw);
+        std::vector<const u64 *> kp(n2 - 1);
+        std::vector<u64> gp(n2 - 1);
+        for (int j = 1; j < n2; ++j) {
+            gp[j - 1] = galois_element(N, j * n1);
+            kp[j - 1] = K->find(gp[j - 1])->data;
+        }
+        // all giant-step key inner products summed in one pass per chunk
+        const int chunk = frk::ks_inner_sum_chunk(c, l);
+        for (int j0 = 0; j0 < n2 - 1; j0 += chunk) {
+            const int nj = std::min(chunk, n2 - 1 - j0);
+            frk::ks_inner_sum(c, U, U + (size_t)nE * N, D + (size_t)j0 * dstride, kp.data() + j0, gp.data() + j0, nj,
+                              dstride, l, j0 > 0, qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
+        }
+        frk::automorph_sum(c, S, R + rw, gp.data(), n2 - 1, l + 1, qn, rw, rw, (size_t)n2 * rw);
+        ks_moddown_into(c, U, qn, l, S, lwl, true);
+    }
+    if (qn > 1)
+        for (int qq = 0; qq < qn; ++qq)
+            FR_HIP(hipMemcpyAsync(outp[qq], S + (size_t)qq * rw, rw * 8, hipMemcpyDeviceToDevice, c->stream));
+    return FR_OK;
+}
+
 static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, int n1, const fr_db *const *dbs,
                        const int32_t *groups, fr_ct *out) {
     const fr_db *db0 = dbs[0];
@@ -1219,8 +1268,8 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
         CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
         CHECK(groups[q] >= 0 && groups[q] < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range",
               groups[q]);
-        CHECK(db->ell == db0->ell && db->level == db0->level, FR_EINVAL,
-              "fr_bsgs_diag_matvec_batch: databases differ in ell or level");
+        CHECK(db->ell == db0->ell && db->level == db0->level && db->nl == db0->nl, FR_EINVAL,
+              "fr_bsgs_diag_matvec_batch: databases differ in ell, level or extension");
     }
     const int N = c->N, ell = db0->ell, bl = baby[0].level;
     for (int t = 0; t < nq * n1; ++t) {
@@ -1238,15 +1287,13 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
         for (int t = 0; t < nq * n1; ++t)
             CHECK(out[q].data != baby[t].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases a baby step");
     }
-    const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N, lwl = (size_t)(l + 1) * N;
+    const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N;
     auto diag_of = [&](int q) {
-        return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * (dbs[q]->level + 1) * N);
+        return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->nl * N);
     };
     std::vector<int> order(nq);
     for (int q = 0; q < nq; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
-    const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
-    const size_t dstride = (size_t)ndig * nE * N;
     for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
         Scope sc(c->arena);
         const int qn = std::min(kMatvecChunk, nq - q0);
@@ -1258,41 +1305,11 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
             dp[qq] = diag_of(q);
             for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = baby[(size_t)q * n1 + i].data;
         }
-        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, db0->level, lv, bl);
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, db0->nl - 1, lv, bl);
         rescale_dev(c, P, lv, R, qn * n2);
-        // S_q = R_{q,0} + sum_j sigma_j(R_{q,j}.c0) + ModDown(sum_j KS_j); staged
-        // contiguously unless there is a single query
-        u64 *S = qn == 1 ? out[order[q0]].data : scratch(c, (size_t)qn * rw);
-        if (qn == 1)
-            FR_HIP(hipMemcpyAsync(S, R, rw * 8, hipMemcpyDeviceToDevice, c->stream));
-        else
-            FR_HIP(hipMemcpy2DAsync(S, rw * 8, R, n2 * rw * 8, rw * 8, qn, hipMemcpyDeviceToDevice, c->stream));
-        if (n2 > 1) {
-            // ModUp of every R_{q,j}.c1 (flat item f = q n2 + j, f >= 1; the
-            // j = 0 items of later queries are converted and left unused)
-            u64 *D = scratch(c, ((size_t)qn * n2 - 1) * dstride);
-            u64 *U = scratch(c, (size_t)qn * 2 * nE * N);
-            ks_modup(c, R + rw + lwl, l, D, qn * n2 - 1, rw);
-            std::vector<const u64 *> kp(n2 - 1);
-            std::vector<u64> gp(n2 - 1);
-            for (int j = 1; j < n2; ++j) {
-                gp[j - 1] = galois_element(N, j * n1);
-                kp[j - 1] = K->find(gp[j - 1])->data;
-            }
-            // all giant-step key inner products summed in one pass per chunk
-            const int chunk = frk::ks_inner_sum_chunk(c, l);
-            for (int j0 = 0; j0 < n2 - 1; j0 += chunk) {
-                const int nj = std::min(chunk, n2 - 1 - j0);
-                frk::ks_inner_sum(c, U, U + (size_t)nE * N, D + (size_t)j0 * dstride, kp.data() + j0, gp.data() + j0,
-                                  nj, dstride, l, j0 > 0, qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
-            }
-            frk::automorph_sum(c, S, R + rw, gp.data(), n2 - 1, l + 1, qn, rw, rw, (size_t)n2 * rw);
-            ks_moddown_into(c, U, qn, l, S, lwl, true);
-        }
-        if (qn > 1)
-            for (int qq = 0; qq < qn; ++qq)
-                FR_HIP(hipMemcpyAsync(out[order[q0 + qq]].data, S + (size_t)qq * rw, rw * 8, hipMemcpyDeviceToDevice,
-                                      c->stream));
+        std::vector<u64 *> op(qn);
+        for (int qq = 0; qq < qn; ++qq) op[qq] = out[order[q0 + qq]].data;
+        if (int e = giant_steps(c, K, R, qn, n2, n1, l, op.data())) return e;
     }
     FR_HIP(hipGetLastError());
     for (int q = 0; q < nq; ++q) {
@@ -1315,6 +1332,166 @@ extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_c
           "fr_bsgs_diag_matvec_batch: null argument or empty batch");
     c->arena.reset();
     return matvec_impl(c, K, baby, nq, n1, dbs, groups, out);
+}
+
+// ---------------------------------------------------------------------------
+// the BSGS product with the baby steps' ModDown hoisted past the inner sums
+// ---------------------------------------------------------------------------
+// Appends to every diagonal its residues mod the special primes, those of
+// the plaintext's centered integer coefficients (exact mixed-radix lift).
+extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
+    CHECK(c && db, FR_EINVAL, "fr_db_extend: null argument");
+    CHECK(db->ctx == c, FR_EINVAL, "fr_db_extend: database of another context");
+    const int N = c->N, l = db->level, L1 = l + 1, nP = c->nP, nE = L1 + nP;
+    if (db->nl == nE) return FR_OK;
+    const size_t nd = (size_t)db->G * db->ell, lw = (size_t)L1 * N, ew = (size_t)nE * N, pw = (size_t)nP * N;
+    u64 *ext = nullptr;
+    if (hipMalloc(&ext, nd * ew * 8) != hipSuccess)
+        return fr_fail(FR_ENOMEM, "fr_db_extend: cannot allocate %zu bytes of diagonals", nd * ew * 8);
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t batch = 16;
+    u64 *X = scratch(c, batch * lw), *Xp = scratch(c, batch * pw);
+    for (size_t d0 = 0; d0 < nd; d0 += batch) {
+        const int nb = (int)std::min(batch, nd - d0);
+        FR_HIP(hipMemcpy2DAsync(ext + d0 * ew, ew * 8, db->data + d0 * lw, lw * 8, lw * 8, nb, hipMemcpyDeviceToDevice,
+                                c->stream));
+        FR_HIP(hipMemcpyAsync(X, db->data + d0 * lw, nb * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::mont_scale(c, X, L1, qmap(), nb, lw, false);
+        frk::ntt_inv(c, X, L1, qmap(), nb, lw);
+        if (int e = frk::crt_extend(c, Xp, X, l, nb, pw, lw)) {
+            (void)hipFree(ext);
+            return e;
+        }
+        frk::ntt_fwd(c, Xp, nP, pmap(c), nb, pw);
+        frk::mont_scale(c, Xp, nP, pmap(c), nb, pw, true);
+        FR_HIP(hipMemcpy2DAsync(ext + d0 * ew + lw, ew * 8, Xp, pw * 8, pw * 8, nb, hipMemcpyDeviceToDevice,
+                                c->stream));
+    }
+    FR_HIP(hipStreamSynchronize(c->stream));
+    (void)hipFree(db->data);
+    db->data = ext;
+    db->nl = nE;
+    return FR_OK;
+}
+
+// out (np polynomials of l limbs) = Rescale(ModDown(U)) for np polynomials
+// U over Q_l U P (eval domain, nE limbs each; np even)
+static void moddown_rescale(fr_ctx *c, const u64 *U, int np, int l, u64 *out) {
+    Scope sc(c->arena);
+    const int N = c->N, nE = l + 1 + c->nP;
+    if (relin_folds(c)) {
+        // the top limb and the P limbs in coefficient form drive one forward
+        // transform of l limbs whose last pass writes the result
+        u64 *Xu = scratch(c, (size_t)np * nE * N);
+        LimbMap top_and_p{l, INT_MAX, 0, l + 1, c->L + 1};
+        frk::ntt_inv(c, Xu, c->nP + 1, top_and_p, np, (size_t)nE * N, U, (size_t)nE * N);
+        u64 *Z = scratch(c, (size_t)np * l * N);
+        frk::relin_rescale_prep(c, Z, Xu, nullptr, l, np, (size_t)l * N, (size_t)nE * N, 0, true);
+        frk::ntt_fwd_relin_rescale(c, Z, l, np, U, (size_t)nE * N, nullptr, 0, out, (size_t)l * N);
+        return;
+    }
+    u64 *T = scratch(c, (size_t)np * (l + 1) * N);
+    ks_moddown_into(c, U, np / 2, l, T, (size_t)(l + 1) * N, false);
+    rescale_dev(c, T, l, out, np / 2);
+}
+
+// Queries q against group groups[q] of extended databases dbs[q] (one ell,
+// n1 and level, the queries' level).  Per chunk of queries: one ModUp of
+// every c1, the baby steps B_i = (P sigma_i(c0) + U0_i, U1_i) over Q_l U P
+// (no ModDown), the inner sums over Q_l U P in one MAC pass, one merged
+// ModDown + rescale per inner sum, then the giant steps.
+static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int nq, const fr_db *const *dbs,
+                               const int32_t *groups, fr_ct *out) {
+    const fr_db *db0 = dbs[0];
+    CHECK(db0, FR_EINVAL, "fr_bsgs_matvec_hoisted: null database");
+    const int N = c->N, l = db0->level, L1 = l + 1, nE = L1 + c->nP, n1 = db0->n1, ell = db0->ell;
+    for (int q = 0; q < nq; ++q) {
+        const fr_db *db = dbs[q];
+        CHECK(db, FR_EINVAL, "fr_bsgs_matvec_hoisted: null database");
+        CHECK(db->nl == db->level + 1 + c->nP, FR_EINVAL,
+              "fr_bsgs_matvec_hoisted: database not extended to the special primes (fr_db_extend)");
+        CHECK(db->ell == ell && db->level == l && db->n1 == n1, FR_EINVAL,
+              "fr_bsgs_matvec_hoisted_batch: databases differ in ell, n1 or level");
+        CHECK(groups[q] >= 0 && groups[q] < db->G, FR_EINVAL, "fr_bsgs_matvec_hoisted: group %d out of range",
+              groups[q]);
+        if (int e = check_ct(c, &qs[q], "fr_bsgs_matvec_hoisted")) return e;
+        CHECK(qs[q].level == l, FR_ELEVEL, "fr_bsgs_matvec_hoisted: query level %d differs from the database's %d",
+              qs[q].level, l);
+    }
+    CHECK(l >= 1, FR_ELEVEL, "fr_bsgs_matvec_hoisted: no level left to rescale");
+    const int n2 = (ell + n1 - 1) / n1;
+    for (int i = 1; i < n1; ++i)
+        CHECK(K->find(galois_element(N, i)), FR_ENOKEY, "fr_bsgs_matvec_hoisted: no key for baby step %d", i);
+    for (int j = 1; j < n2; ++j)
+        CHECK(K->find(galois_element(N, j * n1)), FR_ENOKEY, "fr_bsgs_matvec_hoisted: no key for giant step %d",
+              j * n1);
+    for (int q = 0; q < nq; ++q) {
+        if (int e = check_out(c, &out[q], l - 1, "fr_bsgs_matvec_hoisted")) return e;
+        for (int t = 0; t < nq; ++t)
+            CHECK(out[q].data != qs[t].data, FR_EINVAL, "fr_bsgs_matvec_hoisted: output aliases a query");
+    }
+    const size_t lw = (size_t)L1 * N, bw = (size_t)2 * nE * N, bq = (size_t)n1 * bw, pw = bw;
+    const int ndig = num_digits(c, l);
+    const size_t dstride = (size_t)ndig * nE * N;
+    auto diag_of = [&](int q) { return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->nl * N); };
+    std::vector<int> order(nq);
+    for (int q = 0; q < nq; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
+    for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
+        Scope sc(c->arena);
+        const int qn = std::min(kMatvecChunk, nq - q0);
+        // the chunk's queries staged contiguously: [qn][2][l+1][N]
+        u64 *C = scratch(c, (size_t)qn * 2 * lw);
+        for (int qq = 0; qq < qn; ++qq)
+            FR_HIP(hipMemcpyAsync(C + qq * 2 * lw, qs[order[q0 + qq]].data, 2 * lw * 8, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        u64 *D = scratch(c, (size_t)qn * dstride);
+        ks_modup(c, C + lw, l, D, qn, 2 * lw);
+        // baby steps over Q_l U P: [qn][n1][2][nE][N]
+        u64 *Bb = scratch(c, (size_t)qn * bq);
+        frk::scale_ext(c, Bb, C, l, qn, bq, 2 * lw);
+        for (int i = 1; i < n1; ++i) {
+            const u64 g = galois_element(N, i);
+            u64 *Ui = Bb + i * bw;
+            frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, qn, dstride, bq, nullptr, 0, C,
+                          2 * lw);
+        }
+        // inner sums over Q_l U P: [qn][n2][2][nE][N]
+        u64 *P = scratch(c, (size_t)qn * n2 * pw);
+        std::vector<const u64 *> bp((size_t)qn * n1), dp(qn);
+        for (int qq = 0; qq < qn; ++qq) {
+            dp[qq] = diag_of(order[q0 + qq]);
+            for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = Bb + qq * bq + i * bw;
+        }
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, nE - 1, nE - 1, nE - 1, l, c->L - l);
+        u64 *R = scratch(c, (size_t)qn * n2 * 2 * l * N);
+        moddown_rescale(c, P, qn * n2 * 2, l, R);
+        std::vector<u64 *> op(qn);
+        for (int qq = 0; qq < qn; ++qq) op[qq] = out[order[q0 + qq]].data;
+        if (int e = giant_steps(c, K, R, qn, n2, n1, l - 1, op.data())) return e;
+    }
+    FR_HIP(hipGetLastError());
+    for (int q = 0; q < nq; ++q) {
+        out[q].level = l - 1;
+        out[q].scale = (qs[q].scale * dbs[q]->scale) / (double)c->mod[l];
+    }
+    return FR_OK;
+}
+
+extern "C" int fr_bsgs_matvec_hoisted(fr_ctx *c, const fr_keys *K, const fr_ct *query, const fr_db *db, int32_t group,
+                                      fr_ct *out) {
+    CHECK(c && K && query && db && out, FR_EINVAL, "fr_bsgs_matvec_hoisted: null argument");
+    c->arena.reset();
+    return matvec_hoisted_impl(c, K, query, 1, &db, &group, out);
+}
+
+extern "C" int fr_bsgs_matvec_hoisted_batch(fr_ctx *c, const fr_keys *K, const fr_ct *queries, int32_t nq,
+                                            const fr_db *const *dbs, const int32_t *groups, fr_ct *out) {
+    CHECK(c && K && queries && dbs && groups && out && nq >= 1, FR_EINVAL,
+          "fr_bsgs_matvec_hoisted_batch: null argument or empty batch");
+    c->arena.reset();
+    return matvec_hoisted_impl(c, K, queries, nq, dbs, groups, out);
 }
 
 // ---------------------------------------------------------------------------

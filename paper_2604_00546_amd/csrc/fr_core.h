@@ -150,7 +150,7 @@ struct fr_ctx {
     // ModDown tables: phat_inv[nP], phat_inv_sh[nP], phat_mod[L+1][nP]
     // (Montgomery-scaled by 2^64 mod q_i),
     // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits),
-    // -e P 2^64 mod q_i [L+1][nP+1] (e = 0..nP)
+    // -e P 2^64 mod q_i [L+1][nP+1] (e = 0..nP), P 2^64 mod q_i [L+1]
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
     u64 P_inv_q[FR_MAXMOD], P_inv_q_sh[FR_MAXMOD];  // P^-1 mod q_i and Shoup companions
@@ -204,8 +204,11 @@ struct fr_keys {
 struct fr_db {
     fr_ctx *ctx;
     int G, ell, B, n1, level;
+    int nl;  // limbs per diagonal: level+1, or level+1+nP once extended
     double scale;
-    u64 *data = nullptr;  // [G][ell][level+1][N] eval domain, Montgomery-scaled
+    // [G][ell][nl][N] eval domain, Montgomery-scaled; limbs 0..level are the
+    // q_i, the extended form appends the special primes p_0..p_{nP-1}
+    u64 *data = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -259,7 +262,8 @@ bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U
                      bool accumulate);
 // last step of a relinearised product merged with its rescale: out[p] =
 // (d[p] + (U[p] - NTT(Z[p])) P^-1) q_l^-1 on limbs 0..l-1 (Z from
-// relin_rescale_prep); false when the ring has no radix-16 kernels
+// relin_rescale_prep; d null: no d term, Rescale(ModDown(U))); false when
+// the ring has no radix-16 kernels
 bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 *U, size_t su, const u64 *d,
                            size_t sd, u64 *out, size_t so);
 void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
@@ -284,25 +288,31 @@ void automorph(const fr_ctx *c, u64 *out, const u64 *in, u64 g, int nlimbs, int 
 // multiply every limb by 2^64 mod q (to Montgomery-scaled) or by 2^-64 (back)
 void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly,
                 size_t poly_stride, bool to_mont);
+// fast base conversion of every digit of `batch` items at once: D[b][t] =
+// [ndig][nE][N] per item (item stride sd), own limbs copied in coefficient
+// form (one forward transform over all nE limbs then completes every digit)
+void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx);
 // fast base conversion of one digit: coefficient-form x[level+1][N] ->
 // D[nE][N] coefficient form on every extended limb outside the digit
-// every digit of `batch` items at once: D[b][t] = [ndig][nE][N] per item
-// (item stride sd), own limbs copied in coefficient form (one forward
-// transform over all nE limbs then completes every digit)
-void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx);
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,
                  size_t sx = 0);
 // U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p];
 // with fold_d (relinearisation, items fold_sd words apart) the top limb e =
-// level is replaced by d_l + P^-1 U_l (its only later use)
+// level is replaced by d_l + P^-1 U_l (its only later use); with rot_c0
+// (items c0_sd words apart, level+1 limbs) U0 also takes P c0[e][auto_src(p,
+// g)] on the limbs e <= level: the rotation of (c0, c1) held over Q_l U P,
+// before its ModDown
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
               bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0, const u64 *fold_d = nullptr,
-              size_t fold_sd = 0);
-// ModDown of U (eval domain, P limbs already coefficient form in Upc):
-// giant steps of rotations per key-sum launch at this level (bounded so the
+              size_t fold_sd = 0, const u64 *rot_c0 = nullptr, size_t c0_sd = 0);
+// out[b][p][e] = P in[b][p][e] on the limbs e <= level and 0 on the special
+// limbs (a ciphertext at level `level` lifted to Q_l U P; out items so words
+// apart, polynomials nE limbs apart; in items si words apart)
+void scale_ext(const fr_ctx *c, u64 *out, const u64 *in, int level, int nb, size_t so, size_t si);
 // t01 = (sum a0 b0, sum a0 b1 + a1 b0), t2 = sum a1 b1 over n ciphertext
 // pairs (nl limbs per polynomial; t01 = [2][nl][N], t2 = [nl][N])
 void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *const *a, const u64 *const *b);
+// giant steps of rotations per key-sum launch at this level (bounded so the
 // 128-bit lazy sums cannot overflow)
 int ks_inner_sum_chunk(const fr_ctx *c, int level);
 // U{0,1} (+)= sum over nj rotations (keys ksk[j], Galois elements g[j]; their
@@ -314,9 +324,14 @@ void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int n
                    size_t sij, size_t sib);
 // Z[p][i] (i < level) for the merged ModDown + rescale of relinearised
 // products: Xu holds the coefficient forms of U's limbs level..level+nP at
-// their storage positions, Xd that of d's limb level
+// their storage positions, Xd that of d's limb level; Xd null: U's limb
+// level already holds d_l + P^-1 U_l, or (no_d) there is no d term
 void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, int level, int npoly, size_t sz,
-                        size_t sxu, size_t sxd);
+                        size_t sxu, size_t sxd, bool no_d = false);
+// exact residues mod the special primes of the centered integers (-Q_l/2,
+// Q_l/2] given by their level+1 limbs (coefficient form): Xp[b][j][N] from
+// X[b][level+1][N] (mixed-radix digits, no floating point)
+int crt_extend(fr_ctx *c, u64 *Xp, const u64 *X, int level, int npoly, size_t sxp, size_t sx);
 // v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly);
 // out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)
@@ -331,8 +346,10 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 // queries: baby[q * n1 + i] is baby step i of query q, diag[q] the diagonal
 // group it is scored against (queries sharing a group should be adjacent);
 // the n2 outputs of query q start at P + q * pq
+// Limbs m > lq use the modulus m + pofs (a product over Q_lq U P with the
+// special primes stored after limb lq).
 void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
-              int ell, int db_level, int level, int baby_level);
+              int ell, int db_level, int level, int baby_level, int lq = 1 << 30, int pofs = 0);
 // batched element-wise helpers (items addressed by pointer)
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
 // polynomials of every source; out items contiguous [B][2][nl][N]

@@ -34,8 +34,8 @@ struct NttLaunch {
     // (+ epi_out if epi_acc) instead of y (rescale or ModDown finish)
     int pre_top;
     int epi_acc;
-    // epi_in2 != nullptr: epi_out = (epi_in2 + (epi_in - y) qinv) qinv2
-    // (ModDown merged with the rescale of a relinearised product)
+    // qinv2 != nullptr: epi_out = (epi_in2 + (epi_in - y) qinv) qinv2, without
+    // the epi_in2 term when it is null (ModDown merged with a rescale)
     const u64 *epi_in2;
     size_t epi_in2_stride;
     const u64 *qinv2, *qinv2_sh;
@@ -382,13 +382,14 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
         const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
         u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
         const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
-        if (a.epi_in2) {
-            const u64 *in2 = a.epi_in2 + blockIdx.y * a.epi_in2_stride + w;
+        if (a.qinv2) {
+            const u64 *in2 = a.epi_in2 ? a.epi_in2 + blockIdx.y * a.epi_in2_stride + w : nullptr;
             const u64 q2i = a.qinv2[mi], q2s = a.qinv2_sh[mi];
 #pragma unroll
             for (int k = 0; k < E; ++k) {
-                const u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
-                out[u0 + E * k] = shoup(addq(in2[u0 + E * k], r, q), q2i, q2s, q);
+                u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
+                if (in2) r = addq(in2[u0 + E * k], r, q);
+                out[u0 + E * k] = shoup(r, q2i, q2s, q);
             }
             return;
         }

@@ -169,7 +169,8 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
                                                  const ModConst *mods, int accumulate, size_t sd, size_t su,
                                                  int batch, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
-                                                 u64 pinv_top_sh) {
+                                                 u64 pinv_top_sh, const u64 *rot_c0, size_t c0_sd,
+                                                 const u64 *pmont) {
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
     const int p = tile * kT + threadIdx.x, e = blockIdx.y;
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
         mac128(l0, h0, d, kb);
         mac128(l1, h1, d, ka);
     }
+    if (rot_c0 && e <= level) mac128(l0, h0, rot_c0[item * c0_sd + (size_t)e * N + src], pmont[e]);
     u64 u0 = redc_any(l0, h0, m), u1 = redc_any(l1, h1, m);
     const size_t w = (size_t)e * N + p;
     if (accumulate) {
@@ -301,7 +303,8 @@ __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, G
 // in a [nE][N] layout per polynomial; Xd: coefficient form of d's limb l.
 __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu, const u64 *Xd, int N, int level,
                                                            int nP, int pbase, int L1, const u64 *tab,
-                                                           const ModConst *mods, size_t sz, size_t sxu, size_t sxd) {
+                                                           const ModConst *mods, size_t sz, size_t sxu, size_t sxd,
+                                                           int no_d) {
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
     const u64 *pinv = tab + 2 * nP + (size_t)L1 * nP, *pinv_sh = pinv + L1;
@@ -327,10 +330,15 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
     };
     const ModConst mt = mods[level];
     const u64 qt = mt.q;
-    // folded (Xd null): limb `level` of U already holds d_l + P^-1 U_l
-    const u64 x = Xd ? addq(Xd[poly * sxd + k], shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt),
-                            qt)
-                     : subq(xu[0], shoup(fbc(level, mt), pinv[level], pinv_sh[level], qt), qt);
+    // folded (Xd null): limb `level` of U already holds d_l + P^-1 U_l;
+    // no_d: x = P^-1 (U_l - FBC_l), the top limb of ModDown(U) alone
+    u64 x;
+    if (Xd || no_d) {
+        x = shoup(subq(xu[0], fbc(level, mt), qt), pinv[level], pinv_sh[level], qt);
+        if (Xd) x = addq(Xd[poly * sxd + k], x, qt);
+    } else {
+        x = subq(xu[0], shoup(fbc(level, mt), pinv[level], pinv_sh[level], qt), qt);
+    }
     const bool neg = x > (qt >> 1);
     const u64 mag = neg ? qt - x : x;
     const int i0 = blockIdx.y * kFbcTargets, i1 = min(level, i0 + kFbcTargets);
@@ -471,7 +479,7 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 template <int NJ, bool FULL>
 __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
                                                   int nj, int ell, int dbl, int bl, int lv, int N,
-                                                  const ModConst *mods, int accumulate) {
+                                                  const ModConst *mods, int accumulate, int lq, int pofs) {
     int q, tile;
     item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
     const int lane = threadIdx.x & 63, p = lane >> 5;
@@ -501,7 +509,7 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
     }
-    const ModConst mc = mods[m];
+    const ModConst mc = mods[m <= lq ? m : m + pofs];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
         if (jj < nj) {
@@ -616,7 +624,69 @@ __global__ __launch_bounds__(kT) void k_tensor_batch(u64 *t01, u64 *t2, TensorBa
     t2[b * lw + w] = mulmod(x1, y1, m);
 }
 
+// out[b][p][e] = P in[b][p][e] (e <= level), 0 on the special limbs: a
+// ciphertext lifted to Q_l U P (pmont: P 2^64 mod q_e)
+__global__ __launch_bounds__(kT) void k_scale_ext(u64 *out, const u64 *in, int level, int nE, int N, size_t so,
+                                                  size_t si, const u64 *pmont, const ModConst *mods) {
+    const int k = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, p = blockIdx.z & 1, b = blockIdx.z >> 1;
+    u64 r = 0;
+    if (e <= level) {
+        const u64 x = in[b * si + ((size_t)p * (level + 1) + e) * N + k], pm = pmont[e];
+        r = redc(x * pm, mulhi64(x, pm), mods[e]);
+    }
+    out[b * so + ((size_t)p * nE + e) * N + k] = r;
+}
+
+// Exact residues mod the special primes of centered integers given by
+// their limbs mod q_0..q_l (coefficient form).  Garner's mixed-radix digits
+//   v_0 = x_0,  v_i = ((x_i - v_0) q_0^-1 - v_1) q_1^-1 ... - v_{i-1}) q_{i-1}^-1 mod q_i,
+// give m = sum_i v_i M_i (M_i = q_0 .. q_{i-1}) in [0, Q); m is negative in
+// centered form when its digits exceed those of (Q-1)/2 (compared from the
+// top); then [m]_p = sum_i v_i [M_i]_p (- [Q]_p).  Table (per level l,
+// L1 = l+1): inv[L1][L1] (q_k^-1 mod q_i at [i][k]), mp[L1][nP] ([M_i]_{p_j}
+// 2^64, Montgomery), qp[nP] ([Q]_{p_j}), h[L1] (digits of (Q-1)/2).
+constexpr int kCrtMax = 32;
+__global__ __launch_bounds__(kT) void k_crt_extend(u64 *Xp, const u64 *X, int N, int level, int nP, int pbase,
+                                                   const u64 *tab, const ModConst *mods, size_t sxp, size_t sx) {
+    const int k = blockIdx.x * kT + threadIdx.x, b = blockIdx.z, L1 = level + 1;
+    const u64 *inv = tab, *mp = tab + (size_t)L1 * L1, *qp = mp + (size_t)L1 * nP, *h = qp + nP;
+    const u64 *x = X + b * sx + k;
+    u64 v[kCrtMax];
+#pragma unroll
+    for (int i = 0; i < kCrtMax; ++i) {
+        if (i < L1) {
+            const ModConst mi = mods[i];
+            u64 t = x[(size_t)i * N];
+            for (int j = 0; j < i; ++j) t = mulmod(subq(t, reduce64(v[j], mi), mi.q), inv[(size_t)i * L1 + j], mi);
+            v[i] = t;
+        }
+    }
+    bool neg = false;
+    for (int i = level; i >= 0; --i) {
+        if (v[i] != h[i]) {
+            neg = v[i] > h[i];
+            break;
+        }
+    }
+    for (int j = 0; j < nP; ++j) {
+        const ModConst mj = mods[pbase + j];
+        u64 lo = 0, hi = 0;
+#pragma unroll
+        for (int i = 0; i < kCrtMax; ++i)
+            if (i < L1) mac128(lo, hi, v[i], mp[(size_t)i * nP + j]);
+        u64 r = redc_any(lo, hi, mj);
+        if (neg) r = subq(r, qp[j], mj.q);
+        Xp[b * sxp + (size_t)j * N + k] = r;
+    }
+}
+
 inline dim3 grid(const fr_ctx *c, int ny, int nz) { return dim3(c->N / kT, ny, nz); }
+
+// P 2^64 mod q_i [L+1], the last ModDown table
+inline const u64 *pmont_tab(const fr_ctx *c) {
+    const int L1 = c->L + 1, nP = c->nP;
+    return c->d_moddown + 2 * nP + (size_t)L1 * nP + 3 * (size_t)L1 + nP + (size_t)L1 * (nP + 1);
+}
 
 }  // namespace
 
@@ -702,11 +772,12 @@ void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size
 }
 
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate,
-              int batch, size_t sd, size_t su, const u64 *fold_d, size_t fold_sd) {
+              int batch, size_t sd, size_t su, const u64 *fold_d, size_t fold_sd, const u64 *rot_c0, size_t c0_sd) {
     const int nE_ = level + 1 + c->nP, nd_ = (level + 1 + c->alpha - 1) / c->alpha;
-    // digits and outputs per batch item, the shared key once
+    // digits and outputs per batch item (and c0 when folded in), the shared key once
     ProfScope ps(c, K_KS,
-                 (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_) + 2.0 * nd_ * nE_) * 8.0 * c->N);
+                 (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_ + (rot_c0 ? level + 1.0 : 0.0)) +
+                  2.0 * nd_ * nE_) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
     u64 pinv = 0, pinv_sh = 0;
@@ -716,7 +787,14 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
     }
     hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
                        c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch, fold_d,
-                       fold_sd, pinv, pinv_sh);
+                       fold_sd, pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
+}
+
+void scale_ext(const fr_ctx *c, u64 *out, const u64 *in, int level, int nb, size_t so, size_t si) {
+    const int nE = level + 1 + c->nP;
+    ProfScope ps(c, K_ELEM, nb * 2.0 * (level + 1 + nE) * 8.0 * c->N);
+    hipLaunchKernelGGL(k_scale_ext, grid(c, nE, 2 * nb), dim3(kT), 0, c->stream, out, in, level, nE, c->N, so, si,
+                       pmont_tab(c), c->d_mod);
 }
 
 void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *const *a, const u64 *const *b) {
@@ -765,11 +843,11 @@ void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int n
 }
 
 void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, int level, int npoly, size_t sz,
-                        size_t sxu, size_t sxd) {
+                        size_t sxu, size_t sxd, bool no_d) {
     ProfScope ps(c, K_MODDOWN, npoly * (2.0 + c->nP + 1.0 * level) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + kFbcTargets - 1) / kFbcTargets, npoly);
     hipLaunchKernelGGL(k_relin_rescale_prep, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
-                       c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd);
+                       c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd, (int)no_d);
 }
 
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
@@ -805,7 +883,7 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 
 template <int NJ>
 static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1,
-                        const u64 *const *diag, int ell, int db_level, int level, int baby_level) {
+                        const u64 *const *diag, int ell, int db_level, int level, int baby_level, int lq, int pofs) {
     const int n2 = (ell + n1 - 1) / n1;
     for (int q0 = 0; q0 < nq; q0 += kMacQ) {
         const int qn = std::min(kMacQ, nq - q0);
@@ -831,7 +909,7 @@ static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *ba
                 const bool full = nj == NJ && (j0 + NJ - 1) * n1 + i0 + nb - 1 < ell;
                 auto kern = full ? k_bsgs_mac3<NJ, true> : k_bsgs_mac3<NJ, false>;
                 hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, P + q0 * pq, pq, bp, qn, nb, i0, n1, j0, nj, ell,
-                                   db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0));
+                                   db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0), lq, pofs);
             }
         }
     }
@@ -839,18 +917,18 @@ static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *ba
 
 // giant steps per thread: 16, or the smallest power of two covering n2
 void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
-              int ell, int db_level, int level, int baby_level) {
+              int ell, int db_level, int level, int baby_level, int lq, int pofs) {
     const int n2 = (ell + n1 - 1) / n1;
     if (n2 > 8)
-        bsgs_mac_nj<16>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+        bsgs_mac_nj<16>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
     else if (n2 > 4)
-        bsgs_mac_nj<8>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+        bsgs_mac_nj<8>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
     else if (n2 > 2)
-        bsgs_mac_nj<4>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+        bsgs_mac_nj<4>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
     else if (n2 > 1)
-        bsgs_mac_nj<2>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+        bsgs_mac_nj<2>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
     else
-        bsgs_mac_nj<1>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level);
+        bsgs_mac_nj<1>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
 }
 
 void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,
@@ -964,6 +1042,40 @@ void encrypt_combine(const fr_ctx *c, u64 *c0, u64 *c1, const u64 *v, const u64 
 void decrypt_combine(const fr_ctx *c, u64 *out, const u64 *c0, const u64 *c1, const u64 *s_mont, int nlimbs) {
     hipLaunchKernelGGL(k_decrypt_combine, grid(c, nlimbs, 1), dim3(kT), 0, c->stream, out, c0, c1, s_mont, c->N,
                        c->d_mod);
+}
+
+int crt_extend(fr_ctx *c, u64 *Xp, const u64 *X, int level, int npoly, size_t sxp, size_t sx) {
+    const int L1 = level + 1, nP = c->nP;
+    if (L1 > kCrtMax) return fr_fail(FR_EINVAL, "crt_extend: %d limbs exceed %d", L1, kCrtMax);
+    std::vector<u64> t((size_t)L1 * L1 + (size_t)L1 * nP + nP + L1, 0);
+    u64 *inv = t.data(), *mp = inv + (size_t)L1 * L1, *qp = mp + (size_t)L1 * nP, *h = qp + nP;
+    for (int i = 0; i < L1; ++i)
+        for (int j = 0; j < i; ++j) inv[(size_t)i * L1 + j] = frh::invmod_h(c->mod[j] % c->mod[i], c->mod[i]);
+    for (int j = 0; j < nP; ++j) {
+        const u64 p = c->mod[c->L + 1 + j], r64 = (0 - p) % p;
+        u64 M = 1 % p;
+        for (int i = 0; i < L1; ++i) {
+            mp[(size_t)i * nP + j] = frh::mulmod_h(M, r64, p);
+            M = frh::mulmod_h(M, c->mod[i] % p, p);
+        }
+        qp[j] = M;
+    }
+    // (Q-1)/2 digit by digit from the top: Q-1 has the digits q_i - 1
+    u64 r = 0;
+    for (int i = level; i >= 0; --i) {
+        const u64 cur = (c->mod[i] - 1) + r * c->mod[i];
+        h[i] = cur >> 1;
+        r = cur & 1;
+    }
+    u64 *d = (u64 *)c->arena.get(t.size() * 8);
+    if (!d) return fr_fail(FR_ENOMEM, "crt_extend: scratch");
+    if (hipMemcpyAsync(d, t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return fr_fail(FR_EHIP, "crt_extend: table upload");
+    hipLaunchKernelGGL(k_crt_extend, dim3(c->N / kT, 1, npoly), dim3(kT), 0, c->stream, Xp, X, c->N, level, nP,
+                       c->L + 1, d, c->d_mod, sxp, sx);
+    // the table lives in host memory until the copy has run
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fr_fail(FR_EHIP, "crt_extend: synchronize");
+    return FR_OK;
 }
 
 }  // namespace frk

@@ -79,6 +79,9 @@ SIGNATURES = {
     "fr_db_import": (C.c_int, [_P, _U64P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                C.POINTER(_P)]),
     "fr_db_export": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _U64P]),
+    "fr_db_extend": (C.c_int, [_P, _P]),
+    "fr_bsgs_matvec_hoisted": (C.c_int, [_P, _P, _CTP, _P, C.c_int32, _CTP]),
+    "fr_bsgs_matvec_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, _I32P, _CTP]),
     "fr_db_groups": (C.c_int, [_P]),
     "fr_db_destroy": (None, [_P]),
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
@@ -242,6 +245,12 @@ class Db:
         out = np.zeros((self.level + 1) * self.ctx.N, dtype=np.uint64)
         _check(lib().fr_db_export(self.ctx.ptr, self.ptr, g, d, _u64(out)), "fr_db_export")
         return out.reshape(self.level + 1, self.ctx.N)
+
+    def extend(self) -> "Db":
+        """Append every diagonal's residues mod the special primes (needed by
+        the hoisted product; idempotent)."""
+        _check(lib().fr_db_extend(self.ctx.ptr, self.ptr), "fr_db_extend")
+        return self
 
 
 class Context:
@@ -461,6 +470,34 @@ class Context:
         dptr = (C.c_void_p * nq)(*[d.ptr for d in dbs])
         _check(lib().fr_bsgs_diag_matvec_batch(self.ptr, keys.ptr, arr, nq, n1, dptr, grp.ctypes.data_as(_I32P),
                                                oarr), "fr_bsgs_diag_matvec_batch")
+        for o, d in zip(outs, oarr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
+
+    def bsgs_matvec_hoisted(self, keys: Keys, query: Ct, db: Db, group: int = 0, out: Ct | None = None) -> Ct:
+        """Score ciphertext from the query itself, baby steps held over Q_l U P
+        (db extended)."""
+        if out is None:
+            out = self.new_ct(max(query.level - 1, 0))
+        _check(lib().fr_bsgs_matvec_hoisted(self.ptr, keys.ptr, query.ref, db.ptr, group, out.ref),
+               "fr_bsgs_matvec_hoisted")
+        return out
+
+    def bsgs_matvec_hoisted_batch(self, keys: Keys, queries: Sequence[Ct], db, group=0,
+                                  outs: List[Ct] | None = None) -> List[Ct]:
+        """One score ciphertext per query; db / group: one for all, or one per query."""
+        queries = list(queries)
+        nq = len(queries)
+        dbs = list(db) if isinstance(db, (list, tuple)) else [db] * nq
+        grp = np.ascontiguousarray(list(group) if isinstance(group, (list, tuple)) else [group] * nq,
+                                   dtype=np.int32)
+        arr = (CtDesc * nq)(*[q.desc for q in queries])
+        if outs is None:
+            outs = [self.new_ct(max(q.level - 1, 0)) for q in queries]
+        oarr = (CtDesc * nq)(*[o.desc for o in outs])
+        dptr = (C.c_void_p * nq)(*[d.ptr for d in dbs])
+        _check(lib().fr_bsgs_matvec_hoisted_batch(self.ptr, keys.ptr, arr, nq, dptr, grp.ctypes.data_as(_I32P),
+                                                  oarr), "fr_bsgs_matvec_hoisted_batch")
         for o, d in zip(outs, oarr):
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs

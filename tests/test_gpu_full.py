@@ -86,6 +86,22 @@ def test_full_hot_path_bitexact(F, gctx, config2):
     assert np.max(np.abs(dec[len(exact):])) <= 2 ** -20
 
 
+@pytest.mark.timeout(900)
+def test_full_hoisted_bitexact(F, gctx, config2):
+    """The product with the baby steps held over Q_l U P (one ModDown per
+    inner sum) at N = 2^16 over one group of 512 diagonals: the oracle's
+    words, and scores within 2^-20."""
+    g, c = gctx, config2
+    gdb = c["gdb"].extend()
+    gs = g.bsgs_matvec_hoisted(c["kg"], c["gq"], gdb, 0)
+    os_ = c["o"].bsgs_matvec_hoisted(c["ko"], c["oq"], c["odb"], 0)
+    _same(g, gs, os_)
+    exact = c["wl"].exact_scores()
+    dec = g.decrypt_decode(c["kg"], gs)
+    assert np.max(np.abs(dec[: len(exact)] - exact)) <= 2 ** -20
+    assert np.max(np.abs(dec[len(exact):])) <= 2 ** -20
+
+
 def test_full_size_encoder_within_one(F, gctx, config2):
     """Device encoder of the pre-rotated diagonals vs the oracle's, sampled diagonals."""
     g, c = gctx, config2
@@ -121,6 +137,11 @@ def test_identification_2p15(F, gctx):
         y = g.decrypt_decode(keys, Y)
         assert np.max(np.abs(y - np.polynomial.chebyshev.chebval(exact, coeffs))) <= 2 ** -12
         assert np.array_equal(np.nonzero(y >= 0.5)[0], wl.planted)
+    # the hoisted product (baby steps over Q_l U P) scores the same
+    H = g.bsgs_matvec_hoisted(keys, q, db.extend(), 0)
+    assert np.max(np.abs(g.decrypt_decode(keys, H) - exact)) <= 2 ** -20
+    YH = g.decrypt_decode(keys, g.chebyshev_eval(keys, H, coeffs, 8))
+    assert np.array_equal(np.nonzero(YH >= 0.5)[0], wl.planted)
     # membership: the sum of the polynomial over all 2^15 slots in every slot
     # (328 planted matches plus the ripple of the degree-63 step elsewhere)
     count = g.decrypt_decode(keys, g.membership_aggregate(keys, [Y]))
@@ -159,3 +180,12 @@ def test_batched_path_equals_alone_2p15(F, gctx):
         assert np.max(np.abs(g.decrypt_decode(keys, S[q]) - exact)) <= 2 ** -20
     y0 = g.decrypt_decode(keys, Y[0])
     assert np.array_equal(np.nonzero(y0 >= 0.5)[0], wl.planted)
+    # hoisted product, batched and alone
+    db.extend()
+    HB = g.bsgs_matvec_hoisted_batch(keys, qs, db, 0)
+    for q in range(3):
+        h1 = g.bsgs_matvec_hoisted(keys, qs[q], db, 0)
+        assert (h1.level, h1.scale) == (HB[q].level, HB[q].scale)
+        assert np.array_equal(g.ct_export(h1), g.ct_export(HB[q]))
+        exact = wl.templates.astype(np.float64) @ Q[q].astype(np.float64)
+        assert np.max(np.abs(g.decrypt_decode(keys, HB[q]) - exact)) <= 2 ** -20
