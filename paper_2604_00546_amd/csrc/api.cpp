@@ -1731,33 +1731,58 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
             u64 *stage = scratch(c, (size_t)B * sw);
             u64 *out = scratch(c, (size_t)B * ow);
-            std::vector<ScalarItem> items(B);
+            // the integer terms (source node, k) of every node of the wave
+            const int nL = (int)L.size();
+            std::vector<std::vector<std::pair<int, long long>>> terms(nL);
             std::vector<long long> cst(B, 0);
             bool any_const = false;
-            for (int b = 0; b < B; ++b) {
-                const CNode &nd = nodes[L[b / nq]];
-                const int q = b % nq;
-                ScalarItem &it = items[b];
+            for (int j = 0; j < nL; ++j) {
+                const CNode &nd = nodes[L[j]];
                 if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
                     const int la = nodes[nd.a].level;
                     const long long k = nd.op == C_ADJUST
                                             ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
                                             : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
-                    it.src.push_back(B_(nd.a, q));
-                    it.k.push_back(k);
-                    it.lp1.push_back(la + 1);
+                    terms[j].push_back({nd.a, k});
                 } else {
                     for (size_t t = 0; t < nd.ins.size(); ++t) {
                         const int src = nd.ins[t], ls = nodes[src].level;
-                        it.src.push_back(B_(src, q));
-                        it.k.push_back(rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls]));
-                        it.lp1.push_back(ls + 1);
+                        terms[j].push_back(
+                            {src, rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls])});
                     }
-                    cst[b] = rne_ll(nd.cf[0] * D[lam]);
+                    for (int q = 0; q < nq; ++q) cst[j * nq + q] = rne_ll(nd.cf[0] * D[lam]);
                     any_const = true;
                 }
             }
-            frk::scalar_batch(c, stage, lam + 2, B, items.data());
+            // every source of the wave read once for all its outputs when
+            // they are few, else item by item
+            std::vector<int> su;
+            for (auto &tj : terms)
+                for (auto &t : tj)
+                    if (std::find(su.begin(), su.end(), t.first) == su.end()) su.push_back(t.first);
+            const int ns = (int)su.size();
+            std::vector<long long> Km((size_t)nL * ns, 0);
+            std::vector<int> slp1(ns);
+            std::vector<const u64 *> sp((size_t)nq * ns);
+            for (int s = 0; s < ns; ++s) {
+                slp1[s] = nodes[su[s]].level + 1;
+                for (int q = 0; q < nq; ++q) sp[(size_t)q * ns + s] = B_(su[s], q);
+            }
+            for (int j = 0; j < nL; ++j)
+                for (auto &t : terms[j]) {
+                    const int s = (int)(std::find(su.begin(), su.end(), t.first) - su.begin());
+                    Km[(size_t)j * ns + s] += t.second;
+                }
+            if (!frk::scalar_mat(c, stage, lam + 2, nL, nq, sp.data(), slp1.data(), ns, Km.data(), nq * sw, sw)) {
+                std::vector<ScalarItem> items(B);
+                for (int b = 0; b < B; ++b)
+                    for (auto &t : terms[b / nq]) {
+                        items[b].src.push_back(B_(t.first, b % nq));
+                        items[b].k.push_back(t.second);
+                        items[b].lp1.push_back(nodes[t.first].level + 1);
+                    }
+                frk::scalar_batch(c, stage, lam + 2, B, items.data());
+            }
             rescale_dev(c, stage, lam + 1, out, B);
             if (any_const) frk::add_const_batch(c, out, lam + 1, B, cst.data(), ow);
             for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * ow;

@@ -354,6 +354,13 @@ void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
 // polynomials of every source; out items contiguous [B][2][nl][N]
 void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const ScalarItem *items);
+// out[b][q] = sum_s K[b][s] src[q][s] (src [nq][ns] pointers, sources of
+// lp1[s] limbs per polynomial; K [nb][ns] small signed integers) on the
+// first nl limbs of both polynomials, output (b, q) at out + b ob + q oq;
+// each source read once for all outputs.  False (nothing launched) beyond
+// 16 outputs, 16 sources or 8 queries.
+bool scalar_mat(const fr_ctx *c, u64 *out, int nl, int nb, int nq, const u64 *const *src, const int *lp1, int ns,
+                const long long *K, size_t ob, size_t oq);
 // c0 limbs of item b (items `item` words apart) += v[b]
 void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item);
 // out[b] = a[b] +/- b[b] (+ cst[b] on c0)

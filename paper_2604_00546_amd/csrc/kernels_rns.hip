@@ -341,12 +341,18 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
     }
     const bool neg = x > (qt >> 1);
     const u64 mag = neg ? qt - x : x;
+    // Z_i = FBC_i + [P]_{q_i} [c]_{q_i}: the product with |c| joins the same
+    // Montgomery sum, against P 2^64 (or -P 2^64) mod q_i
+    const u64 *pm = epm + (size_t)L1 * (nP + 1);
     const int i0 = blockIdx.y * kFbcTargets, i1 = min(level, i0 + kFbcTargets);
     for (int i = i0; i < i1; ++i) {
         const ModConst mi = mods[i];
-        const u64 r = reduce64(mag, mi);
-        const u64 ci = neg ? (r ? mi.q - r : 0) : r;
-        Z[poly * sz + (size_t)i * N + k] = addq(fbc(i, mi), mulmod(ci, pmod[i], mi), mi.q);
+        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDigit; ++j)
+            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
+        mac128(al, ah, mag, neg ? mi.q - pm[i] : pm[i]);
+        Z[poly * sz + (size_t)i * N + k] = redc_any(al, ah, mi);
     }
 }
 
@@ -575,6 +581,46 @@ __global__ __launch_bounds__(kT) void k_scalar_batch(u64 *out, ScalarBatch sb, i
         acc = addq(acc, mulmod(x, smod_dev(sb.k[b][t], m), m), m.q);
     }
     *o = acc;
+}
+
+// Scalar combinations sharing their sources (a wave of Chebyshev leaves,
+// scalars and level adjustments): for query q (blockIdx.z) and output b,
+//   out[b][q] = sum_s K[b][s] src[q][s]   on the first nl limbs of both polynomials,
+// K small signed integers, reduced per limb and Montgomery-scaled into LDS
+// by the block.  A thread reads its word of every source once, then forms
+// each output as a 128-bit lazy sum of at most kMatS products below 2^122,
+// reduced once; zero entries are skipped by a per-output bit mask (uniform).
+constexpr int kMatS = 16, kMatB = 16, kMatQ = 8;
+struct ScalarMat {
+    const u64 *src[kMatQ][kMatS];
+    int lp1[kMatS];  // (level + 1) of each source: its polynomial stride in limbs
+    long long k[kMatB][kMatS];
+    unsigned nz[kMatB];  // bit s: K[b][s] != 0
+    int ns, nb;
+};
+__global__ __launch_bounds__(kT) void k_scalar_mat(u64 *out, size_t ob, size_t oq, ScalarMat sm, int nl, int N,
+                                                   const ModConst *mods) {
+    __shared__ u64 kc[kMatB * kMatS];
+    const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y % nl, p = blockIdx.y / nl, q = blockIdx.z;
+    const ModConst m = mods[i];
+    for (int t = threadIdx.x; t < kMatB * kMatS; t += kT) {
+        const int b = t / kMatS, s = t % kMatS;
+        kc[t] = (b < sm.nb && s < sm.ns) ? shoup(smod_dev(sm.k[b][s], m), m.r64, m.r64_sh, m.q) : 0;
+    }
+    u64 x[kMatS];
+#pragma unroll
+    for (int s = 0; s < kMatS; ++s)
+        x[s] = s < sm.ns ? sm.src[q][s][((size_t)p * sm.lp1[s] + i) * N + k] : 0;
+    __syncthreads();
+    u64 *o = out + q * oq + ((size_t)p * nl + i) * N + k;
+    for (int b = 0; b < sm.nb; ++b) {
+        const unsigned nz = sm.nz[b];
+        u64 lo = 0, hi = 0;
+#pragma unroll
+        for (int s = 0; s < kMatS; ++s)
+            if (nz >> s & 1u) mac128(lo, hi, x[s], kc[b * kMatS + s]);
+        o[b * ob] = redc_any(lo, hi, m);
+    }
 }
 
 // c0 of item b (items [B][2][nl][N]) gets the constant v_b on every word
@@ -977,6 +1023,27 @@ void scalar_batch(const fr_ctx *c, u64 *out, int nl, int B, const ScalarItem *it
                                out + (size_t)b0 * 2 * nl * c->N, sb, nl, c->N, c->d_mod);
         }
     }
+}
+
+bool scalar_mat(const fr_ctx *c, u64 *out, int nl, int nb, int nq, const u64 *const *src, const int *lp1, int ns,
+                const long long *K, size_t ob, size_t oq) {
+    if (nb > kMatB || ns > kMatS || nq > kMatQ || nb < 1 || ns < 1) return false;
+    ScalarMat sm{};
+    sm.ns = ns;
+    sm.nb = nb;
+    for (int s = 0; s < ns; ++s) {
+        sm.lp1[s] = lp1[s];
+        for (int q = 0; q < nq; ++q) sm.src[q][s] = src[(size_t)q * ns + s];
+    }
+    for (int b = 0; b < nb; ++b)
+        for (int s = 0; s < ns; ++s) {
+            sm.k[b][s] = K[(size_t)b * ns + s];
+            if (sm.k[b][s]) sm.nz[b] |= 1u << s;
+        }
+    ProfScope ps(c, K_ELEM, (double)nq * (ns + nb) * 2.0 * nl * 8.0 * c->N);
+    hipLaunchKernelGGL(k_scalar_mat, grid(c, 2 * nl, nq), dim3(kT), 0, c->stream, out, ob, oq, sm, nl, c->N,
+                       c->d_mod);
+    return true;
 }
 
 void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item) {
