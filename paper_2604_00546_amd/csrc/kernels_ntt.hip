@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_cols2(NttLaunch a) {
         k_fwd_cols2_body<LE, false>(a, tile);
 }
 
-template <int LE, bool SMALL>
+template <int LE, bool SMALL, bool EPI>
 __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     const int s = a.map.storage(blockIdx.z);
@@ -349,6 +349,20 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
     u64 v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = xb[u0 + E * k];
+    // the epilogue's operands are fetched now, their latency hidden by the
+    // butterflies (issued after v, so waiting for v leaves them in flight)
+    const size_t w = (size_t)s * a.N + (size_t)gb * R;
+    u64 pin[EPI ? E : 1], pin2[EPI ? E : 1];
+    if constexpr (EPI) {
+        const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
+#pragma unroll
+        for (int k = 0; k < E; ++k) pin[k] = in[u0 + E * k];
+        if (a.epi_in2) {
+            const u64 *in2 = a.epi_in2 + blockIdx.y * a.epi_in2_stride + w;
+#pragma unroll
+            for (int k = 0; k < E; ++k) pin2[k] = in2[u0 + E * k];
+        }
+    }
 #pragma unroll
     for (int sl = 0; sl < LE; ++sl) {
         const int half = E >> (sl + 1);
@@ -377,25 +391,29 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int k = 0; k < E; ++k) tb[rsw<LE>(E * u0 + k, blk)] = v[k];
     __syncthreads();
-    if (a.epi_out) {  // rescale / ModDown finish: (in - y) qinv (+ out)
-        const size_t w = (size_t)s * a.N + (size_t)gb * R;
+    // rescale / ModDown finish: (in - y) qinv (+ out).  The plain variant
+    // keeps the same branch, read directly (it never runs there; kept so both
+    // variants compile to the same register budget for the common part)
+    if (EPI || a.epi_out) {
         const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
+        const u64 *in2 = a.epi_in2 ? a.epi_in2 + blockIdx.y * a.epi_in2_stride + w : nullptr;
+        auto x_in = [&](int k) { if constexpr (EPI) return pin[k]; else return in[u0 + E * k]; };
+        auto x_in2 = [&](int k) { if constexpr (EPI) return pin2[k]; else return in2[u0 + E * k]; };
         u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
         const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
         if (a.qinv2) {
-            const u64 *in2 = a.epi_in2 ? a.epi_in2 + blockIdx.y * a.epi_in2_stride + w : nullptr;
             const u64 q2i = a.qinv2[mi], q2s = a.qinv2_sh[mi];
 #pragma unroll
             for (int k = 0; k < E; ++k) {
-                u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
-                if (in2) r = addq(in2[u0 + E * k], r, q);
+                u64 r = shoup(subq(x_in(k), fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
+                if (in2) r = addq(x_in2(k), r, q);
                 out[u0 + E * k] = shoup(r, q2i, q2s, q);
             }
             return;
         }
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            u64 r = shoup(subq(in[u0 + E * k], fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
+            u64 r = shoup(subq(x_in(k), fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq), q), qi, qs, q);
             if (a.epi_acc) r = addq(r, out[u0 + E * k], q);
             out[u0 + E * k] = r;
         }
@@ -405,15 +423,16 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
     for (int k = 0; k < E; ++k) xb[u0 + E * k] = fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq);
 }
 
-template <int LE>
+// EPI: the launch carries an epilogue (epi_out set)
+template <int LE, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     __shared__ u64 tile[BLKS * R];
     const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.z))].q;
     if (qb < kSmallQ)
-        k_fwd_rows2_body<LE, true>(a, tile);
+        k_fwd_rows2_body<LE, true, EPI>(a, tile);
     else
-        k_fwd_rows2_body<LE, false>(a, tile);
+        k_fwd_rows2_body<LE, false, EPI>(a, tile);
 }
 
 template <int LE, bool SMALL>
@@ -579,10 +598,10 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
         dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
             hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-            hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, false>), gr, dim3(kThreads), 0, c->stream, a);
         } else {
             hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
-            hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, false>), gr, dim3(kThreads), 0, c->stream, a);
         }
         return;
     }
@@ -610,10 +629,10 @@ bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xto
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
     }
     return true;
 }
@@ -635,10 +654,10 @@ bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U
     dim3 g(R / (kThreads / E), nl, npoly), gr(R / (kThreads / E), npoly, nl);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
     }
     return true;
 }
@@ -662,10 +681,10 @@ bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(k_fwd_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
     }
     return true;
 }
