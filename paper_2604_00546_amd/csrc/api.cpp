@@ -86,6 +86,7 @@ struct Scope {
         size_t tot = 0;
         for (auto &ch : a.chunks) tot += ch.used;
         a.peak = std::max(a.peak, tot);
+        if (a.hold) return;  // space handed out while held stays taken
         for (size_t i = 0; i < a.chunks.size(); ++i) a.chunks[i].used = i < used.size() ? used[i] : 0;
     }
 };
@@ -516,6 +517,12 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
         return fr_fail(FR_EINVAL, "fr_ctx_create: not enough primes of the requested sizes");
     }
     int e = ctx_build(c);
+    for (int a = 0; !e && a < fr_ctx::kAux; ++a)
+        if (hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join[a], hipEventDisableTiming) != hipSuccess)
+            e = fr_fail(FR_EHIP, "fr_ctx_create: auxiliary stream");
+    if (!e && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+        e = fr_fail(FR_EHIP, "fr_ctx_create: event");
     if (e) {
         fr_ctx_destroy(c);
         return e;
@@ -533,6 +540,11 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
                     (void *)c->d_fft_w, (void *)c->d_zeta, (void *)c->d_slot_pos, (void *)c->d_flag})
         if (p) (void)hipFree(p);
     c->arena.release();
+    for (int a = 0; a < fr_ctx::kAux; ++a)
+        if (c->aux[a]) (void)hipStreamDestroy(c->aux[a]);
+    for (int a = 0; a < fr_ctx::kAux; ++a)
+        if (c->ev_join[a]) (void)hipEventDestroy(c->ev_join[a]);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->prof) {
         for (auto &e : c->prof->ev) (void)hipEventDestroy(e);
         delete c->prof;
@@ -1715,7 +1727,18 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
     const KeyEntry *rk = K->find(0);
     CHECK(rk, FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
     auto lw = [&](int level) { return (size_t)(level + 1) * N; };
+    // The groups of one depth (scalar family, products and additions, each
+    // per level) depend only on earlier depths: they run concurrently, one
+    // stream each, joined before the next depth.  Arena space is not reused
+    // inside the loop, so no group's scratch is handed to another stream.
+    c->arena.hold++;
+    struct HoldGuard {
+        Arena &a;
+        ~HoldGuard() { a.hold--; }
+    } hold_guard{c->arena};
+    const hipStream_t main_stream = c->stream;
     for (int d = 1; d <= maxd; ++d) {
+        std::vector<std::function<int()>> groups;
         // --- scalar family (adjust, scalar, leaf), grouped by output level
         std::vector<std::vector<int>> by_level(FR_MAXLEVEL), mul_by_level(FR_MAXLEVEL);
         for (int i = 0; i < n; ++i) {
@@ -1725,90 +1748,96 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             if (op == C_MUL) mul_by_level[nodes[i].level + 1].push_back(i);
         }
         for (int lam = 0; lam < FR_MAXLEVEL; ++lam) {
-            const auto &L = by_level[lam];
-            if (L.empty()) continue;
-            const int B = (int)L.size() * nq;  // item b = node L[b / nq], query b % nq
-            const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
-            u64 *stage = scratch(c, (size_t)B * sw);
-            u64 *out = scratch(c, (size_t)B * ow);
-            // the integer terms (source node, k) of every node of the wave
-            const int nL = (int)L.size();
-            std::vector<std::vector<std::pair<int, long long>>> terms(nL);
-            std::vector<long long> cst(B, 0);
-            bool any_const = false;
-            for (int j = 0; j < nL; ++j) {
-                const CNode &nd = nodes[L[j]];
-                if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
-                    const int la = nodes[nd.a].level;
-                    const long long k = nd.op == C_ADJUST
-                                            ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
-                                            : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
-                    terms[j].push_back({nd.a, k});
-                } else {
-                    for (size_t t = 0; t < nd.ins.size(); ++t) {
-                        const int src = nd.ins[t], ls = nodes[src].level;
-                        terms[j].push_back(
-                            {src, rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls])});
+            if (by_level[lam].empty()) continue;
+            groups.push_back([&, lam]() -> int {
+                const auto &L = by_level[lam];
+                const int B = (int)L.size() * nq;  // item b = node L[b / nq], query b % nq
+                const size_t sw = 2 * lw(lam + 1), ow = 2 * lw(lam);
+                u64 *stage = scratch(c, (size_t)B * sw);
+                u64 *out = scratch(c, (size_t)B * ow);
+                // the integer terms (source node, k) of every node of the wave
+                const int nL = (int)L.size();
+                std::vector<std::vector<std::pair<int, long long>>> terms(nL);
+                std::vector<long long> cst(B, 0);
+                bool any_const = false;
+                for (int j = 0; j < nL; ++j) {
+                    const CNode &nd = nodes[L[j]];
+                    if (nd.op == C_ADJUST || nd.op == C_SCALAR) {
+                        const int la = nodes[nd.a].level;
+                        const long long k = nd.op == C_ADJUST
+                                                ? rne_ll((D[lam] * (double)c->mod[lam + 1]) / D[la])
+                                                : rne_ll(((nd.cst * D[lam]) * (double)c->mod[la]) / D[la]);
+                        terms[j].push_back({nd.a, k});
+                    } else {
+                        for (size_t t = 0; t < nd.ins.size(); ++t) {
+                            const int src = nd.ins[t], ls = nodes[src].level;
+                            terms[j].push_back(
+                                {src, rne_ll(((nd.cf[t + 1] * D[lam]) * (double)c->mod[lam + 1]) / D[ls])});
+                        }
+                        for (int q = 0; q < nq; ++q) cst[j * nq + q] = rne_ll(nd.cf[0] * D[lam]);
+                        any_const = true;
                     }
-                    for (int q = 0; q < nq; ++q) cst[j * nq + q] = rne_ll(nd.cf[0] * D[lam]);
-                    any_const = true;
                 }
-            }
-            // every source of the wave read once for all its outputs when
-            // they are few, else item by item
-            std::vector<int> su;
-            for (auto &tj : terms)
-                for (auto &t : tj)
-                    if (std::find(su.begin(), su.end(), t.first) == su.end()) su.push_back(t.first);
-            const int ns = (int)su.size();
-            std::vector<long long> Km((size_t)nL * ns, 0);
-            std::vector<int> slp1(ns);
-            std::vector<const u64 *> sp((size_t)nq * ns);
-            for (int s = 0; s < ns; ++s) {
-                slp1[s] = nodes[su[s]].level + 1;
-                for (int q = 0; q < nq; ++q) sp[(size_t)q * ns + s] = B_(su[s], q);
-            }
-            for (int j = 0; j < nL; ++j)
-                for (auto &t : terms[j]) {
-                    const int s = (int)(std::find(su.begin(), su.end(), t.first) - su.begin());
-                    Km[(size_t)j * ns + s] += t.second;
+                // every source of the wave read once for all its outputs when
+                // they are few, else item by item
+                std::vector<int> su;
+                for (auto &tj : terms)
+                    for (auto &t : tj)
+                        if (std::find(su.begin(), su.end(), t.first) == su.end()) su.push_back(t.first);
+                const int ns = (int)su.size();
+                std::vector<long long> Km((size_t)nL * ns, 0);
+                std::vector<int> slp1(ns);
+                std::vector<const u64 *> sp((size_t)nq * ns);
+                for (int s = 0; s < ns; ++s) {
+                    slp1[s] = nodes[su[s]].level + 1;
+                    for (int q = 0; q < nq; ++q) sp[(size_t)q * ns + s] = B_(su[s], q);
                 }
-            if (!frk::scalar_mat(c, stage, lam + 2, nL, nq, sp.data(), slp1.data(), ns, Km.data(), nq * sw, sw)) {
-                std::vector<ScalarItem> items(B);
-                for (int b = 0; b < B; ++b)
-                    for (auto &t : terms[b / nq]) {
-                        items[b].src.push_back(B_(t.first, b % nq));
-                        items[b].k.push_back(t.second);
-                        items[b].lp1.push_back(nodes[t.first].level + 1);
+                for (int j = 0; j < nL; ++j)
+                    for (auto &t : terms[j]) {
+                        const int s = (int)(std::find(su.begin(), su.end(), t.first) - su.begin());
+                        Km[(size_t)j * ns + s] += t.second;
                     }
-                frk::scalar_batch(c, stage, lam + 2, B, items.data());
-            }
-            rescale_dev(c, stage, lam + 1, out, B);
-            if (any_const) frk::add_const_batch(c, out, lam + 1, B, cst.data(), ow);
-            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * ow;
+                if (!frk::scalar_mat(c, stage, lam + 2, nL, nq, sp.data(), slp1.data(), ns, Km.data(), nq * sw, sw)) {
+                    std::vector<ScalarItem> items(B);
+                    for (int b = 0; b < B; ++b)
+                        for (auto &t : terms[b / nq]) {
+                            items[b].src.push_back(B_(t.first, b % nq));
+                            items[b].k.push_back(t.second);
+                            items[b].lp1.push_back(nodes[t.first].level + 1);
+                        }
+                    frk::scalar_batch(c, stage, lam + 2, B, items.data());
+                }
+                rescale_dev(c, stage, lam + 1, out, B);
+                if (any_const) frk::add_const_batch(c, out, lam + 1, B, cst.data(), ow);
+                for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * ow;
+                return FR_OK;
+            });
         }
         // --- relinearised products, grouped by input level
         for (int lv = 1; lv < FR_MAXLEVEL; ++lv) {
-            const auto &L = mul_by_level[lv];
-            if (L.empty()) continue;
-            const int B = (int)L.size() * nq, nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
-            const size_t cw = 2 * lw(lv);
-            u64 *T01 = scratch(c, (size_t)B * cw);
-            u64 *T2 = scratch(c, (size_t)B * lw(lv));
-            u64 *Dg = scratch(c, (size_t)B * ndig * nE * N);
-            u64 *U = scratch(c, (size_t)B * 2 * nE * N);
-            u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
-            std::vector<const u64 *> xa(B), yb(B);
-            for (int b = 0; b < B; ++b) {
-                xa[b] = B_(nodes[L[b / nq]].a, b % nq);
-                yb[b] = B_(nodes[L[b / nq]].b, b % nq);
-            }
-            frk::tensor_batch(c, T01, T2, lv + 1, B, xa.data(), yb.data());
-            ks_modup(c, T2, lv, Dg, B, lw(lv));
-            frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
-                          (size_t)2 * nE * N, relin_folds(c) ? T01 : nullptr, cw);
-            relin_rescale_into(c, T01, U, B, lv, out);
-            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
+            if (mul_by_level[lv].empty()) continue;
+            groups.push_back([&, lv]() -> int {
+                const auto &L = mul_by_level[lv];
+                const int B = (int)L.size() * nq, nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
+                const size_t cw = 2 * lw(lv);
+                u64 *T01 = scratch(c, (size_t)B * cw);
+                u64 *T2 = scratch(c, (size_t)B * lw(lv));
+                u64 *Dg = scratch(c, (size_t)B * ndig * nE * N);
+                u64 *U = scratch(c, (size_t)B * 2 * nE * N);
+                u64 *out = scratch(c, (size_t)B * 2 * lw(lv - 1));
+                std::vector<const u64 *> xa(B), yb(B);
+                for (int b = 0; b < B; ++b) {
+                    xa[b] = B_(nodes[L[b / nq]].a, b % nq);
+                    yb[b] = B_(nodes[L[b / nq]].b, b % nq);
+                }
+                frk::tensor_batch(c, T01, T2, lv + 1, B, xa.data(), yb.data());
+                ks_modup(c, T2, lv, Dg, B, lw(lv));
+                frk::ks_inner(c, U, U + (size_t)nE * N, Dg, rk->data, 1, lv, false, B, (size_t)ndig * nE * N,
+                              (size_t)2 * nE * N, relin_folds(c) ? T01 : nullptr, cw);
+                relin_rescale_into(c, T01, U, B, lv, out);
+                for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = out + (size_t)b * 2 * lw(lv - 1);
+                return FR_OK;
+            });
         }
         // --- additions, grouped by level
         for (int lv = 0; lv < FR_MAXLEVEL; ++lv) {
@@ -1819,24 +1848,44 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                     L.push_back(i);
             }
             if (L.empty()) continue;
-            const int B = (int)L.size() * nq;
-            const size_t w = lw(lv);
-            u64 *o = scratch(c, (size_t)B * 2 * w);
-            std::vector<const u64 *> xa(B), yb(B);
-            std::vector<u64 *> outs(B);
-            std::vector<long long> cst(B, 0);
-            std::vector<int> op(B, 0);
-            for (int b = 0; b < B; ++b) {
-                const CNode &nd = nodes[L[b / nq]];
-                const int q = b % nq;
-                xa[b] = B_(nd.a, q);
-                yb[b] = nd.op == C_TWICE_M1 ? B_(nd.a, q) : B_(nd.b, q);
-                outs[b] = o + (size_t)b * 2 * w;
-                op[b] = nd.op == C_SUB;
-                if (nd.op == C_TWICE_M1) cst[b] = rne_ll(-1.0 * D[lv]);
-            }
-            frk::pair_batch(c, lv + 1, B, xa.data(), yb.data(), outs.data(), cst.data(), op.data());
-            for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = outs[b];
+            groups.push_back([&, lv, L]() -> int {
+                const int B = (int)L.size() * nq;
+                const size_t w = lw(lv);
+                u64 *o = scratch(c, (size_t)B * 2 * w);
+                std::vector<const u64 *> xa(B), yb(B);
+                std::vector<u64 *> outs(B);
+                std::vector<long long> cst(B, 0);
+                std::vector<int> op(B, 0);
+                for (int b = 0; b < B; ++b) {
+                    const CNode &nd = nodes[L[b / nq]];
+                    const int q = b % nq;
+                    xa[b] = B_(nd.a, q);
+                    yb[b] = nd.op == C_TWICE_M1 ? B_(nd.a, q) : B_(nd.b, q);
+                    outs[b] = o + (size_t)b * 2 * w;
+                    op[b] = nd.op == C_SUB;
+                    if (nd.op == C_TWICE_M1) cst[b] = rne_ll(-1.0 * D[lv]);
+                }
+                frk::pair_batch(c, lv + 1, B, xa.data(), yb.data(), outs.data(), cst.data(), op.data());
+                for (int b = 0; b < B; ++b) B_(L[b / nq], b % nq) = outs[b];
+                return FR_OK;
+            });
+        }
+        // fork: group 0 on the caller's stream, the others on the auxiliary
+        // streams after everything enqueued so far; join before the next depth
+        const int ng = (int)groups.size(), naux = std::min(ng - 1, fr_ctx::kAux);
+        if (naux > 0) {
+            FR_HIP(hipEventRecord(c->ev_fork, main_stream));
+            for (int a = 0; a < naux; ++a) FR_HIP(hipStreamWaitEvent(c->aux[a], c->ev_fork, 0));
+        }
+        for (int g = 0; g < ng; ++g) {
+            c->stream = g == 0 ? main_stream : c->aux[(g - 1) % fr_ctx::kAux];
+            const int e = groups[g]();
+            c->stream = main_stream;
+            if (e) return e;
+        }
+        for (int a = 0; a < naux; ++a) {
+            FR_HIP(hipEventRecord(c->ev_join[a], c->aux[a]));
+            FR_HIP(hipStreamWaitEvent(main_stream, c->ev_join[a], 0));
         }
     }
     return FR_OK;

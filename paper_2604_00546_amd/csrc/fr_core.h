@@ -118,6 +118,7 @@ struct Arena {  // bump allocator over device chunks, reset per top-level call
     struct Chunk { char *base; size_t size, used; };
     std::vector<Chunk> chunks;
     size_t peak = 0;
+    int hold = 0;  // > 0: scopes do not give space back (work on several streams)
     void *get(size_t bytes);  // 256-byte aligned; nullptr on failure
     void reset();
     void release();
@@ -164,6 +165,11 @@ struct fr_ctx {
     u32 *d_slot_pos = nullptr;  // (5^j mod 2N - 1) / 2, j < N/2
     u64 cdt[20];
     hipStream_t stream = nullptr;
+    // auxiliary streams (default priority) and events for independent work
+    // of one call that runs concurrently; joined into `stream` before return
+    static const int kAux = 3;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
     Arena arena;
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;
