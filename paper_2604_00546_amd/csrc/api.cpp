@@ -164,8 +164,17 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
         return;
     }
     // large batches: per digit, transforming only the converted limbs and
-    // copying the digit's own evaluation-form limbs
+    // copying the digit's own evaluation-form limbs.  The digits are
+    // independent: outside a region that already spreads work over the
+    // auxiliary streams, digit t > 0 runs on one of them
+    const hipStream_t main_stream = c->stream;
+    const int naux = c->arena.hold ? 0 : std::min(ndig - 1, fr_ctx::kAux);
+    if (naux > 0) {
+        (void)hipEventRecord(c->ev_fork, main_stream);
+        for (int a = 0; a < naux; ++a) (void)hipStreamWaitEvent(c->aux[a], c->ev_fork, 0);
+    }
     for (int t = 0; t < ndig; ++t) {
+        c->stream = (naux > 0 && t > 0) ? c->aux[(t - 1) % naux] : main_stream;
         u64 *Dt = D + (size_t)t * nE * N;
         const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
         frk::modup_digit(c, Dt, X, level, t, batch, dstride, lw);
@@ -177,6 +186,11 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
         else
             (void)hipMemcpy2DAsync(Dt + (size_t)lo * N, dstride * 8, c1 + (size_t)lo * N, c1_stride * 8,
                                    (size_t)nd * N * 8, batch, hipMemcpyDeviceToDevice, c->stream);
+    }
+    c->stream = main_stream;
+    for (int a = 0; a < naux; ++a) {
+        (void)hipEventRecord(c->ev_join[a], c->aux[a]);
+        (void)hipStreamWaitEvent(main_stream, c->ev_join[a], 0);
     }
 }
 
