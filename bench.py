@@ -47,7 +47,7 @@ ROOFLINE_KERNEL = {"class": "ntt", "bound": "alu"}
 # limbs, both passes), from the FETCH_SIZE / WRITE_SIZE counter runs recorded
 # in profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
 # since those counters were taken
-NTT_TRAFFIC_BYTES_PER_LAUNCH = None
+NTT_TRAFFIC_BYTES_PER_LAUNCH = 126252887
 
 
 def log(*a):
@@ -152,6 +152,8 @@ def mixed_batches(s, nbatch, d1):
     dbs = {}
     for e in range(10, 16):  # one resident database per size (prefixes of one template set)
         dbs[e] = ctx.db_load(s["wl"].templates[: 1 << e], ell, s["B"], n1, ctx.L, 2.0 ** 40)
+        if s["route"] == "hoisted":
+            dbs[e].extend()
     nmax = int(sizes.max())
     Q = synth.query_batch(4, nmax, ell)
     qs = [ctx.encrypt(s["keys"], ctx.encode(synth.replicate_query(Q[q], ctx.N // 2), ctx.L, 2.0 ** 40),
@@ -162,15 +164,24 @@ def mixed_batches(s, nbatch, d1):
     chebs = [ctx.new_ct(ctx.L - 1) for _ in range(nmax)]
     torch.cuda.synchronize()
 
+    hoisted = s["route"] == "hoisted"
+
     def run_batched(b, sz):
-        ctx.rotate_hoisted_batch(s["keys"], qs[:b], range(1, n1), outs=rows[:b])
-        ctx.bsgs_diag_matvec_batch(s["keys"], babies[:b], [dbs[int(e)] for e in sz], [0] * b, outs=scores[:b])
+        if hoisted:
+            ctx.bsgs_matvec_hoisted_batch(s["keys"], qs[:b], [dbs[int(e)] for e in sz], [0] * b, outs=scores[:b])
+        else:
+            ctx.rotate_hoisted_batch(s["keys"], qs[:b], range(1, n1), outs=rows[:b])
+            ctx.bsgs_diag_matvec_batch(s["keys"], babies[:b], [dbs[int(e)] for e in sz], [0] * b,
+                                       outs=scores[:b])
         ctx.chebyshev_eval_batch(s["keys"], scores[:b], s["coeffs"], d1, outs=chebs[:b])
 
     def run_plain(b, sz):
         for q in range(b):
-            ctx.rotate_hoisted(s["keys"], qs[q], range(1, n1), outs=rows[q])
-            ctx.bsgs_diag_matvec(s["keys"], babies[q], dbs[int(sz[q])], 0, out=scores[q])
+            if hoisted:
+                ctx.bsgs_matvec_hoisted(s["keys"], qs[q], dbs[int(sz[q])], 0, out=scores[q])
+            else:
+                ctx.rotate_hoisted(s["keys"], qs[q], range(1, n1), outs=rows[q])
+                ctx.bsgs_diag_matvec(s["keys"], babies[q], dbs[int(sz[q])], 0, out=scores[q])
             ctx.chebyshev_eval(s["keys"], scores[q], s["coeffs"], d1, out=chebs[q])
 
     out = {}
@@ -203,6 +214,9 @@ def served(s, seconds, d1, rates=(10.0, 50.0, 200.0), pool=64):
     from paper_2604_00546_amd import serve, synth
     ctx, ell, n1 = s["ctx"], s["ell"], s["n1"]
     dbs = {e: ctx.db_load(s["wl"].templates[: 1 << e], ell, s["B"], n1, ctx.L, 2.0 ** 40) for e in range(9, 16)}
+    if s["route"] == "hoisted":
+        for d in dbs.values():
+            d.extend()
     Q = synth.query_batch(5, pool, ell)
     qs = [ctx.encrypt(s["keys"], ctx.encode(synth.replicate_query(Q[q], ctx.N // 2), ctx.L, 2.0 ** 40),
                       synth.int_seed(5, synth.SUB_ENC, q)) for q in range(pool)]
@@ -412,6 +426,8 @@ def cpu_baseline(s, d1):
     keys = o.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
     wl = s["wl"]
     db = o.db_build(wl.templates, wl.K, s["ell"], s["B"], s["n1"], o.L, 2.0 ** 40)
+    if s["route"] == "hoisted":
+        db.extend()
     q = o.encrypt(keys, o.encode(synth.replicate_query(wl.query, o.N // 2), o.L, 2.0 ** 40), 5)
     t0 = time.time()
     if s["route"] == "hoisted":
@@ -424,8 +440,9 @@ def cpu_baseline(s, d1):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": s["K"] / dt, "unit": "scores/s", "cores": cores, "kind": "oracle",
             "sample": f"one full query (31 hoisted rotations, BSGS matvec over 512 diagonals, degree-63 "
-                      f"Chebyshev) of the same 2^15 x 512 workload; {dt:.1f} s wall on {cores} OpenMP threads; "
-                      f"key generation and diagonal encoding excluded as setup"}
+                      f"Chebyshev; route {s['route']}) of the same 2^15 x 512 workload; {dt:.1f} s wall on "
+                      f"{cores} OpenMP threads; key generation and diagonal encoding (with the special-prime "
+                      f"limbs) excluded as setup"}
 
 
 def main():

@@ -1309,6 +1309,12 @@ static void db_cache_ntt_p(const or_ctx *c, or_db *db) {
     }
 }
 
+/* Builds the special-prime limbs of every diagonal now (else on first use). */
+int or_db_extend(const or_ctx *c, or_db *db) {
+    db_cache_ntt_p(c, db);
+    return 0;
+}
+
 int or_db_export_special(const or_ctx *c, or_db *db, int g, int d, uint64_t *out) {
     if (g < 0 || g >= db->G || d < 0 || d >= db->ell) { set_err("or_db_export_special: bad index"); return -1; }
     pt_special_residues(c, db->pt[(size_t)g * db->ell + d], out);

@@ -134,6 +134,8 @@ int or_db_export(const or_db *db, int g, int d, uint64_t *out);
 /* Residues of plaintext (g, d)'s centered integer coefficients modulo the
  * special primes, coefficient form [nP][N]. */
 int or_db_export_special(const or_ctx *ctx, or_db *db, int g, int d, uint64_t *out);
+/* Builds those residues for every diagonal now (else on the first hoisted product). */
+int or_db_extend(const or_ctx *ctx, or_db *db);
 /* Pre-rotated diagonal slot vector (group g, diagonal d) before encoding. */
 int or_db_slots(const or_ctx *ctx, const float *T, int K, int ell, int B, int n1,
                 int g, int d, double *v);

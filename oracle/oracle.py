@@ -101,6 +101,7 @@ def lib():
         "or_bsgs_matvec": (_CT, [_P, _P, C.POINTER(_CT), C.c_int, _P, C.c_int]),
         "or_bsgs_matvec_hoisted": (_CT, [_P, _P, _CT, C.c_int, _P, C.c_int]),
         "or_db_export_special": (C.c_int, [_P, _P, C.c_int, C.c_int, _U64P]),
+        "or_db_extend": (C.c_int, [_P, _P]),
         "or_cheb_step_coeffs": (None, [C.c_int, C.c_double, _DP]),
         "or_cheb_clenshaw": (C.c_double, [_DP, C.c_int, C.c_double]),
         "or_chebyshev": (_CT, [_P, _P, _CT, _DP, C.c_int, C.c_int]),
@@ -293,6 +294,11 @@ class Db:
 
     def export_all(self) -> np.ndarray:
         return np.stack([np.stack([self.export(g, d) for d in range(self.ell)]) for g in range(self.G)])
+
+    def extend(self) -> "Db":
+        """Build the special-prime limbs of every diagonal now."""
+        lib().or_db_extend(self.ctx.ptr, self.ptr)
+        return self
 
     def export_special(self, g: int, d: int) -> np.ndarray:
         """Residues of plaintext (g, d)'s centered coefficients mod the special primes, [nP][N]."""

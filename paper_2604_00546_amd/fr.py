@@ -234,6 +234,7 @@ class Db:
         self.ctx, self.ptr = ctx, ptr
         self.ell, self.B, self.n1, self.level, self.scale = ell, B, n1, level, scale
         self.G = lib().fr_db_groups(ptr)
+        self.extended = False
 
     def __del__(self):
         try:
@@ -250,6 +251,7 @@ class Db:
         """Append every diagonal's residues mod the special primes (needed by
         the hoisted product; idempotent)."""
         _check(lib().fr_db_extend(self.ctx.ptr, self.ptr), "fr_db_extend")
+        self.extended = True
         return self
 
 

@@ -7,8 +7,9 @@ a fixed pool of query slots whose size follows the paper's stream-pool rule
 free HBM and C the size of one ciphertext), and runs continuous batching:
 whenever the device finishes a batch, every request that has arrived since
 is admitted into the free slots and the next batch runs the whole path for
-all of them at once (hoisted rotations, the BSGS matvec with each request's
-own database and group, the Chebyshev threshold).  Requests that arrive
+all of them at once (the BSGS matvec with each request's own database and
+group, from hoisted baby steps held over Q_l U P when every database of the
+batch is extended, the Chebyshev threshold).  Requests that arrive
 while a batch is in flight are admitted as soon as the slots free up.
 
 `plain` runs the same trace one request at a time through the one-query
@@ -77,11 +78,15 @@ class Server:
 
     def _run_batch(self, reqs: List[Request]):
         c, b = self.ctx, len(reqs)
-        rows = self._rows[:b]
-        c.rotate_hoisted_batch(self.keys, [r.query for r in reqs], range(1, self.n1), outs=rows)
-        babies = [[r.query] + rows[i] for i, r in enumerate(reqs)]
-        c.bsgs_diag_matvec_batch(self.keys, babies, [r.db for r in reqs], [r.group for r in reqs],
-                                 outs=self._scores[:b])
+        if all(r.db.extended for r in reqs):
+            c.bsgs_matvec_hoisted_batch(self.keys, [r.query for r in reqs], [r.db for r in reqs],
+                                        [r.group for r in reqs], outs=self._scores[:b])
+        else:
+            rows = self._rows[:b]
+            c.rotate_hoisted_batch(self.keys, [r.query for r in reqs], range(1, self.n1), outs=rows)
+            babies = [[r.query] + rows[i] for i, r in enumerate(reqs)]
+            c.bsgs_diag_matvec_batch(self.keys, babies, [r.db for r in reqs], [r.group for r in reqs],
+                                     outs=self._scores[:b])
         c.chebyshev_eval_batch(self.keys, self._scores[:b], self.coeffs, self.d1, outs=self._chebs[:b])
         if self.keep_results:
             for i, r in enumerate(reqs):
@@ -128,8 +133,11 @@ def plain(ctx, keys, coeffs, d1, n1, trace: List[Request], keep_results: bool = 
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.admitted = time.perf_counter() - t0
-        ctx.rotate_hoisted(keys, r.query, range(1, n1), outs=rows)
-        ctx.bsgs_diag_matvec(keys, [r.query] + rows, r.db, r.group, out=score)
+        if r.db.extended:
+            ctx.bsgs_matvec_hoisted(keys, r.query, r.db, r.group, out=score)
+        else:
+            ctx.rotate_hoisted(keys, r.query, range(1, n1), outs=rows)
+            ctx.bsgs_diag_matvec(keys, [r.query] + rows, r.db, r.group, out=score)
         ctx.chebyshev_eval(keys, score, coeffs, d1, out=cheb)
         if keep_results:
             r.result = _clone(ctx, cheb)

@@ -76,6 +76,32 @@ def test_served_thresholds(S):
     assert np.max(np.abs(y[:K] - want)) <= 2 ** -12
 
 
+def test_served_hoisted_equal_alone(S):
+    """With extended databases the loop runs the hoisted product: every
+    request's result equals the same request through the one-query hoisted
+    call, and the plain loop gives the same words."""
+    g, serve, keys = S["g"], S["serve"], S["keys"]
+    dbs = {}
+    reqs = []
+    for r in S["reqs"]:
+        if id(r.db) not in dbs:
+            dbs[id(r.db)] = g.db_import(np.stack([[r.db.export(0, d) for d in range(ELL)]]), 1, ELL, 16, N1, g.L,
+                                        2.0 ** 40).extend()
+        reqs.append(serve.Request(r.rid, r.arrival, r.kind, r.query, dbs[id(r.db)], 0))
+    srv = serve.Server(g, keys, S["coeffs"], 8, N1, slots=4, keep_results=True)
+    srv.run(reqs)
+    assert sum(srv.batches) == NR and len(srv.batches) >= 3
+    first = {}
+    for r in reqs:
+        a = g.chebyshev_eval(keys, g.bsgs_matvec_hoisted(keys, r.query, r.db, 0), S["coeffs"], 8)
+        assert (r.result.level, r.result.scale) == (a.level, a.scale)
+        assert np.array_equal(g.ct_export(r.result), g.ct_export(a)), f"request {r.rid}"
+        first[r.rid] = r.result
+    serve.plain(g, keys, S["coeffs"], 8, N1, reqs, keep_results=True)
+    for r in reqs:
+        assert np.array_equal(g.ct_export(r.result), g.ct_export(first[r.rid]))
+
+
 def test_slot_count_rule(S):
     n = S["serve"].slot_count(S["g"])
     assert 2 <= n <= 64
