@@ -1137,7 +1137,21 @@ extern "C" void fr_db_destroy(fr_db *db) {
 
 extern "C" int fr_db_groups(const fr_db *db) { return db ? db->G : 0; }
 
+// byte layout of a diagonal of nl limbs at level `level` (limbs past the
+// level are the special primes): limbs of moduli below 2^40 packed in 5 B
+static size_t db_layout(const fr_ctx *c, int level, int nl, DbLayout &lay) {
+    size_t o = 0;
+    for (int m = 0; m < nl; ++m) {
+        const u64 q = c->mod[m <= level ? m : c->L + 1 + (m - level - 1)];
+        lay.packed[m] = q < (1ull << 40);
+        lay.off[m] = (unsigned)o;
+        o += (lay.packed[m] ? 5 : 8) * (size_t)c->N;
+    }
+    return o;
+}
+
 static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double scale, fr_db **out) {
+    CHECK(level + 1 + c->nP <= kDbMaxLimbs, FR_EINVAL, "fr_db: at most %d limbs per diagonal", kDbMaxLimbs);
     fr_db *db = new fr_db();
     db->ctx = c;
     db->G = G;
@@ -1147,10 +1161,10 @@ static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double 
     db->level = level;
     db->nl = level + 1;
     db->scale = scale;
-    if (hipMalloc(&db->data, (size_t)G * ell * (level + 1) * c->N * 8) != hipSuccess) {
+    db->stride = db_layout(c, level, db->nl, db->lay);
+    if (hipMalloc(&db->data, (size_t)G * ell * db->stride) != hipSuccess) {
         delete db;
-        return fr_fail(FR_ENOMEM, "fr_db: cannot allocate %zu bytes of diagonals",
-                       (size_t)G * ell * (level + 1) * c->N * 8);
+        return fr_fail(FR_ENOMEM, "fr_db: cannot allocate %zu bytes of diagonals", (size_t)G * ell * db->stride);
     }
     *out = db;
     return FR_OK;
@@ -1178,14 +1192,15 @@ extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int
     double *work = (double *)c->arena.get((size_t)batch * c->N * 16);
     CHECK(slots && work, FR_ENOMEM, "fr_db_load: scratch");
     const size_t pw = (size_t)(level + 1) * c->N;
+    u64 *dst = scratch(c, (size_t)batch * pw);
     for (int g = 0; g < G; ++g)
         for (int d0 = 0; d0 < ell; d0 += batch) {
             const int nd = std::min(batch, ell - d0);
-            u64 *dst = db->data + ((size_t)g * ell + d0) * pw;
             frk::db_slots(c, slots, Td, K, ell, B, n1, g, d0, nd);
             frk::encode_slots(c, dst, slots, h, level, scale, nd, (size_t)h, pw, work);
             frk::ntt_fwd(c, dst, level + 1, qmap(), nd, pw);
             frk::mont_scale(c, dst, level + 1, qmap(), nd, pw, true);
+            frk::db_pack(c, db->data + ((size_t)g * ell + d0) * db->stride, db->stride, db->lay, dst, level + 1, nd);
         }
     if (int e = flag_check(c, "fr_db_load")) return e;
     *out = guard.release();
@@ -1202,10 +1217,17 @@ extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t 
     if (int e = db_alloc(c, G, ell, B, n1, level, scale, &db)) return e;
     std::unique_ptr<fr_db, void (*)(fr_db *)> guard(db, fr_db_destroy);
     const size_t pw = (size_t)(level + 1) * c->N;
-    for (int p = 0; p < G * ell; ++p) {
-        if (int e = import_poly(c, host + p * pw, level + 1, 1, db->data + p * pw)) return e;
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int batch = 32;
+    u64 *t = scratch(c, (size_t)batch * pw);
+    for (int p0 = 0; p0 < G * ell; p0 += batch) {
+        const int nd = std::min(batch, G * ell - p0);
+        for (int p = 0; p < nd; ++p)
+            if (int e = import_poly(c, host + (size_t)(p0 + p) * pw, level + 1, 1, t + p * pw)) return e;
+        frk::mont_scale(c, t, level + 1, qmap(), nd, pw, true);
+        frk::db_pack(c, db->data + (size_t)p0 * db->stride, db->stride, db->lay, t, level + 1, nd);
     }
-    frk::mont_scale(c, db->data, level + 1, qmap(), G * ell, pw, true);
     FR_HIP(hipStreamSynchronize(c->stream));
     *out = guard.release();
     return FR_OK;
@@ -1219,8 +1241,7 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
     const size_t pw = (size_t)(db->level + 1) * c->N;
     u64 *t = scratch(c, pw);
     CHECK(t, FR_ENOMEM, "fr_db_export: scratch");
-    FR_HIP(hipMemcpyAsync(t, db->data + ((size_t)g * db->ell + d) * db->nl * c->N, pw * 8, hipMemcpyDeviceToDevice,
-                          c->stream));
+    frk::db_unpack(c, t, db->data + ((size_t)g * db->ell + d) * db->stride, db->stride, db->lay, db->level + 1, 1);
     frk::mont_scale(c, t, db->level + 1, qmap(), 1, 0, false);
     frk::ntt_inv(c, t, db->level + 1, qmap(), 1, 0);
     FR_HIP(hipMemcpyAsync(host, t, pw * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1314,9 +1335,7 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
             CHECK(out[q].data != baby[t].data, FR_EINVAL, "fr_bsgs_diag_matvec: output aliases a baby step");
     }
     const size_t pw = (size_t)2 * (lv + 1) * N, rw = (size_t)2 * (l + 1) * N;
-    auto diag_of = [&](int q) {
-        return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->nl * N);
-    };
+    auto diag_of = [&](int q) { return (const unsigned char *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->stride); };
     std::vector<int> order(nq);
     for (int q = 0; q < nq; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
@@ -1325,13 +1344,14 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
         const int qn = std::min(kMatvecChunk, nq - q0);
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
         u64 *R = scratch(c, (size_t)qn * n2 * rw);
-        std::vector<const u64 *> bp((size_t)qn * n1), dp(qn);
+        std::vector<const u64 *> bp((size_t)qn * n1);
+        std::vector<const unsigned char *> dp(qn);
         for (int qq = 0; qq < qn; ++qq) {
             const int q = order[q0 + qq];
             dp[qq] = diag_of(q);
             for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = baby[(size_t)q * n1 + i].data;
         }
-        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, db0->nl - 1, lv, bl);
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), db0->stride, db0->lay, ell, lv, bl);
         rescale_dev(c, P, lv, R, qn * n2);
         std::vector<u64 *> op(qn);
         for (int qq = 0; qq < qn; ++qq) op[qq] = out[order[q0 + qq]].data;
@@ -1370,19 +1390,22 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
     CHECK(db->ctx == c, FR_EINVAL, "fr_db_extend: database of another context");
     const int N = c->N, l = db->level, L1 = l + 1, nP = c->nP, nE = L1 + nP;
     if (db->nl == nE) return FR_OK;
+    DbLayout lay{};
+    const size_t stride = db_layout(c, l, nE, lay);
     const size_t nd = (size_t)db->G * db->ell, lw = (size_t)L1 * N, ew = (size_t)nE * N, pw = (size_t)nP * N;
-    u64 *ext = nullptr;
-    if (hipMalloc(&ext, nd * ew * 8) != hipSuccess)
-        return fr_fail(FR_ENOMEM, "fr_db_extend: cannot allocate %zu bytes of diagonals", nd * ew * 8);
+    unsigned char *ext = nullptr;
+    if (hipMalloc(&ext, nd * stride) != hipSuccess)
+        return fr_fail(FR_ENOMEM, "fr_db_extend: cannot allocate %zu bytes of diagonals", nd * stride);
     c->arena.reset();
     Scope sc(c->arena);
     const size_t batch = 16;
-    u64 *X = scratch(c, batch * lw), *Xp = scratch(c, batch * pw);
+    // Y: the diagonals over all nE limbs (64-bit words), X: the q limbs'
+    // coefficient form, Xp: the special limbs
+    u64 *Y = scratch(c, batch * ew), *X = scratch(c, batch * lw), *Xp = scratch(c, batch * pw);
     for (size_t d0 = 0; d0 < nd; d0 += batch) {
         const int nb = (int)std::min(batch, nd - d0);
-        FR_HIP(hipMemcpy2DAsync(ext + d0 * ew, ew * 8, db->data + d0 * lw, lw * 8, lw * 8, nb, hipMemcpyDeviceToDevice,
-                                c->stream));
-        FR_HIP(hipMemcpyAsync(X, db->data + d0 * lw, nb * lw * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::db_unpack(c, X, db->data + d0 * db->stride, db->stride, db->lay, L1, nb);
+        FR_HIP(hipMemcpy2DAsync(Y, ew * 8, X, lw * 8, lw * 8, nb, hipMemcpyDeviceToDevice, c->stream));
         frk::mont_scale(c, X, L1, qmap(), nb, lw, false);
         frk::ntt_inv(c, X, L1, qmap(), nb, lw);
         if (int e = frk::crt_extend(c, Xp, X, l, nb, pw, lw)) {
@@ -1391,13 +1414,15 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
         }
         frk::ntt_fwd(c, Xp, nP, pmap(c), nb, pw);
         frk::mont_scale(c, Xp, nP, pmap(c), nb, pw, true);
-        FR_HIP(hipMemcpy2DAsync(ext + d0 * ew + lw, ew * 8, Xp, pw * 8, pw * 8, nb, hipMemcpyDeviceToDevice,
-                                c->stream));
+        FR_HIP(hipMemcpy2DAsync(Y + lw, ew * 8, Xp, pw * 8, pw * 8, nb, hipMemcpyDeviceToDevice, c->stream));
+        frk::db_pack(c, ext + d0 * stride, stride, lay, Y, nE, nb);
     }
     FR_HIP(hipStreamSynchronize(c->stream));
     (void)hipFree(db->data);
     db->data = ext;
     db->nl = nE;
+    db->stride = stride;
+    db->lay = lay;
     return FR_OK;
 }
 
@@ -1460,7 +1485,7 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
     const size_t lw = (size_t)L1 * N, bw = (size_t)2 * nE * N, bq = (size_t)n1 * bw, pw = bw;
     const int ndig = num_digits(c, l);
     const size_t dstride = (size_t)ndig * nE * N;
-    auto diag_of = [&](int q) { return (const u64 *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->nl * N); };
+    auto diag_of = [&](int q) { return (const unsigned char *)(dbs[q]->data + (size_t)groups[q] * ell * dbs[q]->stride); };
     std::vector<int> order(nq);
     for (int q = 0; q < nq; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
@@ -1485,12 +1510,14 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
         }
         // inner sums over Q_l U P: [qn][n2][2][nE][N]
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
-        std::vector<const u64 *> bp((size_t)qn * n1), dp(qn);
+        std::vector<const u64 *> bp((size_t)qn * n1);
+        std::vector<const unsigned char *> dp(qn);
         for (int qq = 0; qq < qn; ++qq) {
             dp[qq] = diag_of(order[q0 + qq]);
             for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = Bb + qq * bq + i * bw;
         }
-        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), ell, nE - 1, nE - 1, nE - 1, l, c->L - l);
+        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), db0->stride, db0->lay, ell, nE - 1, nE - 1,
+                      l, c->L - l);
         u64 *R = scratch(c, (size_t)qn * n2 * 2 * l * N);
         moddown_rescale(c, P, qn * n2 * 2, l, R);
         std::vector<u64 *> op(qn);

@@ -207,14 +207,26 @@ struct fr_keys {
     }
 };
 
+// Byte layout of one diagonal: limb m at off[m]; a limb whose modulus is
+// below 2^40 is packed (packed[m] = 1) as N low 32-bit words followed by N
+// high bytes, any other as N 64-bit words.
+constexpr int kDbMaxLimbs = 32;
+struct DbLayout {
+    unsigned off[kDbMaxLimbs];
+    unsigned char packed[kDbMaxLimbs];
+};
+
 struct fr_db {
     fr_ctx *ctx;
     int G, ell, B, n1, level;
     int nl;  // limbs per diagonal: level+1, or level+1+nP once extended
     double scale;
-    // [G][ell][nl][N] eval domain, Montgomery-scaled; limbs 0..level are the
-    // q_i, the extended form appends the special primes p_0..p_{nP-1}
-    u64 *data = nullptr;
+    // [G][ell] diagonals of `stride` bytes each (layout `lay`), eval domain,
+    // Montgomery-scaled; limbs 0..level are the q_i, the extended form
+    // appends the special primes p_0..p_{nP-1}
+    size_t stride = 0;
+    DbLayout lay{};
+    unsigned char *data = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -354,8 +366,14 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 // the n2 outputs of query q start at P + q * pq
 // Limbs m > lq use the modulus m + pofs (a product over Q_lq U P with the
 // special primes stored after limb lq).
-void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
-              int ell, int db_level, int level, int baby_level, int lq = 1 << 30, int pofs = 0);
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1,
+              const unsigned char *const *diag, size_t dstride, const DbLayout &lay, int ell, int level,
+              int baby_level, int lq = 1 << 30, int pofs = 0);
+// diagonals between 64-bit limbs and the packed byte layout: nd diagonals,
+// nl limbs each, src / dst nl N words apart on the 64-bit side
+void db_pack(const fr_ctx *c, unsigned char *dst, size_t dstride, const DbLayout &lay, const u64 *src, int nl, int nd);
+void db_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, size_t sstride, const DbLayout &lay, int nl,
+               int nd);
 // batched element-wise helpers (items addressed by pointer)
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
 // polynomials of every source; out items contiguous [B][2][nl][N]

@@ -431,8 +431,16 @@ __global__ __launch_bounds__(kT) void k_rescale_finish(u64 *out, const u64 *in, 
 constexpr int kMacQ = 8;  // queries per MAC launch (baby pointer table in the kernel arguments)
 struct BabyPtrs {
     const u64 *p[kMacQ][32];
-    const u64 *diag[kMacQ];  // diagonal group of each query
+    const unsigned char *diag[kMacQ];  // diagonal group of each query
 };
+
+// one diagonal word: a 64-bit limb, or a packed limb's low word and high byte
+template <bool PK>
+__device__ __forceinline__ u64 diag_word(const unsigned char *limb, size_t off, int k, int N) {
+    if (PK)
+        return (u64)reinterpret_cast<const u32 *>(limb + off)[k] | ((u64)(limb + off + 4 * (size_t)N)[k] << 32);
+    return reinterpret_cast<const u64 *>(limb + off)[k];
+}
 
 // b = e - a s + [limb in digit] (P mod q) s'   (key generation, eval domain;
 // limbs are global modulus indices; s_mont Montgomery-scaled)
@@ -482,16 +490,13 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 // loaded before the products that use them.  Positions past ell or nj read
 // diagonal 0 and contribute zero (a launch whose tile lies inside the
 // matrix is compiled without those guards).
-template <int NJ, bool FULL>
-__global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
-                                                  int nj, int ell, int dbl, int bl, int lv, int N,
-                                                  const ModConst *mods, int accumulate, int lq, int pofs) {
-    int q, tile;
-    item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
+template <int NJ, bool FULL, bool PK>
+__device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp, int q, int tile, int nb, int i0,
+                                          int n1, int j0, int nj, int ell, size_t dstride, unsigned loff, int bl,
+                                          int lv, int N, const ModConst &mc, int accumulate) {
     const int lane = threadIdx.x & 63, p = lane >> 5;
     const int k = tile * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
-    const size_t pt = (size_t)(dbl + 1) * N;
-    const u64 *dg = bp.diag[q] + (size_t)m * N + k;
+    const unsigned char *dg = bp.diag[q] + loff;
     const size_t boff = ((size_t)p * (bl + 1) + m) * N + k;
     P += q * pq;
     unsigned __int128 acc[NJ];
@@ -504,10 +509,10 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
         for (int jj = 0; jj < NJ; ++jj) {
             const int d = (j0 + jj) * n1 + i;
             if (FULL) {
-                w[jj] = dg[(size_t)d * pt];
+                w[jj] = diag_word<PK>(dg, (size_t)d * dstride, k, N);
             } else {
                 const bool ok = jj < nj && d < ell;
-                w[jj] = dg[(ok ? (size_t)d : 0) * pt];
+                w[jj] = diag_word<PK>(dg, (ok ? (size_t)d : 0) * dstride, k, N);
                 if (!ok) w[jj] = 0;
             }
         }
@@ -515,7 +520,6 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
     }
-    const ModConst mc = mods[m <= lq ? m : m + pofs];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
         if (jj < nj) {
@@ -525,6 +529,42 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
             P[o] = r;
         }
     }
+}
+
+template <int NJ, bool FULL>
+__global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
+                                                  int nj, int ell, size_t dstride, DbLayout lay, int bl, int lv, int N,
+                                                  const ModConst *mods, int accumulate, int lq, int pofs) {
+    int q, tile;
+    item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
+    const int m = blockIdx.y;
+    const ModConst mc = mods[m <= lq ? m : m + pofs];
+    if (lay.packed[m])
+        mac3_body<NJ, FULL, true>(P, pq, bp, q, tile, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
+                                  accumulate);
+    else
+        mac3_body<NJ, FULL, false>(P, pq, bp, q, tile, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
+                                   accumulate);
+}
+
+// 64-bit limbs <-> the packed diagonal layout (grid: N / kT, nl, nd)
+__global__ __launch_bounds__(kT) void k_db_pack(unsigned char *dst, size_t dstride, DbLayout lay, const u64 *src,
+                                                int nl, int N) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y, d = blockIdx.z;
+    const u64 x = src[((size_t)d * nl + m) * N + k];
+    unsigned char *limb = dst + d * dstride + lay.off[m];
+    if (lay.packed[m]) {
+        reinterpret_cast<u32 *>(limb)[k] = (u32)x;
+        limb[4 * (size_t)N + k] = (unsigned char)(x >> 32);
+    } else {
+        reinterpret_cast<u64 *>(limb)[k] = x;
+    }
+}
+__global__ __launch_bounds__(kT) void k_db_unpack(u64 *dst, const unsigned char *src, size_t sstride, DbLayout lay,
+                                                  int nl, int N) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y, d = blockIdx.z;
+    const unsigned char *limb = src + d * sstride + lay.off[m];
+    dst[((size_t)d * nl + m) * N + k] = lay.packed[m] ? diag_word<true>(limb, 0, k, N) : diag_word<false>(limb, 0, k, N);
 }
 
 // out_b[i][p] = (U_b[i][p] - V_b[i][p]) P^-1 + in_b[i][auto_src(p, g)]: the
@@ -929,7 +969,10 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 
 template <int NJ>
 static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1,
-                        const u64 *const *diag, int ell, int db_level, int level, int baby_level, int lq, int pofs) {
+                        const unsigned char *const *diag, size_t dstride, const DbLayout &lay, int ell, int level,
+                        int baby_level, int lq, int pofs) {
+    double dbytes = 0.0;  // bytes of the limbs read per diagonal
+    for (int m = 0; m <= level; ++m) dbytes += (lay.packed[m] ? 5.0 : 8.0) * c->N;
     const int n2 = (ell + n1 - 1) / n1;
     for (int q0 = 0; q0 < nq; q0 += kMacQ) {
         const int qn = std::min(kMacQ, nq - q0);
@@ -948,33 +991,45 @@ static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *ba
                 for (int jj = 0; jj < nj; ++jj)
                     for (int ii = 0; ii < nb; ++ii) used += ((j0 + jj) * n1 + i0 + ii < ell);
                 ProfScope ps(c, K_MAC,
-                             8.0 * c->N * (level + 1) *
-                                 (ngroups * used + qn * (2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj)));
+                             dbytes * ngroups * used +
+                                 8.0 * c->N * (level + 1) * qn * (2.0 * nb + (i0 > 0 ? 4.0 : 2.0) * nj));
                 dim3 g(c->N / (kT / 2) * qn, level + 1, 1);
                 // every (j, i) of the tile inside the matrix: no per-term guards
                 const bool full = nj == NJ && (j0 + NJ - 1) * n1 + i0 + nb - 1 < ell;
                 auto kern = full ? k_bsgs_mac3<NJ, true> : k_bsgs_mac3<NJ, false>;
                 hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, P + q0 * pq, pq, bp, qn, nb, i0, n1, j0, nj, ell,
-                                   db_level, baby_level, level, c->N, c->d_mod, (int)(i0 > 0), lq, pofs);
+                                   dstride, lay, baby_level, level, c->N, c->d_mod, (int)(i0 > 0), lq, pofs);
             }
         }
     }
 }
 
 // giant steps per thread: 16, or the smallest power of two covering n2
-void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1, const u64 *const *diag,
-              int ell, int db_level, int level, int baby_level, int lq, int pofs) {
+void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq, int n1,
+              const unsigned char *const *diag, size_t dstride, const DbLayout &lay, int ell, int level,
+              int baby_level, int lq, int pofs) {
     const int n2 = (ell + n1 - 1) / n1;
     if (n2 > 8)
-        bsgs_mac_nj<16>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
+        bsgs_mac_nj<16>(c, P, pq, baby, nq, n1, diag, dstride, lay, ell, level, baby_level, lq, pofs);
     else if (n2 > 4)
-        bsgs_mac_nj<8>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
+        bsgs_mac_nj<8>(c, P, pq, baby, nq, n1, diag, dstride, lay, ell, level, baby_level, lq, pofs);
     else if (n2 > 2)
-        bsgs_mac_nj<4>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
+        bsgs_mac_nj<4>(c, P, pq, baby, nq, n1, diag, dstride, lay, ell, level, baby_level, lq, pofs);
     else if (n2 > 1)
-        bsgs_mac_nj<2>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
+        bsgs_mac_nj<2>(c, P, pq, baby, nq, n1, diag, dstride, lay, ell, level, baby_level, lq, pofs);
     else
-        bsgs_mac_nj<1>(c, P, pq, baby, nq, n1, diag, ell, db_level, level, baby_level, lq, pofs);
+        bsgs_mac_nj<1>(c, P, pq, baby, nq, n1, diag, dstride, lay, ell, level, baby_level, lq, pofs);
+}
+
+void db_pack(const fr_ctx *c, unsigned char *dst, size_t dstride, const DbLayout &lay, const u64 *src, int nl, int nd) {
+    if (nd <= 0) return;
+    hipLaunchKernelGGL(k_db_pack, grid(c, nl, nd), dim3(kT), 0, c->stream, dst, dstride, lay, src, nl, c->N);
+}
+
+void db_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, size_t sstride, const DbLayout &lay, int nl,
+               int nd) {
+    if (nd <= 0) return;
+    hipLaunchKernelGGL(k_db_unpack, grid(c, nl, nd), dim3(kT), 0, c->stream, dst, src, sstride, lay, nl, c->N);
 }
 
 void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,
