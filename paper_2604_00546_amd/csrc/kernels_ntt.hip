@@ -239,6 +239,21 @@ __device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u6
 // primes below this take the reduction-free butterflies
 constexpr u64 kSmallQ = 1ull << 46;
 
+// A stage's twiddles are tw[base + (k >> sh)] for its elements k < E.  With
+// HOLD all E >> sh of them are fetched before the stage's butterflies and
+// the scheduler may not sink the loads back to their uses, so they overlap
+// instead of each waiting for the one before (more registers: measured
+// worth it only in the plain forward row pass, whose large-stage twiddles
+// come from L2).  Without HOLD each is loaded at its use.
+#define NTT_STAGE_TW(HOLD, BASE, SH)                                                                     \
+    ulonglong2 tws[E];                                                                                    \
+    const int tbase_ = (BASE);                                                                            \
+    if (HOLD) {                                                                                           \
+        _Pragma("unroll") for (int t = 0; t < E; ++t) if (t < (E >> (SH))) tws[t] = tw[tbase_ + t];      \
+        __builtin_amdgcn_sched_barrier(0);                                                                \
+    }
+#define NTT_TW(HOLD, K, SH) ((HOLD) ? tws[(K) >> (SH)] : tw[tbase_ + ((K) >> (SH))])
+
 // LDS layouts of the transposes.  A row tile of R = E^2 words is read both
 // as i = u + E k and as i = E u + k (u the lane's index); word i = E r + c of
 // the tile of sub-transform `blk` is stored at E (r ^ blk mod E) + (c ^ r),
@@ -296,11 +311,12 @@ __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int st = 0; st < LE; ++st) {
         const int half = E >> (st + 1);
+        NTT_STAGE_TW(false, 1 << st, LE - st)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (1 << st) + (k >> (LE - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                const ulonglong2 t2 = NTT_TW(false, k, LE - st);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
             }
     }
 #pragma unroll
@@ -311,11 +327,12 @@ __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int st = LE; st < LR; ++st) {
         const int half = 1 << (LR - st - 1);
+        NTT_STAGE_TW(false, (1 << st) + (g << (st - LE)), LR - st)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (1 << st) + ((E * g + k) >> (LR - st));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                const ulonglong2 t2 = NTT_TW(false, k, LR - st);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
             }
     }
 #pragma unroll
@@ -366,11 +383,12 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int sl = 0; sl < LE; ++sl) {
         const int half = E >> (sl + 1);
+        NTT_STAGE_TW(!EPI, (1 << (LR + sl)) + (gb << sl), LE - sl)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (1 << (LR + sl)) + (gb << sl) + (k >> (LE - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                const ulonglong2 t2 = NTT_TW(!EPI, k, LE - sl);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
             }
     }
 #pragma unroll
@@ -381,11 +399,12 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int sl = LE; sl < LR; ++sl) {
         const int half = 1 << (LR - sl - 1);
+        NTT_STAGE_TW(!EPI, (1 << (LR + sl)) + (gb << sl) + (u0 << (sl - LE)), LR - sl)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (1 << (LR + sl)) + (gb << sl) + ((E * u0 + k) >> (LR - sl));
-                { const ulonglong2 t2 = tw[ti]; ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4); }
+                const ulonglong2 t2 = NTT_TW(!EPI, k, LR - sl);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
             }
     }
 #pragma unroll
@@ -458,11 +477,12 @@ __device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int lt = 0; lt < LE; ++lt) {
         const int half = 1 << lt;
+        NTT_STAGE_TW(false, (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (u0 << (LE - lt - 1)), lt + 1)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + ((E * u0 + k) >> (lt + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1)); }
+                const ulonglong2 t2 = NTT_TW(false, k, lt + 1);
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1));
             }
     }
 #pragma unroll
@@ -473,11 +493,12 @@ __device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int lt = LE; lt < LR; ++lt) {
         const int half = 1 << (lt - LE);
+        NTT_STAGE_TW(false, (N >> (lt + 1)) + (gb << (LR - lt - 1)), lt + 1 - LE)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (k >> (lt + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1)); }
+                const ulonglong2 t2 = NTT_TW(false, k, lt + 1 - LE);
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1));
             }
     }
 #pragma unroll
@@ -513,11 +534,12 @@ __device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int ltp = 0; ltp < LE; ++ltp) {
         const int half = 1 << ltp;
+        NTT_STAGE_TW(false, (N >> (LR + ltp + 1)) + (g << (LE - ltp - 1)), ltp + 1)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (N >> (LR + ltp + 1)) + ((E * g + k) >> (ltp + 1));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1)); }
+                const ulonglong2 t2 = NTT_TW(false, k, ltp + 1);
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1));
             }
     }
 #pragma unroll
@@ -528,11 +550,12 @@ __device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
     for (int ltp = LE; ltp < LR; ++ltp) {
         const int half = 1 << (ltp - LE);
+        NTT_STAGE_TW(false, N >> (LR + ltp + 1), ltp + 1 - LE)
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
-                const int ti = (N >> (LR + ltp + 1)) + (k >> (ltp + 1 - LE));
-                { const ulonglong2 t2 = tw[ti]; gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1)); }
+                const ulonglong2 t2 = NTT_TW(false, k, ltp + 1 - LE);
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1));
             }
     }
 #pragma unroll
