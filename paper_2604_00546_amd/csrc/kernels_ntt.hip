@@ -442,6 +442,172 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
     for (int k = 0; k < E; ++k) xb[u0 + E * k] = fwd_final<SMALL>(tb[rsw<LE>(u0 + E * k, blk)], mcq);
 }
 
+// ---------------------------------------------------------------------------
+// Row passes for small launches at N = 2^16 (R = 256 words per row): 64
+// threads per row, 4 words per thread, 4 rounds of 2 stages with an LDS
+// exchange between rounds.  A thread's chain of dependent work is a quarter
+// of the radix-16 pass's, which is what bounds a launch of a few limb
+// polynomials.  Same stages, same twiddles, same butterflies in the same
+// order as k_fwd_rows2 / k_inv_rows2, so the words are the same.
+// ---------------------------------------------------------------------------
+constexpr int kRowT = 64, kRowsPerBlk = kThreads / kRowT;
+
+// word index within the row of element k (< 4) of thread t in a round whose
+// two stages pair words 2^lo and 2^(lo+1) apart: bits lo, lo+1 are k
+__device__ __forceinline__ int row4_idx(int t, int k, int lo) {
+    return ((t >> lo) << (lo + 2)) | (k << lo) | (t & ((1 << lo) - 1));
+}
+
+template <bool SMALL, bool EPI>
+__device__ __forceinline__ void k_fwd_rows4_body(const NttLaunch &a, u64 *tile) {
+    constexpr int LR = 8, R = 256;
+    const int s = a.map.storage(blockIdx.z);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const ModConst mcq = a.mods[mi];
+    u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * a.N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
+    const int blk = threadIdx.x / kRowT, t = threadIdx.x % kRowT;
+    const int gb = blockIdx.x * kRowsPerBlk + blk;
+    u64 *xb = x + (size_t)gb * R;
+    u64 *tb = tile + blk * R;
+    u64 v[4];
+    // forward (CT) stages sl = 0..7 pair words 2^(7 - sl) apart; round r
+    // takes sl = 2r (k, k+2) and 2r+1 (k, k+1) on words row4_idx(t, k, 6 - 2r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = xb[row4_idx(t, k, 6)];
+    // every twiddle of the thread, fetched at once: in stage 2r both pairs
+    // share one (their words differ below bit 8 - 2r), stage 2r+1 takes two
+    auto twi = [&](int sl, int k, int lo) { return (1 << (LR + sl)) + (gb << sl) + (row4_idx(t, k, lo) >> (LR - sl)); };
+    ulonglong2 tws[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 6 - 2 * r;
+        tws[r][0] = tw[twi(2 * r, 0, lo)];
+        tws[r][1] = tw[twi(2 * r + 1, 0, lo)];
+        tws[r][2] = tw[twi(2 * r + 1, 2, lo)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 6 - 2 * r;
+        if (r > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = tb[row4_idx(t, k, lo)];
+        }
+        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4);
+        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4);
+        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4);
+        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4);
+        if (r < 3) {  // a thread writes back the words it read this round
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tb[row4_idx(t, k, lo)] = v[k];
+            __syncthreads();
+        }
+    }
+    // the last round's words are row4_idx(t, k, 0) = 4 t + k
+    const size_t w = (size_t)s * a.N + (size_t)gb * R + 4 * t;
+    if constexpr (EPI) {  // rescale / ModDown finish: (in - y) qinv (+ out)
+        const u64 *in = a.epi_in + blockIdx.y * a.epi_in_stride + w;
+        u64 *out = a.epi_out + blockIdx.y * a.epi_out_stride + w;
+        const u64 qi = a.qinv[mi], qs = a.qinv_sh[mi];
+        if (a.qinv2) {
+            const u64 *in2 = a.epi_in2 ? a.epi_in2 + blockIdx.y * a.epi_in2_stride + w : nullptr;
+            const u64 q2i = a.qinv2[mi], q2s = a.qinv2_sh[mi];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                u64 r = shoup(subq(in[k], fwd_final<SMALL>(v[k], mcq), q), qi, qs, q);
+                if (in2) r = addq(in2[k], r, q);
+                out[k] = shoup(r, q2i, q2s, q);
+            }
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            u64 r = shoup(subq(in[k], fwd_final<SMALL>(v[k], mcq), q), qi, qs, q);
+            if (a.epi_acc) r = addq(r, out[k], q);
+            out[k] = r;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xb[4 * t + k] = fwd_final<SMALL>(v[k], mcq);
+    }
+}
+
+template <bool EPI>
+__global__ __launch_bounds__(kThreads) void k_fwd_rows4(NttLaunch a) {
+    __shared__ u64 tile[kRowsPerBlk * 256];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.z))].q;
+    if (qb < kSmallQ)
+        k_fwd_rows4_body<true, EPI>(a, tile);
+    else
+        k_fwd_rows4_body<false, EPI>(a, tile);
+}
+
+template <bool SMALL>
+__device__ __forceinline__ void k_inv_rows4_body(const NttLaunch &a, u64 *tile) {
+    constexpr int LR = 8, R = 256;
+    const int s = a.map.storage(blockIdx.z);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const int N = a.N;
+    u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
+    const int blk = threadIdx.x / kRowT, t = threadIdx.x % kRowT;
+    const int gb = blockIdx.x * kRowsPerBlk + blk;
+    u64 *xb = x + (size_t)gb * R;
+    const u64 *xsb = (a.src ? a.src + blockIdx.y * a.src_poly_stride + (size_t)s * N : x) + (size_t)gb * R;
+    u64 *tb = tile + blk * R;
+    u64 v[4];
+    // inverse (GS) stages lt = 0..7 pair words 2^lt apart; round r takes
+    // lt = 2r (k, k+1) and 2r+1 (k, k+2) on words row4_idx(t, k, 2r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = xsb[row4_idx(t, k, 0)];
+    // every twiddle of the thread, fetched at once: stage 2r takes two (pairs
+    // (0,1), (2,3)), in stage 2r+1 the pairs (0,2), (1,3) share one
+    auto twi = [&](int lt, int k, int lo) {
+        return (N >> (lt + 1)) + (gb << (LR - lt - 1)) + (row4_idx(t, k, lo) >> (lt + 1));
+    };
+    ulonglong2 tws[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 2 * r;
+        tws[r][0] = tw[twi(2 * r, 0, lo)];
+        tws[r][1] = tw[twi(2 * r, 2, lo)];
+        tws[r][2] = tw[twi(2 * r + 1, 0, lo)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 2 * r, lt = 2 * r;
+        if (r > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = tb[row4_idx(t, k, lo)];
+        }
+        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, q << (lt + 1));
+        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, q << (lt + 1));
+        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        if (r < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tb[row4_idx(t, k, lo)] = v[k];
+            __syncthreads();
+        }
+    }
+    // the last round's words are row4_idx(t, k, 6) = t + 64 k
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xb[t + 64 * k] = v[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_inv_rows4(NttLaunch a) {
+    __shared__ u64 tile[kRowsPerBlk * 256];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.z))].q;
+    if (qb < kSmallQ)
+        k_inv_rows4_body<true>(a, tile);
+    else
+        k_inv_rows4_body<false>(a, tile);
+}
+
 // EPI: the launch carries an epilogue (epi_out set)
 template <int LE, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
@@ -605,6 +771,27 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     return a;
 }
 
+// limb polynomials up to which the N = 2^16 row passes take 4 words per
+// thread (a launch this small is bound by one thread's chain of work;
+// thresholds from measured pass durations)
+constexpr int kSmallFwdRows = 32, kSmallInvRows = 48;
+
+template <bool EPI>
+void fwd_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 gr) {
+    if (npoly * nlimbs <= kSmallFwdRows)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows4<EPI>), dim3(256 / kRowsPerBlk, npoly, nlimbs), dim3(kThreads),
+                           0, c->stream, a);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, EPI>), gr, dim3(kThreads), 0, c->stream, a);
+}
+
+void inv_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 gr) {
+    if (npoly * nlimbs <= kSmallInvRows)
+        hipLaunchKernelGGL(k_inv_rows4, dim3(256 / kRowsPerBlk, npoly, nlimbs), dim3(kThreads), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(k_inv_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+}
+
 }  // namespace
 
 namespace frk {
@@ -621,7 +808,7 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
         dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
             hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, false>), gr, dim3(kThreads), 0, c->stream, a);
+            fwd_rows16<false>(c, a, npoly, nlimbs, gr);
         } else {
             hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, false>), gr, dim3(kThreads), 0, c->stream, a);
@@ -652,7 +839,7 @@ bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xto
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
+        fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
@@ -677,7 +864,7 @@ bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U
     dim3 g(R / (kThreads / E), nl, npoly), gr(R / (kThreads / E), npoly, nl);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
+        fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
@@ -704,7 +891,7 @@ bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<4, true>), gr, dim3(kThreads), 0, c->stream, a);
+        fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows2<3, true>), gr, dim3(kThreads), 0, c->stream, a);
@@ -721,7 +908,7 @@ void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
         dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
-            hipLaunchKernelGGL(k_inv_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);
+            inv_rows16(c, a, npoly, nlimbs, gr);
             hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
         } else {
             hipLaunchKernelGGL(k_inv_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
