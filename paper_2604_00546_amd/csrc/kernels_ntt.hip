@@ -608,6 +608,139 @@ __global__ __launch_bounds__(kThreads) void k_inv_rows4(NttLaunch a) {
         k_inv_rows4_body<false>(a, tile);
 }
 
+// Column passes for small launches at N = 2^16: the same 4-words-per-thread
+// rounds down each column (64 threads per column), 16 columns per block of
+// 1024 threads so that a wave's loads cover 16 consecutive columns.
+constexpr int kColT = 64, kColsPerBlk = 16, kColThreads = kColT * kColsPerBlk;
+
+template <bool SMALL>
+__device__ __forceinline__ void k_fwd_cols4_body(const NttLaunch &a, u64 *tile) {
+    constexpr int LR = 8, R = 256;
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const u64 q = a.mods[mi].q, q4 = 4 * q;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
+    const int c = threadIdx.x % kColsPerBlk, g = threadIdx.x / kColsPerBlk;
+    const int col = blockIdx.x * kColsPerBlk + c;
+    const u64 *xs = a.src ? a.src + blockIdx.z * a.src_poly_stride + (a.pre_top >= 0 ? 0 : (size_t)s * a.N) : x;
+    u64 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = xs[col + (size_t)row4_idx(g, k, 6) * R];
+    if (a.pre_top >= 0) {  // centered residue of the top limb in this limb
+        const u64 qt = a.mods[a.pre_top].q;
+        const ModConst mc = a.mods[mi];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (v[k] > (qt >> 1)) {
+                const u64 neg = reduce64(qt - v[k], mc);
+                v[k] = neg ? mc.q - neg : 0;
+            } else {
+                v[k] = reduce64(v[k], mc);
+            }
+        }
+    }
+    // stages st = 0..7 pair rows 2^(7 - st) apart, twiddle (1 << st) + (j >> (8 - st))
+    ulonglong2 tws[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 6 - 2 * r;
+        tws[r][0] = tw[(1 << (2 * r)) + (row4_idx(g, 0, lo) >> (LR - 2 * r))];
+        tws[r][1] = tw[(1 << (2 * r + 1)) + (row4_idx(g, 0, lo) >> (LR - 2 * r - 1))];
+        tws[r][2] = tw[(1 << (2 * r + 1)) + (row4_idx(g, 2, lo) >> (LR - 2 * r - 1))];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    u64 *tc = tile + c;  // column c of the tile, rows kColsPerBlk words apart
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 6 - 2 * r;
+        if (r > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = tc[row4_idx(g, k, lo) * kColsPerBlk];
+        }
+        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4);
+        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4);
+        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4);
+        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4);
+        if (r < 3) {  // a thread writes back the words it read this round
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tc[row4_idx(g, k, lo) * kColsPerBlk] = v[k];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[col + (size_t)(4 * g + k) * R] = v[k];
+}
+
+__global__ __launch_bounds__(kColThreads) void k_fwd_cols4(NttLaunch a) {
+    __shared__ u64 tile[256 * kColsPerBlk];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.y))].q;
+    if (qb < kSmallQ)
+        k_fwd_cols4_body<true>(a, tile);
+    else
+        k_fwd_cols4_body<false>(a, tile);
+}
+
+template <bool SMALL>
+__device__ __forceinline__ void k_inv_cols4_body(const NttLaunch &a, u64 *tile) {
+    constexpr int LR = 8, R = 256;
+    const int s = a.map.storage(blockIdx.y);
+    const int mi = a.map.modidx(s);
+    const ModConst mc = a.mods[mi];
+    const u64 q = mc.q, q4 = 4 * q;
+    const int N = a.N;
+    u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
+    const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
+    const int c = threadIdx.x % kColsPerBlk, g = threadIdx.x / kColsPerBlk;
+    const int col = blockIdx.x * kColsPerBlk + c;
+    u64 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = x[col + (size_t)(4 * g + k) * R];
+    // stages ltp = 0..7 pair rows 2^ltp apart, twiddle (N >> (9 + ltp)) + (j >> (ltp + 1))
+    ulonglong2 tws[4][3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 2 * r;
+        tws[r][0] = tw[(N >> (LR + 2 * r + 1)) + (row4_idx(g, 0, lo) >> (2 * r + 1))];
+        tws[r][1] = tw[(N >> (LR + 2 * r + 1)) + (row4_idx(g, 2, lo) >> (2 * r + 1))];
+        tws[r][2] = tw[(N >> (LR + 2 * r + 2)) + (row4_idx(g, 0, lo) >> (2 * r + 2))];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    u64 *tc = tile + c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = 2 * r, lt = LR + 2 * r;
+        if (r > 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = tc[row4_idx(g, k, lo) * kColsPerBlk];
+        }
+        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, q << (lt + 1));
+        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, q << (lt + 1));
+        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        if (r < 3) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tc[row4_idx(g, k, lo) * kColsPerBlk] = v[k];
+            __syncthreads();
+        }
+    }
+    // the last round's rows are row4_idx(g, k, 6) = g + 64 k
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u64 r = shoup_lazy(v[k], mc.ninv, mc.ninv_sh, q);
+        x[col + (size_t)(g + 64 * k) * R] = r >= q ? r - q : r;
+    }
+}
+
+__global__ __launch_bounds__(kColThreads) void k_inv_cols4(NttLaunch a) {
+    __shared__ u64 tile[256 * kColsPerBlk];
+    const u64 qb = a.mods[a.map.modidx(a.map.storage(blockIdx.y))].q;
+    if (qb < kSmallQ)
+        k_inv_cols4_body<true>(a, tile);
+    else
+        k_inv_cols4_body<false>(a, tile);
+}
+
 // EPI: the launch carries an epilogue (epi_out set)
 template <int LE, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_fwd_rows2(NttLaunch a) {
@@ -774,7 +907,21 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
 // limb polynomials up to which the N = 2^16 row passes take 4 words per
 // thread (a launch this small is bound by one thread's chain of work;
 // thresholds from measured pass durations)
-constexpr int kSmallFwdRows = 32, kSmallInvRows = 48;
+constexpr int kSmallFwdRows = 32, kSmallInvRows = 48, kSmallFwdCols = 32, kSmallInvCols = 48;
+
+void fwd_cols16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 g) {
+    if (npoly * nlimbs <= kSmallFwdCols)
+        hipLaunchKernelGGL(k_fwd_cols4, g, dim3(kColThreads), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+}
+
+void inv_cols16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 g) {
+    if (npoly * nlimbs <= kSmallInvCols)
+        hipLaunchKernelGGL(k_inv_cols4, g, dim3(kColThreads), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+}
 
 template <bool EPI>
 void fwd_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 gr) {
@@ -807,7 +954,7 @@ void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
         // limb, so the limb's large-stage twiddles stay in L2
         dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
-            hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+            fwd_cols16(c, a, npoly, nlimbs, g);
             fwd_rows16<false>(c, a, npoly, nlimbs, gr);
         } else {
             hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
@@ -838,7 +985,7 @@ bool ntt_fwd_rescale(const fr_ctx *c, u64 *tmp, int l, int npoly, const u64 *xto
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
-        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        fwd_cols16(c, a, npoly, (int)gr.z, g);
         fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
@@ -863,7 +1010,7 @@ bool ntt_fwd_moddown(const fr_ctx *c, u64 *V, int level, int npoly, const u64 *U
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), nl, npoly), gr(R / (kThreads / E), npoly, nl);
     if (LE == 4) {
-        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        fwd_cols16(c, a, npoly, (int)gr.z, g);
         fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
@@ -890,7 +1037,7 @@ bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
-        hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+        fwd_cols16(c, a, npoly, (int)gr.z, g);
         fwd_rows16<true>(c, a, npoly, (int)gr.z, gr);
     } else {
         hipLaunchKernelGGL(k_fwd_cols2<3>, g, dim3(kThreads), 0, c->stream, a);
@@ -909,7 +1056,7 @@ void ntt_inv(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npo
         dim3 g(R / (kThreads / E), nlimbs, npoly), gr(R / (kThreads / E), npoly, nlimbs);
         if (LE == 4) {
             inv_rows16(c, a, npoly, nlimbs, gr);
-            hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
+            inv_cols16(c, a, npoly, nlimbs, g);
         } else {
             hipLaunchKernelGGL(k_inv_rows2<3>, gr, dim3(kThreads), 0, c->stream, a);
             hipLaunchKernelGGL(k_inv_cols2<3>, g, dim3(kThreads), 0, c->stream, a);

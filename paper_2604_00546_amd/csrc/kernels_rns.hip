@@ -483,13 +483,51 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 //   P_j[c][m][k] = sum_i baby_i[c][m][k] * diag_{j n1 + i}[m][k]
 // A wave covers 32 coefficients of one limb for both polynomials (lanes
 // 0..31: c0, lanes 32..63: c1), so each diagonal word is fetched once per
-// wave and shared by the two half-waves.  A thread keeps NJ 128-bit lazy sums
-// of full products (at most 32 products below 2^122 each) and reduces each
-// with one Montgomery reduction at the end (the diagonals are
-// Montgomery-scaled by 2^64).  All NJ diagonal words of a baby step are
-// loaded before the products that use them.  Positions past ell or nj read
-// diagonal 0 and contribute zero (a launch whose tile lies inside the
-// matrix is compiled without those guards).
+// wave and shared by the two half-waves.  All NJ diagonal words of a baby
+// step are loaded before the products that use them; a load's address is a
+// wave-uniform row pointer plus a 32-bit lane offset.  Positions past ell or
+// nj read diagonal 0 and contribute zero (a launch whose tile lies inside the
+// matrix is compiled without those guards).  The diagonals are
+// Montgomery-scaled by 2^64, so each sum, held exactly, takes one Montgomery
+// reduction at the end; at most 32 terms per launch.
+//
+// 64-bit limbs: 128-bit lazy sums of full products (each below 2^122).
+// Packed limbs (q < 2^40, diagonal word w = wl + wh 2^32 with wh < 2^8; baby
+// word b below 2^45, canonical words are below q): with b = b0 + b1 2^27
+// (b0 < 2^27, b0s = b0 2^5), the product splits as
+//   b w = b0 wl + 2^27 (b1 wl + b0s wh) + 2^59 b1 wh,
+// three sums that cannot overflow their words over 32 terms (below 2^64,
+// 2^56 and 2^32): three 32 x 32 -> 64-bit and one 24-bit multiply-add per
+// term in place of a full 64 x 64 product and its carries.
+// A wave-uniform address held in scalar registers as an opaque value, so the
+// compiler cannot fold lane offsets into it ahead of time: loads then take
+// the form uniform base + 32-bit lane offset, with no per-lane 64-bit adds.
+typedef const __attribute__((address_space(1))) unsigned char gbyte;
+__device__ __forceinline__ gbyte *uniform_ptr(const unsigned char *p) {
+    const u64 v = reinterpret_cast<u64>(p);
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)v), hi = __builtin_amdgcn_readfirstlane((u32)(v >> 32));
+    return reinterpret_cast<gbyte *>(((u64)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T gload(gbyte *base, u32 off) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) T *>(base + off);
+}
+
+// P_j = (hi:lo) 2^-64 mod q (+ P_j) for the tile's giant steps
+template <int NJ>
+__device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi, int j0, int nj, int p, int lv, int m,
+                                           int N, int k, const ModConst &mc, int accumulate) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        if (jj < nj) {
+            const size_t o = (((size_t)(j0 + jj) * 2 + p) * (lv + 1) + m) * N + k;
+            u64 r = redc_any(lo[jj], hi[jj], mc);
+            if (accumulate) r = addq(r, P[o], mc.q);
+            P[o] = r;
+        }
+    }
+}
+
 template <int NJ, bool FULL, bool PK>
 __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp, int q, int tile, int nb, int i0,
                                           int n1, int j0, int nj, int ell, size_t dstride, unsigned loff, int bl,
@@ -497,37 +535,75 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
     const int lane = threadIdx.x & 63, p = lane >> 5;
     const int k = tile * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
     const unsigned char *dg = bp.diag[q] + loff;
-    const size_t boff = ((size_t)p * (bl + 1) + m) * N + k;
+    // diagonal (j0 + jj) n1 + i0 + ii at base + ii dstride + jj jstride
+    const unsigned char *base = dg + ((size_t)j0 * n1 + i0) * dstride;
+    const size_t jstride = (size_t)n1 * dstride;
+    const u32 boff = (u32)((((size_t)p * (bl + 1) + m) * N + k) * 8);
+    const u32 vw = (PK ? 4u : 8u) * (u32)k, vh = 4u * (u32)N + (u32)k;  // word (low word), high byte
     P += q * pq;
-    unsigned __int128 acc[NJ];
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
-    for (int ii = 0; ii < nb; ++ii) {
-        const int i = i0 + ii;
-        u64 w[NJ];
+    // the words of baby step ii: its baby word and NJ diagonal words (zero
+    // past ell or nj).  The lane offsets are redefined at each call so that
+    // they stay 32-bit operands of the loads instead of hoisted 64-bit sums.
+    auto fetch = [&](int ii, u64 &b, auto *w, u32 *wh) {
+        const unsigned char *row = base + (size_t)ii * dstride;
+        u32 ow = vw, oh = vh, ob = boff;
+        asm volatile("" : "+v"(ow), "+v"(oh), "+v"(ob));
+        b = gload<u64>(uniform_ptr(reinterpret_cast<const unsigned char *>(bp.p[q][ii])), ob);
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
-            const int d = (j0 + jj) * n1 + i;
-            if (FULL) {
-                w[jj] = diag_word<PK>(dg, (size_t)d * dstride, k, N);
+            const bool ok = FULL || (jj < nj && (j0 + jj) * n1 + i0 + ii < ell);
+            gbyte *r = uniform_ptr(ok ? row + jj * jstride : dg);
+            if constexpr (PK) {
+                w[jj] = gload<u32>(r, ow);
+                wh[jj] = gload<unsigned char>(r, oh);
+                if (!ok) wh[jj] = 0;
             } else {
-                const bool ok = jj < nj && d < ell;
-                w[jj] = diag_word<PK>(dg, (ok ? (size_t)d : 0) * dstride, k, N);
-                if (!ok) w[jj] = 0;
+                w[jj] = gload<u64>(r, ow);
+            }
+            if (!ok) w[jj] = 0;
+        }
+    };
+    if constexpr (PK) {
+        // A = sum b0 wl, Bm = sum (b1 wl + b0s wh), D = sum b1 wh
+        u64 A[NJ], Bm[NJ];
+        u32 D[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) A[jj] = Bm[jj] = 0, D[jj] = 0;
+        for (int ii = 0; ii < nb; ++ii) {
+            u64 b;
+            u32 wl[NJ], wh[NJ];
+            fetch(ii, b, wl, wh);
+            const u32 b0 = (u32)b & 0x7ffffffu, b1 = (u32)(b >> 27) & 0xffffffu, b0s = b0 << 5;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                A[jj] += (u64)b0 * wl[jj];
+                Bm[jj] += (u64)b1 * wl[jj];
+                Bm[jj] += (u64)b0s * wh[jj];
+                D[jj] += b1 * wh[jj];
             }
         }
-        const u64 b = bp.p[q][ii][boff];
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
-    }
-#pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-        if (jj < nj) {
-            const size_t o = (((size_t)(j0 + jj) * 2 + p) * (lv + 1) + m) * N + k;
-            u64 r = redc_any((u64)acc[jj], (u64)(acc[jj] >> 64), mc);
-            if (accumulate) r = addq(r, P[o], mc.q);
-            P[o] = r;
+        for (int jj = 0; jj < NJ; ++jj) {
+            const unsigned __int128 s =
+                (unsigned __int128)A[jj] + ((unsigned __int128)Bm[jj] << 27) + ((unsigned __int128)D[jj] << 59);
+            A[jj] = (u64)s;
+            Bm[jj] = (u64)(s >> 64);
         }
+        mac3_store<NJ>(P, A, Bm, j0, nj, p, lv, m, N, k, mc, accumulate);
+    } else {
+        unsigned __int128 acc[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
+        for (int ii = 0; ii < nb; ++ii) {
+            u64 b, w[NJ];
+            fetch(ii, b, w, nullptr);
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
+        }
+        u64 lo[NJ], hi[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) lo[jj] = (u64)acc[jj], hi[jj] = (u64)(acc[jj] >> 64);
+        mac3_store<NJ>(P, lo, hi, j0, nj, p, lv, m, N, k, mc, accumulate);
     }
 }
 

@@ -120,6 +120,8 @@ def test_hoisted_rejects_bad_inputs(H):
     (1000, 128, 4, 40, 1),   # n1 > 32: baby steps in two MAC chunks; second of two groups
     (64, 64, 32, 64, 0),     # the diagonal method: n2 = 1, no giant step
     (20, 128, 1, 8, 0),      # B = 1: one block per plaintext
+    (200, 96, 8, 7, 0),      # odd n1: an odd number of baby steps per MAC launch
+    (500, 128, 4, 33, 0),    # n1 = 33: MAC chunks of 32 and 1 baby steps
 ])
 def test_hoisted_ragged_shapes_bitexact(oracle_mod, K, ell, B, n1, group):
     from paper_2604_00546_amd import fr
