@@ -54,14 +54,16 @@ typedef struct fr_db fr_db;
 /* Parameter set (§3.2; primes by the rule documented in the design notes:
  * q_0 = the largest q0_bits-bit prime = 1 mod 2N, q_1..q_L the next
  * largest mid_bits-bit primes in descending order, p_j the largest
- * special_bits-bit primes not already used). */
+ * special_bits-bit primes not already used).  Primes are at most 60 bits:
+ * the base conversions and scalar combinations form exact sums of products
+ * of 30-bit halves, which needs residues below 2^60. */
 typedef struct fr_params {
     int32_t log_n;        /* 10 .. 16 */
-    int32_t q0_bits;      /* 30 .. 61 */
+    int32_t q0_bits;      /* 30 .. 60 */
     int32_t n_mid;        /* L: number of primes after q_0 */
-    int32_t mid_bits;     /* 30 .. 61 */
+    int32_t mid_bits;     /* 30 .. 60 */
     int32_t n_special;    /* number of special primes */
-    int32_t special_bits; /* 30 .. 61 */
+    int32_t special_bits; /* 30 .. 60 */
     int32_t dnum;         /* key-switching digits; alpha = ceil((L+1)/dnum) */
 } fr_params;
 

@@ -512,9 +512,9 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
     CHECK(p->n_mid >= 0 && p->n_special >= 1 && p->dnum >= 1 && 1 + p->n_mid + p->n_special <= FR_MAXMOD &&
               p->n_mid + 1 <= FR_MAXLEVEL,
           FR_EINVAL, "fr_ctx_create: bad prime counts");
-    CHECK(p->q0_bits >= 30 && p->q0_bits <= 61 && p->mid_bits >= 30 && p->mid_bits <= 61 && p->special_bits >= 30 &&
-              p->special_bits <= 61,
-          FR_EINVAL, "fr_ctx_create: prime sizes must be 30..61 bits");
+    CHECK(p->q0_bits >= 30 && p->q0_bits <= 60 && p->mid_bits >= 30 && p->mid_bits <= 60 && p->special_bits >= 30 &&
+              p->special_bits <= 60,
+          FR_EINVAL, "fr_ctx_create: prime sizes must be 30..60 bits");
     const int alpha = (p->n_mid + 1 + p->dnum - 1) / p->dnum;
     CHECK(alpha <= 8 && p->n_special <= 8 && p->dnum <= 8, FR_EINVAL,
           "fr_ctx_create: digit size and special primes limited to 8");

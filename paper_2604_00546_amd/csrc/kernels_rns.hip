@@ -16,6 +16,38 @@ constexpr int kMaxDigit = 8;  // alpha <= 8 (checked at context creation)
 constexpr int kTargetsPerThread = 8;  // ModUp conversions: target limbs per thread
 constexpr int kFbcTargets = 8;  // ModDown conversions: target limbs per thread
 
+// Exact sum of at most 16 products y w with y, w < 2^60 (residues and table
+// constants of primes below 2^60).  With 30-bit halves y = y0 + y1 2^30 and
+// w = w0 + w1 2^30, each of the four partial sums (y0 w0, y0 w1, y1 w0,
+// y1 w1) stays below 2^64 (terms below 2^60, plus a start value below 2^60
+// in the first), so a term takes four 32 x 32 -> 64-bit multiply-adds and no
+// carry handling; the 128-bit total is formed once.
+__device__ __forceinline__ void split30(u64 y, u32 &y0, u32 &y1) {
+    y0 = (u32)y & 0x3fffffffu;
+    y1 = (u32)(y >> 30);
+}
+struct Dot30 {
+    u64 a, b1 = 0, b2 = 0, c = 0;
+    __device__ __forceinline__ explicit Dot30(u64 start = 0) : a(start) {}
+    __device__ __forceinline__ void add(u32 y0, u32 y1, u32 w0, u32 w1) {
+        a += (u64)y0 * w0;
+        b1 += (u64)y0 * w1;
+        b2 += (u64)y1 * w0;
+        c += (u64)y1 * w1;
+    }
+    __device__ __forceinline__ void add(u32 y0, u32 y1, u64 w) {
+        u32 w0, w1;
+        split30(w, w0, w1);
+        add(y0, y1, w0, w1);
+    }
+    // (hi:lo) 2^-64 mod q
+    __device__ __forceinline__ u64 redc(const ModConst &m) const {
+        const unsigned __int128 s =
+            (unsigned __int128)a + (((unsigned __int128)b1 + b2) << 30) + ((unsigned __int128)c << 60);
+        return redc_any((u64)s, (u64)(s >> 64), m);
+    }
+};
+
 // Batch item and tile of a block when every tile is processed for `batch`
 // items.  Workgroups are placed on the 8 XCDs round-robin by linear id, so
 // with ntiles a multiple of 8 the `batch` blocks of one tile are consecutive
@@ -105,20 +137,20 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
     D += blockIdx.z * sd;
     x += blockIdx.z * sx;
     const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
-    u64 y[kMaxDigit];
+    u32 y0[kMaxDigit], y1[kMaxDigit];
 #pragma unroll
     for (int d = 0; d < kMaxDigit; ++d)
-        if (d < nd) y[d] = shoup(x[(size_t)(lo + d) * N + k], dinv[d], dinv_sh[d], mods[lo + d].q);
+        if (d < nd) split30(shoup(x[(size_t)(lo + d) * N + k], dinv[d], dinv_sh[d], mods[lo + d].q), y0[d], y1[d]);
     const int ntarget = nE - nd;
     const int t0 = blockIdx.y * kTargetsPerThread, t1 = min(ntarget, t0 + kTargetsPerThread);
     for (int te = t0; te < t1; ++te) {
         const int e = te < lo ? te : te + nd;
         const int gm = e <= level ? e : pbase + (e - level - 1);
-        u64 al = 0, ah = 0;
+        Dot30 acc;
 #pragma unroll
         for (int d = 0; d < kMaxDigit; ++d)
-            if (d < nd) mac128(al, ah, y[d], dhat[(size_t)e * nd + d]);
-        D[(size_t)e * N + k] = redc_any(al, ah, mods[gm]);
+            if (d < nd) acc.add(y0[d], y1[d], dhat[(size_t)e * nd + d]);
+        D[(size_t)e * N + k] = acc.redc(mods[gm]);
     }
 }
 
@@ -140,24 +172,24 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
     x += b * sx;
     const u64 *tab = mt.tab[t - tfirst];
     const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
-    u64 y[kMaxDigit];
+    u32 y0[kMaxDigit], y1[kMaxDigit];
 #pragma unroll
     for (int d = 0; d < kMaxDigit; ++d)
         if (d < nd) {
             const u64 xv = x[(size_t)(lo + d) * N + k];
             if (blockIdx.y == 0) D[(size_t)(lo + d) * N + k] = xv;
-            y[d] = shoup(xv, dinv[d], dinv_sh[d], mods[lo + d].q);
+            split30(shoup(xv, dinv[d], dinv_sh[d], mods[lo + d].q), y0[d], y1[d]);
         }
     const int ntarget = nE - nd;
     const int t0 = blockIdx.y * kTargetsPerThread, t1 = min(ntarget, t0 + kTargetsPerThread);
     for (int te = t0; te < t1; ++te) {
         const int e = te < lo ? te : te + nd;
         const int gm = e <= level ? e : pbase + (e - level - 1);
-        u64 al = 0, ah = 0;
+        Dot30 acc;
 #pragma unroll
         for (int d = 0; d < kMaxDigit; ++d)
-            if (d < nd) mac128(al, ah, y[d], dhat[(size_t)e * nd + d]);
-        D[(size_t)e * N + k] = redc_any(al, ah, mods[gm]);
+            if (d < nd) acc.add(y0[d], y1[d], dhat[(size_t)e * nd + d]);
+        D[(size_t)e * N + k] = acc.redc(mods[gm]);
     }
 }
 
@@ -320,14 +352,19 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
             s = s + (double)y[j] * invp[j];
         }
     const u64 e = (u64)rint(s);
+    u32 y0[kMaxDigit], y1[kMaxDigit];
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; ++j)
+        if (j < nP) split30(y[j], y0[j], y1[j]);
     const u64 *epm = reinterpret_cast<const u64 *>(invp + nP);  // [L1][nP+1]: -e P 2^64 mod q_i
-    auto fbc = [&](int i, const ModConst &mi) {
-        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
+    auto fbc_sum = [&](int i) {
+        Dot30 acc(epm[(size_t)i * (nP + 1) + e]);
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
-            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        return redc_any(al, ah, mi);
+            if (j < nP) acc.add(y0[j], y1[j], phat_mod[(size_t)i * nP + j]);
+        return acc;
     };
+    auto fbc = [&](int i, const ModConst &mi) { return fbc_sum(i).redc(mi); };
     const ModConst mt = mods[level];
     const u64 qt = mt.q;
     // folded (Xd null): limb `level` of U already holds d_l + P^-1 U_l;
@@ -345,14 +382,13 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
     // Montgomery sum, against P 2^64 (or -P 2^64) mod q_i
     const u64 *pm = epm + (size_t)L1 * (nP + 1);
     const int i0 = blockIdx.y * kFbcTargets, i1 = min(level, i0 + kFbcTargets);
+    u32 m0, m1;
+    split30(mag, m0, m1);
     for (int i = i0; i < i1; ++i) {
         const ModConst mi = mods[i];
-        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxDigit; ++j)
-            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        mac128(al, ah, mag, neg ? mi.q - pm[i] : pm[i]);
-        Z[poly * sz + (size_t)i * N + k] = redc_any(al, ah, mi);
+        Dot30 acc = fbc_sum(i);
+        acc.add(m0, m1, neg ? mi.q - pm[i] : pm[i]);
+        Z[poly * sz + (size_t)i * N + k] = acc.redc(mi);
     }
 }
 
@@ -379,15 +415,18 @@ __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int 
             s = s + (double)y[j] * invp[j];
         }
     const u64 e = (u64)rint(s);
+    u32 y0[kMaxDigit], y1[kMaxDigit];
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; ++j)
+        if (j < nP) split30(y[j], y0[j], y1[j]);
     const u64 *epm = reinterpret_cast<const u64 *>(invp + nP);  // [L1][nP+1]: -e P 2^64 mod q_i
     const int i0 = blockIdx.y * kFbcTargets, i1 = min(level + 1, i0 + kFbcTargets);
     for (int i = i0; i < i1; ++i) {
-        const ModConst mi = mods[i];
-        u64 al = epm[(size_t)i * (nP + 1) + e], ah = 0;
+        Dot30 acc(epm[(size_t)i * (nP + 1) + e]);
 #pragma unroll
         for (int j = 0; j < kMaxDigit; ++j)
-            if (j < nP) mac128(al, ah, y[j], phat_mod[(size_t)i * nP + j]);
-        V[poly * sv + (size_t)i * N + k] = redc_any(al, ah, mi);
+            if (j < nP) acc.add(y0[j], y1[j], phat_mod[(size_t)i * nP + j]);
+        V[poly * sv + (size_t)i * N + k] = acc.redc(mods[i]);
     }
 }
 
@@ -703,9 +742,10 @@ __global__ __launch_bounds__(kT) void k_scalar_batch(u64 *out, ScalarBatch sb, i
 // scalars and level adjustments): for query q (blockIdx.z) and output b,
 //   out[b][q] = sum_s K[b][s] src[q][s]   on the first nl limbs of both polynomials,
 // K small signed integers, reduced per limb and Montgomery-scaled into LDS
-// by the block.  A thread reads its word of every source once, then forms
-// each output as a 128-bit lazy sum of at most kMatS products below 2^122,
-// reduced once; zero entries are skipped by a per-output bit mask (uniform).
+// by the block (as 30-bit halves).  A thread reads its word of every source
+// once, then forms each output as an exact sum of at most kMatS products
+// (Dot30), reduced once; zero entries are skipped by a per-output bit mask
+// (uniform).
 constexpr int kMatS = 16, kMatB = 16, kMatQ = 8;
 struct ScalarMat {
     const u64 *src[kMatQ][kMatS];
@@ -721,21 +761,25 @@ __global__ __launch_bounds__(kT) void k_scalar_mat(u64 *out, size_t ob, size_t o
     const ModConst m = mods[i];
     for (int t = threadIdx.x; t < kMatB * kMatS; t += kT) {
         const int b = t / kMatS, s = t % kMatS;
-        kc[t] = (b < sm.nb && s < sm.ns) ? shoup(smod_dev(sm.k[b][s], m), m.r64, m.r64_sh, m.q) : 0;
+        const u64 w = (b < sm.nb && s < sm.ns) ? shoup(smod_dev(sm.k[b][s], m), m.r64, m.r64_sh, m.q) : 0;
+        kc[t] = (w >> 30) << 32 | (w & 0x3fffffffu);  // its 30-bit halves
     }
-    u64 x[kMatS];
+    u32 x0[kMatS], x1[kMatS];
 #pragma unroll
     for (int s = 0; s < kMatS; ++s)
-        x[s] = s < sm.ns ? sm.src[q][s][((size_t)p * sm.lp1[s] + i) * N + k] : 0;
+        split30(s < sm.ns ? sm.src[q][s][((size_t)p * sm.lp1[s] + i) * N + k] : 0, x0[s], x1[s]);
     __syncthreads();
     u64 *o = out + q * oq + ((size_t)p * nl + i) * N + k;
     for (int b = 0; b < sm.nb; ++b) {
         const unsigned nz = sm.nz[b];
-        u64 lo = 0, hi = 0;
+        Dot30 acc;
 #pragma unroll
         for (int s = 0; s < kMatS; ++s)
-            if (nz >> s & 1u) mac128(lo, hi, x[s], kc[b * kMatS + s]);
-        o[b * ob] = redc_any(lo, hi, m);
+            if (nz >> s & 1u) {
+                const u64 w = kc[b * kMatS + s];
+                acc.add(x0[s], x1[s], (u32)w, (u32)(w >> 32));
+            }
+        o[b * ob] = acc.redc(m);
     }
 }
 
