@@ -40,10 +40,12 @@ struct Dot30 {
         split30(w, w0, w1);
         add(y0, y1, w0, w1);
     }
-    // (hi:lo) 2^-64 mod q
+    __device__ __forceinline__ unsigned __int128 total() const {
+        return (unsigned __int128)a + (((unsigned __int128)b1 + b2) << 30) + ((unsigned __int128)c << 60);
+    }
+    // (total) 2^-64 mod q
     __device__ __forceinline__ u64 redc(const ModConst &m) const {
-        const unsigned __int128 s =
-            (unsigned __int128)a + (((unsigned __int128)b1 + b2) << 30) + ((unsigned __int128)c << 60);
+        const unsigned __int128 s = total();
         return redc_any((u64)s, (u64)(s >> 64), m);
     }
 };
@@ -197,6 +199,9 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
 // Montgomery-scaled so one reduction yields the canonical sum.
 // fold (relinearisation): the top limb of U becomes d_l + P^-1 U_l (d an item
 // of fold_sd words, [2][level+1][N]); U_l is read by nothing else afterwards
+// ND > 0: compiled for exactly ND digits, every word of the thread in flight
+// before the sums (ND = 0: any count, one digit at a time)
+template <int ND>
 __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
                                                  int logN, int nE, int level, int pbase, int ndig, int nmod,
                                                  const ModConst *mods, int accumulate, size_t sd, size_t su,
@@ -212,16 +217,42 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     const int gm = e <= level ? e : pbase + (e - level - 1);
     const ModConst m = mods[gm];
     const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
-    u64 l0 = 0, h0 = 0, l1 = 0, h1 = 0;
-    for (int t = 0; t < ndig; ++t) {
-        const u64 d = D[((size_t)t * nE + e) * N + src];
-        const u64 kb = ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
-        const u64 ka = ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
-        mac128(l0, h0, d, kb);
-        mac128(l1, h1, d, ka);
+    Dot30 s0, s1;
+    if constexpr (ND > 0) {
+        u64 d[ND], kb[ND], ka[ND];
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+            d[t] = D[((size_t)t * nE + e) * N + src];
+            kb[t] = ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
+            ka[t] = ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+        }
+        const u64 c0 = (rot_c0 && e <= level) ? rot_c0[item * c0_sd + (size_t)e * N + src] : 0;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+            u32 d0, d1;
+            split30(d[t], d0, d1);
+            s0.add(d0, d1, kb[t]);
+            s1.add(d0, d1, ka[t]);
+        }
+        if (rot_c0 && e <= level) {
+            u32 c00, c01;
+            split30(c0, c00, c01);
+            s0.add(c00, c01, pmont[e]);
+        }
+    } else {
+        for (int t = 0; t < ndig; ++t) {
+            u32 d0, d1;
+            split30(D[((size_t)t * nE + e) * N + src], d0, d1);
+            s0.add(d0, d1, ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p]);
+            s1.add(d0, d1, ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p]);
+        }
+        if (rot_c0 && e <= level) {
+            u32 c00, c01;
+            split30(rot_c0[item * c0_sd + (size_t)e * N + src], c00, c01);
+            s0.add(c00, c01, pmont[e]);
+        }
     }
-    if (rot_c0 && e <= level) mac128(l0, h0, rot_c0[item * c0_sd + (size_t)e * N + src], pmont[e]);
-    u64 u0 = redc_any(l0, h0, m), u1 = redc_any(l1, h1, m);
+    u64 u0 = s0.redc(m), u1 = s1.redc(m);
     const size_t w = (size_t)e * N + p;
     if (accumulate) {
         u0 = addq(u0, U0[w], m.q);
@@ -278,6 +309,7 @@ struct GiantKeys {
     const u64 *ksk[kGiant];
     u64 g[kGiant];
 };
+template <int ND>
 __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64 *D, GiantKeys gk, int nj, size_t sdj,
                                                      int N, int logN, int nE, int level, int pbase, int ndig, int nmod,
                                                      const ModConst *mods, int accumulate, size_t sd, size_t su,
@@ -290,20 +322,40 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64
     U1 += item * su;
     const int gm = e <= level ? e : pbase + (e - level - 1);
     const ModConst m = mods[gm];
-    u64 l0 = 0, h0 = 0, l1 = 0, h1 = 0;
+    // exact sums of each giant step's digits (Dot30), added up in 128 bits
+    unsigned __int128 t0 = 0, t1 = 0;
     for (int jj = 0; jj < nj; ++jj) {
         const u32 src = auto_src((u32)p, gk.g[jj], logN);
         const u64 *Dj = D + jj * sdj;
         const u64 *kj = gk.ksk[jj];
-        for (int t = 0; t < ndig; ++t) {
-            const u64 d = Dj[((size_t)t * nE + e) * N + src];
-            const u64 kb = kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
-            const u64 ka = kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
-            mac128(l0, h0, d, kb);
-            mac128(l1, h1, d, ka);
+        Dot30 s0, s1;
+        if constexpr (ND > 0) {
+            u64 d[ND], kb[ND], ka[ND];
+#pragma unroll
+            for (int t = 0; t < ND; ++t) {
+                d[t] = Dj[((size_t)t * nE + e) * N + src];
+                kb[t] = kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
+                ka[t] = kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+            }
+#pragma unroll
+            for (int t = 0; t < ND; ++t) {
+                u32 d0, d1;
+                split30(d[t], d0, d1);
+                s0.add(d0, d1, kb[t]);
+                s1.add(d0, d1, ka[t]);
+            }
+        } else {
+            for (int t = 0; t < ndig; ++t) {
+                u32 d0, d1;
+                split30(Dj[((size_t)t * nE + e) * N + src], d0, d1);
+                s0.add(d0, d1, kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p]);
+                s1.add(d0, d1, kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p]);
+            }
         }
+        t0 += s0.total();
+        t1 += s1.total();
     }
-    u64 u0 = redc_any(l0, h0, m), u1 = redc_any(l1, h1, m);
+    u64 u0 = redc_any((u64)t0, (u64)(t0 >> 64), m), u1 = redc_any((u64)t1, (u64)(t1 >> 64), m);
     const size_t w = (size_t)e * N + p;
     if (accumulate) {
         u0 = addq(u0, U0[w], m.q);
@@ -991,9 +1043,10 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
         pinv = c->P_inv_q[level];
         pinv_sh = c->P_inv_q_sh[level];
     }
-    hipLaunchKernelGGL(k_ks_inner, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N,
-                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch, fold_d,
-                       fold_sd, pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
+    auto kern = ndig == 1 ? k_ks_inner<1> : ndig == 2 ? k_ks_inner<2> : ndig == 3 ? k_ks_inner<3> : k_ks_inner<0>;
+    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN,
+                       nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
+                       pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
 }
 
 void scale_ext(const fr_ctx *c, u64 *out, const u64 *in, int level, int nb, size_t so, size_t si) {
@@ -1032,8 +1085,12 @@ void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *co
     }
     ProfScope ps(c, K_KS, (batch * ((double)nj * ndig * nE + (accumulate ? 4.0 : 2.0) * nE) + 2.0 * nj * ndig * nE) *
                               8.0 * c->N);
-    hipLaunchKernelGGL(k_ks_inner_sum, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, nj, sdj,
-                       c->N, c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+    auto kern = ndig == 1   ? k_ks_inner_sum<1>
+                : ndig == 2 ? k_ks_inner_sum<2>
+                : ndig == 3 ? k_ks_inner_sum<3>
+                            : k_ks_inner_sum<0>;
+    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, nj, sdj, c->N,
+                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
 }
 
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,

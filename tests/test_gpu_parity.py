@@ -137,6 +137,15 @@ def test_missing_key_raises(pair, keys, F):
     assert e.value.code == F.FR_ENOKEY
 
 
+def test_primes_above_60_bits_rejected(F):
+    """The base conversions form exact sums from 30-bit halves of residues,
+    so contexts with a prime above 60 bits are refused at creation."""
+    p = dict(F.small_params(), special_bits=61)
+    with pytest.raises(F.FrError, match="30..60") as e:
+        F.Context(**p)
+    assert e.value.code == F.FR_EINVAL
+
+
 def test_rescale_add_mul_bitexact(pair, keys):
     g, o = pair
     rnd = np.random.default_rng(6)
