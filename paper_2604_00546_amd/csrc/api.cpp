@@ -530,6 +530,15 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
         delete c;
         return fr_fail(FR_EINVAL, "fr_ctx_create: not enough primes of the requested sizes");
     }
+    {  // key-switching key storage: limbs of moduli below 2^40 in 5 bytes per word
+        size_t o = 0;
+        for (int m = 0; m < c->nmod; ++m) {
+            c->klay.packed[m] = c->mod[m] < (1ull << 40);
+            c->klay.off[m] = (unsigned)o;
+            o += (c->klay.packed[m] ? 5 : 8) * (size_t)c->N;
+        }
+        c->klay.block = o;
+    }
     int e = ctx_build(c);
     for (int a = 0; !e && a < fr_ctx::kAux; ++a)
         if (hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking) != hipSuccess ||
@@ -636,16 +645,18 @@ extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t 
         if (g != 1 && std::find(kids.begin(), kids.end(), g) == kids.end()) kids.push_back(g);
     }
     u64 *sp = scratch(c, (size_t)(L + 1) * lw);
-    CHECK(sp, FR_ENOMEM, "fr_keygen: scratch");
+    // a key in 64-bit limbs [dnum][2][nm][N], packed into its KeyLayout blocks
+    u64 *kt = scratch(c, (size_t)c->dnum * 2 * nm * lw);
+    CHECK(sp && kt, FR_ENOMEM, "fr_keygen: scratch");
     for (u64 kid : kids) {
         KeyEntry ke{kid, nullptr};
-        FR_HIP(hipMalloc(&ke.data, (size_t)c->dnum * 2 * nm * lw * 8));
+        FR_HIP(hipMalloc(&ke.data, (size_t)c->dnum * 2 * c->klay.block));
         K->ksk.push_back(ke);
         if (kid == 0) frk::mul_pt(c, sp, K->s_eval, K->s_eval, L + 1, 1, 0, 0);
         else frk::automorph(c, sp, K->s_eval, kid, L + 1, 1, 0, 0, false);
         for (int t = 0; t < c->dnum; ++t) {
-            u64 *b = ke.data + (size_t)(t * 2 + 0) * nm * lw;
-            u64 *a = ke.data + (size_t)(t * 2 + 1) * nm * lw;
+            u64 *b = kt + (size_t)(t * 2 + 0) * nm * lw;
+            u64 *a = kt + (size_t)(t * 2 + 1) * nm * lw;
             frk::sample_uniform(c, a, seed, poly_ksk(kid, t), all, nm);
             frk::ntt_fwd(c, a, nm, all, 1, 0);
             frk::sample_small(c, e, seed, poly_ksk(kid, t), KIND_GAUSS, all, nm);
@@ -653,7 +664,8 @@ extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t 
             const int dlo = t * c->alpha, dhi = std::min(dlo + c->alpha, L + 1);
             frk::key_combine(c, b, a, e, K->s_mont, sp, dlo, dhi, nm);
         }
-        frk::mont_scale(c, ke.data, nm, all, 2 * c->dnum, (size_t)nm * lw, true);
+        frk::mont_scale(c, kt, nm, all, 2 * c->dnum, (size_t)nm * lw, true);
+        frk::key_pack(c, ke.data, kt, 2 * c->dnum);
     }
     FR_HIP(hipGetLastError());
     FR_HIP(hipStreamSynchronize(c->stream));
@@ -692,7 +704,7 @@ extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_
         const size_t w = (size_t)c->dnum * 2 * nm * N;
         u64 *t = scratch(c, w);
         CHECK(t, FR_ENOMEM, "fr_keys_export: scratch");
-        FR_HIP(hipMemcpyAsync(t, ke->data, w * 8, hipMemcpyDeviceToDevice, c->stream));
+        frk::key_unpack(c, t, ke->data, 2 * c->dnum);
         frk::mont_scale(c, t, nm, allmap(c), 2 * c->dnum, (size_t)nm * N, false);
         frk::ntt_inv(c, t, nm, allmap(c), 2 * c->dnum, (size_t)nm * N);
         FR_HIP(hipMemcpyAsync(host, t, w * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1284,7 +1296,7 @@ static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2
         u64 *U = scratch(c, (size_t)qn * 2 * nE * N);
         CHECK(D && U, FR_ENOMEM, "giant steps: scratch");
         ks_modup(c, R + rw + lwl, l, D, qn * n2 - 1, rw);
-        std::vector<const u64 *> kp(n2 - 1);
+        std::vector<const unsigned char *> kp(n2 - 1);
         std::vector<u64> gp(n2 - 1);
         for (int j = 1; j < n2; ++j) {
             gp[j - 1] = galois_element(N, j * n1);

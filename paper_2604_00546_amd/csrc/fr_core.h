@@ -127,6 +127,15 @@ struct Arena {  // bump allocator over device chunks, reset per top-level call
 // kernel timing hook: events around every launch of one kernel class
 enum KernelClass { K_NONE = 0, K_NTT = 1, K_MODUP = 2, K_KS = 3, K_MODDOWN = 4, K_MAC = 5, K_RESCALE = 6,
                    K_TENSOR = 7, K_ELEM = 8 };
+// Key-switching key storage: per (digit, b or a) a block of nmod limbs; the
+// limb of a modulus below 2^40 holds 5 bytes per word (N low words, then N
+// high bytes), the others 8.  The layout depends only on the moduli.
+struct KeyLayout {
+    unsigned off[FR_MAXMOD];
+    unsigned char packed[FR_MAXMOD];
+    size_t block;  // bytes per (digit, b or a) block
+};
+
 struct Prof {
     int cls = K_NONE;
     std::vector<hipEvent_t> ev;  // pairs
@@ -171,6 +180,7 @@ struct fr_ctx {
     hipStream_t aux[kAux] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
     Arena arena;
+    KeyLayout klay{};
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;
 };
@@ -191,7 +201,7 @@ struct ProfScope {
 
 struct KeyEntry {
     u64 kid;
-    u64 *data;  // [dnum][2][nmod][N], eval domain, Montgomery-scaled
+    unsigned char *data;  // [dnum][2] blocks of KeyLayout, eval domain, Montgomery-scaled
 };
 
 struct fr_keys {
@@ -320,7 +330,7 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
 // (items c0_sd words apart, level+1 limbs) U0 also takes P c0[e][auto_src(p,
 // g)] on the limbs e <= level: the rotation of (c0, c1) held over Q_l U P,
 // before its ModDown
-void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level,
+void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *ksk, u64 g, int level,
               bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0, const u64 *fold_d = nullptr,
               size_t fold_sd = 0, const u64 *rot_c0 = nullptr, size_t c0_sd = 0);
 // out[b][p][e] = P in[b][p][e] on the limbs e <= level and 0 on the special
@@ -335,7 +345,7 @@ void tensor_sum(const fr_ctx *c, u64 *t01, u64 *t2, int nl, int n, const u64 *co
 int ks_inner_sum_chunk(const fr_ctx *c, int level);
 // U{0,1} (+)= sum over nj rotations (keys ksk[j], Galois elements g[j]; their
 // digits D + j sdj) of the key inner products, for `batch` items
-void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *const *ksk, const u64 *g, int nj,
+void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *const *ksk, const u64 *g, int nj,
                   size_t sdj, int level, bool accumulate, int batch, size_t sd, size_t su);
 // out[b] += sum_j sigma_{g_j}(in[b][j]) on nlimbs limbs of one polynomial
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
@@ -374,6 +384,10 @@ void bsgs_mac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby, int nq
 void db_pack(const fr_ctx *c, unsigned char *dst, size_t dstride, const DbLayout &lay, const u64 *src, int nl, int nd);
 void db_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, size_t sstride, const DbLayout &lay, int nl,
                int nd);
+// key-switching key blocks between 64-bit limbs ([nb][nmod][N]) and the
+// KeyLayout bytes (nb blocks, KeyLayout::block bytes apart)
+void key_pack(const fr_ctx *c, unsigned char *dst, const u64 *src, int nb);
+void key_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, int nb);
 // batched element-wise helpers (items addressed by pointer)
 // out[b] = sum_t k[b][t] * src[b][t] over the first nl limbs of both
 // polynomials of every source; out items contiguous [B][2][nl][N]

@@ -199,32 +199,32 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
 // Montgomery-scaled so one reduction yields the canonical sum.
 // fold (relinearisation): the top limb of U becomes d_l + P^-1 U_l (d an item
 // of fold_sd words, [2][level+1][N]); U_l is read by nothing else afterwards
+// one key word: a 64-bit limb, or a packed limb's low word and high byte
+template <bool PK>
+__device__ __forceinline__ u64 key_word(const unsigned char *limb, int p, int N) {
+    if (PK) return (u64)reinterpret_cast<const u32 *>(limb)[p] | ((u64)limb[4 * (size_t)N + p] << 32);
+    return reinterpret_cast<const u64 *>(limb)[p];
+}
+
 // ND > 0: compiled for exactly ND digits, every word of the thread in flight
-// before the sums (ND = 0: any count, one digit at a time)
-template <int ND>
-__global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int N,
-                                                 int logN, int nE, int level, int pbase, int ndig, int nmod,
-                                                 const ModConst *mods, int accumulate, size_t sd, size_t su,
-                                                 int batch, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
-                                                 u64 pinv_top_sh, const u64 *rot_c0, size_t c0_sd,
-                                                 const u64 *pmont) {
-    int item, tile;
-    item_tile(blockIdx.x, batch, N / kT, item, tile);
-    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
-    D += item * sd;
-    U0 += item * su;
-    U1 += item * su;
-    const int gm = e <= level ? e : pbase + (e - level - 1);
-    const ModConst m = mods[gm];
-    const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
+// before the sums (ND = 0: any count, one digit at a time).  PK: the key limb
+// is packed (5 bytes per word).
+template <int ND, bool PK>
+__device__ __forceinline__ void ks_inner_body(u64 *U0, u64 *U1, const u64 *D, const unsigned char *kl0,
+                                              size_t kblock, u32 src, int p, int e, int N, int nE, int level,
+                                              int ndig, const ModConst &m, int accumulate, int item,
+                                              const u64 *fold_d, size_t fold_sd, u64 pinv_top, u64 pinv_top_sh,
+                                              const u64 *rot_c0, size_t c0_sd, const u64 *pmont) {
+    // key limb of digit t, part ab (0: b, 1: a)
+    auto kw = [&](int t, int ab) { return key_word<PK>(kl0 + (size_t)(t * 2 + ab) * kblock, p, N); };
     Dot30 s0, s1;
     if constexpr (ND > 0) {
         u64 d[ND], kb[ND], ka[ND];
 #pragma unroll
         for (int t = 0; t < ND; ++t) {
             d[t] = D[((size_t)t * nE + e) * N + src];
-            kb[t] = ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
-            ka[t] = ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+            kb[t] = kw(t, 0);
+            ka[t] = kw(t, 1);
         }
         const u64 c0 = (rot_c0 && e <= level) ? rot_c0[item * c0_sd + (size_t)e * N + src] : 0;
 #pragma unroll
@@ -243,8 +243,8 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
         for (int t = 0; t < ndig; ++t) {
             u32 d0, d1;
             split30(D[((size_t)t * nE + e) * N + src], d0, d1);
-            s0.add(d0, d1, ksk[(((size_t)t * 2 + 0) * nmod + gm) * N + p]);
-            s1.add(d0, d1, ksk[(((size_t)t * 2 + 1) * nmod + gm) * N + p]);
+            s0.add(d0, d1, kw(t, 0));
+            s1.add(d0, d1, kw(t, 1));
         }
         if (rot_c0 && e <= level) {
             u32 c00, c01;
@@ -265,6 +265,31 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
     }
     U0[w] = u0;
     U1[w] = u1;
+}
+
+template <int ND>
+__global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const unsigned char *ksk,
+                                                 KeyLayout kl, u64 g, int N, int logN, int nE, int level, int pbase,
+                                                 int ndig, const ModConst *mods, int accumulate, size_t sd, size_t su,
+                                                 int batch, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
+                                                 u64 pinv_top_sh, const u64 *rot_c0, size_t c0_sd,
+                                                 const u64 *pmont) {
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
+    D += item * sd;
+    U0 += item * su;
+    U1 += item * su;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    const u32 src = g == 1 ? (u32)p : auto_src((u32)p, g, logN);
+    const unsigned char *kl0 = ksk + kl.off[gm];
+    if (kl.packed[gm])
+        ks_inner_body<ND, true>(U0, U1, D, kl0, kl.block, src, p, e, N, nE, level, ndig, m, accumulate, item, fold_d,
+                                fold_sd, pinv_top, pinv_top_sh, rot_c0, c0_sd, pmont);
+    else
+        ks_inner_body<ND, false>(U0, U1, D, kl0, kl.block, src, p, e, N, nE, level, ndig, m, accumulate, item, fold_d,
+                                 fold_sd, pinv_top, pinv_top_sh, rot_c0, c0_sd, pmont);
 }
 
 // Summed tensor products of ciphertext pairs (encrypted-database product):
@@ -306,36 +331,28 @@ __global__ __launch_bounds__(kT) void k_tensor_sum(u64 *t01, u64 *t2, PairPtrs p
 // The 128-bit lazy sum holds nj * ndig <= 64 products below 2^122.
 constexpr int kGiant = 16;
 struct GiantKeys {
-    const u64 *ksk[kGiant];
+    const unsigned char *ksk[kGiant];
     u64 g[kGiant];
 };
-template <int ND>
-__global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64 *D, GiantKeys gk, int nj, size_t sdj,
-                                                     int N, int logN, int nE, int level, int pbase, int ndig, int nmod,
-                                                     const ModConst *mods, int accumulate, size_t sd, size_t su,
-                                                     int batch) {
-    int item, tile;
-    item_tile(blockIdx.x, batch, N / kT, item, tile);
-    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
-    D += item * sd;
-    U0 += item * su;
-    U1 += item * su;
-    const int gm = e <= level ? e : pbase + (e - level - 1);
-    const ModConst m = mods[gm];
+template <int ND, bool PK>
+__device__ __forceinline__ void ks_inner_sum_body(u64 *U0, u64 *U1, const u64 *D, const GiantKeys &gk, int nj,
+                                                  size_t sdj, unsigned koff, size_t kblock, int p, int e, int N,
+                                                  int logN, int nE, int ndig, const ModConst &m, int accumulate) {
     // exact sums of each giant step's digits (Dot30), added up in 128 bits
     unsigned __int128 t0 = 0, t1 = 0;
     for (int jj = 0; jj < nj; ++jj) {
         const u32 src = auto_src((u32)p, gk.g[jj], logN);
         const u64 *Dj = D + jj * sdj;
-        const u64 *kj = gk.ksk[jj];
+        const unsigned char *kl0 = gk.ksk[jj] + koff;
+        auto kw = [&](int t, int ab) { return key_word<PK>(kl0 + (size_t)(t * 2 + ab) * kblock, p, N); };
         Dot30 s0, s1;
         if constexpr (ND > 0) {
             u64 d[ND], kb[ND], ka[ND];
 #pragma unroll
             for (int t = 0; t < ND; ++t) {
                 d[t] = Dj[((size_t)t * nE + e) * N + src];
-                kb[t] = kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p];
-                ka[t] = kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p];
+                kb[t] = kw(t, 0);
+                ka[t] = kw(t, 1);
             }
 #pragma unroll
             for (int t = 0; t < ND; ++t) {
@@ -348,8 +365,8 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64
             for (int t = 0; t < ndig; ++t) {
                 u32 d0, d1;
                 split30(Dj[((size_t)t * nE + e) * N + src], d0, d1);
-                s0.add(d0, d1, kj[(((size_t)t * 2 + 0) * nmod + gm) * N + p]);
-                s1.add(d0, d1, kj[(((size_t)t * 2 + 1) * nmod + gm) * N + p]);
+                s0.add(d0, d1, kw(t, 0));
+                s1.add(d0, d1, kw(t, 1));
             }
         }
         t0 += s0.total();
@@ -363,6 +380,27 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64
     }
     U0[w] = u0;
     U1[w] = u1;
+}
+
+template <int ND>
+__global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64 *D, GiantKeys gk, KeyLayout kl,
+                                                     int nj, size_t sdj, int N, int logN, int nE, int level,
+                                                     int pbase, int ndig, const ModConst *mods, int accumulate,
+                                                     size_t sd, size_t su, int batch) {
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const int p = tile * kT + threadIdx.x, e = blockIdx.y;
+    D += item * sd;
+    U0 += item * su;
+    U1 += item * su;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    if (kl.packed[gm])
+        ks_inner_sum_body<ND, true>(U0, U1, D, gk, nj, sdj, kl.off[gm], kl.block, p, e, N, logN, nE, ndig, m,
+                                    accumulate);
+    else
+        ks_inner_sum_body<ND, false>(U0, U1, D, gk, nj, sdj, kl.off[gm], kl.block, p, e, N, logN, nE, ndig, m,
+                                     accumulate);
 }
 
 // out[b][i][k] += sum_j in[b][j][i][auto_src(k, g_j)] (c0 parts of the giant
@@ -734,6 +772,25 @@ __global__ __launch_bounds__(kT) void k_db_unpack(u64 *dst, const unsigned char 
     dst[((size_t)d * nl + m) * N + k] = lay.packed[m] ? diag_word<true>(limb, 0, k, N) : diag_word<false>(limb, 0, k, N);
 }
 
+// key blocks between 64-bit limbs [nb][nm][N] and the KeyLayout bytes
+// (grid: N / kT, nm, nb)
+__global__ __launch_bounds__(kT) void k_key_pack(unsigned char *dst, KeyLayout kl, const u64 *src, int nm, int N) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y, b = blockIdx.z;
+    const u64 x = src[((size_t)b * nm + m) * N + k];
+    unsigned char *limb = dst + b * kl.block + kl.off[m];
+    if (kl.packed[m]) {
+        reinterpret_cast<u32 *>(limb)[k] = (u32)x;
+        limb[4 * (size_t)N + k] = (unsigned char)(x >> 32);
+    } else {
+        reinterpret_cast<u64 *>(limb)[k] = x;
+    }
+}
+__global__ __launch_bounds__(kT) void k_key_unpack(u64 *dst, KeyLayout kl, const unsigned char *src, int nm, int N) {
+    const int k = blockIdx.x * kT + threadIdx.x, m = blockIdx.y, b = blockIdx.z;
+    const unsigned char *limb = src + b * kl.block + kl.off[m];
+    dst[((size_t)b * nm + m) * N + k] = kl.packed[m] ? key_word<true>(limb, k, N) : key_word<false>(limb, k, N);
+}
+
 // out_b[i][p] = (U_b[i][p] - V_b[i][p]) P^-1 + in_b[i][auto_src(p, g)]: the
 // ModDown finish of one rotation of several ciphertexts fused with the
 // automorphism of c0 (c1 part: no add).  U_b, V_b are consecutive items.
@@ -1029,13 +1086,22 @@ void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size
     }
 }
 
-void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u64 g, int level, bool accumulate,
+// bytes of one key limb set (the nE limbs a key switch at `level` reads)
+static double key_limb_bytes(const fr_ctx *c, int level) {
+    double b = 0.0;
+    for (int e = 0; e < level + 1 + c->nP; ++e)
+        b += (c->klay.packed[e <= level ? e : c->L + 1 + (e - level - 1)] ? 5.0 : 8.0) * c->N;
+    return b;
+}
+
+void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *ksk, u64 g, int level, bool accumulate,
               int batch, size_t sd, size_t su, const u64 *fold_d, size_t fold_sd, const u64 *rot_c0, size_t c0_sd) {
     const int nE_ = level + 1 + c->nP, nd_ = (level + 1 + c->alpha - 1) / c->alpha;
     // digits and outputs per batch item (and c0 when folded in), the shared key once
     ProfScope ps(c, K_KS,
-                 (batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_ + (rot_c0 ? level + 1.0 : 0.0)) +
-                  2.0 * nd_ * nE_) * 8.0 * c->N);
+                 batch * (1.0 * nd_ * nE_ + (accumulate ? 4.0 : 2.0) * nE_ + (rot_c0 ? level + 1.0 : 0.0)) * 8.0 *
+                         c->N +
+                     2.0 * nd_ * key_limb_bytes(c, level));
     const int nE = level + 1 + c->nP;
     const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
     u64 pinv = 0, pinv_sh = 0;
@@ -1044,8 +1110,8 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *ksk, u
         pinv_sh = c->P_inv_q_sh[level];
     }
     auto kern = ndig == 1 ? k_ks_inner<1> : ndig == 2 ? k_ks_inner<2> : ndig == 3 ? k_ks_inner<3> : k_ks_inner<0>;
-    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, g, c->N, c->logN,
-                       nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
+    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, c->klay, g, c->N,
+                       c->logN, nE, level, c->L + 1, ndig, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
                        pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
 }
 
@@ -1075,7 +1141,7 @@ int ks_inner_sum_chunk(const fr_ctx *c, int level) {
     return std::max(1, std::min(kGiant, 64 / ndig));
 }
 
-void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *const *ksk, const u64 *g, int nj,
+void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *const *ksk, const u64 *g, int nj,
                   size_t sdj, int level, bool accumulate, int batch, size_t sd, size_t su) {
     const int nE = level + 1 + c->nP, ndig = (level + c->alpha) / c->alpha;
     GiantKeys gk{};
@@ -1083,14 +1149,15 @@ void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const u64 *co
         gk.ksk[j] = ksk[j];
         gk.g[j] = g[j];
     }
-    ProfScope ps(c, K_KS, (batch * ((double)nj * ndig * nE + (accumulate ? 4.0 : 2.0) * nE) + 2.0 * nj * ndig * nE) *
-                              8.0 * c->N);
+    ProfScope ps(c, K_KS,
+                 batch * ((double)nj * ndig * nE + (accumulate ? 4.0 : 2.0) * nE) * 8.0 * c->N +
+                     2.0 * nj * ndig * key_limb_bytes(c, level));
     auto kern = ndig == 1   ? k_ks_inner_sum<1>
                 : ndig == 2 ? k_ks_inner_sum<2>
                 : ndig == 3 ? k_ks_inner_sum<3>
                             : k_ks_inner_sum<0>;
-    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, nj, sdj, c->N,
-                       c->logN, nE, level, c->L + 1, ndig, c->nmod, c->d_mod, (int)accumulate, sd, su, batch);
+    hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, c->klay, nj, sdj,
+                       c->N, c->logN, nE, level, c->L + 1, ndig, c->d_mod, (int)accumulate, sd, su, batch);
 }
 
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
@@ -1207,6 +1274,14 @@ void db_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, size_t sstri
                int nd) {
     if (nd <= 0) return;
     hipLaunchKernelGGL(k_db_unpack, grid(c, nl, nd), dim3(kT), 0, c->stream, dst, src, sstride, lay, nl, c->N);
+}
+
+void key_pack(const fr_ctx *c, unsigned char *dst, const u64 *src, int nb) {
+    hipLaunchKernelGGL(k_key_pack, grid(c, c->nmod, nb), dim3(kT), 0, c->stream, dst, c->klay, src, c->nmod, c->N);
+}
+
+void key_unpack(const fr_ctx *c, u64 *dst, const unsigned char *src, int nb) {
+    hipLaunchKernelGGL(k_key_unpack, grid(c, c->nmod, nb), dim3(kT), 0, c->stream, dst, c->klay, src, c->nmod, c->N);
 }
 
 void moddown_rot(const fr_ctx *c, u64 *const *out, const u64 *U, const u64 *V, const u64 *const *in, u64 g,
