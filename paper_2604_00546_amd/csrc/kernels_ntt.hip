@@ -203,24 +203,32 @@ __global__ __launch_bounds__(kThreads) void k_inv_cols(NttLaunch a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - mulhi64(a, wp) * q; }
 
+// 2^64 - q, hidden from the compiler so that a w - h q is formed as
+// a w + h (2^64 - q): the second product then accumulates onto the first
+__device__ __forceinline__ u64 opaque_neg(u64 q) {
+    u64 nq = 0 - q;
+    asm("" : "+s"(nq));
+    return nq;
+}
+
 // a * w - h q with h the high word of a * wp built from the three partial
 // products that reach it (the low 32x32 product and the carries out of the
 // middle products' low halves are dropped): h is at most 2 below the exact
 // quotient estimate, so the result lies in [0, 4q) for any 64-bit a.
-__device__ __forceinline__ u64 shoup_lazy4(u64 a, u64 w, u64 wp, u64 q) {
+__device__ __forceinline__ u64 shoup_lazy4(u64 a, u64 w, u64 wp, u64 nq) {
     const u32 a0 = (u32)a, a1 = (u32)(a >> 32), p0 = (u32)wp, p1 = (u32)(wp >> 32);
     const u64 h = (u64)a1 * p1 + __umulhi(a0, p1) + __umulhi(a1, p0);
-    return a * w - h * q;
+    return a * w + h * nq;
 }
 
 // Forward butterfly.  Large primes: inputs and outputs in [0, 8q), x
 // reduced below 4q first.  Small primes (q < 2^46, SMALL): no reduction at
 // all, the bound grows by 4q per stage (at most 65q after 16 stages).
 template <bool SMALL>
-__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4) {
+__device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4, u64 nq) {
     u64 x = X;
     if (!SMALL) x = X >= q4 ? X - q4 : X;
-    const u64 t = shoup_lazy4(Y, w, wp, q);
+    const u64 t = shoup_lazy4(Y, w, wp, nq);
     X = x + t;
     Y = x - t + q4;
 }
@@ -229,12 +237,12 @@ __device__ __forceinline__ void ct_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u6
 // bound) keeps the difference positive; the bound doubles per stage (below
 // q 2^17 after 16 stages).
 template <bool SMALL>
-__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4, u64 M) {
+__device__ __forceinline__ void gs_bfly(u64 &X, u64 &Y, u64 w, u64 wp, u64 q, u64 q4, u64 nq, u64 M) {
     u64 s = X + Y;
     if (!SMALL) s = s >= q4 ? s - q4 : s;
     const u64 d = X - Y + (SMALL ? M : q4);
     X = s;
-    Y = shoup_lazy4(d, w, wp, q);
+    Y = shoup_lazy4(d, w, wp, nq);
 }
 // primes below this take the reduction-free butterflies
 constexpr u64 kSmallQ = 1ull << 46;
@@ -287,6 +295,7 @@ __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int c = threadIdx.x % COLS, g = threadIdx.x / COLS;
@@ -316,7 +325,7 @@ __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, LE - st);
-                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq);
             }
     }
 #pragma unroll
@@ -332,7 +341,7 @@ __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, LR - st);
-                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq);
             }
     }
 #pragma unroll
@@ -356,6 +365,7 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const ModConst mcq = a.mods[mi];
     u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
@@ -388,7 +398,7 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(!EPI, k, LE - sl);
-                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq);
             }
     }
 #pragma unroll
@@ -404,7 +414,7 @@ __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(!EPI, k, LR - sl);
-                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4);
+                ct_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq);
             }
     }
 #pragma unroll
@@ -464,6 +474,7 @@ __device__ __forceinline__ void k_fwd_rows4_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const ModConst mcq = a.mods[mi];
     u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
@@ -495,10 +506,10 @@ __device__ __forceinline__ void k_fwd_rows4_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = tb[row4_idx(t, k, lo)];
         }
-        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4);
-        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4);
-        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4);
-        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4);
+        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4, nq);
+        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4, nq);
+        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4, nq);
+        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4, nq);
         if (r < 3) {  // a thread writes back the words it read this round
 #pragma unroll
             for (int k = 0; k < 4; ++k) tb[row4_idx(t, k, lo)] = v[k];
@@ -550,6 +561,7 @@ __device__ __forceinline__ void k_inv_rows4_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const int N = a.N;
     u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -584,10 +596,10 @@ __device__ __forceinline__ void k_inv_rows4_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = tb[row4_idx(t, k, lo)];
         }
-        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, q << (lt + 1));
-        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, q << (lt + 1));
-        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
-        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, nq, q << (lt + 1));
+        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, nq, q << (lt + 1));
+        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, nq, q << (lt + 2));
+        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, nq, q << (lt + 2));
         if (r < 3) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) tb[row4_idx(t, k, lo)] = v[k];
@@ -619,6 +631,7 @@ __device__ __forceinline__ void k_fwd_cols4_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.y);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * a.N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * a.N;
     const int c = threadIdx.x % kColsPerBlk, g = threadIdx.x / kColsPerBlk;
@@ -658,10 +671,10 @@ __device__ __forceinline__ void k_fwd_cols4_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = tc[row4_idx(g, k, lo) * kColsPerBlk];
         }
-        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4);
-        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4);
-        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4);
-        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4);
+        ct_bfly<SMALL>(v[0], v[2], tws[r][0].x, tws[r][0].y, q, q4, nq);
+        ct_bfly<SMALL>(v[1], v[3], tws[r][0].x, tws[r][0].y, q, q4, nq);
+        ct_bfly<SMALL>(v[0], v[1], tws[r][1].x, tws[r][1].y, q, q4, nq);
+        ct_bfly<SMALL>(v[2], v[3], tws[r][2].x, tws[r][2].y, q, q4, nq);
         if (r < 3) {  // a thread writes back the words it read this round
 #pragma unroll
             for (int k = 0; k < 4; ++k) tc[row4_idx(g, k, lo) * kColsPerBlk] = v[k];
@@ -688,6 +701,7 @@ __device__ __forceinline__ void k_inv_cols4_body(const NttLaunch &a, u64 *tile) 
     const int mi = a.map.modidx(s);
     const ModConst mc = a.mods[mi];
     const u64 q = mc.q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -714,10 +728,10 @@ __device__ __forceinline__ void k_inv_cols4_body(const NttLaunch &a, u64 *tile) 
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = tc[row4_idx(g, k, lo) * kColsPerBlk];
         }
-        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, q << (lt + 1));
-        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, q << (lt + 1));
-        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
-        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, q << (lt + 2));
+        gs_bfly<SMALL>(v[0], v[1], tws[r][0].x, tws[r][0].y, q, q4, nq, q << (lt + 1));
+        gs_bfly<SMALL>(v[2], v[3], tws[r][1].x, tws[r][1].y, q, q4, nq, q << (lt + 1));
+        gs_bfly<SMALL>(v[0], v[2], tws[r][2].x, tws[r][2].y, q, q4, nq, q << (lt + 2));
+        gs_bfly<SMALL>(v[1], v[3], tws[r][2].x, tws[r][2].y, q, q4, nq, q << (lt + 2));
         if (r < 3) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) tc[row4_idx(g, k, lo) * kColsPerBlk] = v[k];
@@ -759,6 +773,7 @@ __device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) 
     const int s = a.map.storage(blockIdx.z);
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const int N = a.N;
     u64 *x = a.data + blockIdx.y * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -781,7 +796,7 @@ __device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, lt + 1);
-                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1));
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq, q << (lt + 1));
             }
     }
 #pragma unroll
@@ -797,7 +812,7 @@ __device__ __forceinline__ void k_inv_rows2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, lt + 1 - LE);
-                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (lt + 1));
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq, q << (lt + 1));
             }
     }
 #pragma unroll
@@ -822,6 +837,7 @@ __device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) 
     const int mi = a.map.modidx(s);
     const ModConst mc = a.mods[mi];
     const u64 q = mc.q, q4 = 4 * q;
+    const u64 nq = opaque_neg(q);
     const int N = a.N;
     u64 *x = a.data + blockIdx.z * a.poly_stride + (size_t)s * N;
     const ulonglong2 *tw = a.tw2 + (size_t)mi * N;
@@ -838,7 +854,7 @@ __device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, ltp + 1);
-                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1));
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq, q << (LR + ltp + 1));
             }
     }
 #pragma unroll
@@ -854,7 +870,7 @@ __device__ __forceinline__ void k_inv_cols2_body(const NttLaunch &a, u64 *tile) 
         for (int k = 0; k < E; ++k)
             if ((k & half) == 0) {
                 const ulonglong2 t2 = NTT_TW(false, k, ltp + 1 - LE);
-                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, q << (LR + ltp + 1));
+                gs_bfly<SMALL>(v[k], v[k + half], t2.x, t2.y, q, q4, nq, q << (LR + ltp + 1));
             }
     }
 #pragma unroll
