@@ -546,6 +546,9 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
             e = fr_fail(FR_EHIP, "fr_ctx_create: auxiliary stream");
     if (!e && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
         e = fr_fail(FR_EHIP, "fr_ctx_create: event");
+    for (int i = 0; !e && i < fr_ctx::kDagEv; ++i)
+        if (hipEventCreateWithFlags(&c->ev_dag[i], hipEventDisableTiming) != hipSuccess)
+            e = fr_fail(FR_EHIP, "fr_ctx_create: event");
     if (e) {
         fr_ctx_destroy(c);
         return e;
@@ -568,6 +571,8 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
     for (int a = 0; a < fr_ctx::kAux; ++a)
         if (c->ev_join[a]) (void)hipEventDestroy(c->ev_join[a]);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (int i = 0; i < fr_ctx::kDagEv; ++i)
+        if (c->ev_dag[i]) (void)hipEventDestroy(c->ev_dag[i]);
     if (c->prof) {
         for (auto &e : c->prof->ev) (void)hipEventDestroy(e);
         delete c->prof;
@@ -1781,17 +1786,27 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
     CHECK(rk, FR_ENOKEY, "fr_chebyshev_eval: relinearisation key missing");
     auto lw = [&](int level) { return (size_t)(level + 1) * N; };
     // The groups of one depth (scalar family, products and additions, each
-    // per level) depend only on earlier depths: they run concurrently, one
-    // stream each, joined before the next depth.  Arena space is not reused
-    // inside the loop, so no group's scratch is handed to another stream.
+    // per level) depend only on earlier depths.  They are spread over the
+    // caller's stream and the auxiliary streams; a group waits only for the
+    // groups that produced its inputs (an event recorded after each group),
+    // and every stream is joined into the caller's at the end.  Arena space
+    // is not reused inside the call, so no group's scratch is handed to
+    // another stream.
     c->arena.hold++;
     struct HoldGuard {
         Arena &a;
         ~HoldGuard() { a.hold--; }
     } hold_guard{c->arena};
     const hipStream_t main_stream = c->stream;
+    const int nstream = 1 + fr_ctx::kAux;
+    auto stream_of = [&](int s) { return s == 0 ? main_stream : c->aux[s - 1]; };
+    std::vector<int> prod_ev(n, -1), prod_st(n, 0);  // event slot / stream of each node's group
+    int ev_next = 0, rr = 0;
+    bool aux_used = false;
+    FR_HIP(hipEventRecord(c->ev_fork, main_stream));  // the inputs, for the auxiliary streams
     for (int d = 1; d <= maxd; ++d) {
         std::vector<std::function<int()>> groups;
+        std::vector<std::vector<int>> gin, gout;  // input and output nodes of each group
         // --- scalar family (adjust, scalar, leaf), grouped by output level
         std::vector<std::vector<int>> by_level(FR_MAXLEVEL), mul_by_level(FR_MAXLEVEL);
         for (int i = 0; i < n; ++i) {
@@ -1802,6 +1817,13 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         }
         for (int lam = 0; lam < FR_MAXLEVEL; ++lam) {
             if (by_level[lam].empty()) continue;
+            gout.push_back(by_level[lam]);
+            gin.emplace_back();
+            for (int i : by_level[lam]) {
+                const CNode &nd = nodes[i];
+                if (nd.op == C_ADJUST || nd.op == C_SCALAR) gin.back().push_back(nd.a);
+                else gin.back().insert(gin.back().end(), nd.ins.begin(), nd.ins.end());
+            }
             groups.push_back([&, lam]() -> int {
                 const auto &L = by_level[lam];
                 const int B = (int)L.size() * nq;  // item b = node L[b / nq], query b % nq
@@ -1869,6 +1891,12 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         // --- relinearised products, grouped by input level
         for (int lv = 1; lv < FR_MAXLEVEL; ++lv) {
             if (mul_by_level[lv].empty()) continue;
+            gout.push_back(mul_by_level[lv]);
+            gin.emplace_back();
+            for (int i : mul_by_level[lv]) {
+                gin.back().push_back(nodes[i].a);
+                gin.back().push_back(nodes[i].b);
+            }
             groups.push_back([&, lv]() -> int {
                 const auto &L = mul_by_level[lv];
                 const int B = (int)L.size() * nq, nE = lv + 1 + c->nP, ndig = num_digits(c, lv);
@@ -1901,6 +1929,12 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                     L.push_back(i);
             }
             if (L.empty()) continue;
+            gout.push_back(L);
+            gin.emplace_back();
+            for (int i : L) {
+                gin.back().push_back(nodes[i].a);
+                if (nodes[i].op != C_TWICE_M1) gin.back().push_back(nodes[i].b);
+            }
             groups.push_back([&, lv, L]() -> int {
                 const int B = (int)L.size() * nq;
                 const size_t w = lw(lv);
@@ -1923,24 +1957,40 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                 return FR_OK;
             });
         }
-        // fork: group 0 on the caller's stream, the others on the auxiliary
-        // streams after everything enqueued so far; join before the next depth
-        const int ng = (int)groups.size(), naux = std::min(ng - 1, fr_ctx::kAux);
-        if (naux > 0) {
-            FR_HIP(hipEventRecord(c->ev_fork, main_stream));
-            for (int a = 0; a < naux; ++a) FR_HIP(hipStreamWaitEvent(c->aux[a], c->ev_fork, 0));
-        }
-        for (int g = 0; g < ng; ++g) {
-            c->stream = g == 0 ? main_stream : c->aux[(g - 1) % fr_ctx::kAux];
+        // each group on the next stream in turn, after the events of the
+        // groups (on other streams) that produced its inputs
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const int st = rr++ % nstream;
+            const hipStream_t s = stream_of(st);
+            if (st > 0 && !aux_used) {
+                for (int a = 0; a < fr_ctx::kAux; ++a) FR_HIP(hipStreamWaitEvent(c->aux[a], c->ev_fork, 0));
+                aux_used = true;
+            }
+            std::vector<int> waited;
+            for (int x : gin[g]) {
+                const int ev = prod_ev[x];
+                if (ev < 0 || prod_st[x] == st || std::find(waited.begin(), waited.end(), ev) != waited.end())
+                    continue;
+                FR_HIP(hipStreamWaitEvent(s, c->ev_dag[ev], 0));
+                waited.push_back(ev);
+            }
+            c->stream = s;
             const int e = groups[g]();
             c->stream = main_stream;
             if (e) return e;
+            const int ev = ev_next++ % fr_ctx::kDagEv;
+            FR_HIP(hipEventRecord(c->ev_dag[ev], s));
+            for (int x : gout[g]) {
+                prod_ev[x] = ev;
+                prod_st[x] = st;
+            }
         }
-        for (int a = 0; a < naux; ++a) {
+    }
+    if (aux_used)
+        for (int a = 0; a < fr_ctx::kAux; ++a) {
             FR_HIP(hipEventRecord(c->ev_join[a], c->aux[a]));
             FR_HIP(hipStreamWaitEvent(main_stream, c->ev_join[a], 0));
         }
-    }
     return FR_OK;
 }
 

@@ -179,6 +179,10 @@ struct fr_ctx {
     static const int kAux = 3;
     hipStream_t aux[kAux] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
+    // ring of events marking finished groups of a recorded DAG (a later
+    // record of a slot only makes a waiter wait longer)
+    static const int kDagEv = 64;
+    hipEvent_t ev_dag[kDagEv] = {};
     Arena arena;
     KeyLayout klay{};
     int *d_flag = nullptr;  // device error flag
