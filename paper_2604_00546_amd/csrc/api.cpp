@@ -1509,11 +1509,13 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
     for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
         Scope sc(c->arena);
         const int qn = std::min(kMatvecChunk, nq - q0);
-        // the chunk's queries staged contiguously: [qn][2][l+1][N]
-        u64 *C = scratch(c, (size_t)qn * 2 * lw);
-        for (int qq = 0; qq < qn; ++qq)
-            FR_HIP(hipMemcpyAsync(C + qq * 2 * lw, qs[order[q0 + qq]].data, 2 * lw * 8, hipMemcpyDeviceToDevice,
-                                  c->stream));
+        // the chunk's queries staged contiguously: [qn][2][l+1][N] (read
+        // only; a single query is read in place)
+        u64 *C = qn == 1 ? qs[order[q0]].data : scratch(c, (size_t)qn * 2 * lw);
+        if (qn > 1)
+            for (int qq = 0; qq < qn; ++qq)
+                FR_HIP(hipMemcpyAsync(C + qq * 2 * lw, qs[order[q0 + qq]].data, 2 * lw * 8, hipMemcpyDeviceToDevice,
+                                      c->stream));
         u64 *D = scratch(c, (size_t)qn * dstride);
         ks_modup(c, C + lw, l, D, qn, 2 * lw);
         // baby steps over Q_l U P: [qn][n1][2][nE][N]
