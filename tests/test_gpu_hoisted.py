@@ -170,3 +170,27 @@ def test_many_digits_bitexact(oracle_mod):
     dec = g.decrypt_decode(kg, gs)
     exact = wl.exact_scores()
     assert np.max(np.abs(dec[: min(wl.K, 8 * ell)] - exact[: 8 * ell])) <= 2 ** -20
+
+
+def test_packed_special_primes_bitexact(oracle_mod):
+    """Two 40-bit special primes: the special limbs of the keys and of the
+    extended diagonals are stored packed (5 bytes per residue) as well.
+    Rotations, the relinearised product and the hoisted product are compared
+    bit-exactly."""
+    from paper_2604_00546_amd import fr
+    p = dict(fr.small_params(), n_special=2, special_bits=40)
+    g, o = fr.Context(**p), oracle_mod.Context(**_oparams(p))
+    ell, n1 = 64, 8
+    rots = fr.bsgs_rotation_set(ell, n1)
+    seed = synth.int_seed(8, synth.SUB_KEYS)
+    kg, ko = g.keygen(seed, rots), o.keygen(seed, rots)
+    wl = synth.make_workload(8, 400, ell, extra=ell + n1)
+    odb = o.db_build(wl.templates, wl.K, ell, 8, n1, o.L, 2.0 ** 40)
+    gdb = g.db_import(odb.export_all(), odb.G, ell, 8, n1, g.L, 2.0 ** 40).extend()
+    opt = o.encode(synth.replicate_query(wl.query, g.N // 2), o.L, 2.0 ** 40)
+    es = synth.int_seed(8, synth.SUB_ENC)
+    gq, oq = g.encrypt(kg, g.pt_import(opt.coeffs(), g.L, 2.0 ** 40), es), o.encrypt(ko, opt, es)
+    for a, b in zip(g.rotate_hoisted(kg, gq, [1, 5, 16]), o.rotate_hoisted(ko, oq, [1, 5, 16])):
+        _same_oracle(g, a, b)
+    _same_oracle(g, g.mul_relin_rescale(kg, gq, gq), o.mul_relin_rescale(ko, oq, oq))
+    _same_oracle(g, g.bsgs_matvec_hoisted(kg, gq, gdb, 0), o.bsgs_matvec_hoisted(ko, oq, odb, 0))
