@@ -157,10 +157,13 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
     frk::ntt_inv(c, X, level + 1, qmap(), batch, lw, c1, c1_stride);
     if (batch * ndig <= kModupMerge) {
         // small batches: every digit in one conversion launch and one
-        // transform (which also re-derives the digit's own limbs)
-        frk::modup_all(c, D, X, level, batch, dstride, lw);
+        // transform; the conversion copies each digit's own limbs in
+        // evaluation form and the transform leaves them alone (where the
+        // transform cannot, it re-derives them from coefficient form)
+        const bool own = frk::ntt_own_skip_ok(c);
+        frk::modup_all(c, D, X, level, batch, dstride, lw, own ? c1 : nullptr, c1_stride);
         LimbMap ext{0, INT_MAX, 0, level + 1, c->L + 1};
-        frk::ntt_fwd(c, D, nE, ext, ndig * batch, (size_t)nE * N);
+        frk::ntt_fwd(c, D, nE, ext, ndig * batch, (size_t)nE * N, nullptr, 0, own ? c->alpha : 0, ndig, level + 1);
         return;
     }
     // large batches: per digit, transforming only the converted limbs and

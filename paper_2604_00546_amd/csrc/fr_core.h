@@ -278,7 +278,12 @@ namespace frk {
 // src set the transform is out of place: it reads src (same limb map,
 // src_poly_stride between polynomials) and writes data.
 void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
-             const u64 *src = nullptr, size_t src_poly_stride = 0);
+             const u64 *src = nullptr, size_t src_poly_stride = 0, int own_alpha = 0, int own_ndig = 1,
+             int own_nlq = 0);
+// whether ntt_fwd honours own_alpha (ModUp digit sets: polynomial z is digit
+// z % own_ndig, whose own limbs are already in evaluation form and are left
+// untouched); on other rings it transforms every limb
+bool ntt_own_skip_ok(const fr_ctx *c);
 // rescale fused into one forward transform (radix-16 kernels; returns false
 // when the ring has no such kernels): out[p] = (in[p] - NTT(centered(xtop[p])
 // mod q_i)) q_l^-1 for limbs i < l; xtop[p] is the coefficient form of limb l
@@ -321,9 +326,12 @@ void automorph(const fr_ctx *c, u64 *out, const u64 *in, u64 g, int nlimbs, int 
 void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly,
                 size_t poly_stride, bool to_mont);
 // fast base conversion of every digit of `batch` items at once: D[b][t] =
-// [ndig][nE][N] per item (item stride sd), own limbs copied in coefficient
-// form (one forward transform over all nE limbs then completes every digit)
-void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx);
+// [ndig][nE][N] per item (item stride sd).  The digit's own limbs are
+// copied from own (the evaluation-form input, items so words apart) when
+// given, else in coefficient form (a forward transform over all nE limbs
+// then completes every digit)
+void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx,
+               const u64 *own = nullptr, size_t so = 0);
 // fast base conversion of one digit: coefficient-form x[level+1][N] ->
 // D[nE][N] coefficient form on every extended limb outside the digit
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,

@@ -43,7 +43,17 @@ struct NttLaunch {
     const u64 *epi_in;
     size_t epi_out_stride, epi_in_stride;
     const u64 *qinv, *qinv_sh;
+    // ModUp digit sets (own_alpha > 0): polynomial z is digit z % own_ndig,
+    // whose own limbs [t alpha, min(t alpha + alpha, own_nlq)) are already in
+    // evaluation form; the forward passes leave them untouched
+    int own_alpha, own_ndig, own_nlq;
 };
+
+__device__ __forceinline__ bool own_skip(const NttLaunch &a, int s, int poly) {
+    if (!a.own_alpha) return false;
+    const int lo = (poly % a.own_ndig) * a.own_alpha;
+    return s >= lo && s < lo + a.own_alpha && s < a.own_nlq;
+}
 
 __global__ __launch_bounds__(kThreads) void k_fwd_cols(NttLaunch a) {
     __shared__ u64 tile[kTile];
@@ -293,6 +303,7 @@ template <int LE, bool SMALL>
 __device__ __forceinline__ void k_fwd_cols2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, COLS = kThreads / E;
     const int s = a.map.storage(blockIdx.y);
+    if (own_skip(a, s, blockIdx.z)) return;
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
     const u64 nq = opaque_neg(q);
@@ -363,6 +374,7 @@ template <int LE, bool SMALL, bool EPI>
 __device__ __forceinline__ void k_fwd_rows2_body(const NttLaunch &a, u64 *tile) {
     constexpr int E = 1 << LE, LR = 2 * LE, R = 1 << LR, BLKS = kThreads / E;
     const int s = a.map.storage(blockIdx.z);
+    if (own_skip(a, s, blockIdx.y)) return;
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
     const u64 nq = opaque_neg(q);
@@ -472,6 +484,7 @@ template <bool SMALL, bool EPI>
 __device__ __forceinline__ void k_fwd_rows4_body(const NttLaunch &a, u64 *tile) {
     constexpr int LR = 8, R = 256;
     const int s = a.map.storage(blockIdx.z);
+    if (own_skip(a, s, blockIdx.y)) return;
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
     const u64 nq = opaque_neg(q);
@@ -629,6 +642,7 @@ template <bool SMALL>
 __device__ __forceinline__ void k_fwd_cols4_body(const NttLaunch &a, u64 *tile) {
     constexpr int LR = 8, R = 256;
     const int s = a.map.storage(blockIdx.y);
+    if (own_skip(a, s, blockIdx.z)) return;
     const int mi = a.map.modidx(s);
     const u64 q = a.mods[mi].q, q4 = 4 * q;
     const u64 nq = opaque_neg(q);
@@ -917,6 +931,9 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     a.epi_in = nullptr;
     a.epi_out_stride = a.epi_in_stride = 0;
     a.qinv = a.qinv_sh = nullptr;
+    a.own_alpha = 0;
+    a.own_ndig = 1;
+    a.own_nlq = 0;
     return a;
 }
 
@@ -959,11 +976,18 @@ void inv_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3
 
 namespace frk {
 
+bool ntt_own_skip_ok(const fr_ctx *c) { return c->logN == 16 || c->logN == 12; }
+
 void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
-             const u64 *src, size_t src_poly_stride) {
+             const u64 *src, size_t src_poly_stride, int own_alpha, int own_ndig, int own_nlq) {
     if (nlimbs <= 0 || npoly <= 0) return;
     ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, false, src, src_poly_stride);
+    if (own_alpha > 0 && ntt_own_skip_ok(c)) {
+        a.own_alpha = own_alpha;
+        a.own_ndig = own_ndig;
+        a.own_nlq = own_nlq;
+    }
     if (c->logN == 16 || c->logN == 12) {
         const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
         // the row passes walk every polynomial of one limb before the next

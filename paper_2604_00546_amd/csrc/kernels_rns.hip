@@ -166,12 +166,13 @@ struct ModupTabs {
 };
 __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
                                                   int level, int pbase, ModupTabs mt, const ModConst *mods, size_t sd,
-                                                  size_t sx) {
+                                                  size_t sx, const u64 *own, size_t so) {
     const int k = blockIdx.x * kT + threadIdx.x;
     const int t = tfirst + blockIdx.z % nt, b = blockIdx.z / nt;
     const int lo = t * alpha, nd = min(alpha, level + 1 - lo);
     D += b * sd + (size_t)t * nE * N;
     x += b * sx;
+    if (own) own += b * so;
     const u64 *tab = mt.tab[t - tfirst];
     const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
     u32 y0[kMaxDigit], y1[kMaxDigit];
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
     for (int d = 0; d < kMaxDigit; ++d)
         if (d < nd) {
             const u64 xv = x[(size_t)(lo + d) * N + k];
-            if (blockIdx.y == 0) D[(size_t)(lo + d) * N + k] = xv;
+            if (blockIdx.y == 0) D[(size_t)(lo + d) * N + k] = own ? own[(size_t)(lo + d) * N + k] : xv;
             split30(shoup(xv, dinv[d], dinv_sh[d], mods[lo + d].q), y0[d], y1[d]);
         }
     const int ntarget = nE - nd;
@@ -1069,7 +1070,8 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
                        c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx);
 }
 
-void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx) {
+void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx, const u64 *own,
+               size_t so) {
     const int nE = level + 1 + c->nP, ndig = (level + c->alpha) / c->alpha;
     for (int t0 = 0; t0 < ndig; t0 += kMaxDigit) {
         const int nt = std::min(kMaxDigit, ndig - t0);
@@ -1082,7 +1084,7 @@ void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size
         }
         dim3 g(c->N / kT, (maxt + kTargetsPerThread - 1) / kTargetsPerThread, nt * batch);
         hipLaunchKernelGGL(k_modup_all, g, dim3(kT), 0, c->stream, D, x, c->N, t0, nt, c->alpha, nE, level, c->L + 1,
-                           mt, c->d_mod, sd, sx);
+                           mt, c->d_mod, sd, sx, own, so);
     }
 }
 
