@@ -981,9 +981,12 @@ bool ntt_own_skip_ok(const fr_ctx *c) { return c->logN == 16 || c->logN == 12; }
 void ntt_fwd(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int npoly, size_t poly_stride,
              const u64 *src, size_t src_poly_stride, int own_alpha, int own_ndig, int own_nlq) {
     if (nlimbs <= 0 || npoly <= 0) return;
-    ProfScope ps(c, K_NTT, 16.0 * nlimbs * npoly * c->N);
+    const bool own = own_alpha > 0 && ntt_own_skip_ok(c);
+    // limb polynomials transformed (a digit's own limbs are not)
+    const double lp = (double)nlimbs * npoly - (own ? (double)(npoly / own_ndig) * own_nlq : 0.0);
+    ProfScope ps(c, K_NTT, 16.0 * lp * c->N);
     NttLaunch a = make_launch(c, data, map, poly_stride, false, src, src_poly_stride);
-    if (own_alpha > 0 && ntt_own_skip_ok(c)) {
+    if (own) {
         a.own_alpha = own_alpha;
         a.own_ndig = own_ndig;
         a.own_nlq = own_nlq;
