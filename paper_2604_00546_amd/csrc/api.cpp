@@ -447,14 +447,19 @@ static int ctx_build(fr_ctx *c) {
     for (int i = 0; i <= L; ++i) md.push_back(to_mont(c->P_mod_q[i], c->mod[i]));
     if (int e = upload(&c->d_moddown, md)) return e;
 
-    // rescale tables
-    std::vector<u64> rs((size_t)(L + 1) * (L + 1) * 2, 0);
+    // rescale tables: q_l^-1 mod q_i, then (P q_l)^-1 mod q_i (ModDown and
+    // rescale in one product), each [L+1][value, companion][L+1]
+    const size_t rtab = (size_t)(L + 1) * (L + 1) * 2;
+    std::vector<u64> rs(2 * rtab, 0);
     for (int l = 1; l <= L; ++l)
         for (int i = 0; i < l; ++i) {
             const u64 qi = c->mod[i];
             const u64 v = invmod_h(c->mod[l] % qi, qi);
             rs[(size_t)l * (L + 1) * 2 + i] = v;
             rs[(size_t)l * (L + 1) * 2 + (L + 1) + i] = shoup_companion(v, qi);
+            const u64 w = mulmod_h(v, c->P_inv_q[i], qi);
+            rs[rtab + (size_t)l * (L + 1) * 2 + i] = w;
+            rs[rtab + (size_t)l * (L + 1) * 2 + (L + 1) + i] = shoup_companion(w, qi);
         }
     if (int e = upload(&c->d_rescale, rs)) return e;
 

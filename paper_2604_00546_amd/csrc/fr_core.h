@@ -164,7 +164,8 @@ struct fr_ctx {
     u64 *d_moddown = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
     u64 P_inv_q[FR_MAXMOD], P_inv_q_sh[FR_MAXMOD];  // P^-1 mod q_i and Shoup companions
-    // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each
+    // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each; then
+    // (P q_l)^-1 mod q_i in the same layout (ModDown and rescale in one product)
     u64 *d_rescale = nullptr;
     // CRT lift per level: qhat_inv[i], qhat_inv_sh[i], qhat_mod64[i], Q_mod64,
     // inv_q (double) -- laid out as [L+1][4 * (L+1) + 1] words

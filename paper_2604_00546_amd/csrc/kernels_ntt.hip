@@ -1073,10 +1073,17 @@ bool ntt_fwd_relin_rescale(const fr_ctx *c, u64 *Z, int l, int npoly, const u64 
     a.epi_in_stride = su;
     a.epi_in2 = d;
     a.epi_in2_stride = sd;
-    a.qinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;  // P^-1 mod q_i and companions
-    a.qinv_sh = a.qinv + (c->L + 1);
-    a.qinv2 = c->d_rescale + (size_t)l * (c->L + 1) * 2;  // q_l^-1 mod q_i and companions
-    a.qinv2_sh = a.qinv2 + (c->L + 1);
+    const size_t rtab = (size_t)(c->L + 1) * (c->L + 1) * 2;
+    if (d) {
+        a.qinv = c->d_moddown + 2 * c->nP + (size_t)(c->L + 1) * c->nP;  // P^-1 mod q_i and companions
+        a.qinv_sh = a.qinv + (c->L + 1);
+        a.qinv2 = c->d_rescale + (size_t)l * (c->L + 1) * 2;  // q_l^-1 mod q_i and companions
+        a.qinv2_sh = a.qinv2 + (c->L + 1);
+    } else {
+        // no d term: one product by (P q_l)^-1 mod q_i (the same canonical words)
+        a.qinv = c->d_rescale + rtab + (size_t)l * (c->L + 1) * 2;
+        a.qinv_sh = a.qinv + (c->L + 1);
+    }
     const int LE = c->logN / 4, E = 1 << LE, R = 1 << (2 * LE);
     dim3 g(R / (kThreads / E), l, npoly), gr(R / (kThreads / E), npoly, l);
     if (LE == 4) {
