@@ -194,3 +194,36 @@ def test_packed_special_primes_bitexact(oracle_mod):
         _same_oracle(g, a, b)
     _same_oracle(g, g.mul_relin_rescale(kg, gq, gq), o.mul_relin_rescale(ko, oq, oq))
     _same_oracle(g, g.bsgs_matvec_hoisted(kg, gq, gdb, 0), o.bsgs_matvec_hoisted(ko, oq, odb, 0))
+
+
+@pytest.mark.parametrize("log_n", [11, 13])
+def test_other_ring_sizes_bitexact(oracle_mod, log_n):
+    """Rings other than 2^12 and 2^16 take the generic transform passes and
+    the unfused relinearisation and ModUp paths: rotations, the relinearised
+    product, the single-hoisted and the hoisted products are compared
+    bit-exactly, and the decrypted scores held to 2^-20."""
+    from paper_2604_00546_amd import fr
+    p = dict(fr.small_params(), log_n=log_n)
+    g, o = fr.Context(**p), oracle_mod.Context(**_oparams(p))
+    ell, n1 = 64, 8
+    B = (g.N // 2) // ell
+    rots = fr.bsgs_rotation_set(ell, n1)
+    seed = synth.int_seed(9, synth.SUB_KEYS)
+    kg, ko = g.keygen(seed, rots), o.keygen(seed, rots)
+    wl = synth.make_workload(9, 300, ell, extra=ell + n1)
+    odb = o.db_build(wl.templates, wl.K, ell, B, n1, o.L, 2.0 ** 40)
+    gdb = g.db_import(odb.export_all(), odb.G, ell, B, n1, g.L, 2.0 ** 40)
+    opt = o.encode(synth.replicate_query(wl.query, g.N // 2), o.L, 2.0 ** 40)
+    es = synth.int_seed(9, synth.SUB_ENC)
+    gq, oq = g.encrypt(kg, g.pt_import(opt.coeffs(), g.L, 2.0 ** 40), es), o.encrypt(ko, opt, es)
+    gr, orr = g.rotate_hoisted(kg, gq, range(1, n1)), o.rotate_hoisted(ko, oq, range(1, n1))
+    for a, b in zip(gr, orr):
+        _same_oracle(g, a, b)
+    _same_oracle(g, g.mul_relin_rescale(kg, gq, gq), o.mul_relin_rescale(ko, oq, oq))
+    _same_oracle(g, g.bsgs_diag_matvec(kg, [gq] + gr, gdb, 0), o.bsgs_matvec(ko, [oq] + orr, odb, 0))
+    gdb.extend()
+    gs = g.bsgs_matvec_hoisted(kg, gq, gdb, 0)
+    _same_oracle(g, gs, o.bsgs_matvec_hoisted(ko, oq, odb, 0))
+    dec = g.decrypt_decode(kg, gs)
+    exact = wl.exact_scores()
+    assert np.max(np.abs(dec[: wl.K] - exact)) <= 2 ** -20
