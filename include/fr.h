@@ -8,7 +8,10 @@
  * --------------------------------
  * - Return value: FR_OK (0) or a negative fr_status; fr_last_error() then
  *   holds a thread-local message.  A failing call leaves its outputs' level
- *   and scale untouched and never frees caller memory.
+ *   and scale untouched and never frees caller memory.  Argument, level and
+ *   key errors are found before any device work, so those outputs are not
+ *   written at all; FR_ENOMEM (see fr_ctx_set_scratch_limit) can come after
+ *   part of the work has run.
  * - Ring: R = Z[X]/(X^N + 1), N = 2^log_n.  Ciphertext modulus
  *   Q_l = q_0 ... q_l, special modulus P = p_0 ... p_{nP-1} (§3.2).
  * - fr_ct / fr_pt describe CALLER-OWNED device memory of uint64 words:
@@ -89,6 +92,23 @@ void fr_ctx_destroy(fr_ctx *ctx);
 /* stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) */
 int fr_ctx_set_stream(fr_ctx *ctx, void *stream);
 int fr_ctx_sync(fr_ctx *ctx);
+/* Device scratch (the memory term of Eq. stream-pool, §5.1.2).  Each context
+ * keeps a growable device arena for the intermediate results of its calls
+ * (ModUp digits, key inner products, inner sums, the Chebyshev ladder's
+ * nodes); it grows on demand and is kept for later calls.
+ * - fr_ctx_set_scratch_limit: the arena may total at most `bytes` (0: no
+ *   limit).  If more is allocated now, the context waits for its streams and
+ *   releases the arena.
+ * - A call that needs more scratch than the limit (or than free device
+ *   memory) returns FR_ENOMEM.  Its work already queued finishes before it
+ *   returns; its outputs' level and scale are untouched, but the words of an
+ *   output buffer may have been partly written.  The context stays usable.
+ * - fr_ctx_scratch_info: bytes allocated now, and the most one call used.
+ * - fr_ctx_reserve: grow the arena to at least `bytes` now (FR_ENOMEM if it
+ *   cannot), so that later calls of that size allocate nothing. */
+int fr_ctx_set_scratch_limit(fr_ctx *ctx, uint64_t bytes);
+int fr_ctx_scratch_info(const fr_ctx *ctx, uint64_t *allocated, uint64_t *peak);
+int fr_ctx_reserve(fr_ctx *ctx, uint64_t bytes);
 /* N, L, nP, alpha, dnum */
 int fr_ctx_dims(const fr_ctx *ctx, int32_t *n, int32_t *L, int32_t *n_special, int32_t *alpha,
                 int32_t *dnum);
@@ -195,7 +215,7 @@ int fr_bsgs_diag_matvec_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *bab
                               int32_t n1, const fr_db *const *dbs, const int32_t *groups, fr_ct *out);
 
 /* ---- the same product with the baby steps' ModDown hoisted past the inner
- * sums (double hoisting of the plaintext-matrix BSGS, §2 hoisting and double
+ * sums (double hoisting of the plaintext-matrix BSGS, §3.4.2 hoisting and double
  * hoisting) ----
  * fr_db_extend appends to every diagonal of db its residues modulo the
  * special primes (those of the plaintext's centered integer coefficients,
@@ -255,6 +275,24 @@ int fr_tensor_sum_relin_rescale(fr_ctx *ctx, const fr_keys *keys, const fr_ct *a
  * keys 2^i, i < log2(N/2) (FR_ENOKEY otherwise).  out must not alias any
  * input; out->level = in[0].level. */
 int fr_membership_aggregate(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t n, fr_ct *out);
+
+/* ---- parity hook: ModDown on caller-given residues (hybrid key switching
+ * of §3.4.2; the rescale of §3.2) ----
+ * u_host: [2][level+1+nP][N] canonical coefficient-form residues over
+ * Q_level U P (limbs q_0..q_level, then p_0..p_{nP-1}); d_host (mode 2
+ * only): [2][level+1][N] over Q_level.  ModDown(u) = round(u / P)
+ * coefficient-wise (u minus its centered residue mod P, divided by P), with
+ * the rounding decided exactly.  The result runs through the same device
+ * path as the hot path's ModDown of that kind:
+ *   mode 0: out = ModDown(u) at `level` (key switching of a rotation);
+ *   mode 1: out = Rescale(ModDown(u)) at level-1 (the inner sums of
+ *           fr_bsgs_matvec_hoisted);
+ *   mode 2: out = Rescale(d + ModDown(u)) at level-1 (a relinearised
+ *           product).
+ * out->scale is set to 1.  Synchronises.  FR_EINVAL for a residue that is
+ * not canonical; FR_ELEVEL for level < 1 in modes 1 and 2. */
+int fr_moddown_parity(fr_ctx *ctx, int32_t mode, const uint64_t *u_host, const uint64_t *d_host, int32_t level,
+                      fr_ct *out);
 
 /* ---- kernel timing hook (for the benchmark's roofline figures) ----
  * While a class is selected, every launch of that kernel class is bracketed

@@ -735,7 +735,7 @@ int or_decode_direct(const or_ctx *c, const or_pt *p, double *z) {
     return 0;
 }
 /* the same through an inverse DFT: m(zeta^(2t+1)) = IDFT(m_k zeta^k)[t] * N */
-static int or_decode_fft(const or_ctx *c, const or_pt *p, double *z) {
+int or_decode_fft(const or_ctx *c, const or_pt *p, double *z) {
     int N = c->N, h = N / 2;
     double *m = malloc(sizeof(double) * N);
     or_pt_lift(c, p, m);
@@ -1412,7 +1412,7 @@ static or_ct *giant_sum(const or_ctx *c, const or_keys *K, or_ct **P, int n2, in
 }
 
 /* BSGS product with the ModDown of the baby steps hoisted past the inner
- * sums (double hoisting of the plaintext-matrix BSGS, §2 hoisting and double
+ * sums (double hoisting of the plaintext-matrix BSGS, §3.4.2 hoisting and double
  * hoisting).  Baby step i is kept over the extended basis Q_l U P,
  *   B_i = (P sigma_i(c0) + U0_i, U1_i),  U_i = sum_t sigma_i(ModUp_t(c1)) ksk_{i,t},
  *   B_0 = (P c0, P c1)  (zero on the special primes),

@@ -96,6 +96,7 @@ int or_pt_lift(const or_ctx *ctx, const or_pt *p, double *coeffs);
 /* Decode the N/2 real slot values. */
 int or_decode(const or_ctx *ctx, const or_pt *p, double *z);
 int or_decode_direct(const or_ctx *ctx, const or_pt *p, double *z);
+int or_decode_fft(const or_ctx *ctx, const or_pt *p, double *z);
 or_ct *or_ct_import(const or_ctx *ctx, const uint64_t *c, int level, double scale);
 or_ct *or_ct_copy(const or_ctx *ctx, const or_ct *a);
 void or_ct_free(or_ct *c);

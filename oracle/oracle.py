@@ -77,6 +77,7 @@ def lib():
         "or_pt_lift": (C.c_int, [_P, _PT, _DP]),
         "or_decode": (C.c_int, [_P, _PT, _DP]),
         "or_decode_direct": (C.c_int, [_P, _PT, _DP]),
+        "or_decode_fft": (C.c_int, [_P, _PT, _DP]),
         "or_ct_import": (_CT, [_P, _U64P, C.c_int, C.c_double]),
         "or_ct_copy": (_CT, [_P, _CT]),
         "or_ct_free": (None, [_CT]),
@@ -394,7 +395,7 @@ class Context:
 
     def decode(self, pt: Pt, method: str = "auto") -> np.ndarray:
         out = np.zeros(self.N // 2, dtype=np.float64)
-        f = lib().or_decode if method == "auto" else lib().or_decode_direct
+        f = {"auto": lib().or_decode, "direct": lib().or_decode_direct, "fft": lib().or_decode_fft}[method]
         f(self.ptr, pt.ptr, _f64(out))
         return out
 

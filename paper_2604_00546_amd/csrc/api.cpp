@@ -29,6 +29,26 @@ int fr_fail(int code, const char *fmt, ...) {
 
 extern "C" const char *fr_last_error(void) { return g_err; }
 
+// An entry point abandoned because the device scratch could not grow: the
+// work already queued (on the caller's and the auxiliary streams) finishes
+// before the call returns, so the caller may free or reuse its buffers.
+static int arena_full(fr_ctx *c, const ArenaFull &e) {
+    if (c) {
+        for (auto &a : c->aux)
+            if (a) (void)hipStreamSynchronize(a);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    return fr_fail(FR_ENOMEM, "device scratch exhausted: %zu more bytes needed, %zu allocated, limit %zu", e.bytes,
+                   e.allocated, e.limit);
+}
+#define FR_CATCH(ctx)                                                                 \
+    catch (const ArenaFull &e_) {                                                     \
+        return arena_full(ctx, e_);                                                   \
+    }                                                                                 \
+    catch (const std::bad_alloc &) {                                                  \
+        return fr_fail(FR_ENOMEM, "host allocation failed");                         \
+    }
+
 #define CHECK(cond, code, ...) \
     do {                       \
         if (!(cond)) return fr_fail(code, __VA_ARGS__); \
@@ -53,11 +73,32 @@ void *Arena::get(size_t bytes) {
             return p;
         }
     }
-    size_t sz = std::max(bytes, (size_t)256 << 20);
+    const size_t have = allocated();
+    if (have > limit || limit - have < bytes) return nullptr;
+    const size_t sz = std::min(std::max(bytes, (size_t)256 << 20), limit - have);
     char *b = nullptr;
-    if (hipMalloc(&b, sz) != hipSuccess) return nullptr;
+    if (hipMalloc(&b, sz) != hipSuccess) {
+        (void)hipGetLastError();  // clear the sticky allocation error
+        return nullptr;
+    }
     chunks.push_back({b, sz, bytes});
     return b;
+}
+bool Arena::grow(size_t bytes) {
+    const size_t have = allocated();
+    if (have > limit || limit - have < bytes) return false;
+    char *b = nullptr;
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    chunks.push_back({b, bytes, 0});
+    return true;
+}
+size_t Arena::allocated() const {
+    size_t t = 0;
+    for (auto &ch : chunks) t += ch.size;
+    return t;
 }
 void Arena::reset() {
     size_t used = 0;
@@ -96,14 +137,14 @@ inline LimbMap allmap(const fr_ctx *c) { return LimbMap{0, INT_MAX, 0, c->nmod, 
 inline LimbMap pmap(const fr_ctx *c) { return LimbMap{0, INT_MAX, 0, 0, c->L + 1}; }
 inline LimbMap single(int mod) { return LimbMap{0, INT_MAX, 0, 0, mod}; }
 
-// device scratch from the arena; a failed allocation stops the process on
-// the host rather than letting a kernel run on a null pointer
+// device scratch from the arena; when the arena cannot grow (device memory
+// or the context's scratch limit) the call is abandoned with ArenaFull,
+// which every entry point turns into FR_ENOMEM, so no kernel is ever given
+// a null pointer
 u64 *scratch(fr_ctx *c, size_t words) {
-    void *p = c->arena.get(std::max<size_t>(words, 1) * 8);
-    if (!p) {
-        std::fprintf(stderr, "libfrhip: device scratch allocation of %zu bytes failed\n", words * 8);
-        std::abort();
-    }
+    const size_t bytes = std::max<size_t>(words, 1) * 8;
+    void *p = c->arena.get(bytes);
+    if (!p) throw ArenaFull{bytes, c->arena.allocated(), c->arena.limit};
     return (u64 *)p;
 }
 
@@ -171,6 +212,7 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
     // independent: outside a region that already spreads work over the
     // auxiliary streams, digit t > 0 runs on one of them
     const hipStream_t main_stream = c->stream;
+    StreamRestore restore(c->stream);
     const int naux = c->arena.hold ? 0 : std::min(ndig - 1, fr_ctx::kAux);
     if (naux > 0) {
         (void)hipEventRecord(c->ev_fork, main_stream);
@@ -446,6 +488,27 @@ static int ctx_build(fr_ctx *c) {
     // [i] = P 2^64 mod q_i: P times a word inside a Montgomery-reduced sum
     for (int i = 0; i <= L; ++i) md.push_back(to_mont(c->P_mod_q[i], c->mod[i]));
     if (int e = upload(&c->d_moddown, md)) return e;
+    {  // Phat_j and P as multiword integers (ModDown's exact overflow decision)
+        std::vector<u64> pb((size_t)kPbigRows * kPbigWords, 0);
+        auto mul_small = [](u64 *w, u64 m) {
+            u64 carry = 0;
+            for (int k = 0; k < kPbigWords; ++k) {
+                const unsigned __int128 t = (unsigned __int128)w[k] * m + carry;
+                w[k] = (u64)t;
+                carry = (u64)(t >> 64);
+            }
+        };
+        u64 *Pw = pb.data() + (size_t)(kPbigRows - 1) * kPbigWords;
+        Pw[0] = 1;
+        for (int j = 0; j < nP; ++j) {
+            u64 *row = pb.data() + (size_t)j * kPbigWords;
+            row[0] = 1;
+            for (int jj = 0; jj < nP; ++jj)
+                if (jj != j) mul_small(row, c->mod[L + 1 + jj]);
+            mul_small(Pw, c->mod[L + 1 + j]);
+        }
+        if (int e = upload(&c->d_pbig, pb)) return e;
+    }
 
     // rescale tables: q_l^-1 mod q_i, then (P q_l)^-1 mod q_i (ModDown and
     // rescale in one product), each [L+1][value, companion][L+1]
@@ -570,7 +633,7 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
     (void)hipDeviceSynchronize();
     for (void *p : {(void *)c->d_mod, (void *)c->d_tw, (void *)c->d_tw_sh, (void *)c->d_itw, (void *)c->d_itw_sh,
                     (void *)c->d_tw2, (void *)c->d_itw2,
-                    (void *)c->d_modup, (void *)c->d_moddown, (void *)c->d_rescale, (void *)c->d_crt,
+                    (void *)c->d_modup, (void *)c->d_moddown, (void *)c->d_pbig, (void *)c->d_rescale, (void *)c->d_crt,
                     (void *)c->d_fft_w, (void *)c->d_zeta, (void *)c->d_slot_pos, (void *)c->d_flag})
         if (p) (void)hipFree(p);
     c->arena.release();
@@ -588,18 +651,46 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
     delete c;
 }
 
-extern "C" int fr_ctx_set_stream(fr_ctx *c, void *stream) {
+extern "C" int fr_ctx_set_stream(fr_ctx *c, void *stream) try {
     CHECK(c, FR_EINVAL, "null context");
     if (c->stream != (hipStream_t)stream) FR_HIP(hipStreamSynchronize(c->stream));
     c->stream = (hipStream_t)stream;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_ctx_sync(fr_ctx *c) {
+extern "C" int fr_ctx_sync(fr_ctx *c) try {
     CHECK(c, FR_EINVAL, "null context");
     FR_HIP(hipStreamSynchronize(c->stream));
     return FR_OK;
+} FR_CATCH(c)
+
+extern "C" int fr_ctx_set_scratch_limit(fr_ctx *c, uint64_t bytes) try {
+    CHECK(c, FR_EINVAL, "null context");
+    c->arena.limit = bytes ? (size_t)bytes : ~(size_t)0;
+    if (c->arena.allocated() > c->arena.limit) {
+        FR_HIP(hipStreamSynchronize(c->stream));
+        for (auto &a : c->aux) FR_HIP(hipStreamSynchronize(a));
+        c->arena.release();
+    }
+    return FR_OK;
+} FR_CATCH(c)
+
+extern "C" int fr_ctx_scratch_info(const fr_ctx *c, uint64_t *allocated, uint64_t *peak) {
+    CHECK(c, FR_EINVAL, "null context");
+    if (allocated) *allocated = c->arena.allocated();
+    if (peak) *peak = c->arena.peak;
+    return FR_OK;
 }
+
+extern "C" int fr_ctx_reserve(fr_ctx *c, uint64_t bytes) try {
+    CHECK(c, FR_EINVAL, "null context");
+    const size_t have = c->arena.allocated();
+    if (have >= bytes) return FR_OK;
+    CHECK(c->arena.grow((size_t)bytes - have), FR_ENOMEM,
+          "fr_ctx_reserve: cannot grow the scratch to %llu bytes (limit %zu)", (unsigned long long)bytes,
+          c->arena.limit);
+    return FR_OK;
+} FR_CATCH(c)
 
 extern "C" int fr_ctx_dims(const fr_ctx *c, int32_t *n, int32_t *L, int32_t *ns, int32_t *alpha, int32_t *dnum) {
     CHECK(c, FR_EINVAL, "null context");
@@ -626,7 +717,7 @@ extern "C" void fr_keys_destroy(fr_keys *k) {
     delete k;
 }
 
-extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t nrot, fr_keys **out) {
+extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t nrot, fr_keys **out) try {
     CHECK(c && out && (nrot == 0 || rots), FR_EINVAL, "fr_keygen: null argument");
     c->arena.reset();
     Scope sc(c->arena);
@@ -684,9 +775,9 @@ extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t 
     FR_HIP(hipStreamSynchronize(c->stream));
     *out = K.release();
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_t kid, uint64_t *host) {
+extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_t kid, uint64_t *host) try {
     CHECK(c && K && host, FR_EINVAL, "fr_keys_export: null argument");
     c->arena.reset();
     Scope sc(c->arena);
@@ -725,7 +816,7 @@ extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_
         return FR_OK;
     }
     return fr_fail(FR_EINVAL, "fr_keys_export: unknown selector %d", what);
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // encode / import / export / encrypt / decrypt / decode
@@ -742,7 +833,7 @@ static int encode_common(fr_ctx *c, const double *zdev, int n, int level, double
     return FR_OK;
 }
 
-extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) {
+extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) try {
     CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
           "fr_encode: bad size or level");
@@ -753,16 +844,16 @@ extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, d
     if (n) FR_HIP(hipMemcpyAsync(zd, z, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
     FR_HIP(hipStreamSynchronize(c->stream));
     return encode_common(c, zd, n, level, scale, out);
-}
+} FR_CATCH(c)
 
-extern "C" int fr_encode_device(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) {
+extern "C" int fr_encode_device(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) try {
     CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode_device: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
           "fr_encode_device: bad size or level");
     c->arena.reset();
     Scope sc(c->arena);
     return encode_common(c, z, n, level, scale, out);
-}
+} FR_CATCH(c)
 
 static int import_poly(fr_ctx *c, const uint64_t *host, int nl, int npoly, u64 *dst) {
     const size_t w = (size_t)npoly * nl * c->N;
@@ -792,37 +883,37 @@ static int export_poly(fr_ctx *c, const u64 *src, int nl, int npoly, uint64_t *h
     return FR_OK;
 }
 
-extern "C" int fr_pt_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_pt *out) {
+extern "C" int fr_pt_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_pt *out) try {
     CHECK(c && host && out && out->data, FR_EINVAL, "fr_pt_import: null argument");
     CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_pt_import: bad level");
     if (int e = import_poly(c, host, level + 1, 1, out->data)) return e;
     out->level = level;
     out->scale = scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_pt_export(fr_ctx *c, const fr_pt *p, uint64_t *host) {
+extern "C" int fr_pt_export(fr_ctx *c, const fr_pt *p, uint64_t *host) try {
     CHECK(c && p && p->data && host, FR_EINVAL, "fr_pt_export: null argument");
     CHECK(p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_pt_export: bad level");
     return export_poly(c, p->data, p->level + 1, 1, host);
-}
+} FR_CATCH(c)
 
-extern "C" int fr_ct_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_ct *out) {
+extern "C" int fr_ct_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_ct *out) try {
     CHECK(c && host && out && out->data, FR_EINVAL, "fr_ct_import: null argument");
     CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_ct_import: bad level");
     if (int e = import_poly(c, host, level + 1, 2, out->data)) return e;
     out->level = level;
     out->scale = scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_ct_export(fr_ctx *c, const fr_ct *x, uint64_t *host) {
+extern "C" int fr_ct_export(fr_ctx *c, const fr_ct *x, uint64_t *host) try {
     CHECK(c && host, FR_EINVAL, "fr_ct_export: null argument");
     if (int e = check_ct(c, x, "fr_ct_export")) return e;
     return export_poly(c, x->data, x->level + 1, 2, host);
-}
+} FR_CATCH(c)
 
-extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t seed, fr_ct *out) {
+extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t seed, fr_ct *out) try {
     CHECK(c && K && p && p->data, FR_EINVAL, "fr_encrypt: null argument");
     const int l = p->level;
     CHECK(l >= 0 && l <= c->L, FR_EINVAL, "fr_encrypt: bad plaintext level");
@@ -843,9 +934,9 @@ extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t 
     out->level = l;
     out->scale = p->scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *out) {
+extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *out) try {
     CHECK(c && K && out && out->data, FR_EINVAL, "fr_decrypt: null argument");
     if (int e = check_ct(c, x, "fr_decrypt")) return e;
     CHECK(x->level <= out->cap, FR_EINVAL, "fr_decrypt: output capacity");
@@ -855,9 +946,9 @@ extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *ou
     out->level = x->level;
     out->scale = x->scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) {
+extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) try {
     CHECK(c && p && p->data && z, FR_EINVAL, "fr_decode: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_decode: bad size or level");
     c->arena.reset();
@@ -873,7 +964,7 @@ extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) {
     frk::decode_slots(c, zd, m, p->level, p->scale, work);
     if (n) FR_HIP(hipMemcpyAsync(z, zd, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     return flag_check(c, "fr_decode");
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // homomorphic operations
@@ -960,21 +1051,21 @@ static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int
 }
 
 extern "C" int fr_rotate_hoisted(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots, int32_t nrot,
-                                 fr_ct *outs) {
+                                 fr_ct *outs) try {
     CHECK(c && K && in && (nrot == 0 || (rots && outs)), FR_EINVAL, "fr_rotate_hoisted: null argument");
     c->arena.reset();
     return rotate_hoisted_impl(c, K, in, 1, rots, nrot, outs);
-}
+} FR_CATCH(c)
 
 extern "C" int fr_rotate_hoisted_batch(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t nq, const int32_t *rots,
-                                       int32_t nrot, fr_ct *outs) {
+                                       int32_t nrot, fr_ct *outs) try {
     CHECK(c && K && in && nq >= 1 && (nrot == 0 || (rots && outs)), FR_EINVAL,
           "fr_rotate_hoisted_batch: null argument or nq < 1");
     c->arena.reset();
     return rotate_hoisted_impl(c, K, in, nq, rots, nrot, outs);
-}
+} FR_CATCH(c)
 
-extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) {
+extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) try {
     CHECK(c, FR_EINVAL, "null context");
     if (int e = check_ct(c, in, "fr_rescale")) return e;
     CHECK(in->level >= 1, FR_ELEVEL, "fr_rescale: level 0 cannot be rescaled");
@@ -986,7 +1077,7 @@ extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) {
     out->scale = in->scale / (double)c->mod[in->level];
     out->level = in->level - 1;
     return FR_OK;
-}
+} FR_CATCH(c)
 
 static int addsub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out, bool sub) {
     CHECK(c, FR_EINVAL, "null context");
@@ -1007,7 +1098,7 @@ extern "C" int fr_sub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { r
 // Encrypted-database product: Rescale(Relin(sum_k a[k] (x) b[k])), the
 // degree-2 sum relinearised once.
 extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, int32_t n,
-                                           fr_ct *out) {
+                                           fr_ct *out) try {
     CHECK(c && K && a && b && out && n >= 1, FR_EINVAL, "fr_tensor_sum_relin_rescale: null argument or no pair");
     const int l = a[0].level;
     for (int k = 0; k < n; ++k) {
@@ -1041,12 +1132,12 @@ extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr
     out->level = l - 1;
     out->scale = (a[0].scale * b[0].scale) / (double)c->mod[l];
     return FR_OK;
-}
+} FR_CATCH(c)
 
 // Membership aggregation: the group ciphertexts are added, then every slot
 // receives the sum of all N/2 slots through log2(N/2) doublings
 // x <- x + Rot_{2^i}(x), each one key switch.
-extern "C" int fr_membership_aggregate(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t n, fr_ct *out) {
+extern "C" int fr_membership_aggregate(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t n, fr_ct *out) try {
     CHECK(c && K && in && out && n >= 1, FR_EINVAL, "fr_membership_aggregate: null argument or no input");
     const int l = in[0].level;
     for (int i = 0; i < n; ++i) {
@@ -1078,9 +1169,9 @@ extern "C" int fr_membership_aggregate(fr_ctx *c, const fr_keys *K, const fr_ct 
     }
     FR_HIP(hipGetLastError());
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *out) {
+extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *out) try {
     CHECK(c && p && p->data, FR_EINVAL, "fr_mul_plain: null argument");
     if (int e = check_ct(c, a, "fr_mul_plain")) return e;
     const int l = std::min(a->level, p->level);
@@ -1092,9 +1183,9 @@ extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *ou
     out->level = l;
     out->scale = a->scale * p->scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_mul_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, fr_ct *out) {
+extern "C" int fr_mul_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, fr_ct *out) try {
     CHECK(c && K, FR_EINVAL, "null argument");
     if (int e = check_ct(c, a, "fr_mul_relin_rescale")) return e;
     if (int e = check_ct(c, b, "fr_mul_relin_rescale")) return e;
@@ -1108,9 +1199,9 @@ extern "C" int fr_mul_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a,
     out->level = a->level - 1;
     out->scale = (a->scale * b->scale) / (double)c->mod[a->level];
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_mul_int(fr_ctx *c, const fr_ct *a, int64_t k, fr_ct *out) {
+extern "C" int fr_mul_int(fr_ctx *c, const fr_ct *a, int64_t k, fr_ct *out) try {
     CHECK(c, FR_EINVAL, "null context");
     if (int e = check_ct(c, a, "fr_mul_int")) return e;
     if (int e = check_out(c, out, a->level, "fr_mul_int")) return e;
@@ -1120,9 +1211,9 @@ extern "C" int fr_mul_int(fr_ctx *c, const fr_ct *a, int64_t k, fr_ct *out) {
     out->level = a->level;
     out->scale = a->scale * (double)k;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_add_const(fr_ctx *c, const fr_ct *a, double cst, fr_ct *out) {
+extern "C" int fr_add_const(fr_ctx *c, const fr_ct *a, double cst, fr_ct *out) try {
     CHECK(c, FR_EINVAL, "null context");
     if (int e = check_ct(c, a, "fr_add_const")) return e;
     if (int e = check_out(c, out, a->level, "fr_add_const")) return e;
@@ -1133,9 +1224,9 @@ extern "C" int fr_add_const(fr_ctx *c, const fr_ct *a, double cst, fr_ct *out) {
     out->level = a->level;
     out->scale = a->scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_drop_to(fr_ctx *c, const fr_ct *a, int32_t level, fr_ct *out) {
+extern "C" int fr_drop_to(fr_ctx *c, const fr_ct *a, int32_t level, fr_ct *out) try {
     CHECK(c, FR_EINVAL, "null context");
     if (int e = check_ct(c, a, "fr_drop_to")) return e;
     CHECK(level >= 0 && level <= a->level, FR_ELEVEL, "fr_drop_to: bad level");
@@ -1148,7 +1239,7 @@ extern "C" int fr_drop_to(fr_ctx *c, const fr_ct *a, int32_t level, fr_ct *out) 
     out->level = level;
     out->scale = a->scale;
     return FR_OK;
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // database
@@ -1196,7 +1287,7 @@ static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double 
 }
 
 extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int32_t B, int32_t n1, int32_t level,
-                          double scale, fr_db **out) {
+                          double scale, fr_db **out) try {
     CHECK(c && out && (K == 0 || T), FR_EINVAL, "fr_db_load: null argument");
     const int h = c->N / 2;
     CHECK(K >= 0 && ell > 0 && B > 0 && (long long)B * ell <= h && n1 > 0 && n1 <= ell && level >= 0 &&
@@ -1230,10 +1321,10 @@ extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int
     if (int e = flag_check(c, "fr_db_load")) return e;
     *out = guard.release();
     return FR_OK;
-}
+} FR_CATCH(c)
 
 extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t ell, int32_t B, int32_t n1,
-                            int32_t level, double scale, fr_db **out) {
+                            int32_t level, double scale, fr_db **out) try {
     CHECK(c && host && out, FR_EINVAL, "fr_db_import: null argument");
     CHECK(G >= 1 && ell > 0 && B > 0 && (long long)B * ell <= c->N / 2 && n1 > 0 && n1 <= ell && level >= 0 &&
               level <= c->L,
@@ -1256,9 +1347,9 @@ extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t 
     FR_HIP(hipStreamSynchronize(c->stream));
     *out = guard.release();
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, uint64_t *host) {
+extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, uint64_t *host) try {
     CHECK(c && db && host, FR_EINVAL, "fr_db_export: null argument");
     CHECK(g >= 0 && g < db->G && d >= 0 && d < db->ell, FR_EINVAL, "fr_db_export: bad index");
     c->arena.reset();
@@ -1272,7 +1363,7 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
     FR_HIP(hipMemcpyAsync(host, t, pw * 8, hipMemcpyDeviceToHost, c->stream));
     FR_HIP(hipStreamSynchronize(c->stream));
     return FR_OK;
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // the BSGS diagonal matrix-vector product
@@ -1391,26 +1482,26 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
 }
 
 extern "C" int fr_bsgs_diag_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t n1, const fr_db *db,
-                                   int32_t group, fr_ct *out) {
+                                   int32_t group, fr_ct *out) try {
     CHECK(c && K && baby && db && out && n1 >= 1, FR_EINVAL, "fr_bsgs_diag_matvec: null argument");
     c->arena.reset();
     return matvec_impl(c, K, baby, 1, n1, &db, &group, out);
-}
+} FR_CATCH(c)
 
 extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t nq, int32_t n1,
-                                         const fr_db *const *dbs, const int32_t *groups, fr_ct *out) {
+                                         const fr_db *const *dbs, const int32_t *groups, fr_ct *out) try {
     CHECK(c && K && baby && dbs && groups && out && n1 >= 1 && nq >= 1, FR_EINVAL,
           "fr_bsgs_diag_matvec_batch: null argument or empty batch");
     c->arena.reset();
     return matvec_impl(c, K, baby, nq, n1, dbs, groups, out);
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // the BSGS product with the baby steps' ModDown hoisted past the inner sums
 // ---------------------------------------------------------------------------
 // Appends to every diagonal its residues mod the special primes, those of
 // the plaintext's centered integer coefficients (exact mixed-radix lift).
-extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
+extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) try {
     CHECK(c && db, FR_EINVAL, "fr_db_extend: null argument");
     CHECK(db->ctx == c, FR_EINVAL, "fr_db_extend: database of another context");
     const int N = c->N, l = db->level, L1 = l + 1, nP = c->nP, nE = L1 + nP;
@@ -1419,8 +1510,20 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
     const size_t stride = db_layout(c, l, nE, lay);
     const size_t nd = (size_t)db->G * db->ell, lw = (size_t)L1 * N, ew = (size_t)nE * N, pw = (size_t)nP * N;
     unsigned char *ext = nullptr;
-    if (hipMalloc(&ext, nd * stride) != hipSuccess)
+    if (hipMalloc(&ext, nd * stride) != hipSuccess) {
+        (void)hipGetLastError();
         return fr_fail(FR_ENOMEM, "fr_db_extend: cannot allocate %zu bytes of diagonals", nd * stride);
+    }
+    struct ExtGuard {  // frees the new buffer unless it replaces the old one
+        unsigned char *&p;
+        fr_ctx *c;
+        ~ExtGuard() {
+            if (p) {
+                (void)hipStreamSynchronize(c->stream);
+                (void)hipFree(p);
+            }
+        }
+    } ext_guard{ext, c};
     c->arena.reset();
     Scope sc(c->arena);
     const size_t batch = 16;
@@ -1433,10 +1536,7 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
         FR_HIP(hipMemcpy2DAsync(Y, ew * 8, X, lw * 8, lw * 8, nb, hipMemcpyDeviceToDevice, c->stream));
         frk::mont_scale(c, X, L1, qmap(), nb, lw, false);
         frk::ntt_inv(c, X, L1, qmap(), nb, lw);
-        if (int e = frk::crt_extend(c, Xp, X, l, nb, pw, lw)) {
-            (void)hipFree(ext);
-            return e;
-        }
+        if (int e = frk::crt_extend(c, Xp, X, l, nb, pw, lw)) return e;
         frk::ntt_fwd(c, Xp, nP, pmap(c), nb, pw);
         frk::mont_scale(c, Xp, nP, pmap(c), nb, pw, true);
         FR_HIP(hipMemcpy2DAsync(Y + lw, ew * 8, Xp, pw * 8, pw * 8, nb, hipMemcpyDeviceToDevice, c->stream));
@@ -1445,11 +1545,12 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) {
     FR_HIP(hipStreamSynchronize(c->stream));
     (void)hipFree(db->data);
     db->data = ext;
+    ext = nullptr;
     db->nl = nE;
     db->stride = stride;
     db->lay = lay;
     return FR_OK;
-}
+} FR_CATCH(c)
 
 // out (np polynomials of l limbs) = Rescale(ModDown(U)) for np polynomials
 // U over Q_l U P (eval domain, nE limbs each; np even)
@@ -1560,19 +1661,74 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
 }
 
 extern "C" int fr_bsgs_matvec_hoisted(fr_ctx *c, const fr_keys *K, const fr_ct *query, const fr_db *db, int32_t group,
-                                      fr_ct *out) {
+                                      fr_ct *out) try {
     CHECK(c && K && query && db && out, FR_EINVAL, "fr_bsgs_matvec_hoisted: null argument");
     c->arena.reset();
     return matvec_hoisted_impl(c, K, query, 1, &db, &group, out);
-}
+} FR_CATCH(c)
 
 extern "C" int fr_bsgs_matvec_hoisted_batch(fr_ctx *c, const fr_keys *K, const fr_ct *queries, int32_t nq,
-                                            const fr_db *const *dbs, const int32_t *groups, fr_ct *out) {
+                                            const fr_db *const *dbs, const int32_t *groups, fr_ct *out) try {
     CHECK(c && K && queries && dbs && groups && out && nq >= 1, FR_EINVAL,
           "fr_bsgs_matvec_hoisted_batch: null argument or empty batch");
     c->arena.reset();
     return matvec_hoisted_impl(c, K, queries, nq, dbs, groups, out);
-}
+} FR_CATCH(c)
+
+// ---------------------------------------------------------------------------
+// parity hook: the device ModDown paths on caller-given residues
+// ---------------------------------------------------------------------------
+extern "C" int fr_moddown_parity(fr_ctx *c, int32_t mode, const uint64_t *u_host, const uint64_t *d_host,
+                                 int32_t level, fr_ct *out) try {
+    CHECK(c && u_host && out, FR_EINVAL, "fr_moddown_parity: null argument");
+    CHECK(mode >= 0 && mode <= 2, FR_EINVAL, "fr_moddown_parity: unknown mode %d", mode);
+    CHECK(mode != 2 || d_host, FR_EINVAL, "fr_moddown_parity: mode 2 needs d");
+    CHECK(level >= (mode ? 1 : 0) && level <= c->L, FR_ELEVEL, "fr_moddown_parity: bad level %d", level);
+    const int ol = mode ? level - 1 : level;
+    if (int e = check_out(c, out, ol, "fr_moddown_parity")) return e;
+    const int N = c->N, nE = level + 1 + c->nP;
+    const size_t ew = (size_t)nE * N, lw = (size_t)(level + 1) * N;
+    std::vector<u64> hu(u_host, u_host + 2 * ew);
+    for (int p = 0; p < 2; ++p)
+        for (int e = 0; e < nE; ++e) {
+            const u64 q = c->mod[e <= level ? e : c->L + 1 + (e - level - 1)];
+            for (int k = 0; k < N; ++k)
+                CHECK(hu[(size_t)p * ew + (size_t)e * N + k] < q, FR_EINVAL,
+                      "fr_moddown_parity: residue not canonical (limb %d)", e);
+        }
+    c->arena.reset();
+    Scope sc(c->arena);
+    u64 *U = scratch(c, 2 * ew);
+    u64 *d = mode == 2 ? scratch(c, 2 * lw) : nullptr;
+    CHECK(U && (mode != 2 || d), FR_ENOMEM, "fr_moddown_parity: scratch");
+    const LimbMap ext{0, INT_MAX, 0, level + 1, c->L + 1};
+    FR_HIP(hipMemcpyAsync(U, hu.data(), 2 * ew * 8, hipMemcpyHostToDevice, c->stream));
+    frk::ntt_fwd(c, U, nE, ext, 2, ew);
+    if (mode == 2) {
+        for (int p = 0; p < 2; ++p)
+            for (int i = 0; i <= level; ++i)
+                for (int k = 0; k < N; ++k)
+                    CHECK(d_host[(size_t)p * lw + (size_t)i * N + k] < c->mod[i], FR_EINVAL,
+                          "fr_moddown_parity: d residue not canonical (limb %d)", i);
+        FR_HIP(hipMemcpyAsync(d, d_host, 2 * lw * 8, hipMemcpyHostToDevice, c->stream));
+        frk::ntt_fwd(c, d, level + 1, qmap(), 2, lw);
+    }
+    if (mode == 0) {
+        ks_moddown(c, U, level, out->data, false);
+    } else if (mode == 1) {
+        moddown_rescale(c, U, 2, level, out->data);
+    } else {
+        // the relinearised product's path: the key inner product leaves
+        // d_l + P^-1 U_l in U's top limb where the merged step expects it
+        if (relin_folds(c)) frk::fold_top(c, U, d, level, 2, ew, lw);
+        relin_rescale_into(c, d, U, 1, level, out->data);
+    }
+    FR_HIP(hipGetLastError());
+    FR_HIP(hipStreamSynchronize(c->stream));
+    out->level = ol;
+    out->scale = 1.0;
+    return FR_OK;
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // Chebyshev threshold
@@ -1808,6 +1964,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         ~HoldGuard() { a.hold--; }
     } hold_guard{c->arena};
     const hipStream_t main_stream = c->stream;
+    StreamRestore restore(c->stream);
     const int nstream = 1 + fr_ctx::kAux;
     auto stream_of = [&](int s) { return s == 0 ? main_stream : c->aux[s - 1]; };
     std::vector<int> prod_ev(n, -1), prod_st(n, 0);  // event slot / stream of each node's group
@@ -2050,16 +2207,16 @@ int chebyshev_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const d
 }  // namespace
 
 extern "C" int fr_chebyshev_eval(fr_ctx *c, const fr_keys *K, const fr_ct *in, const double *cf, int32_t degree,
-                                 int32_t d1, fr_ct *out) {
+                                 int32_t d1, fr_ct *out) try {
     CHECK(c && K && in && cf && out, FR_EINVAL, "fr_chebyshev_eval: null argument");
     return chebyshev_impl(c, K, in, 1, cf, degree, d1, out);
-}
+} FR_CATCH(c)
 
 extern "C" int fr_chebyshev_eval_batch(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t nq, const double *cf,
-                                       int32_t degree, int32_t d1, fr_ct *out) {
+                                       int32_t degree, int32_t d1, fr_ct *out) try {
     CHECK(c && K && in && cf && out && nq >= 1, FR_EINVAL, "fr_chebyshev_eval_batch: null argument or empty batch");
     return chebyshev_impl(c, K, in, nq, cf, degree, d1, out);
-}
+} FR_CATCH(c)
 
 extern "C" int fr_cheb_out_level(int32_t in_level, int32_t degree, int32_t d1) {
     if (degree < 1 || d1 < 2 || in_level < 0) return -1;
@@ -2088,7 +2245,7 @@ void Prof::end(int, hipStream_t s, double b) {
     bytes += b;
 }
 
-extern "C" int fr_prof_begin(fr_ctx *c, int32_t kernel_class) {
+extern "C" int fr_prof_begin(fr_ctx *c, int32_t kernel_class) try {
     CHECK(c, FR_EINVAL, "null context");
     CHECK(kernel_class >= 0 && kernel_class <= K_ELEM, FR_EINVAL, "fr_prof_begin: unknown class %d", kernel_class);
     if (!c->prof) {
@@ -2101,9 +2258,9 @@ extern "C" int fr_prof_begin(fr_ctx *c, int32_t kernel_class) {
     c->prof->used = 0;
     c->prof->bytes = 0.0;
     return FR_OK;
-}
+} FR_CATCH(c)
 
-extern "C" int fr_prof_end(fr_ctx *c, int32_t *launches, double *total_ms, double *bytes) {
+extern "C" int fr_prof_end(fr_ctx *c, int32_t *launches, double *total_ms, double *bytes) try {
     CHECK(c && c->prof, FR_EINVAL, "fr_prof_end: no timing in progress");
     FR_HIP(hipStreamSynchronize(c->stream));
     double tot = 0.0;
@@ -2118,7 +2275,7 @@ extern "C" int fr_prof_end(fr_ctx *c, int32_t *launches, double *total_ms, doubl
     c->prof->cls = K_NONE;
     c->prof->used = 0;
     return FR_OK;
-}
+} FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
 // host-only planning helpers

@@ -23,6 +23,8 @@ typedef uint32_t u32;
 
 #define FR_MAXMOD 64
 #define FR_MAXLEVEL 48
+// multiword tables of the special modulus (at most 8 special primes below 2^60)
+constexpr int kPbigWords = 9, kPbigRows = 9;
 
 // ---------------------------------------------------------------------------
 // per-modulus constants
@@ -118,10 +120,26 @@ struct Arena {  // bump allocator over device chunks, reset per top-level call
     struct Chunk { char *base; size_t size, used; };
     std::vector<Chunk> chunks;
     size_t peak = 0;
+    size_t limit = ~(size_t)0;  // most bytes the chunks may total
     int hold = 0;  // > 0: scopes do not give space back (work on several streams)
-    void *get(size_t bytes);  // 256-byte aligned; nullptr on failure
+    void *get(size_t bytes);  // 256-byte aligned; nullptr on failure or past the limit
+    size_t allocated() const;
+    bool grow(size_t bytes);  // one more chunk of exactly `bytes` (within the limit)
     void reset();
     void release();
+};
+// thrown by the scratch allocator when the arena cannot grow; every entry
+// point catches it and returns FR_ENOMEM
+struct ArenaFull {
+    size_t bytes, allocated, limit;
+};
+// restores the context's stream on scope exit (work spread over the
+// auxiliary streams switches it temporarily)
+struct StreamRestore {
+    hipStream_t &slot;
+    hipStream_t saved;
+    explicit StreamRestore(hipStream_t &s) : slot(s), saved(s) {}
+    ~StreamRestore() { slot = saved; }
 };
 
 // kernel timing hook: events around every launch of one kernel class
@@ -162,6 +180,10 @@ struct fr_ctx {
     // Pinv[L+1], Pinv_sh[L+1], P mod q_i [L+1], 1/p_j [nP] (double bits),
     // -e P 2^64 mod q_i [L+1][nP+1] (e = 0..nP), P 2^64 mod q_i [L+1]
     u64 *d_moddown = nullptr;
+    // ModDown's exact overflow decision: [kPbigRows][kPbigWords] words, row
+    // j < nP = Phat_j = P / p_j, row kPbigRows - 1 = P, little-endian 64-bit
+    // words (zero-padded)
+    u64 *d_pbig = nullptr;
     u64 P_mod_q[FR_MAXMOD], P_mod_q_sh[FR_MAXMOD];
     u64 P_inv_q[FR_MAXMOD], P_inv_q_sh[FR_MAXMOD];  // P^-1 mod q_i and Shoup companions
     // rescale: qinv[l][i] = q_l^-1 mod q_i and Shoup, [L+1][L+1] each; then
@@ -180,10 +202,14 @@ struct fr_ctx {
     static const int kAux = 3;
     hipStream_t aux[kAux] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
-    // ring of events marking finished groups of a recorded DAG (a later
-    // record of a slot only makes a waiter wait longer)
+    // ring of events marking finished groups of a recorded DAG.  Groups go to
+    // the 1 + kAux streams in turn and take the ring's slots in turn, so with
+    // kDagEv a multiple of the stream count a slot is always re-recorded on
+    // the stream that recorded it before, after the work it marked: a waiter
+    // that reads the newer record waits at least as long as it needs to
     static const int kDagEv = 64;
     hipEvent_t ev_dag[kDagEv] = {};
+    static_assert(kDagEv % (1 + kAux) == 0, "DAG event slots must map to one stream each");
     Arena arena;
     KeyLayout klay{};
     int *d_flag = nullptr;  // device error flag
@@ -373,6 +399,9 @@ void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, i
 // Q_l/2] given by their level+1 limbs (coefficient form): Xp[b][j][N] from
 // X[b][level+1][N] (mixed-radix digits, no floating point)
 int crt_extend(fr_ctx *c, u64 *Xp, const u64 *X, int level, int npoly, size_t sxp, size_t sx);
+// U[p] limb level <- d[p] limb level + P^-1 U[p] limb level (eval domain;
+// polynomials su / sd words apart)
+void fold_top(const fr_ctx *c, u64 *U, const u64 *d, int level, int npoly, size_t su, size_t sd);
 // v = FBC_{P->Q}(Upc) (coefficient form) into V[level+1][N]
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly);
 // out_i = (accumulate ? out_i : 0) + (U_i - V_i) P^-1   (eval domain)

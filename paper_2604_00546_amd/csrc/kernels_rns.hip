@@ -50,6 +50,60 @@ struct Dot30 {
     }
 };
 
+// ModDown's overflow count e = round(X / P) for X = sum_j y_j Phat_j in
+// [0, nP P) (y_j < p_j, Phat_j = P / p_j), i.e. the e that makes X - e P the
+// centered residue of the input mod P.  X / P = sum_j y_j / p_j is summed in
+// FP64 (fixed order, no contraction): |error| < 2^-46 for nP <= 8 terms below
+// 1 each, so rint() is exact unless the sum lies within 2^-40 of a
+// half-integer.  There the decision is taken in integers: with k = floor(s),
+// e = k + 1 exactly when 2 X > (2k + 1) P (P is odd, so the two never tie),
+// compared in kPW-word arithmetic against the tables Phat_j and P.
+constexpr int kPW = kMaxDigit + 1;  // 64-bit words of the multiword integers
+static_assert(kPW == kPbigWords && kMaxDigit + 1 == kPbigRows, "multiword table shape");
+__device__ __forceinline__ u64 overflow_exact(const u64 (&y)[kMaxDigit], int nP, double s, const u64 *pbig) {
+    u64 X[kPW];
+#pragma unroll
+    for (int w = 0; w < kPW; ++w) X[w] = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxDigit; ++j)
+        if (j < nP) {
+            u64 carry = 0;
+#pragma unroll
+            for (int w = 0; w < kPW; ++w) {
+                const u64 ph = pbig[j * kPW + w];
+                u64 lo = ph * y[j], hi = mulhi64(ph, y[j]);
+                lo += X[w];
+                hi += lo < X[w] ? 1u : 0u;
+                lo += carry;
+                hi += lo < carry ? 1u : 0u;
+                X[w] = lo;
+                carry = hi;
+            }
+        }
+    const u64 k = (u64)floor(s), m = 2 * k + 1;
+    const u64 *P = pbig + kMaxDigit * kPW;
+    u64 ycarry = 0, prev = 0, borrow = 0;
+#pragma unroll
+    for (int w = 0; w < kPW; ++w) {
+        const u64 x2 = (X[w] << 1) | (prev >> 63);  // word w of 2 X
+        prev = X[w];
+        u64 yl = P[w] * m;                           // word w of (2k + 1) P
+        const u64 yh = mulhi64(P[w], m);
+        yl += ycarry;
+        ycarry = yh + (yl < ycarry ? 1u : 0u);
+        const u64 d = x2 - yl;                       // 2 X - (2k + 1) P, with borrow
+        const u64 b1 = x2 < yl ? 1u : 0u;
+        const u64 b2 = d < borrow ? 1u : 0u;
+        borrow = b1 | b2;
+    }
+    return borrow ? k : k + 1;
+}
+__device__ __forceinline__ u64 overflow_round(const u64 (&y)[kMaxDigit], int nP, double s, const u64 *pbig) {
+    const double f = s - floor(s);
+    if (fabs(f - 0.5) < 0x1p-40) return overflow_exact(y, nP, s, pbig);
+    return (u64)rint(s);
+}
+
 // Batch item and tile of a block when every tile is processed for `batch`
 // items.  Workgroups are placed on the 8 XCDs round-robin by linear id, so
 // with ntiles a multiple of 8 the `batch` blocks of one tile are consecutive
@@ -427,7 +481,7 @@ __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, G
 __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu, const u64 *Xd, int N, int level,
                                                            int nP, int pbase, int L1, const u64 *tab,
                                                            const ModConst *mods, size_t sz, size_t sxu, size_t sxd,
-                                                           int no_d) {
+                                                           int no_d, const u64 *pbig) {
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
     const u64 *pinv = tab + 2 * nP + (size_t)L1 * nP, *pinv_sh = pinv + L1;
@@ -442,7 +496,7 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
             y[j] = shoup(xu[(size_t)(1 + j) * N], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
             s = s + (double)y[j] * invp[j];
         }
-    const u64 e = (u64)rint(s);
+    const u64 e = overflow_round(y, nP, s, pbig);
     u32 y0[kMaxDigit], y1[kMaxDigit];
 #pragma unroll
     for (int j = 0; j < kMaxDigit; ++j)
@@ -485,14 +539,14 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
 
 // ModDown base conversion P -> Q_level of the P limbs in coefficient form,
 // to the CENTERED residue of u mod P: y_j = [u_j * Phat_j^-1]_{p_j},
-// X = sum_j y_j Phat_j in [0, nP P), e = round(X / P) estimated in FP64 as
-// rint(sum_j y_j / p_j) (fixed order, no contraction), and
+// X = sum_j y_j Phat_j in [0, nP P), e = round(X / P) (overflow_round: FP64
+// estimate, decided in integers near a half-integer), and
 // V_i = (sum_j y_j [Phat_j]_{q_i} - e [P]_{q_i}) mod q_i.
 // tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1],
 //      Pinv_sh[L+1], P_mod_q[L+1], inv_p[nP] (double bits)
 __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP, int pbase,
                                                     int L1, const u64 *tab, const ModConst *mods, size_t sv,
-                                                    size_t su) {
+                                                    size_t su, const u64 *pbig) {
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
     const u64 *pmod = tab + 2 * nP + (size_t)L1 * nP + 2 * L1;
@@ -505,7 +559,7 @@ __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int 
             y[j] = shoup(Upc[poly * su + (size_t)j * N + k], phat_inv[j], phat_inv_sh[j], mods[pbase + j].q);
             s = s + (double)y[j] * invp[j];
         }
-    const u64 e = (u64)rint(s);
+    const u64 e = overflow_round(y, nP, s, pbig);
     u32 y0[kMaxDigit], y1[kMaxDigit];
 #pragma unroll
     for (int j = 0; j < kMaxDigit; ++j)
@@ -519,6 +573,16 @@ __global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int 
             if (j < nP) acc.add(y0[j], y1[j], phat_mod[(size_t)i * nP + j]);
         V[poly * sv + (size_t)i * N + k] = acc.redc(mods[i]);
     }
+}
+
+// U[p] limb `level` <- d[p] limb level + P^-1 U[p] limb level (the top-limb
+// fold that the relinearisation key inner product applies in its epilogue)
+__global__ __launch_bounds__(kT) void k_fold_top(u64 *U, const u64 *d, int N, int level, u64 pinv, u64 pinv_sh,
+                                                 const ModConst *mods, size_t su, size_t sd) {
+    const int k = blockIdx.x * kT + threadIdx.x, p = blockIdx.z;
+    const u64 q = mods[level].q;
+    u64 *u = U + p * su + (size_t)level * N + k;
+    *u = addq(d[p * sd + (size_t)level * N + k], shoup(*u, pinv, pinv_sh, q), q);
 }
 
 __global__ __launch_bounds__(kT) void k_moddown_finish(u64 *out, const u64 *U, const u64 *V, int N, const u64 *pinv,
@@ -1179,14 +1243,18 @@ void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, i
     ProfScope ps(c, K_MODDOWN, npoly * (2.0 + c->nP + 1.0 * level) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + kFbcTargets - 1) / kFbcTargets, npoly);
     hipLaunchKernelGGL(k_relin_rescale_prep, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
-                       c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd, (int)no_d);
+                       c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd, (int)no_d, c->d_pbig);
 }
 
+void fold_top(const fr_ctx *c, u64 *U, const u64 *d, int level, int npoly, size_t su, size_t sd) {
+    hipLaunchKernelGGL(k_fold_top, dim3(c->N / kT, 1, npoly), dim3(kT), 0, c->stream, U, d, c->N, level,
+                       c->P_inv_q[level], c->P_inv_q_sh[level], c->d_mod, su, sd);
+}
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
     ProfScope ps(c, K_MODDOWN, npoly * (1.0 * c->nP + 1.0 * (level + 1)) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + 1 + kFbcTargets - 1) / kFbcTargets, npoly);
     hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
-                       c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N);
+                       c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N, c->d_pbig);
 }
 
 void moddown_finish(const fr_ctx *c, u64 *out, const u64 *U, const u64 *V, int level, int npoly, size_t so,

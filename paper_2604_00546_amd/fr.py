@@ -52,6 +52,9 @@ SIGNATURES = {
     "fr_ctx_set_stream": (C.c_int, [_P, _P]),
     "fr_ctx_sync": (C.c_int, [_P]),
     "fr_ctx_dims": (C.c_int, [_P, _I32P, _I32P, _I32P, _I32P, _I32P]),
+    "fr_ctx_set_scratch_limit": (C.c_int, [_P, C.c_uint64]),
+    "fr_ctx_scratch_info": (C.c_int, [_P, _U64P, _U64P]),
+    "fr_ctx_reserve": (C.c_int, [_P, C.c_uint64]),
     "fr_ctx_modulus": (C.c_uint64, [_P, C.c_int32]),
     "fr_keygen": (C.c_int, [_P, C.c_uint64, _I32P, C.c_int32, C.POINTER(_P)]),
     "fr_keys_destroy": (None, [_P]),
@@ -91,6 +94,7 @@ SIGNATURES = {
     "fr_tensor_sum_relin_rescale": (C.c_int, [_P, _P, _CTP, _CTP, C.c_int32, _CTP]),
     "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
+    "fr_moddown_parity": (C.c_int, [_P, C.c_int32, _U64P, _U64P, C.c_int32, _CTP]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
     "fr_prof_end": (C.c_int, [_P, _I32P, _DP, _DP]),
     "fr_cheb_step_coeffs": (C.c_int, [C.c_int32, C.c_double, _DP]),
@@ -290,6 +294,20 @@ class Context:
     def sync(self):
         _check(lib().fr_ctx_sync(self.ptr), "fr_ctx_sync")
 
+    # device scratch ---------------------------------------------------------------
+    def set_scratch_limit(self, nbytes: int):
+        """At most nbytes of device scratch (0: no limit); calls beyond it raise FR_ENOMEM."""
+        _check(lib().fr_ctx_set_scratch_limit(self.ptr, int(nbytes)), "fr_ctx_set_scratch_limit")
+
+    def scratch_info(self):
+        """(bytes allocated now, most bytes one call has used)."""
+        a, p = C.c_uint64(), C.c_uint64()
+        _check(lib().fr_ctx_scratch_info(self.ptr, C.byref(a), C.byref(p)), "fr_ctx_scratch_info")
+        return a.value, p.value
+
+    def reserve(self, nbytes: int):
+        _check(lib().fr_ctx_reserve(self.ptr, int(nbytes)), "fr_ctx_reserve")
+
     # kernel timing hook ------------------------------------------------------
     KERNEL_CLASSES = {"ntt": 1, "modup": 2, "ks_inner": 3, "moddown": 4, "mac": 5, "rescale": 6, "tensor": 7,
                       "elementwise": 8}
@@ -301,6 +319,18 @@ class Context:
         n, ms, b = C.c_int32(), C.c_double(), C.c_double()
         _check(lib().fr_prof_end(self.ptr, C.byref(n), C.byref(ms), C.byref(b)), "fr_prof_end")
         return n.value, ms.value, b.value
+
+    # parity hook -------------------------------------------------------------
+    def moddown_parity(self, mode: int, u, level: int, d=None) -> Ct:
+        """mode 0: ModDown(u); 1: Rescale(ModDown(u)); 2: Rescale(d + ModDown(u)),
+        u over Q_level U P and d over Q_level in coefficient form, through the
+        device paths of the hot path."""
+        u = np.ascontiguousarray(u, dtype=np.uint64)
+        dd = None if d is None else np.ascontiguousarray(d, dtype=np.uint64)
+        out = self.new_ct(level if mode == 0 else level - 1)
+        _check(lib().fr_moddown_parity(self.ptr, mode, _u64(u), None if dd is None else _u64(dd), level, out.ref),
+               "fr_moddown_parity")
+        return out
 
     # allocation -------------------------------------------------------------
     def new_ct(self, cap: int) -> Ct:

@@ -216,6 +216,24 @@ def test_moddown_is_rounded_division_by_P(deep_ctx):
         assert got == want % Ql
 
 
+@pytest.mark.parametrize("which", ["small", "deep"])
+def test_moddown_rounds_exactly_next_to_half(small_ctx, deep_ctx, which):
+    """ModDown at residues U mod P = (P -+ 1)/2 (+- d) and across the
+    2^-40 band around P/2 (where an FP64 estimate of the overflow cannot
+    decide) equals round(U / P) computed on the integers, and the inputs do
+    reach coefficients where the FP64 rule would round the other way."""
+    import moddown_cases as mc
+    ctx = small_ctx if which == "small" else deep_ctx
+    level = ctx.L
+    u, Us, P = mc.build_u(ctx.moduli, level, ctx.L, ctx.nP, ctx.N, 1024, seed=11)
+    assert mc.fp64_rule_differs(u[0], ctx.moduli, level, ctx.L, ctx.nP) > 0
+    out = ctx.moddown(level, u[0])
+    for k in range(0, ctx.N, 3):
+        want = (2 * Us[0][k] + P) // (2 * P)
+        for i in range(level + 1):
+            assert int(out[i][k]) == want % ctx.q[i], (k, i)
+
+
 # --------------------------------------------------------------------------
 # encoding / decoding
 # --------------------------------------------------------------------------
@@ -245,6 +263,32 @@ def test_encode_matches_canonical_embedding(small_ctx):
     # decode (both methods) recovers the slots
     assert np.max(np.abs(ctx.decode(pt) - z)) < 1e-9
     assert np.max(np.abs(ctx.decode(pt, "direct") - z)) < 1e-9
+
+
+@pytest.mark.parametrize("logN", [12, 14])
+def test_decode_fft_matches_canonical_embedding(oracle_mod, logN):
+    """The FFT decoder (the oracle's choice for log N >= 14) against numpy's
+    polynomial evaluation at zeta^(5^j) and against the O(N^2) definition, on
+    an arbitrary integer polynomial (its slot values are not real, so a
+    wrong twist or conjugation shows in the real parts)."""
+    ctx = oracle_mod.Context(logN=logN, q0_bits=50, n_mid=2, mid_bits=40, n_special=1, special_bits=60, dnum=3)
+    N = ctx.N
+    rnd = np.random.default_rng(40 + logN)
+    m = [int(v) for v in rnd.integers(-2 ** 30, 2 ** 30, N)]
+    res = np.stack([[v % q for v in m] for q in ctx.q]).astype(np.uint64)
+    scale = 2.0 ** 30
+    pt = ctx.pt_import(res, ctx.L, scale)
+    got = ctx.decode(pt, "fft")
+    assert np.array_equal(ctx.decode(pt, "auto"), got) if logN >= 14 else True
+    js = np.sort(rnd.choice(N // 2, 256, replace=False))
+    # the roots zeta^(5^j), zeta = exp(i pi / N), with the exponent reduced
+    # exactly mod 2N before the angle is formed
+    pts = np.exp(1j * np.pi * np.array([pow(5, int(j), 2 * N) for j in js], dtype=np.float64) / N)
+    want = np.polynomial.polynomial.polyval(pts, np.array(m, dtype=np.float64)).real / scale
+    # Horner's error bound in FP64: about 2 N eps sum |m_k| (doubled for margin)
+    tol = 4 * N * np.finfo(np.float64).eps * float(np.sum(np.abs(np.array(m, dtype=np.float64)))) / scale
+    assert np.max(np.abs(got[js] - want)) < tol
+    assert np.max(np.abs(got - ctx.decode(pt, "direct"))) < tol
 
 
 def test_slot_order_rotation_by_sigma5(small_ctx):
