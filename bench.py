@@ -11,7 +11,9 @@ diagonals resident in HBM.  A step is
   16 rescales and the giant-step rotate-sum (n2 = 16),
   the degree-63 Chebyshev threshold at 0.3 on the score ciphertext.
 Inputs (query ciphertext, keys, diagonals) are resident in HBM before the
-timed region; the result ciphertext stays on the device.
+timed region; the result ciphertext stays on the device for `value`.  The
+host-side service time (the same step plus the download of the result
+ciphertext, one query at a time) is reported beside it.
 
 Prints one JSON line: scores/s (= 2^15 x steps / wall time), p50/p99 step
 latency, the roofline figure of the dominant kernel class measured with HIP
@@ -396,6 +398,132 @@ def diagonal_method(s, d1, steps=2):
             "score_max_abs_err": err}
 
 
+def service_time(s, d1, n):
+    """Host-side service time of one query at a time (start of the GPU work
+    until the score ciphertext is on the host): the step, then the download
+    of the Chebyshev output's words into pinned host memory, waited for."""
+    import torch
+    cheb = s["cheb"]
+    words = 2 * (cheb.level + 1) * s["ctx"].N
+    host = torch.empty(words, dtype=torch.int64, pin_memory=True)
+    stream = torch.cuda.current_stream()
+    lat = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        step(s, d1)
+        host.copy_(cheb.buf[:words], non_blocking=True)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()),
+            "queries": n, "bytes_downloaded": words * 8}
+
+
+def hook_roofline(s, d1, cls, name, steps=3):
+    """HBM roofline of one kernel class from the library's timing hook (HIP
+    events around every launch of the class on its stream; algorithmic
+    bytes of each launch) over `steps` extra steps."""
+    ctx = s["ctx"]
+    ctx.prof_begin(cls)
+    for _ in range(steps):
+        step(s, d1)
+    n, ms, b = ctx.prof_end()
+    if not n:
+        return None
+    avg = ms / n
+    gbs = b / n / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "launches_per_step": n / steps, "avg_launch_ms": avg,
+            "bytes_per_launch": b / n}
+
+
+def graph_form(s, d1, steps):
+    """The same step recorded once as a HIP graph (fr_graph_begin/end) and
+    replayed: before each replay one of two encrypted queries is copied into
+    the recorded input buffer, and the replay's result must equal the eager
+    step's words for that query."""
+    import torch
+    from paper_2604_00546_amd import synth
+    ctx, keys = s["ctx"], s["keys"]
+    q2 = ctx.encrypt(keys, ctx.encode(synth.replicate_query(synth.query_batch(3, 1, s["ell"])[0], ctx.N // 2),
+                                      ctx.L, 2.0 ** 40), synth.int_seed(3, synth.SUB_ENC, 77))
+    queries = [s["q"], q2]
+    # eager reference words of both queries
+    ref = []
+    for q in queries:
+        matvec_of(s, q, s["score"])
+        ctx.chebyshev_eval(keys, s["score"], s["coeffs"], d1, out=s["cheb"])
+        ref.append(ctx.ct_export(s["cheb"]))
+    inp = ctx.new_ct(ctx.L)
+    inp.buf.copy_(queries[0].buf)
+    inp.desc.level, inp.desc.scale = queries[0].level, queries[0].scale
+
+    def body():
+        matvec_of(s, inp, s["score"])
+        ctx.chebyshev_eval(keys, s["score"], s["coeffs"], d1, out=s["cheb"])
+
+    body()  # the arena at its full size before the recording
+    graph = ctx.capture(body)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        graph.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        inp.buf.copy_(queries[i % 2].buf)
+        graph.launch()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    last = (steps - 1) % 2
+    same = bool(np.array_equal(ctx.ct_export(s["cheb"]), ref[last]))
+    # host-side service time with the graph: copy in, replay, download, wait
+    words = 2 * (s["cheb"].level + 1) * ctx.N
+    host = torch.empty(words, dtype=torch.int64, pin_memory=True)
+    svc = []
+    for i in range(steps):
+        t1 = time.perf_counter()
+        inp.buf.copy_(queries[i % 2].buf)
+        graph.launch()
+        host.copy_(s["cheb"].buf[:words], non_blocking=True)
+        stream.synchronize()
+        svc.append((time.perf_counter() - t1) * 1e3)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    svc = np.array(svc)
+    step(s, d1)  # the bench query's own result back in score / cheb for the checks
+    torch.cuda.synchronize()
+    return {"steps": steps, "ms_per_step": wall * 1e3 / steps, "value": s["K"] * steps / wall, "unit": "scores/s",
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "service_ms": {"p50": float(np.percentile(svc, 50)), "p99": float(np.percentile(svc, 99)),
+                           "mean": float(svc.mean())},
+            "replays_equal_eager": same}
+
+
+def matvec_of(s, q, out):
+    ctx = s["ctx"]
+    if s["route"] == "hoisted":
+        ctx.bsgs_matvec_hoisted(s["keys"], q, s["db"], 0, out=out)
+    else:
+        baby = [q] + s["baby"][1:]
+        ctx.rotate_hoisted(s["keys"], q, range(1, s["n1"]), outs=s["baby"][1:])
+        ctx.bsgs_diag_matvec(s["keys"], baby, s["db"], 0, out=out)
+
+
+def autotune_step(s, args):
+    """Launch choices and the Chebyshev baby-step degree picked by the
+    project's autotuner on this workload's step (same words for every
+    choice)."""
+    from paper_2604_00546_amd import autotune
+    fr, ctx = s["fr"], s["ctx"]
+    rec = autotune.tune(ctx, lambda: step(s, args.d1), log=log)
+    d = autotune.tune_d1(fr, lambda d1: step(s, d1), len(s["coeffs"]) - 1, ctx.L - 1)
+    rec["d1"] = d
+    rec["trials"] = len(rec["trials"])
+    return rec
+
+
 def fewest_products_d1(fr, degree):
     """Baby-step degree with the fewest relinearised products (ties: smaller)."""
     counts = {d1: fr.cheb_mult_count(degree, d1) for d1 in range(2, degree + 2)}
@@ -416,11 +544,56 @@ def check(s):
             "identification_exact": bool(np.array_equal(found, wl.planted))}
 
 
-def cpu_baseline(s, d1):
-    """The CPU oracle, as it stands, on one full query of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _last10(ts):
+    """Mean and population std of the last 10 of 11 trials (the paper's
+    benchmarking methodology, §6.2), in ms."""
+    t = np.array(ts[1:]) * 1e3
+    return {"trials": len(ts), "mean_ms": float(t.mean()), "std_ms": float(t.std())}
+
+
+def oracle_small_pipeline(trials=11):
+    """The oracle's whole plain pipeline on the small workload (N = 2^12, 64
+    templates x 128-d, n1 = 8, n2 = 16, B = 16, no Chebyshev): encode,
+    encrypt, 7 hoisted rotations, BSGS matvec, decrypt, decode; `trials`
+    runs after key generation and diagonal encoding."""
+    from oracle import oracle as O
+    from paper_2604_00546_amd import synth
+    o = O.Context(**O.small_params())
+    rots = list(range(1, 8)) + [8 * j for j in range(1, 16)]
+    keys = o.keygen(synth.int_seed(1, synth.SUB_KEYS), rots)
+    wl = synth.make_workload(1, 64, 128)
+    db = o.db_build(wl.templates, wl.K, 128, 16, 8, o.L, 2.0 ** 40)
+    qv = synth.replicate_query(wl.query, o.N // 2)
+    ts = []
+    for t in range(trials):
+        t0 = time.perf_counter()
+        q = o.encrypt(keys, o.encode(qv, o.L, 2.0 ** 40), synth.int_seed(1, synth.SUB_ENC, t))
+        baby = [q] + o.rotate_hoisted(keys, q, range(1, 8))
+        o.decrypt_decode(keys, o.bsgs_matvec(keys, baby, db, 0))
+        ts.append(time.perf_counter() - t0)
+    return _last10(ts)
+
+
+def cpu_baseline(s, d1, trials=3, one_thread_query=False):
+    """The CPU oracle, as it stands, timed on the host cores: one full query
+    of the same 2^15 x 512 workload (`trials` runs, all threads), and the
+    small workload's whole pipeline (11 trials) on all threads and on one."""
     from oracle import oracle as O
     from paper_2604_00546_amd import synth
     fr = s["fr"]
+    threads = O.get_threads()
     o = O.Context(**O.paper_params())
     rots = fr.bsgs_rotation_set(s["ell"], s["n1"])
     keys = o.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
@@ -429,20 +602,40 @@ def cpu_baseline(s, d1):
     if s["route"] == "hoisted":
         db.extend()
     q = o.encrypt(keys, o.encode(synth.replicate_query(wl.query, o.N // 2), o.L, 2.0 ** 40), 5)
-    t0 = time.time()
-    if s["route"] == "hoisted":
-        S = o.bsgs_matvec_hoisted(keys, q, db, 0)
-    else:
-        baby = [q] + o.rotate_hoisted(keys, q, range(1, s["n1"]))
-        S = o.bsgs_matvec(keys, baby, db, 0)
-    o.chebyshev(keys, S, s["coeffs"], d1)
-    dt = time.time() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": s["K"] / dt, "unit": "scores/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full query (31 hoisted rotations, BSGS matvec over 512 diagonals, degree-63 "
-                      f"Chebyshev; route {s['route']}) of the same 2^15 x 512 workload; {dt:.1f} s wall on "
-                      f"{cores} OpenMP threads; key generation and diagonal encoding (with the special-prime "
-                      f"limbs) excluded as setup"}
+
+    def query():
+        t0 = time.perf_counter()
+        if s["route"] == "hoisted":
+            S = o.bsgs_matvec_hoisted(keys, q, db, 0)
+        else:
+            baby = [q] + o.rotate_hoisted(keys, q, range(1, s["n1"]))
+            S = o.bsgs_matvec(keys, baby, db, 0)
+        o.chebyshev(keys, S, s["coeffs"], d1)
+        return time.perf_counter() - t0
+
+    ts = [query() for _ in range(trials)]
+    dt = float(np.mean(ts))
+    out = {"value": s["K"] / dt, "unit": "scores/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"one full query (31 hoisted rotations, BSGS matvec over 512 diagonals, degree-63 "
+                     f"Chebyshev; route {s['route']}) of the same 2^15 x 512 workload, mean of {trials} runs "
+                     f"({dt:.2f} s wall, std {float(np.std(ts)):.2f} s) on {threads} OpenMP threads; key "
+                     f"generation and diagonal encoding (with the special-prime limbs) excluded as setup",
+           "query_s": [float(t) for t in ts]}
+    log(f"oracle query: {dt:.2f} s on {threads} threads; small pipeline, 11 trials ...")
+    out["small_pipeline"] = {"workload": "N=2^12, 64 templates x 128-d, n1=8 n2=16 B=16, encode to decode",
+                             f"{threads}_threads": oracle_small_pipeline()}
+    O.set_threads(1)
+    try:
+        out["small_pipeline"]["1_thread"] = oracle_small_pipeline()
+        if one_thread_query:
+            log("oracle query on one thread ...")
+            t1 = query()
+            out["one_thread_query_s"] = t1
+            out["one_thread_scores_per_s"] = s["K"] / t1
+    finally:
+        O.set_threads(threads)
+    return out
 
 
 def main():
@@ -453,6 +646,8 @@ def main():
     ap.add_argument("--d1", type=int, default=None,
                     help="Chebyshev baby-step degree (default: the one with the fewest relinearised products)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-thread-query", action="store_true",
+                    help="also time the oracle's full 2^15 query on one thread (minutes)")
     ap.add_argument("--mix", type=int, default=0,
                     help="also run this many batches of 1..64 queries against databases of 2^10..2^15 "
                          "templates, batched and as a plain loop")
@@ -472,6 +667,9 @@ def main():
                     help="hoisted: baby steps held over Q_l U P, one ModDown per inner sum (fr_bsgs_matvec_hoisted); "
                          "single: hoisted rotations, each with its ModDown, then the product")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch choices and "
+                    "the fewest-products Chebyshev degree")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay form")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, one device-to-device copy of this many MiB (the known-size "
                          "reference for the HBM byte counters)")
@@ -489,6 +687,14 @@ def main():
         step(s, args.d1)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
+    tuned = None
+    if not args.no_autotune:
+        tuned = autotune_step(s, args)
+        args.d1 = tuned["d1"]["d1"]
+        log(f"autotuned: {tuned['choices']}, d1 = {args.d1}")
+        for _ in range(args.warmup):
+            step(s, args.d1)
+        torch.cuda.synchronize()
     if args.calib_copy_mib:
         # known-size device copy just before the timed steps: the reference
         # for the HBM byte counters and the marker that opens the timed
@@ -561,6 +767,14 @@ def main():
                                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                                "launches": n_launch, "avg_launch_ms": avg_ms,
                                "bytes_per_launch": k_bytes / n_launch}
+    out["service_ms"] = service_time(s, args.d1, args.steps)
+    if tuned is not None:
+        out["autotune"] = tuned
+    if not args.no_graph:
+        log("graph form ...")
+        out["graph"] = graph_form(s, args.d1, args.steps)
+    out["roofline_ks"] = hook_roofline(s, args.d1, "ks_inner", "key-switch inner product (k_ks_inner, k_ks_inner_sum)")
+    out["roofline_mac"] = hook_roofline(s, args.d1, "mac", "plaintext-diagonal MAC (k_bsgs_mac3)")
     if args.breakdown:
         ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev3[0].record(stream)
@@ -601,7 +815,7 @@ def main():
         out["mixed_batches"] = mixed_batches(s, args.mix, args.d1)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one query ...")
-        out["cpu_baseline"] = cpu_baseline(s, args.d1)
+        out["cpu_baseline"] = cpu_baseline(s, args.d1, one_thread_query=args.cpu_one_thread_query)
     print(json.dumps(out), flush=True)
 
 

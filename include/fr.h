@@ -23,7 +23,10 @@
  *   fr_ct_export / fr_pt_export for canonical coefficients.
  * - Keys and databases are LIBRARY-OWNED device objects (opaque handles),
  *   created by fr_keygen / fr_db_load / fr_db_import and freed by the
- *   matching destroy call.
+ *   matching destroy call.  They serve every context of the same parameter
+ *   set on the same device (several contexts, each with its own stream and
+ *   scratch, may use them at once; FR_EINVAL for another parameter set);
+ *   they must outlive the work that uses them.
  * - Every device call is asynchronous on the context's stream (set with
  *   fr_ctx_set_stream; default: the null stream).  Calls that return data
  *   to the host (exports, fr_decode) synchronise that stream.  Inputs are
@@ -109,6 +112,32 @@ int fr_ctx_sync(fr_ctx *ctx);
 int fr_ctx_set_scratch_limit(fr_ctx *ctx, uint64_t bytes);
 int fr_ctx_scratch_info(const fr_ctx *ctx, uint64_t *allocated, uint64_t *peak);
 int fr_ctx_reserve(fr_ctx *ctx, uint64_t bytes);
+/* Tuning knobs.  The project's autotuner sets them from measurements; every
+ * value gives the same output words, only the kernel choice and the work per
+ * launch change.
+ * - FR_TUNE_NTT_{FWD_COLS4, FWD_ROWS4, INV_ROWS4, INV_COLS4}: the largest NTT
+ *   launch (in limb polynomials) whose column / row pass at N = 2^16 takes 4
+ *   words per thread in rounds of 2 stages (more threads, shorter chains)
+ *   instead of 16 words per thread in rounds of 4 stages; 0 = never.
+ * - FR_TUNE_MODUP_MERGE: inputs x digits up to which a ModUp runs as one
+ *   conversion launch and one transform over every extended limb.
+ * - FR_TUNE_MATVEC_CHUNK (1..16): queries per chunk of the batched products.
+ * - FR_TUNE_CHEB_CHUNK (1..16): queries per pass of the batched Chebyshev
+ *   evaluation.
+ * FR_EINVAL for an unknown knob or a value out of range, and while a graph
+ * capture is in progress. */
+enum {
+    FR_TUNE_NTT_FWD_COLS4 = 0,
+    FR_TUNE_NTT_FWD_ROWS4 = 1,
+    FR_TUNE_NTT_INV_ROWS4 = 2,
+    FR_TUNE_NTT_INV_COLS4 = 3,
+    FR_TUNE_MODUP_MERGE = 4,
+    FR_TUNE_MATVEC_CHUNK = 5,
+    FR_TUNE_CHEB_CHUNK = 6,
+    FR_TUNE_COUNT = 7
+};
+int fr_ctx_set_tune(fr_ctx *ctx, int32_t knob, int32_t value);
+int fr_ctx_get_tune(const fr_ctx *ctx, int32_t knob, int32_t *value);
 /* N, L, nP, alpha, dnum */
 int fr_ctx_dims(const fr_ctx *ctx, int32_t *n, int32_t *L, int32_t *n_special, int32_t *alpha,
                 int32_t *dnum);
@@ -275,6 +304,30 @@ int fr_tensor_sum_relin_rescale(fr_ctx *ctx, const fr_keys *keys, const fr_ct *a
  * keys 2^i, i < log2(N/2) (FR_ENOKEY otherwise).  out must not alias any
  * input; out->level = in[0].level. */
 int fr_membership_aggregate(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t n, fr_ct *out);
+
+/* ---- captured call sequences (HIP graphs; the per-query launch sequence of
+ * Alg. gpu-bsgs-index replayed as one graph) ----
+ * fr_graph_begin: the device calls made on ctx until fr_graph_end are
+ *   recorded, not run (stream capture of a private stream of the context and
+ *   of its auxiliary streams; the caller's stream is waited for first).
+ *   Only calls that need no host result may be recorded: rotations, the
+ *   products, rescale, add/sub, the Chebyshev evaluation, membership
+ *   aggregation, encryption.  A call that synchronises (exports, imports,
+ *   decode, key or database setup, the timing hook) makes fr_graph_end fail.
+ * fr_graph_end: ends the recording and instantiates the graph (*out, freed
+ *   with fr_graph_destroy).  FR_EHIP if the capture was broken.
+ * fr_graph_launch: replays the graph on the context's stream.  The kernels
+ *   read and write the device addresses of the recording: the callers'
+ *   buffers and the context's scratch, so new data is given by writing it
+ *   into the recorded input buffers before the launch.  Replays and other
+ *   calls of the context are ordered on its stream.  FR_EINVAL if the
+ *   context's scratch was released since the recording
+ *   (fr_ctx_set_scratch_limit below the allocation). */
+typedef struct fr_graph fr_graph;
+int fr_graph_begin(fr_ctx *ctx);
+int fr_graph_end(fr_ctx *ctx, fr_graph **out);
+int fr_graph_launch(fr_ctx *ctx, const fr_graph *graph);
+void fr_graph_destroy(fr_graph *graph);
 
 /* ---- parity hook: ModDown on caller-given residues (hybrid key switching
  * of §3.4.2; the rescale of §3.2) ----

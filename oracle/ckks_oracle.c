@@ -16,6 +16,7 @@
 
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1715,3 +1716,9 @@ int or_chebyshev_count_mults(int n, int d1) {
     free(have);
     return nm;
 }
+
+/* ------------------------------------------------------------------------ */
+/* threads (for timing the oracle at a stated core count)                     */
+/* ------------------------------------------------------------------------ */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }

@@ -51,6 +51,9 @@ int or_ctx_nspecial(const or_ctx *ctx);
 int or_ctx_alpha(const or_ctx *ctx);
 uint64_t or_ctx_modulus(const or_ctx *ctx, int gidx);
 const char *or_last_error(void);
+/* OpenMP threads of the parallel loops (timing at a stated core count) */
+void or_set_threads(int n);
+int or_get_threads(void);
 
 /* ---- randomness: Philox-4x64-10 and the three samplers ---- */
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

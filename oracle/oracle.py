@@ -52,6 +52,8 @@ def lib():
         "or_ctx_alpha": (C.c_int, [_P]),
         "or_ctx_modulus": (C.c_uint64, [_P, C.c_int]),
         "or_last_error": (C.c_char_p, []),
+        "or_set_threads": (None, [C.c_int]),
+        "or_get_threads": (C.c_int, []),
         "or_philox4x64_10": (None, [_U64P, _U64P, _U64P]),
         "or_gauss_cdt": (None, [_U64P]),
         "or_sample_uniform": (None, [C.c_uint64, C.c_uint64, C.c_int, C.c_uint64, C.c_int, _U64P]),
@@ -489,6 +491,15 @@ class Context:
 
 
 # parameter sets of the two ring sizes the tests and the benchmark use
+def set_threads(n: int):
+    """OpenMP threads the oracle's parallel loops use from now on."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
+
+
 def small_params():
     """N = 2^12; Q = one 50-bit + two 40-bit primes; P = one 60-bit prime; dnum 3."""
     return dict(logN=12, q0_bits=50, n_mid=2, mid_bits=40, n_special=1, special_bits=60, dnum=3)

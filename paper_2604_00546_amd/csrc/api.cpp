@@ -170,6 +170,30 @@ int check_out(const fr_ctx *c, const fr_ct *x, int level, const char *what) {
     return FR_OK;
 }
 
+// keys and databases serve every context of their parameter set on the
+// device (several contexts, each on its own stream, can share them)
+bool same_params(const fr_ctx *a, const fr_ctx *b) {
+    return a == b || (a->N == b->N && a->L == b->L && a->nP == b->nP && a->dnum == b->dnum &&
+                      std::memcmp(a->mod, b->mod, sizeof(u64) * a->nmod) == 0);
+}
+int keys_ok(const fr_ctx *c, const fr_keys *K, const char *what) {
+    CHECK(c && K, FR_EINVAL, "%s: null argument", what);
+    CHECK(same_params(c, K->ctx), FR_EINVAL, "%s: keys of another parameter set", what);
+    return FR_OK;
+}
+int db_ok(const fr_ctx *c, const fr_db *db, const char *what) {
+    CHECK(c && db, FR_EINVAL, "%s: null argument", what);
+    CHECK(same_params(c, db->ctx), FR_EINVAL, "%s: database of another parameter set", what);
+    return FR_OK;
+}
+
+// calls that wait for the device or move data to or from the host cannot be
+// recorded into a graph: refused while a capture is in progress
+int no_capture(const fr_ctx *c, const char *what) {
+    CHECK(!c->capturing, FR_EINVAL, "%s: not allowed while a graph capture is in progress", what);
+    return FR_OK;
+}
+
 int flag_check(fr_ctx *c, const char *what) {
     int h = 0;
     FR_HIP(hipMemcpyAsync(&h, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -187,16 +211,15 @@ int flag_check(fr_ctx *c, const char *what) {
 // D[b][t] (b < batch, t < ndig) = ModUp of digit t of c1[b] (eval domain,
 // c1 polynomials c1_stride words apart) over Q_level U P; D items are
 // ndig * nE * N words apart.
-// items x digits up to which ModUp runs as one conversion launch and one
-// transform over all extended limbs
-static const int kModupMerge = 12;
 
 void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t c1_stride = 0) {
     const int N = c->N, nE = level + 1 + c->nP, ndig = num_digits(c, level);
     const size_t lw = (size_t)(level + 1) * N, dstride = (size_t)ndig * nE * N;
     u64 *X = scratch(c, (size_t)batch * lw);
     frk::ntt_inv(c, X, level + 1, qmap(), batch, lw, c1, c1_stride);
-    if (batch * ndig <= kModupMerge) {
+    // items x digits up to which ModUp runs as one conversion launch and one
+    // transform over all extended limbs (a tuning knob)
+    if (batch * ndig <= c->tune[FR_TUNE_MODUP_MERGE]) {
         // small batches: every digit in one conversion launch and one
         // transform; the conversion copies each digit's own limbs in
         // evaluation form and the transform leaves them alone (where the
@@ -642,6 +665,7 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
     for (int a = 0; a < fr_ctx::kAux; ++a)
         if (c->ev_join[a]) (void)hipEventDestroy(c->ev_join[a]);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (int i = 0; i < fr_ctx::kDagEv; ++i)
         if (c->ev_dag[i]) (void)hipEventDestroy(c->ev_dag[i]);
     if (c->prof) {
@@ -653,12 +677,14 @@ extern "C" void fr_ctx_destroy(fr_ctx *c) {
 
 extern "C" int fr_ctx_set_stream(fr_ctx *c, void *stream) try {
     CHECK(c, FR_EINVAL, "null context");
+    CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_stream: a graph capture is in progress");
     if (c->stream != (hipStream_t)stream) FR_HIP(hipStreamSynchronize(c->stream));
     c->stream = (hipStream_t)stream;
     return FR_OK;
 } FR_CATCH(c)
 
 extern "C" int fr_ctx_sync(fr_ctx *c) try {
+    if (c) if (int e_ = no_capture(c, "fr_ctx_sync")) return e_;
     CHECK(c, FR_EINVAL, "null context");
     FR_HIP(hipStreamSynchronize(c->stream));
     return FR_OK;
@@ -668,12 +694,33 @@ extern "C" int fr_ctx_set_scratch_limit(fr_ctx *c, uint64_t bytes) try {
     CHECK(c, FR_EINVAL, "null context");
     c->arena.limit = bytes ? (size_t)bytes : ~(size_t)0;
     if (c->arena.allocated() > c->arena.limit) {
+        CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_scratch_limit: a graph capture is in progress");
         FR_HIP(hipStreamSynchronize(c->stream));
         for (auto &a : c->aux) FR_HIP(hipStreamSynchronize(a));
         c->arena.release();
+        ++c->arena_gen;
     }
     return FR_OK;
 } FR_CATCH(c)
+
+extern "C" int fr_ctx_set_tune(fr_ctx *c, int32_t knob, int32_t value) {
+    CHECK(c, FR_EINVAL, "null context");
+    CHECK(knob >= 0 && knob < FR_TUNE_COUNT, FR_EINVAL, "fr_ctx_set_tune: unknown knob %d", knob);
+    static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1};
+    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16};
+    CHECK(value >= lo[knob] && value <= hi[knob], FR_EINVAL, "fr_ctx_set_tune: knob %d takes %d..%d, not %d", knob,
+          lo[knob], hi[knob], value);
+    CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_tune: a graph capture is in progress");
+    c->tune[knob] = value;
+    return FR_OK;
+}
+
+extern "C" int fr_ctx_get_tune(const fr_ctx *c, int32_t knob, int32_t *value) {
+    CHECK(c && value, FR_EINVAL, "fr_ctx_get_tune: null argument");
+    CHECK(knob >= 0 && knob < FR_TUNE_COUNT, FR_EINVAL, "fr_ctx_get_tune: unknown knob %d", knob);
+    *value = c->tune[knob];
+    return FR_OK;
+}
 
 extern "C" int fr_ctx_scratch_info(const fr_ctx *c, uint64_t *allocated, uint64_t *peak) {
     CHECK(c, FR_EINVAL, "null context");
@@ -683,6 +730,7 @@ extern "C" int fr_ctx_scratch_info(const fr_ctx *c, uint64_t *allocated, uint64_
 }
 
 extern "C" int fr_ctx_reserve(fr_ctx *c, uint64_t bytes) try {
+    if (c) if (int e_ = no_capture(c, "fr_ctx_reserve")) return e_;
     CHECK(c, FR_EINVAL, "null context");
     const size_t have = c->arena.allocated();
     if (have >= bytes) return FR_OK;
@@ -718,6 +766,7 @@ extern "C" void fr_keys_destroy(fr_keys *k) {
 }
 
 extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t nrot, fr_keys **out) try {
+    if (c) if (int e_ = no_capture(c, "fr_keygen")) return e_;
     CHECK(c && out && (nrot == 0 || rots), FR_EINVAL, "fr_keygen: null argument");
     c->arena.reset();
     Scope sc(c->arena);
@@ -778,6 +827,8 @@ extern "C" int fr_keygen(fr_ctx *c, uint64_t seed, const int32_t *rots, int32_t 
 } FR_CATCH(c)
 
 extern "C" int fr_keys_export(fr_ctx *c, const fr_keys *K, int32_t what, uint64_t kid, uint64_t *host) try {
+    if (int e = keys_ok(c, K, "fr_keys_export")) return e;
+    if (c) if (int e_ = no_capture(c, "fr_keys_export")) return e_;
     CHECK(c && K && host, FR_EINVAL, "fr_keys_export: null argument");
     c->arena.reset();
     Scope sc(c->arena);
@@ -834,6 +885,7 @@ static int encode_common(fr_ctx *c, const double *zdev, int n, int level, double
 }
 
 extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) try {
+    if (c) if (int e_ = no_capture(c, "fr_encode")) return e_;
     CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
           "fr_encode: bad size or level");
@@ -847,6 +899,7 @@ extern "C" int fr_encode(fr_ctx *c, const double *z, int32_t n, int32_t level, d
 } FR_CATCH(c)
 
 extern "C" int fr_encode_device(fr_ctx *c, const double *z, int32_t n, int32_t level, double scale, fr_pt *out) try {
+    if (c) if (int e_ = no_capture(c, "fr_encode_device")) return e_;
     CHECK(c && out && out->data && (n == 0 || z), FR_EINVAL, "fr_encode_device: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL,
           "fr_encode_device: bad size or level");
@@ -884,6 +937,7 @@ static int export_poly(fr_ctx *c, const u64 *src, int nl, int npoly, uint64_t *h
 }
 
 extern "C" int fr_pt_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_pt *out) try {
+    if (c) if (int e_ = no_capture(c, "fr_pt_import")) return e_;
     CHECK(c && host && out && out->data, FR_EINVAL, "fr_pt_import: null argument");
     CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_pt_import: bad level");
     if (int e = import_poly(c, host, level + 1, 1, out->data)) return e;
@@ -893,12 +947,14 @@ extern "C" int fr_pt_import(fr_ctx *c, const uint64_t *host, int32_t level, doub
 } FR_CATCH(c)
 
 extern "C" int fr_pt_export(fr_ctx *c, const fr_pt *p, uint64_t *host) try {
+    if (c) if (int e_ = no_capture(c, "fr_pt_export")) return e_;
     CHECK(c && p && p->data && host, FR_EINVAL, "fr_pt_export: null argument");
     CHECK(p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_pt_export: bad level");
     return export_poly(c, p->data, p->level + 1, 1, host);
 } FR_CATCH(c)
 
 extern "C" int fr_ct_import(fr_ctx *c, const uint64_t *host, int32_t level, double scale, fr_ct *out) try {
+    if (c) if (int e_ = no_capture(c, "fr_ct_import")) return e_;
     CHECK(c && host && out && out->data, FR_EINVAL, "fr_ct_import: null argument");
     CHECK(level >= 0 && level <= c->L && level <= out->cap, FR_EINVAL, "fr_ct_import: bad level");
     if (int e = import_poly(c, host, level + 1, 2, out->data)) return e;
@@ -908,12 +964,14 @@ extern "C" int fr_ct_import(fr_ctx *c, const uint64_t *host, int32_t level, doub
 } FR_CATCH(c)
 
 extern "C" int fr_ct_export(fr_ctx *c, const fr_ct *x, uint64_t *host) try {
+    if (c) if (int e_ = no_capture(c, "fr_ct_export")) return e_;
     CHECK(c && host, FR_EINVAL, "fr_ct_export: null argument");
     if (int e = check_ct(c, x, "fr_ct_export")) return e;
     return export_poly(c, x->data, x->level + 1, 2, host);
 } FR_CATCH(c)
 
 extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t seed, fr_ct *out) try {
+    if (int e = keys_ok(c, K, "fr_encrypt")) return e;
     CHECK(c && K && p && p->data, FR_EINVAL, "fr_encrypt: null argument");
     const int l = p->level;
     CHECK(l >= 0 && l <= c->L, FR_EINVAL, "fr_encrypt: bad plaintext level");
@@ -937,6 +995,7 @@ extern "C" int fr_encrypt(fr_ctx *c, const fr_keys *K, const fr_pt *p, uint64_t 
 } FR_CATCH(c)
 
 extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *out) try {
+    if (int e = keys_ok(c, K, "fr_decrypt")) return e;
     CHECK(c && K && out && out->data, FR_EINVAL, "fr_decrypt: null argument");
     if (int e = check_ct(c, x, "fr_decrypt")) return e;
     CHECK(x->level <= out->cap, FR_EINVAL, "fr_decrypt: output capacity");
@@ -949,6 +1008,7 @@ extern "C" int fr_decrypt(fr_ctx *c, const fr_keys *K, const fr_ct *x, fr_pt *ou
 } FR_CATCH(c)
 
 extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) try {
+    if (c) if (int e_ = no_capture(c, "fr_decode")) return e_;
     CHECK(c && p && p->data && z, FR_EINVAL, "fr_decode: null argument");
     CHECK(n >= 0 && n <= c->N / 2 && p->level >= 0 && p->level <= c->L, FR_EINVAL, "fr_decode: bad size or level");
     c->arena.reset();
@@ -972,12 +1032,28 @@ extern "C" int fr_decode(fr_ctx *c, const fr_pt *p, double *z, int32_t n) try {
 // scratch bytes one batched step may take before it is split into chunks
 static const size_t kChunkBytes = (size_t)2 << 30;
 
+static size_t arena_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+// scratch of the hoisted rotations of nq inputs at `level`: before the
+// rotation chunks (the staged c1 parts, the coefficient-form c1, the ModUp
+// digits), and per rotation of a chunk (the key inner products U, the ModDown
+// correction V, the P limbs of U in coefficient form)
+static size_t rotation_base_bytes(const fr_ctx *c, int level, int nq) {
+    const size_t N = c->N, lw = (size_t)(level + 1) * N, nE = level + 1 + c->nP;
+    const size_t stage = nq > 1 ? arena_round((size_t)nq * lw * 8) : 0;
+    return stage + arena_round((size_t)nq * lw * 8) + arena_round((size_t)nq * num_digits(c, level) * nE * N * 8);
+}
+static size_t rotation_scratch_bytes(const fr_ctx *c, int level, int nq) {
+    const size_t N = c->N, lw = (size_t)(level + 1) * N, nE = level + 1 + c->nP;
+    return (size_t)nq * (2 * nE * N + 2 * lw + 2 * c->nP * N) * 8;
+}
+
 // Hoisted rotations of nq ciphertexts (same level): outs[q * nrot + r] =
 // Rot_{rots[r]}(in[q]).  ModUp of every c1 once, then per rotation the key
 // inner product of all queries (one read of the key feeds every query), one
 // batched ModDown preparation per chunk of rotations, and the fused finish.
 static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const int32_t *rots, int nrot,
-                               fr_ct *outs) {
+                               fr_ct *outs, size_t chunk_bytes = kChunkBytes) {
+    if (int e = keys_ok(c, K, "fr_rotate_hoisted")) return e;
     const int N = c->N, l = in[0].level, nE = l + 1 + c->nP;
     const size_t lw = (size_t)(l + 1) * N;
     for (int q = 0; q < nq; ++q) {
@@ -1013,8 +1089,9 @@ static int rotate_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int
         }
         u64 *D = scratch(c, (size_t)nq * dstride);
         ks_modup(c, c1, l, D, nq, lw);
-        const size_t per_rot = (size_t)nq * (2 * nE * N + 2 * lw) * 8;
-        const int rc = (int)std::max<size_t>(1, std::min<size_t>(nl, kChunkBytes / per_rot));
+        // per rotation of a chunk: U, V and the ModDown's P limbs
+        const size_t per_rot = rotation_scratch_bytes(c, l, nq);
+        const int rc = (int)std::max<size_t>(1, std::min<size_t>(nl, chunk_bytes / per_rot));
         std::vector<u64 *> op(nq);
         std::vector<const u64 *> ip(nq);
         for (int q = 0; q < nq; ++q) ip[q] = in[q].data;
@@ -1099,6 +1176,7 @@ extern "C" int fr_sub(fr_ctx *c, const fr_ct *a, const fr_ct *b, fr_ct *out) { r
 // degree-2 sum relinearised once.
 extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, int32_t n,
                                            fr_ct *out) try {
+    if (int e = keys_ok(c, K, "fr_tensor_sum_relin_rescale")) return e;
     CHECK(c && K && a && b && out && n >= 1, FR_EINVAL, "fr_tensor_sum_relin_rescale: null argument or no pair");
     const int l = a[0].level;
     for (int k = 0; k < n; ++k) {
@@ -1138,6 +1216,7 @@ extern "C" int fr_tensor_sum_relin_rescale(fr_ctx *c, const fr_keys *K, const fr
 // receives the sum of all N/2 slots through log2(N/2) doublings
 // x <- x + Rot_{2^i}(x), each one key switch.
 extern "C" int fr_membership_aggregate(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t n, fr_ct *out) try {
+    if (int e = keys_ok(c, K, "fr_membership_aggregate")) return e;
     CHECK(c && K && in && out && n >= 1, FR_EINVAL, "fr_membership_aggregate: null argument or no input");
     const int l = in[0].level;
     for (int i = 0; i < n; ++i) {
@@ -1186,6 +1265,7 @@ extern "C" int fr_mul_plain(fr_ctx *c, const fr_ct *a, const fr_pt *p, fr_ct *ou
 } FR_CATCH(c)
 
 extern "C" int fr_mul_relin_rescale(fr_ctx *c, const fr_keys *K, const fr_ct *a, const fr_ct *b, fr_ct *out) try {
+    if (int e = keys_ok(c, K, "fr_mul_relin_rescale")) return e;
     CHECK(c && K, FR_EINVAL, "null argument");
     if (int e = check_ct(c, a, "fr_mul_relin_rescale")) return e;
     if (int e = check_ct(c, b, "fr_mul_relin_rescale")) return e;
@@ -1288,6 +1368,7 @@ static int db_alloc(fr_ctx *c, int G, int ell, int B, int n1, int level, double 
 
 extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int32_t B, int32_t n1, int32_t level,
                           double scale, fr_db **out) try {
+    if (c) if (int e_ = no_capture(c, "fr_db_load")) return e_;
     CHECK(c && out && (K == 0 || T), FR_EINVAL, "fr_db_load: null argument");
     const int h = c->N / 2;
     CHECK(K >= 0 && ell > 0 && B > 0 && (long long)B * ell <= h && n1 > 0 && n1 <= ell && level >= 0 &&
@@ -1325,6 +1406,7 @@ extern "C" int fr_db_load(fr_ctx *c, const float *T, int32_t K, int32_t ell, int
 
 extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t ell, int32_t B, int32_t n1,
                             int32_t level, double scale, fr_db **out) try {
+    if (c) if (int e_ = no_capture(c, "fr_db_import")) return e_;
     CHECK(c && host && out, FR_EINVAL, "fr_db_import: null argument");
     CHECK(G >= 1 && ell > 0 && B > 0 && (long long)B * ell <= c->N / 2 && n1 > 0 && n1 <= ell && level >= 0 &&
               level <= c->L,
@@ -1350,6 +1432,8 @@ extern "C" int fr_db_import(fr_ctx *c, const uint64_t *host, int32_t G, int32_t 
 } FR_CATCH(c)
 
 extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, uint64_t *host) try {
+    if (int e = db_ok(c, db, "fr_db_export")) return e;
+    if (c) if (int e_ = no_capture(c, "fr_db_export")) return e_;
     CHECK(c && db && host, FR_EINVAL, "fr_db_export: null argument");
     CHECK(g >= 0 && g < db->G && d >= 0 && d < db->ell, FR_EINVAL, "fr_db_export: bad index");
     c->arena.reset();
@@ -1371,11 +1455,10 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
 // BSGS-Diagonal products of nq queries, query q against group groups[q] of
 // dbs[q] (every database with the same ell, n1 and level): baby[q * n1 + i]
 // is baby step i of query q, out[q] its score ciphertext.  Queries are
-// ordered by diagonal group and run in chunks of up to kMatvecChunk: one
+// ordered by diagonal group and run in chunks of up to the matvec chunk knob: one
 // read of every diagonal per chunk and group (the MAC), the n2 rescales of
 // every query in one batch, one ModUp batch of all giant-step inputs, per
 // giant step one key read for the whole chunk, and one ModDown per query.
-static const int kMatvecChunk = 8;
 
 // Giant steps of qn queries from their rescaled inner sums R =
 // [qn][n2][2][l+1][N]: out[q] = R_{q,0} + sum_j Rot_{j n1}(R_{q,j}), every
@@ -1424,10 +1507,11 @@ static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2
 
 static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, int n1, const fr_db *const *dbs,
                        const int32_t *groups, fr_ct *out) {
+    if (int e = keys_ok(c, K, "fr_bsgs_diag_matvec")) return e;
     const fr_db *db0 = dbs[0];
     for (int q = 0; q < nq; ++q) {
         const fr_db *db = dbs[q];
-        CHECK(db, FR_EINVAL, "fr_bsgs_diag_matvec: null database");
+        if (int e = db_ok(c, db, "fr_bsgs_diag_matvec")) return e;
         CHECK(n1 == db->n1, FR_EINVAL, "fr_bsgs_diag_matvec: n1 %d differs from the database's %d", n1, db->n1);
         CHECK(groups[q] >= 0 && groups[q] < db->G, FR_EINVAL, "fr_bsgs_diag_matvec: group %d out of range",
               groups[q]);
@@ -1455,9 +1539,10 @@ static int matvec_impl(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int nq, i
     std::vector<int> order(nq);
     for (int q = 0; q < nq; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
-    for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
+    const int chunk = c->tune[FR_TUNE_MATVEC_CHUNK];
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
         Scope sc(c->arena);
-        const int qn = std::min(kMatvecChunk, nq - q0);
+        const int qn = std::min(chunk, nq - q0);
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
         u64 *R = scratch(c, (size_t)qn * n2 * rw);
         std::vector<const u64 *> bp((size_t)qn * n1);
@@ -1502,6 +1587,7 @@ extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_c
 // Appends to every diagonal its residues mod the special primes, those of
 // the plaintext's centered integer coefficients (exact mixed-radix lift).
 extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) try {
+    if (c) if (int e_ = no_capture(c, "fr_db_extend")) return e_;
     CHECK(c && db, FR_EINVAL, "fr_db_extend: null argument");
     CHECK(db->ctx == c, FR_EINVAL, "fr_db_extend: database of another context");
     const int N = c->N, l = db->level, L1 = l + 1, nP = c->nP, nE = L1 + nP;
@@ -1580,12 +1666,13 @@ static void moddown_rescale(fr_ctx *c, const u64 *U, int np, int l, u64 *out) {
 // ModDown + rescale per inner sum, then the giant steps.
 static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int nq, const fr_db *const *dbs,
                                const int32_t *groups, fr_ct *out) {
+    if (int e = keys_ok(c, K, "fr_bsgs_matvec_hoisted")) return e;
     const fr_db *db0 = dbs[0];
     CHECK(db0, FR_EINVAL, "fr_bsgs_matvec_hoisted: null database");
     const int N = c->N, l = db0->level, L1 = l + 1, nE = L1 + c->nP, n1 = db0->n1, ell = db0->ell;
     for (int q = 0; q < nq; ++q) {
         const fr_db *db = dbs[q];
-        CHECK(db, FR_EINVAL, "fr_bsgs_matvec_hoisted: null database");
+        if (int e = db_ok(c, db, "fr_bsgs_matvec_hoisted")) return e;
         CHECK(db->nl == db->level + 1 + c->nP, FR_EINVAL,
               "fr_bsgs_matvec_hoisted: database not extended to the special primes (fr_db_extend)");
         CHECK(db->ell == ell && db->level == l && db->n1 == n1, FR_EINVAL,
@@ -1615,9 +1702,10 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
     std::vector<int> order(nq);
     for (int q = 0; q < nq; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag_of(a) < diag_of(b); });
-    for (int q0 = 0; q0 < nq; q0 += kMatvecChunk) {
+    const int chunk = c->tune[FR_TUNE_MATVEC_CHUNK];
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
         Scope sc(c->arena);
-        const int qn = std::min(kMatvecChunk, nq - q0);
+        const int qn = std::min(chunk, nq - q0);
         // the chunk's queries staged contiguously: [qn][2][l+1][N] (read
         // only; a single query is read in place)
         u64 *C = qn == 1 ? qs[order[q0]].data : scratch(c, (size_t)qn * 2 * lw);
@@ -1680,6 +1768,7 @@ extern "C" int fr_bsgs_matvec_hoisted_batch(fr_ctx *c, const fr_keys *K, const f
 // ---------------------------------------------------------------------------
 extern "C" int fr_moddown_parity(fr_ctx *c, int32_t mode, const uint64_t *u_host, const uint64_t *d_host,
                                  int32_t level, fr_ct *out) try {
+    if (c) if (int e_ = no_capture(c, "fr_moddown_parity")) return e_;
     CHECK(c && u_host && out, FR_EINVAL, "fr_moddown_parity: null argument");
     CHECK(mode >= 0 && mode <= 2, FR_EINVAL, "fr_moddown_parity: unknown mode %d", mode);
     CHECK(mode != 2 || d_host, FR_EINVAL, "fr_moddown_parity: mode 2 needs d");
@@ -2161,12 +2250,10 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
     return FR_OK;
 }
 
-// queries per Chebyshev pass (bounds the arena: every node output of the
-// pass stays live until the pass ends)
-static const int kChebChunk = 8;
 
 int chebyshev_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const double *cf, int degree, int d1,
                    fr_ct *out) {
+    if (int e = keys_ok(c, K, "fr_chebyshev_eval")) return e;
     CHECK(degree >= 1 && d1 >= 2, FR_EINVAL, "fr_chebyshev_eval: need degree >= 1 and d1 >= 2");
     for (int q = 0; q < nq; ++q) {
         if (int e = check_ct(c, &in[q], "fr_chebyshev_eval")) return e;
@@ -2184,8 +2271,11 @@ int chebyshev_impl(fr_ctx *c, const fr_keys *K, const fr_ct *in, int nq, const d
     D[in[0].level] = in[0].scale;
     for (int l = in[0].level; l >= 1; --l) D[l - 1] = (D[l] * D[l]) / (double)c->mod[l];
     const size_t ow = (size_t)2 * (ol + 1) * c->N;
-    for (int q0 = 0; q0 < nq; q0 += kChebChunk) {
-        const int qn = std::min(kChebChunk, nq - q0);
+    // queries per pass (bounds the arena: every node output of the pass
+    // stays live until the pass ends)
+    const int chunk = c->tune[FR_TUNE_CHEB_CHUNK];
+    for (int q0 = 0; q0 < nq; q0 += chunk) {
+        const int qn = std::min(chunk, nq - q0);
         c->arena.reset();
         Scope sc(c->arena);
         std::vector<const u64 *> ip(qn);
@@ -2233,6 +2323,75 @@ extern "C" int fr_cheb_mult_count(int32_t degree, int32_t d1) {
 }
 
 // ---------------------------------------------------------------------------
+// captured call sequences (HIP graphs)
+// ---------------------------------------------------------------------------
+struct fr_graph {
+    fr_ctx *ctx;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned gen = 0;
+};
+
+extern "C" int fr_graph_begin(fr_ctx *c) try {
+    CHECK(c, FR_EINVAL, "null context");
+    CHECK(!c->capturing, FR_EINVAL, "fr_graph_begin: a capture is already in progress");
+    CHECK(!c->prof || c->prof->cls == K_NONE, FR_EINVAL, "fr_graph_begin: the timing hook is active");
+    if (!c->cap_stream) FR_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    // the recorded work starts after what the caller's stream already holds
+    FR_HIP(hipStreamSynchronize(c->stream));
+    FR_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    c->saved_stream = c->stream;
+    c->stream = c->cap_stream;
+    c->capturing = true;
+    return FR_OK;
+} FR_CATCH(c)
+
+extern "C" int fr_graph_end(fr_ctx *c, fr_graph **out) try {
+    CHECK(c && out, FR_EINVAL, "fr_graph_end: null argument");
+    CHECK(c->capturing, FR_EINVAL, "fr_graph_end: no capture in progress");
+    c->stream = c->saved_stream;
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return fr_fail(FR_EHIP, "fr_graph_end: the capture failed (%s); a recorded call may have needed the host",
+                       hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fr_fail(FR_EHIP, "fr_graph_end: instantiate: %s", hipGetErrorString(ei));
+    }
+    fr_graph *gr = new fr_graph();
+    gr->ctx = c;
+    gr->graph = g;
+    gr->exec = x;
+    gr->gen = c->arena_gen;
+    *out = gr;
+    return FR_OK;
+} FR_CATCH(c)
+
+extern "C" int fr_graph_launch(fr_ctx *c, const fr_graph *g) try {
+    CHECK(c && g, FR_EINVAL, "fr_graph_launch: null argument");
+    CHECK(g->ctx == c, FR_EINVAL, "fr_graph_launch: graph of another context");
+    CHECK(!c->capturing, FR_EINVAL, "fr_graph_launch: a capture is in progress");
+    CHECK(g->gen == c->arena_gen, FR_EINVAL, "fr_graph_launch: the context's scratch was released after the capture");
+    FR_HIP(hipGraphLaunch(g->exec, c->stream));
+    return FR_OK;
+} FR_CATCH(c)
+
+extern "C" void fr_graph_destroy(fr_graph *g) {
+    if (!g) return;
+    (void)hipStreamSynchronize(g->ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// ---------------------------------------------------------------------------
 // kernel timing hook
 // ---------------------------------------------------------------------------
 bool Prof::begin(int k, hipStream_t s) {
@@ -2247,6 +2406,7 @@ void Prof::end(int, hipStream_t s, double b) {
 
 extern "C" int fr_prof_begin(fr_ctx *c, int32_t kernel_class) try {
     CHECK(c, FR_EINVAL, "null context");
+    CHECK(!c->capturing, FR_EINVAL, "fr_prof_begin: a graph capture is in progress");
     CHECK(kernel_class >= 0 && kernel_class <= K_ELEM, FR_EINVAL, "fr_prof_begin: unknown class %d", kernel_class);
     if (!c->prof) {
         c->prof = new Prof();

@@ -214,6 +214,14 @@ struct fr_ctx {
     KeyLayout klay{};
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;
+    // tuning knobs (fr_ctx_set_tune; defaults are measured choices)
+    int tune[FR_TUNE_COUNT] = {32, 32, 48, 48, 12, 8, 8};
+    // graph capture (fr_graph_begin / fr_graph_end): the calls of a capture
+    // run on cap_stream in capture mode; arena_gen counts releases of the
+    // arena, which invalidate graphs recorded before them
+    hipStream_t cap_stream = nullptr, saved_stream = nullptr;
+    bool capturing = false;
+    unsigned arena_gen = 0;
 };
 
 // bracket a launch of class K with timing events when that class is selected
@@ -475,6 +483,7 @@ void db_slots(const fr_ctx *c, double *out, const float *T, int K, int ell, int 
 
 // error helpers (api.cpp)
 int fr_fail(int code, const char *fmt, ...);
+
 #define FR_HIP(call)                                                                 \
     do {                                                                             \
         hipError_t e_ = (call);                                                      \

@@ -937,20 +937,18 @@ NttLaunch make_launch(const fr_ctx *c, u64 *data, const LimbMap &map, size_t pol
     return a;
 }
 
-// limb polynomials up to which the N = 2^16 row passes take 4 words per
-// thread (a launch this small is bound by one thread's chain of work;
-// thresholds from measured pass durations)
-constexpr int kSmallFwdRows = 32, kSmallInvRows = 48, kSmallFwdCols = 32, kSmallInvCols = 48;
-
+// limb polynomials up to which the N = 2^16 passes take 4 words per thread
+// (a launch this small is bound by one thread's chain of work): the
+// context's tuning knobs, set from measured pass durations
 void fwd_cols16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 g) {
-    if (npoly * nlimbs <= kSmallFwdCols)
+    if (npoly * nlimbs <= c->tune[FR_TUNE_NTT_FWD_COLS4])
         hipLaunchKernelGGL(k_fwd_cols4, g, dim3(kColThreads), 0, c->stream, a);
     else
         hipLaunchKernelGGL(k_fwd_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
 }
 
 void inv_cols16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 g) {
-    if (npoly * nlimbs <= kSmallInvCols)
+    if (npoly * nlimbs <= c->tune[FR_TUNE_NTT_INV_COLS4])
         hipLaunchKernelGGL(k_inv_cols4, g, dim3(kColThreads), 0, c->stream, a);
     else
         hipLaunchKernelGGL(k_inv_cols2<4>, g, dim3(kThreads), 0, c->stream, a);
@@ -958,7 +956,7 @@ void inv_cols16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3
 
 template <bool EPI>
 void fwd_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 gr) {
-    if (npoly * nlimbs <= kSmallFwdRows)
+    if (npoly * nlimbs <= c->tune[FR_TUNE_NTT_FWD_ROWS4])
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_rows4<EPI>), dim3(256 / kRowsPerBlk, npoly, nlimbs), dim3(kThreads),
                            0, c->stream, a);
     else
@@ -966,7 +964,7 @@ void fwd_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3
 }
 
 void inv_rows16(const fr_ctx *c, const NttLaunch &a, int npoly, int nlimbs, dim3 gr) {
-    if (npoly * nlimbs <= kSmallInvRows)
+    if (npoly * nlimbs <= c->tune[FR_TUNE_NTT_INV_ROWS4])
         hipLaunchKernelGGL(k_inv_rows4, dim3(256 / kRowsPerBlk, npoly, nlimbs), dim3(kThreads), 0, c->stream, a);
     else
         hipLaunchKernelGGL(k_inv_rows2<4>, gr, dim3(kThreads), 0, c->stream, a);

@@ -53,6 +53,8 @@ SIGNATURES = {
     "fr_ctx_sync": (C.c_int, [_P]),
     "fr_ctx_dims": (C.c_int, [_P, _I32P, _I32P, _I32P, _I32P, _I32P]),
     "fr_ctx_set_scratch_limit": (C.c_int, [_P, C.c_uint64]),
+    "fr_ctx_set_tune": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "fr_ctx_get_tune": (C.c_int, [_P, C.c_int32, _I32P]),
     "fr_ctx_scratch_info": (C.c_int, [_P, _U64P, _U64P]),
     "fr_ctx_reserve": (C.c_int, [_P, C.c_uint64]),
     "fr_ctx_modulus": (C.c_uint64, [_P, C.c_int32]),
@@ -95,6 +97,10 @@ SIGNATURES = {
     "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_moddown_parity": (C.c_int, [_P, C.c_int32, _U64P, _U64P, C.c_int32, _CTP]),
+    "fr_graph_begin": (C.c_int, [_P]),
+    "fr_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
+    "fr_graph_launch": (C.c_int, [_P, _P]),
+    "fr_graph_destroy": (None, [_P]),
     "fr_prof_begin": (C.c_int, [_P, C.c_int32]),
     "fr_prof_end": (C.c_int, [_P, _I32P, _DP, _DP]),
     "fr_cheb_step_coeffs": (C.c_int, [C.c_int32, C.c_double, _DP]),
@@ -259,6 +265,23 @@ class Db:
         return self
 
 
+class Graph:
+    """A recorded call sequence (fr_graph); launch() replays it on the
+    context's stream."""
+
+    def __init__(self, ctx, ptr):
+        self.ctx, self.ptr = ctx, ptr
+
+    def launch(self):
+        _check(lib().fr_graph_launch(self.ctx.ptr, self.ptr), "fr_graph_launch")
+
+    def __del__(self):
+        try:
+            lib().fr_graph_destroy(self.ptr)
+        except Exception:
+            pass
+
+
 class Context:
     """fr_ctx: parameter set, tables and stream (torch's current stream)."""
 
@@ -294,6 +317,21 @@ class Context:
     def sync(self):
         _check(lib().fr_ctx_sync(self.ptr), "fr_ctx_sync")
 
+    # tuning knobs ------------------------------------------------------------------
+    TUNE_KNOBS = {"ntt_fwd_cols4": 0, "ntt_fwd_rows4": 1, "ntt_inv_rows4": 2, "ntt_inv_cols4": 3,
+                  "modup_merge": 4, "matvec_chunk": 5, "cheb_chunk": 6}
+
+    def set_tune(self, knob: str, value: int):
+        _check(lib().fr_ctx_set_tune(self.ptr, self.TUNE_KNOBS[knob], int(value)), "fr_ctx_set_tune")
+
+    def get_tune(self, knob: str) -> int:
+        v = C.c_int32()
+        _check(lib().fr_ctx_get_tune(self.ptr, self.TUNE_KNOBS[knob], C.byref(v)), "fr_ctx_get_tune")
+        return v.value
+
+    def tune_state(self) -> dict:
+        return {k: self.get_tune(k) for k in self.TUNE_KNOBS}
+
     # device scratch ---------------------------------------------------------------
     def set_scratch_limit(self, nbytes: int):
         """At most nbytes of device scratch (0: no limit); calls beyond it raise FR_ENOMEM."""
@@ -319,6 +357,28 @@ class Context:
         n, ms, b = C.c_int32(), C.c_double(), C.c_double()
         _check(lib().fr_prof_end(self.ptr, C.byref(n), C.byref(ms), C.byref(b)), "fr_prof_end")
         return n.value, ms.value, b.value
+
+    # graph capture ------------------------------------------------------------
+    def graph_begin(self):
+        _check(lib().fr_graph_begin(self.ptr), "fr_graph_begin")
+
+    def graph_end(self) -> Graph:
+        ptr = _P()
+        _check(lib().fr_graph_end(self.ptr, C.byref(ptr)), "fr_graph_end")
+        return Graph(self, ptr)
+
+    def capture(self, fn) -> Graph:
+        """Record the device calls fn() makes on this context as one graph."""
+        self.graph_begin()
+        try:
+            fn()
+        except Exception:
+            try:
+                self.graph_end()
+            except FrError:
+                pass
+            raise
+        return self.graph_end()
 
     # parity hook -------------------------------------------------------------
     def moddown_parity(self, mode: int, u, level: int, d=None) -> Ct:

@@ -9,6 +9,7 @@ usage:
   python -m paper_2604_00546_amd.profsum trace <run_kernel_trace.csv> --steps S --calib-mib M
   python -m paper_2604_00546_amd.profsum counters <fetch.csv> <write.csv> --calib-mib M
   python -m paper_2604_00546_amd.profsum sq <sq_counter_collection.csv>
+  python -m paper_2604_00546_amd.profsum ntt <run_kernel_trace.csv> --calib-mib M
 """
 import argparse
 import collections
@@ -51,6 +52,30 @@ def trace(path, steps, calib_mib):
     print(f"{'kernel':40s} {'calls/step':>10s} {'ms/step':>9s} {'avg us':>8s} {'share':>6s}")
     for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         print(f"{k[:40]:40s} {n / steps:10.1f} {t / 1e6 / steps:9.3f} {t / n / 1e3:8.2f} {100 * t / total:5.1f}%")
+
+
+def ntt_sizes(path, calib_mib, n_coeff=65536):
+    """NTT passes of the timed region by launch size: limb polynomials per
+    launch (grid y x z for every pass at N = 2^16), mean duration and the
+    pass's algorithmic HBM rate (16 B per coefficient: one read, one write)."""
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    cand = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"]
+    dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    start = max(cand, key=lambda i: dur(rows[i]))
+    agg = collections.defaultdict(lambda: [0, 0])
+    for r in rows[start + 1:]:
+        k = _short(r["Kernel_Name"])
+        if not k.startswith(("k_fwd_", "k_inv_")):
+            continue
+        lp = int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        a = agg[(k, lp)]
+        a[0] += 1
+        a[1] += dur(r)
+    print(f"{'pass':28s} {'limb polys':>10s} {'launches':>8s} {'mean us':>8s} {'GB/s':>7s} {'total ms':>9s}")
+    for (k, lp), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        us = t / n / 1e3
+        print(f"{k[:28]:28s} {lp:10d} {n:8d} {us:8.2f} {lp * n_coeff * 16 / (us * 1e3):7.0f} {t / 1e6:9.3f}")
 
 
 def counters(fpath, wpath, calib_mib):
@@ -124,9 +149,14 @@ def main():
     c.add_argument("--calib-mib", type=int, required=True)
     q = sub.add_parser("sq")
     q.add_argument("path")
+    n = sub.add_parser("ntt")
+    n.add_argument("path")
+    n.add_argument("--calib-mib", type=int, required=True)
     a = ap.parse_args()
     if a.cmd == "trace":
         trace(a.path, a.steps, a.calib_mib)
+    elif a.cmd == "ntt":
+        ntt_sizes(a.path, a.calib_mib)
     elif a.cmd == "counters":
         counters(a.fetch, a.write, a.calib_mib)
     else:

@@ -1,0 +1,91 @@
+"""HIP-graph capture of the per-query pipeline (hoisted BSGS product, then
+the Chebyshev threshold): every replay equals the eager result word for
+word, with other eager work and synchronisations between the replays and a
+different query written into the recorded input buffer on alternate
+replays."""
+import numpy as np
+import pytest
+
+from paper_2604_00546_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["deep", "paper"])
+def setup(request):
+    import torch
+    from paper_2604_00546_amd import fr
+    p = fr.deep_small_params() if request.param == "deep" else fr.paper_params()
+    g = fr.Context(**p)
+    ell, n1 = (128, 8) if request.param == "deep" else (512, 32)
+    K = 64 if request.param == "deep" else 2048
+    B = g.N // 2 // ell
+    rots = fr.bsgs_rotation_set(ell, n1)
+    keys = g.keygen(synth.int_seed(2, synth.SUB_KEYS), rots)
+    wl = synth.make_workload(2, K, ell)
+    db = g.db_load(wl.templates, ell, B, n1, g.L, 2.0 ** 40).extend()
+    Q = synth.query_batch(2, 2, ell)
+    qs = [g.encrypt(keys, g.encode(synth.replicate_query(Q[i], g.N // 2), g.L, 2.0 ** 40),
+                    synth.int_seed(2, synth.SUB_ENC, i)) for i in range(2)]
+    coeffs = fr.cheb_step_coeffs(63, 0.3)
+    print(f"graph case {request.param}: N={g.N}", flush=True)
+    return torch, fr, g, keys, db, qs, coeffs
+
+
+def test_replays_equal_eager(setup):
+    torch, fr, g, keys, db, qs, coeffs = setup
+    d1 = 8
+    # eager results of both queries
+    want = []
+    for q in qs:
+        s = g.bsgs_matvec_hoisted(keys, q, db, 0)
+        want.append(g.ct_export(g.chebyshev_eval(keys, s, coeffs, d1)))
+    # record the pipeline on fixed buffers
+    inp = g.new_ct(g.L)
+    inp.buf.copy_(qs[0].buf)
+    inp.desc.level, inp.desc.scale = qs[0].level, qs[0].scale
+    score = g.new_ct(g.L - 1)
+    cheb = g.new_ct(g.L - 1)
+    graph = g.capture(lambda: (g.bsgs_matvec_hoisted(keys, inp, db, 0, out=score),
+                               g.chebyshev_eval(keys, score, coeffs, d1, out=cheb)))
+    other = g.new_ct(g.L)
+    for rep in range(4):
+        k = rep % 2
+        inp.buf.copy_(qs[k].buf)  # on the context's stream (torch's current stream)
+        graph.launch()
+        # unrelated eager work and a synchronisation between replays
+        g.rotate_hoisted(keys, qs[1 - k], [1], outs=[other])
+        g.sync()
+        got = g.ct_export(cheb)
+        assert cheb.level == want[k].shape[1] - 1
+        bad = np.argwhere(got != want[k])
+        assert len(bad) == 0, f"replay {rep}: {len(bad)} words differ"
+
+
+def test_host_calls_are_refused_during_capture(setup):
+    torch, fr, g, keys, db, qs, coeffs = setup
+    want = g.ct_export(g.bsgs_matvec_hoisted(keys, qs[0], db, 0))
+    out = g.new_ct(g.L - 1)
+    g.graph_begin()
+    try:
+        g.bsgs_matvec_hoisted(keys, qs[0], db, 0, out=out)
+        with pytest.raises(fr.FrError) as e:
+            g.ct_export(qs[0])  # needs the host: refused, the capture goes on
+        assert e.value.code == fr.FR_EINVAL
+    finally:
+        graph = g.graph_end()
+    graph.launch()
+    assert np.array_equal(g.ct_export(out), want)
+
+
+def test_graph_invalid_after_scratch_release(setup):
+    torch, fr, g, keys, db, qs, coeffs = setup
+    out = g.new_ct(g.L - 1)
+    graph = g.capture(lambda: g.bsgs_matvec_hoisted(keys, qs[0], db, 0, out=out))
+    graph.launch()
+    g.sync()
+    g.set_scratch_limit(1 << 20)  # releases the scratch the graph uses
+    g.set_scratch_limit(0)
+    with pytest.raises(fr.FrError) as e:
+        graph.launch()
+    assert e.value.code == fr.FR_EINVAL

@@ -52,6 +52,8 @@ def test_served_results_equal_alone(S):
     stats = srv.run(S["reqs"])
     assert stats["requests"] == NR
     assert max(srv.batches) <= 4 and sum(srv.batches) == NR and len(srv.batches) >= 3
+    # the first burst fills both lanes: a batch was launched while another ran
+    assert stats["overlapped_batches"] >= 1 and {r.lane for r in S["reqs"]} == {0, 1}
     for r in S["reqs"]:
         assert r.done >= r.admitted >= r.arrival
         a = _alone(S, r)
@@ -105,3 +107,35 @@ def test_served_hoisted_equal_alone(S):
 def test_slot_count_rule(S):
     n = S["serve"].slot_count(S["g"])
     assert 2 <= n <= 64
+
+
+def test_admission_by_scratch_budget(S):
+    """Lanes whose scratch budget holds one request but not two: batches
+    that meet FR_ENOMEM are split, and every result still equals the same
+    request run alone."""
+    g, serve, keys = S["g"], S["serve"], S["keys"]
+    from paper_2604_00546_amd import fr
+    probe = fr.Context(**fr.deep_small_params())
+    r0 = S["reqs"][0]
+    probe.chebyshev_eval(keys, probe.bsgs_matvec_hoisted(keys, r0.query, _extended(S, r0.db), 0), S["coeffs"], 8)
+    one = probe.scratch_info()[1]
+    reqs = [serve.Request(r.rid, 0.0, r.kind, r.query, _extended(S, r.db), 0) for r in S["reqs"][:6]]
+    srv = serve.Server(g, keys, S["coeffs"], 8, N1, slots=6, lanes=2, keep_results=True,
+                       hbm_budget=int(2 * 1.4 * one))
+    stats = srv.run(reqs)
+    assert stats["split_batches"] >= 1 and max(srv.batches) <= 2
+    for r in reqs:
+        a = g.chebyshev_eval(keys, g.bsgs_matvec_hoisted(keys, r.query, r.db, 0), S["coeffs"], 8)
+        assert np.array_equal(g.ct_export(r.result), g.ct_export(a)), f"request {r.rid}"
+
+
+_EXT = {}
+
+
+def _extended(S, db):
+    """An extended copy of db (the hoisted product's databases)."""
+    g = S["g"]
+    if id(db) not in _EXT:
+        _EXT[id(db)] = g.db_import(np.stack([[db.export(0, d) for d in range(ELL)]]), 1, ELL, 16, N1, g.L,
+                                   2.0 ** 40).extend()
+    return _EXT[id(db)]

@@ -556,6 +556,31 @@ def test_matvec_hoisted_paper_chain(deep_ctx):
     assert np.max(np.abs(dh[64:])) <= 2 ** -20
 
 
+@pytest.mark.slow
+def test_score_bound_over_encryption_seeds(oracle_mod):
+    """The 2^-20 score bound at the identification workload (2^15 templates x
+    512-d with 1% planted, N = 2^16, the paper chain, the hoisted product)
+    over five public-key encryptions of the query: the noise margin of the
+    estimate (worst slot about 2^-20.4) holds on every seed, so public-key
+    encryption stands and the secret-key fallback is not needed."""
+    ctx = oracle_mod.Context(**oracle_mod.paper_params())
+    ell, n1, B = 512, 32, 64
+    rots = list(range(1, n1)) + [n1 * j for j in range(1, ell // n1)]
+    keys = ctx.keygen(synth.int_seed(3, synth.SUB_KEYS), rots)
+    wl = synth.make_workload(3, 2 ** 15, ell, planted_frac=0.01)
+    db = ctx.db_build(wl.templates, wl.K, ell, B, n1, ctx.L, 2.0 ** 40)
+    db.extend()
+    exact = wl.exact_scores()
+    pt = ctx.encode(synth.replicate_query(wl.query, ctx.N // 2), ctx.L, 2.0 ** 40)
+    worst = []
+    for k in range(5):
+        ct = ctx.encrypt(keys, pt, synth.int_seed(3, synth.SUB_ENC, 100 + k))
+        dec = ctx.decrypt_decode(keys, ctx.bsgs_matvec_hoisted(keys, ct, db, 0))
+        worst.append(float(np.max(np.abs(dec - exact))))
+    print("worst score error per seed (log2):", [round(math.log2(w), 2) for w in worst])
+    assert max(worst) <= 2 ** -20, worst
+
+
 # --------------------------------------------------------------------------
 # Chebyshev threshold
 # --------------------------------------------------------------------------
