@@ -327,40 +327,85 @@ def rotq_vs_bsgs(s, K, d1, steps=2):
 
 def encrypted_db(s, d1, steps=2):
     """The paper's setting: the 512 diagonals of the 2^15-template database
-    encrypted, the group score Rescale(Relin(sum_d rot_d(q) (x) Enc(diag_d)))
-    over the full rotation table (one relinearisation per group), then the
-    Chebyshev threshold."""
+    encrypted.  Three routes to the group's score, each followed by the
+    Chebyshev threshold:
+      rotation table: Rescale(Relin(sum_d rot_d(q) (x) Enc(diag_d))) over the
+        full table of query rotations, one relinearisation per group;
+      BSGS-TBS: the server pre-rotates the encrypted diagonals by -j n1 with
+        temporary negative giant-step keys (offline, then the keys are
+        freed); online, one relinearisation per giant step and the giant
+        rotate-sum (§5.3.1-§5.3.2);
+      BSGS-TBE: the enroller pre-rotates the plaintext slots before
+        encryption (§5.3.3); the same online product."""
     import torch
     from paper_2604_00546_amd import synth
-    ctx, ell, n1 = s["ctx"], s["ell"], s["n1"]
+    fr, ctx, ell, n1, keys = s["fr"], s["ctx"], s["ell"], s["n1"], s["keys"]
+    n2 = ell // n1
     t = time.time()
     plain = ctx.db_load(s["wl"].templates, ell, s["B"], ell, ctx.L, 2.0 ** 40)
-    ediag = [ctx.encrypt(s["keys"], ctx.pt_import(plain.export(0, d), ctx.L, 2.0 ** 40),
-                         synth.int_seed(3, synth.SUB_ENC, 1000 + d)) for d in range(ell)]
+    enc = [ctx.encrypt(keys, ctx.pt_import(plain.export(0, d), ctx.L, 2.0 ** 40),
+                       synth.int_seed(3, synth.SUB_ENC, 1000 + d)) for d in range(ell)]
     del plain
     torch.cuda.synchronize()
     setup_s = time.time() - t
-    giant = [n1 * j for j in range(1, ell // n1)]
+    giant = [n1 * j for j in range(1, n2)]
     rows = [[ctx.new_ct(ctx.L) for _ in giant] for _ in range(n1)]
-    table = [s["baby"][i] if j == 0 else rows[i][j - 1] for j in range(ell // n1) for i in range(n1)]
+    table = [s["baby"][i] if j == 0 else rows[i][j - 1] for j in range(n2) for i in range(n1)]
     score, cheb = ctx.new_ct(ctx.L - 1), ctx.new_ct(ctx.L - 1)
+    exact = s["wl"].exact_scores()
 
-    def run():
-        ctx.rotate_hoisted(s["keys"], s["q"], range(1, n1), outs=s["baby"][1:])
-        ctx.rotate_hoisted_batch(s["keys"], s["baby"], giant, outs=rows)
-        ctx.tensor_sum_relin_rescale(s["keys"], table, ediag, out=score)
-        ctx.chebyshev_eval(s["keys"], score, s["coeffs"], d1, out=cheb)
-
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    def timed(run):
         run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        err = float(np.max(np.abs(ctx.decrypt_decode(keys, score) - exact)))
+        return {"ms_per_query": dt * 1e3, "scores_per_s": s["K"] / dt, "score_max_abs_err": err}
+
+    def table_route():
+        ctx.rotate_hoisted(keys, s["q"], range(1, n1), outs=s["baby"][1:])
+        ctx.rotate_hoisted_batch(keys, s["baby"], giant, outs=rows)
+        ctx.tensor_sum_relin_rescale(keys, table, enc, out=score)
+        ctx.chebyshev_eval(keys, score, s["coeffs"], d1, out=cheb)
+
+    out = {"encrypted_diagonals": ell, "setup_s": setup_s, "rotation_table": timed(table_route)}
+    del rows, table
+    # BSGS-TBS: homomorphic pre-rotation with temporary negative giant-step keys
+    t = time.time()
+    tmp = ctx.keygen(synth.int_seed(3, synth.SUB_KEYS), [-g for g in giant])
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    err = float(np.max(np.abs(ctx.decrypt_decode(s["keys"], score) - s["wl"].exact_scores())))
-    return {"encrypted_diagonals": ell, "setup_s": setup_s, "ms_per_query": dt * 1e3, "scores_per_s": s["K"] / dt,
-            "score_max_abs_err": err}
+    keygen_s = time.time() - t
+    t = time.time()
+    tbs = list(enc[:n1])
+    for j in range(1, n2):
+        tbs += [row[0] for row in ctx.rotate_hoisted_batch(tmp, enc[j * n1:(j + 1) * n1], [-n1 * j])]
+    torch.cuda.synchronize()
+    prerot_s = time.time() - t
+    del tmp, enc
+    torch.cuda.synchronize()
+
+    def bsgs_route(diag):
+        def run():
+            ctx.rotate_hoisted(keys, s["q"], range(1, n1), outs=s["baby"][1:])
+            ctx.bsgs_encrypted_matvec(keys, s["baby"], diag, out=score)
+            ctx.chebyshev_eval(keys, score, s["coeffs"], d1, out=cheb)
+        return run
+
+    out["bsgs_tbs"] = dict(timed(bsgs_route(tbs)), temp_keys=len(giant), temp_keygen_s=keygen_s,
+                           prerotation_s=prerot_s)
+    del tbs
+    # BSGS-TBE: the enroller encrypts the pre-rotated plaintext diagonals
+    t = time.time()
+    pre = ctx.db_load(s["wl"].templates, ell, s["B"], n1, ctx.L, 2.0 ** 40)
+    tbe = [ctx.encrypt(keys, ctx.pt_import(pre.export(0, d), ctx.L, 2.0 ** 40),
+                       synth.int_seed(3, synth.SUB_ENC, 2000 + d)) for d in range(ell)]
+    del pre
+    torch.cuda.synchronize()
+    out["bsgs_tbe"] = dict(timed(bsgs_route(tbe)), enroll_s=time.time() - t)
+    return out
 
 
 def diagonal_method(s, d1, steps=2):

@@ -295,6 +295,30 @@ int fr_chebyshev_eval_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, i
 int fr_tensor_sum_relin_rescale(fr_ctx *ctx, const fr_keys *keys, const fr_ct *a, const fr_ct *b, int32_t n,
                                 fr_ct *out);
 
+/* ---- giant-step rotate-sum (Eq. bsgs2 of §3.4; the on-demand giant
+ * rotations of §5.3.2) ----
+ * out = in[0] + sum_{j >= 1} Rot_{j stride}(in[j]): the n inputs (one level
+ * and scale) are rotated by their giant steps, the key inner products summed
+ * over Q_l U P and taken through one shared ModDown.  Keys for the rotations
+ * j stride; out at the inputs' level; out must not alias an input. */
+int fr_rotate_sum(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t n, int32_t stride, fr_ct *out);
+
+/* ---- BSGS product against an encrypted database (BSGS-TBS / TBE of
+ * §5.3: pre-rotated encrypted diagonals, Eq. prerotation of §5.3.1; the
+ * online pipeline of §5.3.2 with lazy relinearisation per giant step) ----
+ * baby[i] = Rot_i(query), i < n1; diag[d], d < ell, the group's encrypted
+ * diagonals pre-rotated by -j n1 (d = j n1 + i) -- homomorphically by the
+ * server with temporary negative giant-step keys (TBS: fr_rotate_hoisted_batch
+ * with rotation -j n1 on the diagonals of giant step j) or in the plaintext
+ * slots by the enroller before encryption (TBE); all at one level l >= 1.
+ *   P_j = Rescale(Relin(sum_{i < min(n1, ell - j n1)} baby[i] (x) diag[j n1 + i]))
+ *   out = P_0 + sum_{j >= 1} Rot_{j n1}(P_j)   (level l-1)
+ * The tensor sums are degree 2 and relinearised once per giant step; the
+ * giant rotations share one ModDown.  Needs the s^2 key and the keys for
+ * j n1.  Slot s of out is the score of the group's template s. */
+int fr_bsgs_encrypted_matvec(fr_ctx *ctx, const fr_keys *keys, const fr_ct *baby, int32_t n1, const fr_ct *diag,
+                             int32_t ell, fr_ct *out);
+
 /* ---- membership aggregation (Alg. gpu-bsgs-membership, aggregation step;
  * Alg. membership of the appendix: EvalAddMany then EvalSum over all slots) ----
  * out = EvalSum(in[0] + ... + in[n-1]): the n inputs (one level and scale,

@@ -1412,6 +1412,21 @@ static or_ct *giant_sum(const or_ctx *c, const or_keys *K, or_ct **P, int n2, in
     return S;
 }
 
+/* S = P[0] + sum_{j >= 1} Rot_{j stride}(P[j]) for n ciphertexts of one
+ * level and scale: the giant-step rotate-sum of Eq. bsgs2 (§3.4) on its own,
+ * as the on-demand giant rotations of §5.3.2 apply it to the inner sums of
+ * an encrypted database.  The inputs are left as they are. */
+or_ct *or_rotate_sum(const or_ctx *c, const or_keys *K, const or_ct *const *P, int n, int stride) {
+    if (n < 1) { set_err("or_rotate_sum: no input"); return NULL; }
+    for (int j = 0; j < n; j++)
+        if (!same_shape(P[j], P[0]) || P[j]->scale != P[0]->scale) { set_err("or_rotate_sum: inputs differ"); return NULL; }
+    for (int j = 1; j < n; j++)
+        if (!find_ksk(K, or_galois_element(c, j * stride))) { set_err("or_rotate_sum: missing rotation key"); return NULL; }
+    or_ct **Q = malloc(sizeof(or_ct *) * (size_t)n);
+    for (int j = 0; j < n; j++) Q[j] = or_ct_copy(c, P[j]);
+    return giant_sum(c, K, Q, n, stride);
+}
+
 /* BSGS product with the ModDown of the baby steps hoisted past the inner
  * sums (double hoisting of the plaintext-matrix BSGS, §3.4.2 hoisting and double
  * hoisting).  Baby step i is kept over the extended basis Q_l U P,

@@ -117,6 +117,9 @@ or_ct *or_mul_relin_rescale(const or_ctx *ctx, const or_keys *k, const or_ct *a,
 /* sum of the tensor products of n pairs, relinearised once, rescaled */
 or_ct *or_tensor_sum_relin_rescale(const or_ctx *ctx, const or_keys *k, const or_ct *const *a,
                                    const or_ct *const *b, int n);
+/* P[0] + sum_{j >= 1} Rot_{j stride}(P[j]), the giant rotations sharing one
+ * ModDown (inputs untouched) */
+or_ct *or_rotate_sum(const or_ctx *ctx, const or_keys *k, const or_ct *const *P, int n, int stride);
 /* multiply every limb by the signed integer kc (no rescale, scale *= kc) */
 or_ct *or_mul_int(const or_ctx *ctx, const or_ct *a, int64_t kc);
 /* add round(c * a->scale) to the constant coefficient of c0 */

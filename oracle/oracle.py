@@ -85,6 +85,7 @@ def lib():
         "or_ct_free": (None, [_CT]),
         "or_rotate_hoisted": (C.c_int, [_P, _P, _CT, _I32P, C.c_int, C.POINTER(_CT)]),
         "or_rescale": (_CT, [_P, _CT]),
+        "or_rotate_sum": (_CT, [_P, _P, C.POINTER(_CT), C.c_int, C.c_int]),
         "or_add": (_CT, [_P, _CT, _CT]),
         "or_sub": (_CT, [_P, _CT, _CT]),
         "or_mul_plain": (_CT, [_P, _CT, _PT]),
@@ -448,6 +449,15 @@ class Context:
         r = lib().or_tensor_sum_relin_rescale(self.ptr, keys.ptr, pa, pb, n)
         if not r:
             _err("tensor_sum_relin_rescale")
+        return Ct(self, r)
+
+    def rotate_sum(self, keys: Keys, cts, stride: int) -> Ct:
+        """cts[0] + sum_{j >= 1} Rot_{j stride}(cts[j]), one shared ModDown."""
+        n = len(cts)
+        p = (_CT * n)(*[x.ptr for x in cts])
+        r = lib().or_rotate_sum(self.ptr, keys.ptr, p, n, stride)
+        if not r:
+            _err("rotate_sum")
         return Ct(self, r)
 
     def mul_int(self, a: Ct, k: int) -> Ct:

@@ -1582,6 +1582,103 @@ extern "C" int fr_bsgs_diag_matvec_batch(fr_ctx *c, const fr_keys *K, const fr_c
 } FR_CATCH(c)
 
 // ---------------------------------------------------------------------------
+// giant-step rotate-sum and the encrypted-database BSGS product
+// ---------------------------------------------------------------------------
+// checks shared by the two: n inputs of one level and scale, keys for the
+// rotations j * stride (1 <= j < n), the output's capacity and aliasing
+static int rotate_sum_checks(fr_ctx *c, const fr_keys *K, const fr_ct *in, int n, int stride, const fr_ct *out,
+                             int out_level, const char *what) {
+    for (int j = 0; j < n; ++j) {
+        if (int e = check_ct(c, &in[j], what)) return e;
+        CHECK(in[j].level == in[0].level && in[j].scale == in[0].scale, FR_ELEVEL, "%s: inputs differ in level or scale",
+              what);
+        CHECK(in[j].data != out->data, FR_EINVAL, "%s: output aliases an input", what);
+    }
+    for (int j = 1; j < n; ++j)
+        CHECK(K->find(galois_element(c->N, j * stride)), FR_ENOKEY, "%s: no key for rotation %d", what, j * stride);
+    return check_out(c, out, out_level, what);
+}
+
+extern "C" int fr_rotate_sum(fr_ctx *c, const fr_keys *K, const fr_ct *in, int32_t n, int32_t stride,
+                             fr_ct *out) try {
+    CHECK(c && K && in && out && n >= 1, FR_EINVAL, "fr_rotate_sum: null argument or no input");
+    if (int e = keys_ok(c, K, "fr_rotate_sum")) return e;
+    const int l = in[0].level;
+    if (int e = rotate_sum_checks(c, K, in, n, stride, out, l, "fr_rotate_sum")) return e;
+    c->arena.reset();
+    Scope sc(c->arena);
+    const size_t rw = (size_t)2 * (l + 1) * c->N;
+    u64 *R = scratch(c, (size_t)n * rw);  // the inputs staged contiguously
+    for (int j = 0; j < n; ++j)
+        FR_HIP(hipMemcpyAsync(R + j * rw, in[j].data, rw * 8, hipMemcpyDeviceToDevice, c->stream));
+    u64 *op = out->data;
+    if (int e = giant_steps(c, K, R, 1, n, stride, l, &op)) return e;
+    FR_HIP(hipGetLastError());
+    out->level = l;
+    out->scale = in[0].scale;
+    return FR_OK;
+} FR_CATCH(c)
+
+// P_j = Rescale(Relin(sum_i baby[i] (x) diag[j n1 + i])) for every giant step
+// j (the tensor sums, one ModUp batch, one read of the relinearisation key
+// and one merged ModDown + rescale for all of them), then
+// out = P_0 + sum_{j >= 1} Rot_{j n1}(P_j) with one shared ModDown.
+extern "C" int fr_bsgs_encrypted_matvec(fr_ctx *c, const fr_keys *K, const fr_ct *baby, int32_t n1, const fr_ct *diag,
+                                        int32_t ell, fr_ct *out) try {
+    CHECK(c && K && baby && diag && out && n1 >= 1 && ell >= 1 && n1 <= ell, FR_EINVAL,
+          "fr_bsgs_encrypted_matvec: null argument or bad shape");
+    if (int e = keys_ok(c, K, "fr_bsgs_encrypted_matvec")) return e;
+    const int l = baby[0].level, N = c->N, n2 = (ell + n1 - 1) / n1;
+    for (int i = 0; i < n1; ++i) {
+        if (int e = check_ct(c, &baby[i], "fr_bsgs_encrypted_matvec")) return e;
+        CHECK(baby[i].level == l && baby[i].scale == baby[0].scale, FR_ELEVEL,
+              "fr_bsgs_encrypted_matvec: baby steps differ in level or scale");
+    }
+    for (int d = 0; d < ell; ++d) {
+        if (int e = check_ct(c, &diag[d], "fr_bsgs_encrypted_matvec")) return e;
+        CHECK(diag[d].level == l && diag[d].scale == diag[0].scale, FR_ELEVEL,
+              "fr_bsgs_encrypted_matvec: diagonals differ from the baby steps in level or scale");
+        CHECK(diag[d].data != out->data, FR_EINVAL, "fr_bsgs_encrypted_matvec: output aliases a diagonal");
+    }
+    for (int i = 0; i < n1; ++i)
+        CHECK(baby[i].data != out->data, FR_EINVAL, "fr_bsgs_encrypted_matvec: output aliases a baby step");
+    CHECK(l >= 1, FR_ELEVEL, "fr_bsgs_encrypted_matvec: no level left to rescale");
+    const KeyEntry *rk = K->find(0);
+    CHECK(rk, FR_ENOKEY, "fr_bsgs_encrypted_matvec: relinearisation key missing");
+    for (int j = 1; j < n2; ++j)
+        CHECK(K->find(galois_element(N, j * n1)), FR_ENOKEY, "fr_bsgs_encrypted_matvec: no key for giant step %d",
+              j * n1);
+    if (int e = check_out(c, out, l - 1, "fr_bsgs_encrypted_matvec")) return e;
+    c->arena.reset();
+    Scope sc(c->arena);
+    const int nE = l + 1 + c->nP, ndig = num_digits(c, l);
+    const size_t lw = (size_t)(l + 1) * N, cw = 2 * lw, dstride = (size_t)ndig * nE * N;
+    u64 *T01 = scratch(c, (size_t)n2 * cw), *T2 = scratch(c, (size_t)n2 * lw);
+    std::vector<const u64 *> pa(n1), pb(n1);
+    for (int j = 0; j < n2; ++j) {
+        const int nj = std::min(n1, ell - j * n1);
+        for (int i = 0; i < nj; ++i) {
+            pa[i] = baby[i].data;
+            pb[i] = diag[j * n1 + i].data;
+        }
+        frk::tensor_sum(c, T01 + j * cw, T2 + j * lw, l + 1, nj, pa.data(), pb.data());
+    }
+    u64 *D = scratch(c, (size_t)n2 * dstride);
+    ks_modup(c, T2, l, D, n2, lw);
+    u64 *U = scratch(c, (size_t)n2 * 2 * nE * N);
+    frk::ks_inner(c, U, U + (size_t)nE * N, D, rk->data, 1, l, false, n2, dstride, (size_t)2 * nE * N,
+                  relin_folds(c) ? T01 : nullptr, cw);
+    u64 *R = scratch(c, (size_t)n2 * 2 * l * N);
+    relin_rescale_into(c, T01, U, n2, l, R);
+    u64 *op = out->data;
+    if (int e = giant_steps(c, K, R, 1, n2, n1, l - 1, &op)) return e;
+    FR_HIP(hipGetLastError());
+    out->level = l - 1;
+    out->scale = (baby[0].scale * diag[0].scale) / (double)c->mod[l];
+    return FR_OK;
+} FR_CATCH(c)
+
+// ---------------------------------------------------------------------------
 // the BSGS product with the baby steps' ModDown hoisted past the inner sums
 // ---------------------------------------------------------------------------
 // Appends to every diagonal its residues mod the special primes, those of

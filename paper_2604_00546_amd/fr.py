@@ -94,6 +94,8 @@ SIGNATURES = {
     "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
     "fr_membership_aggregate": (C.c_int, [_P, _P, _CTP, C.c_int32, _CTP]),
     "fr_tensor_sum_relin_rescale": (C.c_int, [_P, _P, _CTP, _CTP, C.c_int32, _CTP]),
+    "fr_rotate_sum": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _CTP]),
+    "fr_bsgs_encrypted_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _CTP, C.c_int32, _CTP]),
     "fr_bsgs_diag_matvec_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _P, _I32P, _CTP]),
     "fr_chebyshev_eval_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_moddown_parity": (C.c_int, [_P, C.c_int32, _U64P, _U64P, C.c_int32, _CTP]),
@@ -617,6 +619,28 @@ class Context:
         pb = (CtDesc * len(b))(*[x.desc for x in b])
         _check(lib().fr_tensor_sum_relin_rescale(self.ptr, keys.ptr, pa, pb, len(a), out.ref),
                "fr_tensor_sum_relin_rescale")
+        return out
+
+    def rotate_sum(self, keys: Keys, cts: Sequence[Ct], stride: int, out: Ct | None = None) -> Ct:
+        """cts[0] + sum_{j >= 1} Rot_{j stride}(cts[j]), one shared ModDown."""
+        cts = list(cts)
+        if out is None:
+            out = self.new_ct(cts[0].level)
+        ins = (CtDesc * len(cts))(*[x.desc for x in cts])
+        _check(lib().fr_rotate_sum(self.ptr, keys.ptr, ins, len(cts), stride, out.ref), "fr_rotate_sum")
+        return out
+
+    def bsgs_encrypted_matvec(self, keys: Keys, baby: Sequence[Ct], diag: Sequence[Ct],
+                              out: Ct | None = None) -> Ct:
+        """BSGS product with pre-rotated encrypted diagonals: one
+        relinearisation per giant step, then the giant rotate-sum."""
+        baby, diag = list(baby), list(diag)
+        if out is None:
+            out = self.new_ct(max(baby[0].level - 1, 0))
+        pb = (CtDesc * len(baby))(*[x.desc for x in baby])
+        pd = (CtDesc * len(diag))(*[x.desc for x in diag])
+        _check(lib().fr_bsgs_encrypted_matvec(self.ptr, keys.ptr, pb, len(baby), pd, len(diag), out.ref),
+               "fr_bsgs_encrypted_matvec")
         return out
 
     def membership_aggregate(self, keys: Keys, cts: Sequence[Ct], out: Ct | None = None) -> Ct:

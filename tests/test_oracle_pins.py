@@ -683,3 +683,76 @@ def test_tensor_sum_relin_rescale(deep_ctx, deep_keys):
     z = ctx.decrypt_decode(K, ctx.tensor_sum_relin_rescale(K, a, b))
     want = sum(x * y for x, y in zip(xs, ys))
     assert np.max(np.abs(z - want)) < 2 ** -20
+
+
+def test_rotate_sum_is_sum_of_rotations(small_ctx, small_keys):
+    """The giant-step rotate-sum with its shared ModDown decrypts to the
+    slot-wise sum of the rotated inputs (and leaves them as they were)."""
+    ctx, K = small_ctx, small_keys
+    rnd = np.random.default_rng(93)
+    h = ctx.N // 2
+    xs = [rnd.uniform(-1, 1, h) for _ in range(4)]
+    cts = [ctx.encrypt(K, ctx.encode(x, ctx.L, 2.0 ** 40), 930 + i) for i, x in enumerate(xs)]
+    before = [c.coeffs().copy() for c in cts]
+    S = ctx.rotate_sum(K, cts, 8)
+    want = sum(np.roll(x, -8 * j) for j, x in enumerate(xs))
+    # four fresh encryptions summed (about 2^-25.6 std per slot each at N = 2^12)
+    # plus three key switches: well inside 2^-22
+    assert np.max(np.abs(ctx.decrypt_decode(K, S) - want)) < 2 ** -22
+    assert all(np.array_equal(c.coeffs(), b) for c, b in zip(cts, before))
+    # one input: the input itself
+    assert np.array_equal(ctx.rotate_sum(K, cts[:1], 8).coeffs(), before[0])
+
+
+@pytest.fixture(scope="module")
+def encdb(deep_ctx, oracle_mod):
+    """Encrypted database of 64 templates x 128-d (one group, B = 16): the
+    plain diagonals encrypted, pre-rotated by the server with temporary
+    negative giant-step keys (TBS), and the enroller's pre-rotated plaintext
+    diagonals encrypted (TBE); the query's baby steps."""
+    ctx = deep_ctx
+    ell, n1, B = 128, 8, 16
+    wl = synth.make_workload(6, 64, ell)
+    keys = ctx.keygen(synth.int_seed(6, synth.SUB_KEYS), ROTS_C1)
+    # the temporary keys belong to the same secret (the same key seed)
+    tmp = ctx.keygen(synth.int_seed(6, synth.SUB_KEYS), [-n1 * j for j in range(1, ell // n1)])
+    plain = ctx.db_build(wl.templates, wl.K, ell, B, ell, ctx.L, 2.0 ** 40)  # n2 = 1: not pre-rotated
+    pre = ctx.db_build(wl.templates, wl.K, ell, B, n1, ctx.L, 2.0 ** 40)
+    enc = [ctx.encrypt(keys, ctx.pt_import(plain.export(0, d), ctx.L, 2.0 ** 40), synth.int_seed(6, synth.SUB_ENC, d))
+           for d in range(ell)]
+    tbs = [enc[d] if d < n1 else ctx.rotate_hoisted(tmp, enc[d], [-n1 * (d // n1)])[0] for d in range(ell)]
+    tbe = [ctx.encrypt(keys, ctx.pt_import(pre.export(0, d), ctx.L, 2.0 ** 40), synth.int_seed(6, synth.SUB_ENC, 500 + d))
+           for d in range(ell)]
+    q = ctx.encrypt(keys, ctx.encode(synth.replicate_query(wl.query, ctx.N // 2), ctx.L, 2.0 ** 40),
+                    synth.int_seed(6, synth.SUB_ENC, 999))
+    baby = [q] + ctx.rotate_hoisted(keys, q, range(1, n1))
+    return dict(ctx=ctx, keys=keys, tmp=tmp, wl=wl, enc=enc, tbs=tbs, tbe=tbe, baby=baby, n1=n1, ell=ell,
+                plain=plain, pre=pre, q=q)
+
+
+def oracle_encrypted_bsgs(ctx, keys, baby, diag, n1):
+    """Eq. bsgs2 over encrypted pre-rotated diagonals: per giant step the
+    relinearised, rescaled sum of baby-step x diagonal products, then the
+    giant rotate-sum."""
+    ell = len(diag)
+    P = [ctx.tensor_sum_relin_rescale(keys, baby[: min(n1, ell - j * n1)], diag[j * n1: j * n1 + n1])
+         for j in range((ell + n1 - 1) // n1)]
+    return ctx.rotate_sum(keys, P, n1)
+
+
+@pytest.mark.parametrize("form", ["tbs", "tbe"])
+def test_encrypted_bsgs_scores(encdb, form):
+    """Both pre-rotations (homomorphic by the server, TBS; in the plaintext
+    slots by the enroller, TBE) give the FP64 scores through the encrypted
+    BSGS product; the TBS diagonals decrypt to the TBE plaintexts."""
+    e = encdb
+    ctx, keys = e["ctx"], e["keys"]
+    S = oracle_encrypted_bsgs(ctx, keys, e["baby"], e[form], e["n1"])
+    dec = ctx.decrypt_decode(keys, S)
+    exact = e["wl"].exact_scores()
+    assert np.max(np.abs(dec[:64] - exact)) < 2 ** -19
+    if form == "tbs":
+        for d in (9, 70, 127):
+            got = ctx.decrypt_decode(keys, e["tbs"][d])
+            want = ctx.decode(ctx.pt_import(e["pre"].export(0, d), ctx.L, 2.0 ** 40))
+            assert np.max(np.abs(got - want)) < 2 ** -22  # one fresh encryption and one key switch
