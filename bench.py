@@ -714,7 +714,9 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch choices and "
                     "the fewest-products Chebyshev degree")
-    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay form")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the HIP-graph replay form (capture is switched off in the library: "
+                         "fr_graph_begin returns FR_EINVAL)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the steps, one device-to-device copy of this many MiB (the known-size "
                          "reference for the HBM byte counters)")
@@ -815,7 +817,7 @@ def main():
     out["service_ms"] = service_time(s, args.d1, args.steps)
     if tuned is not None:
         out["autotune"] = tuned
-    if not args.no_graph:
+    if args.graph:
         log("graph form ...")
         out["graph"] = graph_form(s, args.d1, args.steps)
     out["roofline_ks"] = hook_roofline(s, args.d1, "ks_inner", "key-switch inner product (k_ks_inner, k_ks_inner_sum)")

@@ -347,6 +347,10 @@ int fr_membership_aggregate(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, i
  *   calls of the context are ordered on its stream.  FR_EINVAL if the
  *   context's scratch was released since the recording
  *   (fr_ctx_set_scratch_limit below the allocation). */
+/* Switched off: fr_graph_begin returns FR_EINVAL.  A recording of the
+ * hoisted product followed by the Chebyshev ladder ended in a host fault
+ * inside the HIP runtime's capture end, with no cause established; the
+ * calls stay declared so that callers compile unchanged. */
 typedef struct fr_graph fr_graph;
 int fr_graph_begin(fr_ctx *ctx);
 int fr_graph_end(fr_ctx *ctx, fr_graph **out);
