@@ -194,6 +194,22 @@ int fr_rotate_hoisted(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const i
  * per rotation for the whole batch.  No output may alias any input. */
 int fr_rotate_hoisted_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, int32_t nq,
                             const int32_t *rots, int32_t nrot, fr_ct *outs);
+/* Allocation-free form of fr_rotate_hoisted, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (the same words)
+ * and errors as fr_rotate_hoisted; it calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch (the ModUp digits, the key inner products
+ * and the ModDown corrections) is a fixed device array of
+ * FR_NOALLOC_SCRATCH_BYTES per GPU, created with the library's code object
+ * and held until the process ends; rotations are taken in chunks that fit
+ * in it.  FR_ENOMEM, before any device work, when one rotation of `in`
+ * needs more than the array (at N = 2^16 a rotation needs 77.5 MiB at 15 Q
+ * limbs and 5 special primes, dnum 3).  Every call on one GPU, from any
+ * context or stream, uses the same array and leaves its contents behind:
+ * calls that overlap on one GPU race and must be ordered by the caller. */
+#define FR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int fr_rotate_hoisted_noalloc(fr_ctx *ctx, const fr_keys *keys, const fr_ct *in, const int32_t *rots,
+                              int32_t nrot, fr_ct *outs);
 /* Rescale (§3.2): drop q_l with centered rounding; scale /= q_l. */
 int fr_rescale(fr_ctx *ctx, const fr_ct *in, fr_ct *out);
 int fr_add(fr_ctx *ctx, const fr_ct *a, const fr_ct *b, fr_ct *out);

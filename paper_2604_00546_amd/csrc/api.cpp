@@ -9,6 +9,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 
 #include "fr_core.h"
 
@@ -111,6 +112,37 @@ void Arena::reset() {
 void Arena::release() {
     for (auto &ch : chunks) (void)hipFree(ch.base);
     chunks.clear();
+}
+
+// ---------------------------------------------------------------------------
+// fixed scratch of the allocation-free hoisted rotation
+// ---------------------------------------------------------------------------
+// One array per GPU, created with the code object and held until the process
+// ends.  Host code never passes the symbol itself to a kernel (on the host it
+// only stands in for the device array): the device address comes from
+// hipGetSymbolAddress, once per device, in fr_ctx_create.
+static __device__ __align__(256) unsigned char g_noalloc_scratch[FR_NOALLOC_SCRATCH_BYTES];
+static const int kMaxDevices = 64;
+static void *g_noalloc_addr[kMaxDevices];
+static std::mutex g_noalloc_mu;
+
+// the array's address on the current device (nullptr and a message on failure)
+static void *noalloc_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_noalloc_addr[dev] = ptr;
+    }
+    return g_noalloc_addr[dev];
 }
 
 namespace {
@@ -634,6 +666,15 @@ extern "C" int fr_ctx_create(const fr_params *p, fr_ctx **out) {
         c->klay.block = o;
     }
     int e = ctx_build(c);
+    if (!e) {  // the allocation-free rotation's scratch: a one-chunk arena over this device's array
+        void *fixed = noalloc_address();
+        if (!fixed)
+            e = fr_fail(FR_EHIP, "fr_ctx_create: no address for the fixed scratch array");
+        else {
+            c->fixed_arena.chunks.push_back({(char *)fixed, FR_NOALLOC_SCRATCH_BYTES, 0});
+            c->fixed_arena.limit = FR_NOALLOC_SCRATCH_BYTES;
+        }
+    }
     for (int a = 0; !e && a < fr_ctx::kAux; ++a)
         if (hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_join[a], hipEventDisableTiming) != hipSuccess)
@@ -1140,6 +1181,32 @@ extern "C" int fr_rotate_hoisted_batch(fr_ctx *c, const fr_keys *K, const fr_ct 
           "fr_rotate_hoisted_batch: null argument or nq < 1");
     c->arena.reset();
     return rotate_hoisted_impl(c, K, in, nq, rots, nrot, outs);
+} FR_CATCH(c)
+
+// Allocation-free form of fr_rotate_hoisted: the same sequence with the
+// context's arena swapped for the one-chunk arena over the fixed array (a
+// vector swap: no allocation), rotations taken in chunks that fit beside the
+// ModUp digits.  No kernel of the sequence reads scratch it has not written
+// in the same call, so the array needs no clearing.
+extern "C" int fr_rotate_hoisted_noalloc(fr_ctx *c, const fr_keys *K, const fr_ct *in, const int32_t *rots,
+                                         int32_t nrot, fr_ct *outs) try {
+    CHECK(c && K && in && (nrot == 0 || (rots && outs)), FR_EINVAL, "fr_rotate_hoisted_noalloc: null argument");
+    if (int e = check_ct(c, in, "fr_rotate_hoisted_noalloc")) return e;
+    CHECK(!c->fixed_arena.chunks.empty(), FR_EHIP, "fr_rotate_hoisted_noalloc: no fixed scratch on this device");
+    const size_t base = rotation_base_bytes(c, in->level, 1), per = rotation_scratch_bytes(c, in->level, 1);
+    CHECK(base + per <= FR_NOALLOC_SCRATCH_BYTES, FR_ENOMEM,
+          "fr_rotate_hoisted_noalloc: a rotation at level %d needs %zu bytes of scratch, the fixed array holds %zu",
+          in->level, base + per, (size_t)FR_NOALLOC_SCRATCH_BYTES);
+    struct Swap {
+        fr_ctx *c;
+        explicit Swap(fr_ctx *cc) : c(cc) {
+            c->fixed_arena.chunks[0].used = 0;
+            c->fixed_arena.hold = 0;
+            std::swap(c->arena, c->fixed_arena);
+        }
+        ~Swap() { std::swap(c->arena, c->fixed_arena); }
+    } swap(c);
+    return rotate_hoisted_impl(c, K, in, 1, rots, nrot, outs, FR_NOALLOC_SCRATCH_BYTES - base);
 } FR_CATCH(c)
 
 extern "C" int fr_rescale(fr_ctx *c, const fr_ct *in, fr_ct *out) try {

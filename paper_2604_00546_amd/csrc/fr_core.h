@@ -211,6 +211,9 @@ struct fr_ctx {
     hipEvent_t ev_dag[kDagEv] = {};
     static_assert(kDagEv % (1 + kAux) == 0, "DAG event slots must map to one stream each");
     Arena arena;
+    // fr_rotate_hoisted_noalloc: this device's fixed scratch array (its
+    // address from hipGetSymbolAddress) as a one-chunk arena that never grows
+    Arena fixed_arena;
     KeyLayout klay{};
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;

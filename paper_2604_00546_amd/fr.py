@@ -92,6 +92,7 @@ SIGNATURES = {
     "fr_bsgs_diag_matvec": (C.c_int, [_P, _P, _CTP, C.c_int32, _P, C.c_int32, _CTP]),
     "fr_chebyshev_eval": (C.c_int, [_P, _P, _CTP, _DP, C.c_int32, C.c_int32, _CTP]),
     "fr_rotate_hoisted_batch": (C.c_int, [_P, _P, _CTP, C.c_int32, _I32P, C.c_int32, _CTP]),
+    "fr_rotate_hoisted_noalloc": (C.c_int, [_P, _P, _CTP, _I32P, C.c_int32, _CTP]),
     "fr_membership_aggregate": (C.c_int, [_P, _P, _CTP, C.c_int32, _CTP]),
     "fr_tensor_sum_relin_rescale": (C.c_int, [_P, _P, _CTP, _CTP, C.c_int32, _CTP]),
     "fr_rotate_sum": (C.c_int, [_P, _P, _CTP, C.c_int32, C.c_int32, _CTP]),
@@ -465,6 +466,20 @@ class Context:
         r = np.ascontiguousarray(rots, dtype=np.int32)
         _check(lib().fr_rotate_hoisted(self.ptr, keys.ptr, ct.ref, r.ctypes.data_as(_I32P), len(r), arr),
                "fr_rotate_hoisted")
+        for o, d in zip(outs, arr):
+            o.desc.level, o.desc.scale = d.level, d.scale
+        return outs
+
+    def rotate_hoisted_noalloc(self, keys: Keys, ct: Ct, rots: Sequence[int],
+                               outs: List[Ct] | None = None) -> List[Ct]:
+        """fr_rotate_hoisted with the library's fixed per-GPU scratch array (no device allocation)."""
+        rots = list(rots)
+        if outs is None:
+            outs = [self.new_ct(ct.level) for _ in rots]
+        arr = (CtDesc * max(len(rots), 1))(*[o.desc for o in outs])
+        r = np.ascontiguousarray(rots, dtype=np.int32)
+        _check(lib().fr_rotate_hoisted_noalloc(self.ptr, keys.ptr, ct.ref, r.ctypes.data_as(_I32P), len(r), arr),
+               "fr_rotate_hoisted_noalloc")
         for o, d in zip(outs, arr):
             o.desc.level, o.desc.scale = d.level, d.scale
         return outs
