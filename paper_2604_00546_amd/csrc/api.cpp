@@ -1882,11 +1882,22 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
         // baby steps over Q_l U P: [qn][n1][2][nE][N]
         u64 *Bb = scratch(c, (size_t)qn * bq);
         frk::scale_ext(c, Bb, C, l, qn, bq, 2 * lw);
-        for (int i = 1; i < n1; ++i) {
-            const u64 g = galois_element(N, i);
-            u64 *Ui = Bb + i * bw;
-            frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, qn, dstride, bq, nullptr, 0, C,
-                          2 * lw);
+        if (frk::ks_inner_multi_ok(c, l)) {
+            // every baby step from one read of the digit set and of c0
+            std::vector<const unsigned char *> kp(n1 - 1);
+            std::vector<u64> gp(n1 - 1);
+            for (int i = 1; i < n1; ++i) {
+                gp[i - 1] = galois_element(N, i);
+                kp[i - 1] = K->find(gp[i - 1])->data;
+            }
+            frk::ks_inner_multi(c, Bb + bw, bw, D, kp.data(), gp.data(), n1 - 1, l, qn, dstride, bq, C, 2 * lw);
+        } else {
+            for (int i = 1; i < n1; ++i) {
+                const u64 g = galois_element(N, i);
+                u64 *Ui = Bb + i * bw;
+                frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, qn, dstride, bq, nullptr,
+                              0, C, 2 * lw);
+            }
         }
         // inner sums over Q_l U P: [qn][n2][2][nE][N]
         u64 *P = scratch(c, (size_t)qn * n2 * pw);

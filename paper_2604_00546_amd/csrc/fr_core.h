@@ -383,6 +383,13 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
 void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *ksk, u64 g, int level,
               bool accumulate, int batch = 1, size_t sd = 0, size_t su = 0, const u64 *fold_d = nullptr,
               size_t fold_sd = 0, const u64 *rot_c0 = nullptr, size_t c0_sd = 0);
+// Baby steps of the hoisted product, nrot rotations at once: rotation r's
+// outputs at U + r ub, (U0 over nE limbs, then U1), with P sigma_g(c0) folded
+// into U0 (the words ks_inner gives with rot_c0); the digit set D and c0 are
+// read once for all the rotations.  For 1 to 3 digits (ks_inner_multi_ok).
+bool ks_inner_multi_ok(const fr_ctx *c, int level);
+void ks_inner_multi(const fr_ctx *c, u64 *U, size_t ub, const u64 *D, const unsigned char *const *ksk, const u64 *g,
+                    int nrot, int level, int batch, size_t sd, size_t su, const u64 *c0, size_t c0_sd);
 // out[b][p][e] = P in[b][p][e] on the limbs e <= level and 0 on the special
 // limbs (a ciphertext at level `level` lifted to Q_l U P; out items so words
 // apart, polynomials nE limbs apart; in items si words apart)

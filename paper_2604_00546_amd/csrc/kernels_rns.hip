@@ -347,6 +347,75 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D,
                                  fold_sd, pinv_top, pinv_top_sh, rot_c0, c0_sd, pmont);
 }
 
+// Key inner products of several hoisted rotations of one ModUp digit set,
+// each output over Q_l U P with P sigma_g(c0) folded in (the baby steps of
+// the hoisted product): for rotation b with Galois element g_b,
+//   U0_b[e][p] = sum_t D_t[e][s] * ksk_{b,t,b}[gm(e)][p] + P c0[e][s] (e <= level),
+//   U1_b[e][p] = sum_t D_t[e][s] * ksk_{b,t,a}[gm(e)][p],
+// with s = auto_src(p, g_b).  A thread owns one source word s: it reads the
+// digit words D_t[e][s] and c0[e][s] once and, for each rotation, writes
+// output p = auto_src(s, g_b^-1) (the automorphism maps every aligned block
+// of 64 words onto an aligned block of 64 words, so a wave's keys and
+// outputs still fill whole cache lines).  The digit set and c0 are read
+// once for all the rotations instead of once per rotation.
+constexpr int kMultiRot = 32;
+struct MultiKeys {
+    const unsigned char *ksk[kMultiRot];
+    u64 ginv[kMultiRot];
+};
+template <int ND, bool PK>
+__device__ __forceinline__ void ks_multi_body(u64 *U, size_t ub, const u64 *D, const MultiKeys &mk, int nrot,
+                                              size_t kblock, unsigned koff, u32 s, int e, int N, int logN, int nE,
+                                              int level, const ModConst &m, const u64 *c0, const u64 *pmont) {
+    u32 d0[ND], d1[ND];
+#pragma unroll
+    for (int t = 0; t < ND; ++t) split30(D[((size_t)t * nE + e) * N + s], d0[t], d1[t]);
+    u32 c00 = 0, c01 = 0;
+    const bool has_c0 = e <= level;
+    if (has_c0) split30(c0[(size_t)e * N + s], c00, c01);
+    const u64 pm = has_c0 ? pmont[e] : 0;
+    for (int b = 0; b < nrot; ++b) {
+        const u32 p = auto_src(s, mk.ginv[b], logN);
+        const unsigned char *kl0 = mk.ksk[b] + koff;
+        u64 kb[ND], ka[ND];
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+            kb[t] = key_word<PK>(kl0 + (size_t)(t * 2) * kblock, p, N);
+            ka[t] = key_word<PK>(kl0 + (size_t)(t * 2 + 1) * kblock, p, N);
+        }
+        Dot30 s0, s1;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+            s0.add(d0[t], d1[t], kb[t]);
+            s1.add(d0[t], d1[t], ka[t]);
+        }
+        if (has_c0) s0.add(c00, c01, pm);
+        u64 *Ub = U + b * ub + (size_t)e * N + p;
+        Ub[0] = s0.redc(m);
+        Ub[(size_t)nE * N] = s1.redc(m);
+    }
+}
+
+template <int ND>
+__global__ __launch_bounds__(kT) void k_ks_inner_multi(u64 *U, size_t ub, const u64 *D, MultiKeys mk, int nrot,
+                                                       KeyLayout kl, int N, int logN, int nE, int level, int pbase,
+                                                       const ModConst *mods, size_t sd, size_t su, int batch,
+                                                       const u64 *c0, size_t c0_sd, const u64 *pmont) {
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const u32 s = tile * kT + threadIdx.x;
+    const int e = blockIdx.y;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    D += item * sd;
+    U += item * su;
+    c0 += item * c0_sd;
+    if (kl.packed[gm])
+        ks_multi_body<ND, true>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s, e, N, logN, nE, level, m, c0, pmont);
+    else
+        ks_multi_body<ND, false>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s, e, N, logN, nE, level, m, c0, pmont);
+}
+
 // Summed tensor products of ciphertext pairs (encrypted-database product):
 // t01 (+)= (sum a0 b0, sum a0 b1 + a1 b0), t2 (+)= sum a1 b1 over up to
 // kPairs pairs per launch, each sum a 128-bit lazy accumulation of at most
@@ -1179,6 +1248,36 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned ch
     hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, c->klay, g, c->N,
                        c->logN, nE, level, c->L + 1, ndig, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
                        pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
+}
+
+bool ks_inner_multi_ok(const fr_ctx *c, int level) {
+    const int ndig = (level + 1 + c->alpha - 1) / c->alpha;
+    return ndig >= 1 && ndig <= 3;
+}
+
+void ks_inner_multi(const fr_ctx *c, u64 *U, size_t ub, const u64 *D, const unsigned char *const *ksk, const u64 *g,
+                    int nrot, int level, int batch, size_t sd, size_t su, const u64 *c0, size_t c0_sd) {
+    const int nE = level + 1 + c->nP, ndig = (level + 1 + c->alpha - 1) / c->alpha;
+    const u64 twoN = 2ull * (u64)c->N;
+    for (int r0 = 0; r0 < nrot; r0 += kMultiRot) {
+        const int nr = std::min(kMultiRot, nrot - r0);
+        MultiKeys mk{};
+        for (int b = 0; b < nr; ++b) {
+            mk.ksk[b] = ksk[r0 + b];
+            // g^-1 mod 2N (g odd): Newton's iteration for the inverse mod a power of two
+            u64 x = g[r0 + b];
+            for (int it = 0; it < 6; ++it) x *= 2 - g[r0 + b] * x;
+            mk.ginv[b] = x & (twoN - 1);
+        }
+        // per item: the digit set and c0 once, then per rotation its key and both outputs
+        ProfScope ps(c, K_KS,
+                     batch * (1.0 * ndig * nE + (level + 1.0) + nr * 2.0 * nE) * 8.0 * c->N +
+                         nr * 2.0 * ndig * key_limb_bytes(c, level));
+        auto kern = ndig == 1 ? k_ks_inner_multi<1> : ndig == 2 ? k_ks_inner_multi<2> : k_ks_inner_multi<3>;
+        hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U + r0 * ub, ub, D, mk, nr,
+                           c->klay, c->N, c->logN, nE, level, c->L + 1, c->d_mod, sd, su, batch, c0, c0_sd,
+                           pmont_tab(c));
+    }
 }
 
 void scale_ext(const fr_ctx *c, u64 *out, const u64 *in, int level, int nb, size_t so, size_t si) {
