@@ -762,20 +762,6 @@ __global__ __launch_bounds__(kT) void k_decrypt_combine(u64 *out, const u64 *c0,
 // three sums that cannot overflow their words over 32 terms (below 2^64,
 // 2^56 and 2^32): three 32 x 32 -> 64-bit and one 24-bit multiply-add per
 // term in place of a full 64 x 64 product and its carries.
-// A wave-uniform address held in scalar registers as an opaque value, so the
-// compiler cannot fold lane offsets into it ahead of time: loads then take
-// the form uniform base + 32-bit lane offset, with no per-lane 64-bit adds.
-typedef const __attribute__((address_space(1))) unsigned char gbyte;
-__device__ __forceinline__ gbyte *uniform_ptr(const unsigned char *p) {
-    const u64 v = reinterpret_cast<u64>(p);
-    const u32 lo = __builtin_amdgcn_readfirstlane((u32)v), hi = __builtin_amdgcn_readfirstlane((u32)(v >> 32));
-    return reinterpret_cast<gbyte *>(((u64)hi << 32) | lo);
-}
-template <typename T>
-__device__ __forceinline__ T gload(gbyte *base, u32 off) {
-    return *reinterpret_cast<const __attribute__((address_space(1))) T *>(base + off);
-}
-
 // P_j = (hi:lo) 2^-64 mod q (+ P_j) for the tile's giant steps
 template <int NJ>
 __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi, int j0, int nj, int p, int lv, int m,
@@ -791,41 +777,66 @@ __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi,
     }
 }
 
+// The words of a block's tile go through LDS: for each baby step the
+// block's slice of its NJ diagonals (128 coefficients each: 512 low-word
+// bytes and 128 high bytes of a packed limb, or 1 KiB) and of the baby
+// step's c0 and c1 limbs (1 KiB each) is fetched with 16-byte loads into
+// registers one baby step ahead, stored to one of two LDS stages, and read
+// from there by the lanes (the c0 and the c1 half-wave read the same
+// diagonal words).  Per-lane 4-byte and 1-byte loads of the same bytes
+// stream at about two thirds of the rate of 16-byte loads.
 template <int NJ, bool FULL, bool PK>
 __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp, int q, int tile, int nb, int i0,
                                           int n1, int j0, int nj, int ell, size_t dstride, unsigned loff, int bl,
-                                          int lv, int N, const ModConst &mc, int accumulate) {
-    const int lane = threadIdx.x & 63, p = lane >> 5;
-    const int k = tile * (kT / 2) + (threadIdx.x >> 6) * 32 + (lane & 31), m = blockIdx.y;
+                                          int lv, int N, const ModConst &mc, int accumulate, unsigned char *lds) {
+    constexpr int SLOT = PK ? 640 : 1024;  // bytes of one diagonal's slice of the tile
+    constexpr int U4 = SLOT / 16, TOT = NJ * U4 + 128, PER = (TOT + kT - 1) / kT;
+    constexpr int BABY = NJ * SLOT;  // the stage's baby slice (c0 then c1, 1 KiB each) follows the diagonals'
+    const int t = threadIdx.x, lane = t & 63, p = lane >> 5;
+    const int kk = (t >> 6) * 32 + (lane & 31), k0 = tile * (kT / 2), k = k0 + kk, m = blockIdx.y;
     const unsigned char *dg = bp.diag[q] + loff;
     // diagonal (j0 + jj) n1 + i0 + ii at base + ii dstride + jj jstride
     const unsigned char *base = dg + ((size_t)j0 * n1 + i0) * dstride;
     const size_t jstride = (size_t)n1 * dstride;
-    const u32 boff = (u32)((((size_t)p * (bl + 1) + m) * N + k) * 8);
-    const u32 vw = (PK ? 4u : 8u) * (u32)k, vh = 4u * (u32)N + (u32)k;  // word (low word), high byte
     P += q * pq;
-    // the words of baby step ii: its baby word and NJ diagonal words (zero
-    // past ell or nj).  The lane offsets are redefined at each call so that
-    // they stay 32-bit operands of the loads instead of hoisted 64-bit sums.
-    auto fetch = [&](int ii, u64 &b, auto *w, u32 *wh) {
-        const unsigned char *row = base + (size_t)ii * dstride;
-        u32 ow = vw, oh = vh, ob = boff;
-        asm volatile("" : "+v"(ow), "+v"(oh), "+v"(ob));
-        b = gload<u64>(uniform_ptr(reinterpret_cast<const unsigned char *>(bp.p[q][ii])), ob);
+    uint4 r[PER];
+    // this thread's 16-byte pieces of baby step ii's slices (diagonals zero
+    // past ell or nj), then of the baby step's two limbs
+    auto fetch = [&](int ii) {
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const bool ok = FULL || (jj < nj && (j0 + jj) * n1 + i0 + ii < ell);
-            gbyte *r = uniform_ptr(ok ? row + jj * jstride : dg);
-            if constexpr (PK) {
-                w[jj] = gload<u32>(r, ow);
-                wh[jj] = gload<unsigned char>(r, oh);
-                if (!ok) wh[jj] = 0;
-            } else {
-                w[jj] = gload<u64>(r, ow);
+        for (int u = 0; u < PER; ++u) {
+            const int i = t + u * kT;
+            if (i >= NJ * U4 && i < TOT) {
+                const int w = i - NJ * U4, pb = w >> 6;
+                const unsigned char *bl0 = reinterpret_cast<const unsigned char *>(bp.p[q][ii]);
+                r[u] = *reinterpret_cast<const uint4 *>(bl0 + (((size_t)pb * (bl + 1) + m) * N + k0) * 8 +
+                                                        16 * (w & 63));
+            } else if (i < TOT) {
+                const int jj = i / U4, w = i - jj * U4;
+                const bool ok = FULL || (jj < nj && (j0 + jj) * n1 + i0 + ii < ell);
+                r[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (ok) {
+                    const unsigned char *row = base + (size_t)ii * dstride + jj * jstride;
+                    const unsigned char *src = !PK ? row + 8 * (size_t)k0 + 16 * w
+                                             : w < 32 ? row + 4 * (size_t)k0 + 16 * w
+                                                      : row + 4 * (size_t)N + k0 + 16 * (w - 32);
+                    r[u] = *reinterpret_cast<const uint4 *>(src);
+                }
             }
-            if (!ok) w[jj] = 0;
         }
     };
+    auto stage = [&](int b) {
+        uint4 *dst = reinterpret_cast<uint4 *>(lds + b * (NJ * SLOT + 2048));
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (t + u * kT < TOT) dst[t + u * kT] = r[u];
+    };
+    auto baby = [&](int ii) {
+        return reinterpret_cast<const u64 *>(lds + (ii & 1) * (NJ * SLOT + 2048) + BABY + p * 1024)[kk];
+    };
+    fetch(0);
+    stage(0);
+    __syncthreads();
     if constexpr (PK) {
         // A = sum b0 wl, Bm = sum (b1 wl + b0s wh), D = sum b1 wh
         u64 A[NJ], Bm[NJ];
@@ -833,17 +844,21 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) A[jj] = Bm[jj] = 0, D[jj] = 0;
         for (int ii = 0; ii < nb; ++ii) {
-            u64 b;
-            u32 wl[NJ], wh[NJ];
-            fetch(ii, b, wl, wh);
+            if (ii + 1 < nb) fetch(ii + 1);
+            const u64 b = baby(ii);
+            const unsigned char *st = lds + (ii & 1) * (NJ * SLOT + 2048);
             const u32 b0 = (u32)b & 0x7ffffffu, b1 = (u32)(b >> 27) & 0xffffffu, b0s = b0 << 5;
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
-                A[jj] += (u64)b0 * wl[jj];
-                Bm[jj] += (u64)b1 * wl[jj];
-                Bm[jj] += (u64)b0s * wh[jj];
-                D[jj] += b1 * wh[jj];
+                const u32 wl = reinterpret_cast<const u32 *>(st + jj * SLOT)[kk];
+                const u32 wh = st[jj * SLOT + 512 + kk];
+                A[jj] += (u64)b0 * wl;
+                Bm[jj] += (u64)b1 * wl;
+                Bm[jj] += (u64)b0s * wh;
+                D[jj] += b1 * wh;
             }
+            if (ii + 1 < nb) stage((ii + 1) & 1);
+            __syncthreads();
         }
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
@@ -858,10 +873,14 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
         for (int ii = 0; ii < nb; ++ii) {
-            u64 b, w[NJ];
-            fetch(ii, b, w, nullptr);
+            if (ii + 1 < nb) fetch(ii + 1);
+            const u64 b = baby(ii);
+            const unsigned char *st = lds + (ii & 1) * (NJ * SLOT + 2048);
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) acc[jj] += (unsigned __int128)b * w[jj];
+            for (int jj = 0; jj < NJ; ++jj)
+                acc[jj] += (unsigned __int128)b * reinterpret_cast<const u64 *>(st + jj * SLOT)[kk];
+            if (ii + 1 < nb) stage((ii + 1) & 1);
+            __syncthreads();
         }
         u64 lo[NJ], hi[NJ];
 #pragma unroll
@@ -874,16 +893,17 @@ template <int NJ, bool FULL>
 __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp, int nq, int nb, int i0, int n1, int j0,
                                                   int nj, int ell, size_t dstride, DbLayout lay, int bl, int lv, int N,
                                                   const ModConst *mods, int accumulate, int lq, int pofs) {
+    __shared__ __align__(16) unsigned char lds[2 * (NJ * 1024 + 2048)];
     int q, tile;
     item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
     const int m = blockIdx.y;
     const ModConst mc = mods[m <= lq ? m : m + pofs];
     if (lay.packed[m])
         mac3_body<NJ, FULL, true>(P, pq, bp, q, tile, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
-                                  accumulate);
+                                  accumulate, lds);
     else
         mac3_body<NJ, FULL, false>(P, pq, bp, q, tile, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
-                                   accumulate);
+                                   accumulate, lds);
 }
 
 // 64-bit limbs <-> the packed diagonal layout (grid: N / kT, nl, nd)
