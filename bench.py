@@ -238,6 +238,7 @@ def served(s, seconds, d1, rates=(10.0, 50.0, 200.0), pool=64):
                                   dbs[9] if kinds[i] else dbs[int(sizes[i])]) for i, t in enumerate(arr)]
         srv.batches = []
         b = srv.run(trace())
+        log(f"served {rate:g}/s: continuous batching done ({b['requests']} requests), plain loop ...")
         p = serve.plain(ctx, s["keys"], s["coeffs"], d1, n1, trace())
         out[f"{rate:g}/s"] = {"batched": b, "plain": p}
         log(f"served {rate:g}/s: batched p50 {b['latency_ms']['p50']:.1f} ms p99 {b['latency_ms']['p99']:.1f} ms; "

@@ -181,6 +181,7 @@ class Server:
         """Serve the trace in real time; returns latency and throughput figures."""
         import torch
         trace = sorted(trace, key=lambda r: r.arrival)
+        self.overlapped = self.split = 0  # counted per run
         waiting: List[Request] = []
         nxt, finished = 0, 0
         torch.cuda.synchronize()
