@@ -187,8 +187,11 @@ __global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, 
 // y_d = [x_{lo+d} * Dhat_d^-1]_{q_{lo+d}} (canonical), then for every
 // extended position e outside the digit: D[e] = sum_d y_d * [Dhat_d]_{r_e} mod r_e
 // (table entries Montgomery-scaled: one reduction of the 128-bit sum).
-__global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd, int nE, int level,
+// ND > 0: compiled for exactly ND limbs in the digit; ND = 0: any size
+template <int ND>
+__global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd_rt, int nE, int level,
                                               int pbase, const u64 *tab, const ModConst *mods, size_t sd, size_t sx) {
+    const int nd = ND ? ND : nd_rt;
     const int k = blockIdx.x * kT + threadIdx.x;
     D += blockIdx.z * sd;
     x += blockIdx.z * sx;
@@ -218,12 +221,13 @@ __global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int l
 struct ModupTabs {
     const u64 *tab[kMaxDigit];
 };
-__global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
-                                                  int level, int pbase, ModupTabs mt, const ModConst *mods, size_t sd,
-                                                  size_t sx, const u64 *own, size_t so) {
+template <int ND>
+__device__ __forceinline__ void modup_all_body(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
+                                               int level, int pbase, const ModupTabs &mt, const ModConst *mods,
+                                               size_t sd, size_t sx, const u64 *own, size_t so) {
     const int k = blockIdx.x * kT + threadIdx.x;
     const int t = tfirst + blockIdx.z % nt, b = blockIdx.z / nt;
-    const int lo = t * alpha, nd = min(alpha, level + 1 - lo);
+    const int lo = t * alpha, nd = ND ? ND : min(alpha, level + 1 - lo);
     D += b * sd + (size_t)t * nE * N;
     x += b * sx;
     if (own) own += b * so;
@@ -248,6 +252,19 @@ __global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, i
             if (d < nd) acc.add(y0[d], y1[d], dhat[(size_t)e * nd + d]);
         D[(size_t)e * N + k] = acc.redc(mods[gm]);
     }
+}
+
+// ALPHA > 0: digits of ALPHA limbs take the body compiled for that size (a
+// shorter last digit takes the general one)
+template <int ALPHA>
+__global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
+                                                  int level, int pbase, ModupTabs mt, const ModConst *mods, size_t sd,
+                                                  size_t sx, const u64 *own, size_t so) {
+    const int t = tfirst + blockIdx.z % nt;
+    if (ALPHA && min(alpha, level + 1 - t * alpha) == ALPHA)
+        modup_all_body<ALPHA>(D, x, N, tfirst, nt, alpha, nE, level, pbase, mt, mods, sd, sx, own, so);
+    else
+        modup_all_body<0>(D, x, N, tfirst, nt, alpha, nE, level, pbase, mt, mods, sd, sx, own, so);
 }
 
 // U{0,1}[e][p] (+)= sum_t D_t[e][src(p)] * ksk_t{b,a}[gm(e)][p]; keys are
@@ -547,10 +564,14 @@ __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, G
 // (d + ModDown(U) - NTT(c)) q_l^-1 = (d + (U - NTT(Z)) P^-1) q_l^-1 limb by limb.
 // Xu: coefficient forms of U's limbs at storage index (level .. level+nP)
 // in a [nE][N] layout per polynomial; Xd: coefficient form of d's limb l.
+// NP > 0: compiled for exactly NP special primes (the loops over them
+// unrolled without bounds tests); NP = 0: any count up to kMaxDigit
+template <int NP>
 __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu, const u64 *Xd, int N, int level,
-                                                           int nP, int pbase, int L1, const u64 *tab,
+                                                           int nP_rt, int pbase, int L1, const u64 *tab,
                                                            const ModConst *mods, size_t sz, size_t sxu, size_t sxd,
                                                            int no_d, const u64 *pbig) {
+    const int nP = NP ? NP : nP_rt;
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
     const u64 *pinv = tab + 2 * nP + (size_t)L1 * nP, *pinv_sh = pinv + L1;
@@ -613,9 +634,11 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
 // V_i = (sum_j y_j [Phat_j]_{q_i} - e [P]_{q_i}) mod q_i.
 // tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1],
 //      Pinv_sh[L+1], P_mod_q[L+1], inv_p[nP] (double bits)
-__global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP, int pbase,
+template <int NP>
+__global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP_rt, int pbase,
                                                     int L1, const u64 *tab, const ModConst *mods, size_t sv,
                                                     size_t su, const u64 *pbig) {
+    const int nP = NP ? NP : nP_rt;
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
     const u64 *pmod = tab + 2 * nP + (size_t)L1 * nP + 2 * L1;
@@ -1219,7 +1242,8 @@ void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int ba
     const int nE = level + 1 + c->nP;
     const int ntarget = nE - nd;
     dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, batch);
-    hipLaunchKernelGGL(k_modup, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
+    auto kern = nd == 5 ? k_modup<5> : nd == 4 ? k_modup<4> : nd == 1 ? k_modup<1> : k_modup<0>;
+    hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
                        c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx);
 }
 
@@ -1236,7 +1260,8 @@ void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size
             maxt = std::max(maxt, nE - std::min(c->alpha, level + 1 - t * c->alpha));
         }
         dim3 g(c->N / kT, (maxt + kTargetsPerThread - 1) / kTargetsPerThread, nt * batch);
-        hipLaunchKernelGGL(k_modup_all, g, dim3(kT), 0, c->stream, D, x, c->N, t0, nt, c->alpha, nE, level, c->L + 1,
+        auto kern = c->alpha == 5 ? k_modup_all<5> : c->alpha == 1 ? k_modup_all<1> : k_modup_all<0>;
+        hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, D, x, c->N, t0, nt, c->alpha, nE, level, c->L + 1,
                            mt, c->d_mod, sd, sx, own, so);
     }
 }
@@ -1361,7 +1386,8 @@ void relin_rescale_prep(const fr_ctx *c, u64 *Z, const u64 *Xu, const u64 *Xd, i
                         size_t sxu, size_t sxd, bool no_d) {
     ProfScope ps(c, K_MODDOWN, npoly * (2.0 + c->nP + 1.0 * level) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + kFbcTargets - 1) / kFbcTargets, npoly);
-    hipLaunchKernelGGL(k_relin_rescale_prep, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
+    auto kern = c->nP == 5 ? k_relin_rescale_prep<5> : c->nP == 1 ? k_relin_rescale_prep<1> : k_relin_rescale_prep<0>;
+    hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, Z, Xu, Xd, c->N, level, c->nP, c->L + 1,
                        c->L + 1, c->d_moddown, c->d_mod, sz, sxu, sxd, (int)no_d, c->d_pbig);
 }
 
@@ -1372,7 +1398,8 @@ void fold_top(const fr_ctx *c, u64 *U, const u64 *d, int level, int npoly, size_
 void moddown_fbc(const fr_ctx *c, u64 *V, const u64 *Upc, int level, int npoly) {
     ProfScope ps(c, K_MODDOWN, npoly * (1.0 * c->nP + 1.0 * (level + 1)) * 8.0 * c->N);
     dim3 g(c->N / kT, (level + 1 + kFbcTargets - 1) / kFbcTargets, npoly);
-    hipLaunchKernelGGL(k_moddown_fbc, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
+    auto kern = c->nP == 5 ? k_moddown_fbc<5> : c->nP == 1 ? k_moddown_fbc<1> : k_moddown_fbc<0>;
+    hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, V, Upc, c->N, level, c->nP, c->L + 1, c->L + 1,
                        c->d_moddown, c->d_mod, (size_t)(level + 1) * c->N, (size_t)c->nP * c->N, c->d_pbig);
 }
 
