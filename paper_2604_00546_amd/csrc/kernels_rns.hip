@@ -189,8 +189,9 @@ __global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, 
 // (table entries Montgomery-scaled: one reduction of the 128-bit sum).
 // ND > 0: compiled for exactly ND limbs in the digit; ND = 0: any size
 template <int ND>
-__global__ __launch_bounds__(kT) void k_modup(u64 *D, const u64 *x, int N, int lo, int nd_rt, int nE, int level,
-                                              int pbase, const u64 *tab, const ModConst *mods, size_t sd, size_t sx) {
+__global__ __launch_bounds__(kT) void k_modup(u64 *__restrict__ D, const u64 *__restrict__ x, int N, int lo, int nd_rt,
+                                              int nE, int level, int pbase, const u64 *__restrict__ tab,
+                                              const ModConst *__restrict__ mods, size_t sd, size_t sx) {
     const int nd = ND ? ND : nd_rt;
     const int k = blockIdx.x * kT + threadIdx.x;
     D += blockIdx.z * sd;
@@ -257,9 +258,10 @@ __device__ __forceinline__ void modup_all_body(u64 *D, const u64 *x, int N, int 
 // ALPHA > 0: digits of ALPHA limbs take the body compiled for that size (a
 // shorter last digit takes the general one)
 template <int ALPHA>
-__global__ __launch_bounds__(kT) void k_modup_all(u64 *D, const u64 *x, int N, int tfirst, int nt, int alpha, int nE,
-                                                  int level, int pbase, ModupTabs mt, const ModConst *mods, size_t sd,
-                                                  size_t sx, const u64 *own, size_t so) {
+__global__ __launch_bounds__(kT) void k_modup_all(u64 *__restrict__ D, const u64 *__restrict__ x, int N, int tfirst,
+                                                  int nt, int alpha, int nE, int level, int pbase, ModupTabs mt,
+                                                  const ModConst *__restrict__ mods, size_t sd, size_t sx,
+                                                  const u64 *__restrict__ own, size_t so) {
     const int t = tfirst + blockIdx.z % nt;
     if (ALPHA && min(alpha, level + 1 - t * alpha) == ALPHA)
         modup_all_body<ALPHA>(D, x, N, tfirst, nt, alpha, nE, level, pbase, mt, mods, sd, sx, own, so);
@@ -567,10 +569,11 @@ __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, G
 // NP > 0: compiled for exactly NP special primes (the loops over them
 // unrolled without bounds tests); NP = 0: any count up to kMaxDigit
 template <int NP>
-__global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu, const u64 *Xd, int N, int level,
-                                                           int nP_rt, int pbase, int L1, const u64 *tab,
-                                                           const ModConst *mods, size_t sz, size_t sxu, size_t sxd,
-                                                           int no_d, const u64 *pbig) {
+__global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *__restrict__ Z, const u64 *__restrict__ Xu,
+                                                           const u64 *__restrict__ Xd, int N, int level, int nP_rt,
+                                                           int pbase, int L1, const u64 *__restrict__ tab,
+                                                           const ModConst *__restrict__ mods, size_t sz, size_t sxu,
+                                                           size_t sxd, int no_d, const u64 *__restrict__ pbig) {
     const int nP = NP ? NP : nP_rt;
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
@@ -635,9 +638,10 @@ __global__ __launch_bounds__(kT) void k_relin_rescale_prep(u64 *Z, const u64 *Xu
 // tab: phat_inv[nP], phat_inv_sh[nP], phat_mod[(L+1)][nP], Pinv[L+1],
 //      Pinv_sh[L+1], P_mod_q[L+1], inv_p[nP] (double bits)
 template <int NP>
-__global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *V, const u64 *Upc, int N, int level, int nP_rt, int pbase,
-                                                    int L1, const u64 *tab, const ModConst *mods, size_t sv,
-                                                    size_t su, const u64 *pbig) {
+__global__ __launch_bounds__(kT) void k_moddown_fbc(u64 *__restrict__ V, const u64 *__restrict__ Upc, int N, int level,
+                                                    int nP_rt, int pbase, int L1, const u64 *__restrict__ tab,
+                                                    const ModConst *__restrict__ mods, size_t sv, size_t su,
+                                                    const u64 *__restrict__ pbig) {
     const int nP = NP ? NP : nP_rt;
     const int k = blockIdx.x * kT + threadIdx.x, poly = blockIdx.z;
     const u64 *phat_inv = tab, *phat_inv_sh = tab + nP, *phat_mod = tab + 2 * nP;
