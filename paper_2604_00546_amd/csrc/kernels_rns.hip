@@ -342,12 +342,12 @@ __device__ __forceinline__ void ks_inner_body(u64 *U0, u64 *U1, const u64 *D, co
 }
 
 template <int ND>
-__global__ __launch_bounds__(kT) void k_ks_inner(u64 *U0, u64 *U1, const u64 *D, const unsigned char *ksk,
+__global__ __launch_bounds__(kT) void k_ks_inner(u64 *__restrict__ U0, u64 *__restrict__ U1, const u64 *__restrict__ D, const unsigned char *__restrict__ ksk,
                                                  KeyLayout kl, u64 g, int N, int logN, int nE, int level, int pbase,
-                                                 int ndig, const ModConst *mods, int accumulate, size_t sd, size_t su,
-                                                 int batch, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
-                                                 u64 pinv_top_sh, const u64 *rot_c0, size_t c0_sd,
-                                                 const u64 *pmont) {
+                                                 int ndig, const ModConst *__restrict__ mods, int accumulate, size_t sd, size_t su,
+                                                 int batch, const u64 *__restrict__ fold_d, size_t fold_sd, u64 pinv_top,
+                                                 u64 pinv_top_sh, const u64 *__restrict__ rot_c0, size_t c0_sd,
+                                                 const u64 *__restrict__ pmont) {
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
     const int p = tile * kT + threadIdx.x, e = blockIdx.y;
@@ -416,10 +416,10 @@ __device__ __forceinline__ void ks_multi_body(u64 *U, size_t ub, const u64 *D, c
 }
 
 template <int ND>
-__global__ __launch_bounds__(kT) void k_ks_inner_multi(u64 *U, size_t ub, const u64 *D, MultiKeys mk, int nrot,
+__global__ __launch_bounds__(kT) void k_ks_inner_multi(u64 *__restrict__ U, size_t ub, const u64 *__restrict__ D, MultiKeys mk, int nrot,
                                                        KeyLayout kl, int N, int logN, int nE, int level, int pbase,
-                                                       const ModConst *mods, size_t sd, size_t su, int batch,
-                                                       const u64 *c0, size_t c0_sd, const u64 *pmont) {
+                                                       const ModConst *__restrict__ mods, size_t sd, size_t su, int batch,
+                                                       const u64 *__restrict__ c0, size_t c0_sd, const u64 *__restrict__ pmont) {
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
     const u32 s = tile * kT + threadIdx.x;
@@ -526,9 +526,9 @@ __device__ __forceinline__ void ks_inner_sum_body(u64 *U0, u64 *U1, const u64 *D
 }
 
 template <int ND>
-__global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64 *D, GiantKeys gk, KeyLayout kl,
+__global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *__restrict__ U0, u64 *__restrict__ U1, const u64 *__restrict__ D, GiantKeys gk, KeyLayout kl,
                                                      int nj, size_t sdj, int N, int logN, int nE, int level,
-                                                     int pbase, int ndig, const ModConst *mods, int accumulate,
+                                                     int pbase, int ndig, const ModConst *__restrict__ mods, int accumulate,
                                                      size_t sd, size_t su, int batch) {
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
@@ -548,8 +548,8 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *U0, u64 *U1, const u64
 
 // out[b][i][k] += sum_j in[b][j][i][auto_src(k, g_j)] (c0 parts of the giant
 // steps; in items sij words apart per j and sib per b, out sob per b)
-__global__ __launch_bounds__(kT) void k_automorph_sum(u64 *out, const u64 *in, GiantKeys gk, int nj, int N, int logN,
-                                                      size_t sob, size_t sij, size_t sib, const ModConst *mods) {
+__global__ __launch_bounds__(kT) void k_automorph_sum(u64 *__restrict__ out, const u64 *__restrict__ in, GiantKeys gk, int nj, int N, int logN,
+                                                      size_t sob, size_t sij, size_t sib, const ModConst *__restrict__ mods) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
     const u64 q = mods[i].q;
     const u64 *ib = in + b * sib + (size_t)i * N;
@@ -980,8 +980,8 @@ struct RotItems {
     u64 *out[kRotItems];
     const u64 *in[kRotItems];
 };
-__global__ __launch_bounds__(kT) void k_moddown_rot(RotItems it, const u64 *U, const u64 *V, u64 g, int N, int logN,
-                                                    int lp1, const u64 *pinv, const u64 *pinv_sh, const ModConst *mods,
+__global__ __launch_bounds__(kT) void k_moddown_rot(RotItems it, const u64 *__restrict__ U, const u64 *__restrict__ V, u64 g, int N, int logN,
+                                                    int lp1, const u64 *__restrict__ pinv, const u64 *__restrict__ pinv_sh, const ModConst *__restrict__ mods,
                                                     size_t su) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, p = blockIdx.z & 1, b = blockIdx.z >> 1;
     const u64 q = mods[i].q;
@@ -1122,8 +1122,8 @@ __global__ __launch_bounds__(kT) void k_tensor_batch(u64 *t01, u64 *t2, TensorBa
 
 // out[b][p][e] = P in[b][p][e] (e <= level), 0 on the special limbs: a
 // ciphertext lifted to Q_l U P (pmont: P 2^64 mod q_e)
-__global__ __launch_bounds__(kT) void k_scale_ext(u64 *out, const u64 *in, int level, int nE, int N, size_t so,
-                                                  size_t si, const u64 *pmont, const ModConst *mods) {
+__global__ __launch_bounds__(kT) void k_scale_ext(u64 *__restrict__ out, const u64 *__restrict__ in, int level, int nE, int N, size_t so,
+                                                  size_t si, const u64 *__restrict__ pmont, const ModConst *__restrict__ mods) {
     const int k = blockIdx.x * kT + threadIdx.x, e = blockIdx.y, p = blockIdx.z & 1, b = blockIdx.z >> 1;
     u64 r = 0;
     if (e <= level) {
