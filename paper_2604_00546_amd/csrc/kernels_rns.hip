@@ -376,7 +376,10 @@ __global__ __launch_bounds__(kT) void k_ks_inner(u64 *__restrict__ U0, u64 *__re
 // output p = auto_src(s, g_b^-1) (the automorphism maps every aligned block
 // of 64 words onto an aligned block of 64 words, so a wave's keys and
 // outputs still fill whole cache lines).  The digit set and c0 are read
-// once for all the rotations instead of once per rotation.
+// once for all the rotations instead of once per rotation.  The outputs
+// (31 baby steps of 20 MiB at N = 2^16, more than the last-level cache
+// holds) are written with non-temporal stores, so that their write-backs
+// do not fall into the MAC that reads them next.
 constexpr int kMultiRot = 32;
 struct MultiKeys {
     const unsigned char *ksk[kMultiRot];
@@ -410,8 +413,8 @@ __device__ __forceinline__ void ks_multi_body(u64 *U, size_t ub, const u64 *D, c
         }
         if (has_c0) s0.add(c00, c01, pm);
         u64 *Ub = U + b * ub + (size_t)e * N + p;
-        Ub[0] = s0.redc(m);
-        Ub[(size_t)nE * N] = s1.redc(m);
+        __builtin_nontemporal_store(s0.redc(m), Ub);
+        __builtin_nontemporal_store(s1.redc(m), Ub + (size_t)nE * N);
     }
 }
 
