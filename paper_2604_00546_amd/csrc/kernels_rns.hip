@@ -808,6 +808,11 @@ __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi,
     }
 }
 
+// cache-policy operand of a global-to-LDS load: non-temporal (the words are
+// streamed once; they should not displace what the caches hold for the
+// kernels around this one)
+constexpr int kCachePolicyNT = 2;
+
 // 16 zero bytes: the source of a staged piece of a diagonal past ell or nj
 // (and of a stage's padding)
 __device__ __align__(16) uint4 g_mac_zero = {0u, 0u, 0u, 0u};
@@ -872,7 +877,7 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
                 }
             }
             __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0,
-                                             0);
+                                             kCachePolicyNT);
         }
     };
     auto baby = [&](int ii) {
