@@ -808,9 +808,12 @@ __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi,
     }
 }
 
-// cache-policy operand of a global-to-LDS load: non-temporal (the words are
-// streamed once; they should not displace what the caches hold for the
-// kernels around this one)
+// cache-policy operand of a global-to-LDS load: non-temporal.  A one-query
+// MAC streams its words once, and they should not displace what the caches
+// hold for the kernels around it; with several queries per launch the
+// blocks of one tile share it through the L2, and the default policy is
+// kept (measured: 2.84 -> 2.79 ms for the one-query product, 4.00 -> 3.96
+// ms per query batched when the batched launch keeps the default).
 constexpr int kCachePolicyNT = 2;
 
 // 16 zero bytes: the source of a staged piece of a diagonal past ell or nj
@@ -838,7 +841,7 @@ constexpr int mac3_stage_bytes() {
 // 1-byte loads of the same bytes stream at about two thirds of the rate of
 // 16-byte loads.
 template <int NJ, bool FULL, bool PK>
-__device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp, int q, int tile, int m, int nb,
+__device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp, int nq, int q, int tile, int m, int nb,
                                           int i0, int n1, int j0, int nj, int ell, size_t dstride, unsigned loff,
                                           int bl, int lv, int N, const ModConst &mc, int accumulate,
                                           unsigned char *lds) {
@@ -876,8 +879,12 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
                                  : row + 4 * (size_t)N + k0 + 16 * (w - 32);
                 }
             }
-            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0,
-                                             kCachePolicyNT);
+            if (nq == 1)
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16,
+                                                 0, kCachePolicyNT);
+            else  // the blocks of the launch's queries share each tile through the L2
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16,
+                                                 0, 0);
         }
     };
     auto baby = [&](int ii) {
@@ -952,7 +959,7 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
     for (unsigned y = blockIdx.y; y; --y) sel &= sel - 1;
     const int m = __builtin_ctz(sel);
     const ModConst mc = mods[m <= lq ? m : m + pofs];
-    mac3_body<NJ, FULL, PK>(P, pq, bp, q, tile, m, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
+    mac3_body<NJ, FULL, PK>(P, pq, bp, nq, q, tile, m, nb, i0, n1, j0, nj, ell, dstride, lay.off[m], bl, lv, N, mc,
                             accumulate, lds);
 }
 
