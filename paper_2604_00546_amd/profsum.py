@@ -6,7 +6,7 @@ region.  This script restricts the trace (or the counter collection) to
 those dispatches and prints per-kernel figures per step.
 
 usage:
-  python -m paper_2604_00546_amd.profsum trace <run_kernel_trace.csv> --steps S --calib-mib M
+  python -m paper_2604_00546_amd.profsum trace <run_kernel_trace.csv> [--steps S] --calib-mib M
   python -m paper_2604_00546_amd.profsum counters <fetch.csv> <write.csv> --calib-mib M
   python -m paper_2604_00546_amd.profsum sq <sq_counter_collection.csv>
   python -m paper_2604_00546_amd.profsum ntt <run_kernel_trace.csv> --calib-mib M
@@ -21,25 +21,28 @@ def _short(name: str) -> str:
     return n.split("(")[0]
 
 
-def _after_marker(rows, calib_mib, size_key):
-    """Rows after the calibration copy (the copy kernel that moves calib_mib MiB)."""
-    start = None
-    for i, r in enumerate(rows):
-        if "copyBuffer" in r["Kernel_Name"] and size_key(r) >= calib_mib * 1024 * 0.45:
-            start = i
-    if start is None:
+def _calib_index(rows):
+    """Index of the calibration copy in a time-ordered kernel trace: the
+    first device copy that takes at least half as long as the longest one.
+    (Copies to pinned host memory later in the run, such as the result
+    downloads of the service-time steps, are copy kernels of similar
+    duration; the calibration copy comes before all of them.)"""
+    dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    cand = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"]
+    if not cand:
         raise SystemExit("calibration copy not found in the trace")
-    return rows[start + 1:], rows[start]
+    longest = max(dur(rows[i]) for i in cand)
+    return next(i for i in cand if 2 * dur(rows[i]) >= longest)
 
 
 def trace(path, steps, calib_mib):
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    # the copy kernel's grid covers M MiB; identify it as the last long copy
-    cand = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"]
     dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    start = max(cand, key=lambda i: dur(rows[i]))
-    timed = rows[start + 1:]
+    timed = rows[_calib_index(rows) + 1:]
+    if steps <= 0:
+        # one k_scale_ext per hoisted product: the number of queries in the region
+        steps = sum(1 for r in timed if _short(r["Kernel_Name"]) == "k_scale_ext")
     agg = collections.defaultdict(lambda: [0, 0])
     for r in timed:
         a = agg[_short(r["Kernel_Name"])]
@@ -60,11 +63,9 @@ def ntt_sizes(path, calib_mib, n_coeff=65536):
     pass's algorithmic HBM rate (16 B per coefficient: one read, one write)."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    cand = [i for i, r in enumerate(rows) if _short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer"]
     dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    start = max(cand, key=lambda i: dur(rows[i]))
     agg = collections.defaultdict(lambda: [0, 0])
-    for r in rows[start + 1:]:
+    for r in rows[_calib_index(rows) + 1:]:
         k = _short(r["Kernel_Name"])
         if not k.startswith(("k_fwd_", "k_inv_")):
             continue
@@ -141,7 +142,8 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("path")
-    t.add_argument("--steps", type=int, required=True)
+    t.add_argument("--steps", type=int, default=0,
+                   help="queries in the timed region (default: counted, one k_scale_ext per hoisted product)")
     t.add_argument("--calib-mib", type=int, required=True)
     c = sub.add_parser("counters")
     c.add_argument("fetch")
