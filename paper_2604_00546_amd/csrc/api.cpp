@@ -262,8 +262,8 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
         frk::ntt_fwd(c, D, nE, ext, ndig * batch, (size_t)nE * N, nullptr, 0, own ? c->alpha : 0, ndig, level + 1);
         return;
     }
-    // large batches: per digit, transforming only the converted limbs and
-    // copying the digit's own evaluation-form limbs.  The digits are
+    // large batches: per digit, transforming only the converted limbs (the
+    // conversion launch also copies the digit's own evaluation-form limbs).  The digits are
     // independent: outside a region that already spreads work over the
     // auxiliary streams, digit t > 0 runs on one of them
     const hipStream_t main_stream = c->stream;
@@ -277,15 +277,9 @@ void ks_modup(fr_ctx *c, const u64 *c1, int level, u64 *D, int batch = 1, size_t
         c->stream = (naux > 0 && t > 0) ? c->aux[(t - 1) % naux] : main_stream;
         u64 *Dt = D + (size_t)t * nE * N;
         const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
-        frk::modup_digit(c, Dt, X, level, t, batch, dstride, lw);
+        frk::modup_digit(c, Dt, X, level, t, batch, dstride, lw, c1, c1_stride);
         LimbMap m{0, lo, nd, level + 1, c->L + 1};
         frk::ntt_fwd(c, Dt, nE - nd, m, batch, dstride);
-        if (batch == 1)
-            (void)hipMemcpyAsync(Dt + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)nd * N * 8,
-                                 hipMemcpyDeviceToDevice, c->stream);
-        else
-            (void)hipMemcpy2DAsync(Dt + (size_t)lo * N, dstride * 8, c1 + (size_t)lo * N, c1_stride * 8,
-                                   (size_t)nd * N * 8, batch, hipMemcpyDeviceToDevice, c->stream);
     }
     c->stream = main_stream;
     for (int a = 0; a < naux; ++a) {

@@ -371,9 +371,10 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
 void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx,
                const u64 *own = nullptr, size_t so = 0);
 // fast base conversion of one digit: coefficient-form x[level+1][N] ->
-// D[nE][N] coefficient form on every extended limb outside the digit
+// D[nE][N] coefficient form on every extended limb outside the digit; with
+// own, the digit's own limbs of D are copied from own (items so words apart)
 void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch = 1, size_t sd = 0,
-                 size_t sx = 0);
+                 size_t sx = 0, const u64 *own = nullptr, size_t so = 0);
 // U{0,1}[e][p] (+)= sum_t D_t[e][auto_src(p, g)] * ksk_t{b,a}[gm(e)][p];
 // with fold_d (relinearisation, items fold_sd words apart) the top limb e =
 // level is replaced by d_l + P^-1 U_l (its only later use); with rot_c0

@@ -191,11 +191,18 @@ __global__ __launch_bounds__(kT) void k_mont_scale(u64 *data, int N, size_t ps, 
 template <int ND>
 __global__ __launch_bounds__(kT) void k_modup(u64 *__restrict__ D, const u64 *__restrict__ x, int N, int lo, int nd_rt,
                                               int nE, int level, int pbase, const u64 *__restrict__ tab,
-                                              const ModConst *__restrict__ mods, size_t sd, size_t sx) {
+                                              const ModConst *__restrict__ mods, size_t sd, size_t sx,
+                                              const u64 *__restrict__ own, size_t so) {
     const int nd = ND ? ND : nd_rt;
     const int k = blockIdx.x * kT + threadIdx.x;
     D += blockIdx.z * sd;
     x += blockIdx.z * sx;
+    if (own && blockIdx.y == 0) {  // the digit's own limbs, evaluation form as given
+        own += blockIdx.z * so;
+#pragma unroll
+        for (int d = 0; d < kMaxDigit; ++d)
+            if (d < nd) D[(size_t)(lo + d) * N + k] = own[(size_t)(lo + d) * N + k];
+    }
     const u64 *dinv = tab, *dinv_sh = tab + nd, *dhat = tab + 2 * nd;
     u32 y0[kMaxDigit], y1[kMaxDigit];
 #pragma unroll
@@ -1270,15 +1277,16 @@ void mont_scale(const fr_ctx *c, u64 *data, int nlimbs, const LimbMap &map, int 
                        c->d_mod, (int)to_mont);
 }
 
-void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch, size_t sd, size_t sx) {
-    ProfScope ps(c, K_MODUP, (double)batch * (level + 1 + c->nP) * 8.0 * c->N);
+void modup_digit(const fr_ctx *c, u64 *D, const u64 *x, int level, int t, int batch, size_t sd, size_t sx,
+                 const u64 *own, size_t so) {
     const int lo = t * c->alpha, nd = std::min(c->alpha, level + 1 - lo);
+    ProfScope ps(c, K_MODUP, (double)batch * (level + 1 + c->nP + (own ? 2 * nd : 0)) * 8.0 * c->N);
     const int nE = level + 1 + c->nP;
     const int ntarget = nE - nd;
     dim3 g(c->N / kT, (ntarget + kTargetsPerThread - 1) / kTargetsPerThread, batch);
     auto kern = nd == 5 ? k_modup<5> : nd == 4 ? k_modup<4> : nd == 1 ? k_modup<1> : k_modup<0>;
     hipLaunchKernelGGL(kern, g, dim3(kT), 0, c->stream, D, x, c->N, lo, nd, nE, level, c->L + 1,
-                       c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx);
+                       c->d_modup + c->modup_off[level][t], c->d_mod, sd, sx, own, so);
 }
 
 void modup_all(const fr_ctx *c, u64 *D, const u64 *x, int level, int batch, size_t sd, size_t sx, const u64 *own,
