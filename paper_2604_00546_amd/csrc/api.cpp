@@ -2225,8 +2225,10 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
     StreamRestore restore(c->stream);
     const int nstream = 1 + fr_ctx::kAux;
     auto stream_of = [&](int s) { return s == 0 ? main_stream : c->aux[s - 1]; };
-    std::vector<int> prod_ev(n, -1), prod_st(n, 0);  // event slot / stream of each node's group
-    int ev_next = 0, rr = 0;
+    // event slot, stream and issue order of the group that produced each node
+    std::vector<int> prod_ev(n, -1), prod_st(n, 0), prod_seq(n, -1);
+    constexpr int kSlots = fr_ctx::kDagEv / (1 + fr_ctx::kAux);
+    int ev_next[1 + fr_ctx::kAux] = {}, rr = 0, seq = 0;
     bool aux_used = false;
     FR_HIP(hipEventRecord(c->ev_fork, main_stream));  // the inputs, for the auxiliary streams
     for (int d = 1; d <= maxd; ++d) {
@@ -2382,10 +2384,27 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                 return FR_OK;
             });
         }
-        // each group on the next stream in turn, after the events of the
-        // groups (on other streams) that produced its inputs
+        // each group on the stream of its most recently issued input (that
+        // input's producer is the likeliest to finish last, and a wait on
+        // the group's own stream costs nothing), unless another group of this
+        // depth took that stream already; else on the next free stream in
+        // turn.  It waits for the events of the groups on other streams that
+        // produced its inputs.
+        std::vector<char> taken(nstream, 0);
         for (size_t g = 0; g < groups.size(); ++g) {
-            const int st = rr++ % nstream;
+            int st = -1, latest = -1;
+            for (int x : gin[g])
+                if (prod_seq[x] > latest) latest = prod_seq[x], st = prod_st[x];
+            if (st < 0 || taken[st]) {
+                st = rr % nstream;
+                for (int k = 0; k < nstream; ++k)
+                    if (!taken[(rr + k) % nstream]) {
+                        st = (rr + k) % nstream;
+                        break;
+                    }
+                ++rr;
+            }
+            taken[st] = 1;
             const hipStream_t s = stream_of(st);
             if (st > 0 && !aux_used) {
                 for (int a = 0; a < fr_ctx::kAux; ++a) FR_HIP(hipStreamWaitEvent(c->aux[a], c->ev_fork, 0));
@@ -2403,12 +2422,14 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             const int e = groups[g]();
             c->stream = main_stream;
             if (e) return e;
-            const int ev = ev_next++ % fr_ctx::kDagEv;
+            const int ev = st * kSlots + ev_next[st]++ % kSlots;
             FR_HIP(hipEventRecord(c->ev_dag[ev], s));
             for (int x : gout[g]) {
                 prod_ev[x] = ev;
                 prod_st[x] = st;
+                prod_seq[x] = seq;
             }
+            ++seq;
         }
     }
     if (aux_used)

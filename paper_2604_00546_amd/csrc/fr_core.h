@@ -202,14 +202,14 @@ struct fr_ctx {
     static const int kAux = 3;
     hipStream_t aux[kAux] = {};
     hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
-    // ring of events marking finished groups of a recorded DAG.  Groups go to
-    // the 1 + kAux streams in turn and take the ring's slots in turn, so with
-    // kDagEv a multiple of the stream count a slot is always re-recorded on
-    // the stream that recorded it before, after the work it marked: a waiter
-    // that reads the newer record waits at least as long as it needs to
+    // events marking finished groups of a recorded DAG: kDagEv / (1 + kAux)
+    // slots per stream, taken in turn by the groups that stream runs, so a
+    // slot is only ever re-recorded on the stream that recorded it before,
+    // after the work it marked: a waiter that reads the newer record waits at
+    // least as long as it needs to
     static const int kDagEv = 64;
     hipEvent_t ev_dag[kDagEv] = {};
-    static_assert(kDagEv % (1 + kAux) == 0, "DAG event slots must map to one stream each");
+    static_assert(kDagEv % (1 + kAux) == 0, "DAG event slots must split evenly over the streams");
     Arena arena;
     // fr_rotate_hoisted_noalloc: this device's fixed scratch array (its
     // address from hipGetSymbolAddress) as a one-chunk arena that never grows
