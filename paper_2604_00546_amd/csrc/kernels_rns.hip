@@ -392,31 +392,78 @@ struct MultiKeys {
     const unsigned char *ksk[kMultiRot];
     u64 ginv[kMultiRot];
 };
+// 16 zero bytes: the source of the global-to-LDS loads of a stage's padding
+// (and, in the MAC, of diagonals past ell or nj)
+__device__ __align__(16) uint4 g_zero16 = {0u, 0u, 0u, 0u};
+
+// A block's 256 sources s map, for every rotation, onto one aligned block
+// of 256 outputs p (P0 ... P0 + 255).  So the key words a rotation needs are
+// whole 256-word slices of its 2 ND key limbs: they are copied from HBM into
+// one of two LDS stages, one rotation ahead, by wave-wide 16-byte
+// global-to-LDS loads (lane l of a load lands at byte 16 l of its 1 KiB
+// chunk), and each thread reads its words at p - P0 from there.  A stage
+// holds the slices' low words (1 KiB each) then their high bytes (256 B
+// each) for packed limbs, or the 2 KiB slices of 64-bit limbs.
+template <int ND, bool PK>
+constexpr int ks_multi_stage_bytes() {
+    return ((2 * ND * (PK ? 1280 : 2048) + 1023) / 1024) * 1024;
+}
 template <int ND, bool PK>
 __device__ __forceinline__ void ks_multi_body(u64 *U, size_t ub, const u64 *D, const MultiKeys &mk, int nrot,
-                                              size_t kblock, unsigned koff, u32 s, int e, int N, int logN, int nE,
-                                              int level, const ModConst &m, const u64 *c0, const u64 *pmont) {
+                                              size_t kblock, unsigned koff, u32 s0w, int e, int N, int logN, int nE,
+                                              int level, const ModConst &m, const u64 *c0, const u64 *pmont,
+                                              unsigned char *lds) {
+    constexpr int NL = 2 * ND;                           // key limbs of a rotation: digit t, part b / a
+    constexpr int LOP = PK ? 64 : 128;                   // 16-byte pieces of a limb's slice (low words)
+    constexpr int TOT = NL * LOP + (PK ? NL * 16 : 0);  // pieces of a stage
+    constexpr int NCH = (TOT + 63) / 64, STG = NCH * 1024;
+    static_assert(STG == ks_multi_stage_bytes<ND, PK>(), "stage stride");
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const u32 s = s0w + t;
     u32 d0[ND], d1[ND];
 #pragma unroll
-    for (int t = 0; t < ND; ++t) split30(D[((size_t)t * nE + e) * N + s], d0[t], d1[t]);
+    for (int i = 0; i < ND; ++i) split30(D[((size_t)i * nE + e) * N + s], d0[i], d1[i]);
     u32 c00 = 0, c01 = 0;
     const bool has_c0 = e <= level;
     if (has_c0) split30(c0[(size_t)e * N + s], c00, c01);
     const u64 pm = has_c0 ? pmont[e] : 0;
-    for (int b = 0; b < nrot; ++b) {
-        const u32 p = auto_src(s, mk.ginv[b], logN);
+    auto dma = [&](int b, int st) {
+        const u32 P0 = auto_src(s0w, mk.ginv[b], logN) & ~255u;
         const unsigned char *kl0 = mk.ksk[b] + koff;
-        u64 kb[ND], ka[ND];
+        unsigned char *dst = lds + st * STG;
 #pragma unroll
-        for (int t = 0; t < ND; ++t) {
-            kb[t] = key_word<PK>(kl0 + (size_t)(t * 2) * kblock, p, N);
-            ka[t] = key_word<PK>(kl0 + (size_t)(t * 2 + 1) * kblock, p, N);
+        for (int c = wv; c < NCH; c += kT / 64) {
+            const int i = c * 64 + lane;
+            const void *src = &g_zero16;
+            if (i < NL * LOP) {
+                const int li = i / LOP, w = i - li * LOP;
+                src = kl0 + (size_t)li * kblock + (PK ? 4 : 8) * (size_t)P0 + 16 * w;
+            } else if (i < TOT) {
+                const int j = i - NL * LOP, li = j >> 4;
+                src = kl0 + (size_t)li * kblock + 4 * (size_t)N + P0 + 16 * (j & 15);
+            }
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0,
+                                             0);
         }
+    };
+    dma(0, 0);
+    for (int b = 0; b < nrot; ++b) {
+        __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's loads of stage b
+        __syncthreads();                      // every wave's, and every wave done with stage b - 1
+        if (b + 1 < nrot) dma(b + 1, (b + 1) & 1);
+        const u32 p = auto_src(s, mk.ginv[b], logN), r = p & 255u;
+        const unsigned char *st = lds + (b & 1) * STG;
+        auto kw = [&](int li) -> u64 {
+            if (PK)
+                return (u64)reinterpret_cast<const u32 *>(st + li * 1024)[r] |
+                       ((u64)st[NL * 1024 + li * 256 + r] << 32);
+            return reinterpret_cast<const u64 *>(st + li * 2048)[r];
+        };
         Dot30 s0, s1;
 #pragma unroll
-        for (int t = 0; t < ND; ++t) {
-            s0.add(d0[t], d1[t], kb[t]);
-            s1.add(d0[t], d1[t], ka[t]);
+        for (int i = 0; i < ND; ++i) {
+            s0.add(d0[i], d1[i], kw(2 * i));
+            s1.add(d0[i], d1[i], kw(2 * i + 1));
         }
         if (has_c0) s0.add(c00, c01, pm);
         u64 *Ub = U + b * ub + (size_t)e * N + p;
@@ -430,9 +477,10 @@ __global__ __launch_bounds__(kT) void k_ks_inner_multi(u64 *__restrict__ U, size
                                                        KeyLayout kl, int N, int logN, int nE, int level, int pbase,
                                                        const ModConst *__restrict__ mods, size_t sd, size_t su, int batch,
                                                        const u64 *__restrict__ c0, size_t c0_sd, const u64 *__restrict__ pmont) {
+    __shared__ __align__(16) unsigned char lds[2 * ks_multi_stage_bytes<ND, false>()];
     int item, tile;
     item_tile(blockIdx.x, batch, N / kT, item, tile);
-    const u32 s = tile * kT + threadIdx.x;
+    const u32 s0w = tile * kT;
     const int e = blockIdx.y;
     const int gm = e <= level ? e : pbase + (e - level - 1);
     const ModConst m = mods[gm];
@@ -440,9 +488,11 @@ __global__ __launch_bounds__(kT) void k_ks_inner_multi(u64 *__restrict__ U, size
     U += item * su;
     c0 += item * c0_sd;
     if (kl.packed[gm])
-        ks_multi_body<ND, true>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s, e, N, logN, nE, level, m, c0, pmont);
+        ks_multi_body<ND, true>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s0w, e, N, logN, nE, level, m, c0, pmont,
+                                lds);
     else
-        ks_multi_body<ND, false>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s, e, N, logN, nE, level, m, c0, pmont);
+        ks_multi_body<ND, false>(U, ub, D, mk, nrot, kl.block, kl.off[gm], s0w, e, N, logN, nE, level, m, c0, pmont,
+                                 lds);
 }
 
 // Summed tensor products of ciphertext pairs (encrypted-database product):
@@ -823,10 +873,6 @@ __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi,
 // ms per query batched when the batched launch keeps the default).
 constexpr int kCachePolicyNT = 2;
 
-// 16 zero bytes: the source of a staged piece of a diagonal past ell or nj
-// (and of a stage's padding)
-__device__ __align__(16) uint4 g_mac_zero = {0u, 0u, 0u, 0u};
-
 // stage stride of the MAC's LDS tile (NJ diagonal slices and two baby
 // limbs, in whole 1 KiB chunks)
 template <int NJ, bool PK>
@@ -873,7 +919,7 @@ __device__ __forceinline__ void mac3_body(u64 *P, size_t pq, const BabyPtrs &bp,
 #pragma unroll
         for (int c = wv; c < NCH; c += kT / 64) {
             const int i = c * 64 + lane;
-            const void *src = &g_mac_zero;
+            const void *src = &g_zero16;
             if (i >= NJ * U4 && i < TOT) {
                 const int w = i - NJ * U4, pb = w >> 6;
                 src = bl0 + (((size_t)pb * (bl + 1) + m) * N + k0) * 8 + 16 * (w & 63);
