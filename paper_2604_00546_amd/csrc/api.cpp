@@ -2001,7 +2001,7 @@ extern "C" int fr_moddown_parity(fr_ctx *c, int32_t mode, const uint64_t *u_host
 // same wave, relinearised products and rescales of one wave in one batch.
 namespace {
 
-enum COp { C_INPUT, C_ADJUST, C_MUL, C_ADD, C_SUB, C_TWICE_M1, C_SCALAR, C_LEAF };
+enum COp { C_INPUT, C_ADJUST, C_MUL, C_ADD, C_SUB, C_TWICE_M1, C_TWICE_SUB, C_SCALAR, C_LEAF };
 
 struct CNode {
     COp op;
@@ -2069,6 +2069,7 @@ struct Recorder {
     }
     H add(const H &a, const H &b) { return bin(C_ADD, a, b); }
     H sub(const H &a, const H &b) { return bin(C_SUB, a, b); }
+    H twice_sub(const H &a, const H &b) { return bin(C_TWICE_SUB, a, b); }  // 2 a - b
     H twice_minus_const(const H &a) {
         if (!a) return H();
         CNode n{C_TWICE_M1};
@@ -2124,10 +2125,9 @@ struct Cheb {
         if (a == b) {
             res = be.twice_minus_const(prod);
         } else {
-            H two = be.add(prod, prod);
-            if (!two) return H();
-            H t1 = be.adjust(T[1], be.level(two));
-            res = be.sub(two, t1);
+            // 2 T_a T_b - T_1 in one pass (the same words as a doubling and a subtraction)
+            H t1 = be.adjust(T[1], be.level(prod));
+            res = be.twice_sub(prod, t1);
         }
         T[i] = res;
         return res;
@@ -2352,7 +2352,8 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
             std::vector<int> L;
             for (int i = 0; i < n; ++i) {
                 const COp op = nodes[i].op;
-                if (depth[i] == d && nodes[i].level == lv && (op == C_ADD || op == C_SUB || op == C_TWICE_M1))
+                if (depth[i] == d && nodes[i].level == lv &&
+                    (op == C_ADD || op == C_SUB || op == C_TWICE_M1 || op == C_TWICE_SUB))
                     L.push_back(i);
             }
             if (L.empty()) continue;
@@ -2376,7 +2377,7 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
                     xa[b] = B_(nd.a, q);
                     yb[b] = nd.op == C_TWICE_M1 ? B_(nd.a, q) : B_(nd.b, q);
                     outs[b] = o + (size_t)b * 2 * w;
-                    op[b] = nd.op == C_SUB;
+                    op[b] = nd.op == C_SUB ? 1 : nd.op == C_TWICE_SUB ? 2 : 0;
                     if (nd.op == C_TWICE_M1) cst[b] = rne_ll(-1.0 * D[lv]);
                 }
                 frk::pair_batch(c, lv + 1, B, xa.data(), yb.data(), outs.data(), cst.data(), op.data());

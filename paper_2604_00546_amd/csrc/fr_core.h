@@ -462,7 +462,8 @@ bool scalar_mat(const fr_ctx *c, u64 *out, int nl, int nb, int nq, const u64 *co
                 const long long *K, size_t ob, size_t oq);
 // c0 limbs of item b (items `item` words apart) += v[b]
 void add_const_batch(const fr_ctx *c, u64 *data, int nl, int B, const long long *v, size_t item);
-// out[b] = a[b] +/- b[b] (+ cst[b] on c0)
+// out[b] = a[b] + b[b] (op 0), a[b] - b[b] (op 1) or 2 a[b] - b[b] (op 2),
+// + cst[b] on c0
 void pair_batch(const fr_ctx *c, int nl, int B, const u64 *const *a, const u64 *const *b, u64 *const *out,
                 const long long *cst, const int *op);
 // tensor of B pairs: d0, d1 -> t01 + b * 2 lw, d2 -> t2 + b * lw

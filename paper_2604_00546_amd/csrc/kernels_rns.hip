@@ -1174,15 +1174,17 @@ struct PairBatch {
     const u64 *b[kBatch];
     u64 *out[kBatch];
     long long cst[kBatch];  // added to c0 after the operation (0: none)
-    int op[kBatch];         // 0 add, 1 sub
+    int op[kBatch];         // 0 add, 1 sub, 2 twice a minus b
 };
-// out_b = a_b (+/-) b_b  (+ cst_b on c0), ciphertexts of nl limbs per polynomial
+// out_b = a_b + b_b, a_b - b_b or 2 a_b - b_b (+ cst_b on c0), ciphertexts of nl
+// limbs per polynomial
 __global__ __launch_bounds__(kT) void k_pair_batch(PairBatch pb, int nl, int N, const ModConst *mods) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y % nl, p = blockIdx.y / nl, b = blockIdx.z;
     const ModConst m = mods[i];
     const size_t w = ((size_t)p * nl + i) * N + k;
     const u64 x = pb.a[b][w], y = pb.b[b][w];
-    u64 r = pb.op[b] ? subq(x, y, m.q) : addq(x, y, m.q);
+    const int op = pb.op[b];
+    u64 r = op == 0 ? addq(x, y, m.q) : subq(op == 2 ? addq(x, x, m.q) : x, y, m.q);
     if (p == 0 && pb.cst[b]) r = addq(r, smod_dev(pb.cst[b], m), m.q);
     pb.out[b][w] = r;
 }
