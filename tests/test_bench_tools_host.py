@@ -1,9 +1,10 @@
-"""Host tests of the rocprofv3 summaries (paper_2604_00546_amd.profsum) on
-small synthetic CSV files: the timed region starts after the calibration
-copy (the first device copy at least half as long as the longest one, so
-the result downloads of later service-time steps, also copy kernels, do not
-move it), the queries in the region are counted, and the byte counters are
-scaled by what they read for the calibration copy."""
+"""Host tests of the measurement tools.  The rocprofv3 summaries
+(paper_2604_00546_amd.profsum) on small synthetic CSV files: the timed
+region starts after the calibration copy (the first device copy at least
+half as long as the longest one, so the result downloads of later
+service-time steps, also copy kernels, do not move it), the queries in the
+region are counted, and the byte counters are scaled by what they read for
+the calibration copy.  And bench.py's refusal of more than one GPU."""
 import contextlib
 import csv
 import io
@@ -106,3 +107,17 @@ def test_counters_scaled_by_the_calibration_copy(tmp_path):
     n, rd, wr = line.split()[1:]
     # dispatches after the calibration copy only: (1024 + 3072) / 2 KiB x 2 = 4 MiB read, 512 KiB written
     assert (int(n), float(rd), float(wr)) == (2, 4.0, 0.5)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it exits with status 2 and
+    says so, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
