@@ -713,7 +713,8 @@ def main():
     ap.add_argument("--batch", type=int, default=16,
                     help="queries per batch for the batched-form figure (0: skip it)")
     ap.add_argument("--route", choices=("hoisted", "single"), default="hoisted",
-                    help="hoisted: baby steps held over Q_l U P, one ModDown per inner sum (fr_bsgs_matvec_hoisted); "
+                    help="hoisted: baby steps held over Q_l U P, inner sums' first polynomials summed before one "
+                         "ModDown, one ModDown per second polynomial (fr_bsgs_matvec_hoisted); "
                          "single: hoisted rotations, each with its ModDown, then the product")
     ap.add_argument("--breakdown", action="store_true", help="extra pass timing every kernel class")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch choices and "
@@ -800,7 +801,8 @@ def main():
                                f"(d1={args.d1}); RNS-CKKS N=2^16, Q=60+14x40 bits, P=5x60 bits, dnum=3, "
                                "scale 2^40", "templates": s["K"], "dim": s["ell"], "ring_dim": ctx.N,
                    "form": "plain, one query at a time",
-                   "route": ("baby steps held over Q_l U P, one ModDown per inner sum" if args.route == "hoisted"
+                   "route": ("baby steps held over Q_l U P; inner sums' first polynomials rotated and summed "
+                             "before one ModDown, one ModDown per second polynomial" if args.route == "hoisted"
                              else "hoisted rotations with one ModDown each, then the product")},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},

@@ -271,8 +271,11 @@ int fr_bsgs_diag_matvec_batch(fr_ctx *ctx, const fr_keys *keys, const fr_ct *bab
  * itself (query level = database level = l >= 1, n1 = the database's):
  *   B_0 = (P c0, P c1),  B_i = (P sigma_i(c0) + U0_i, U1_i) over Q_l U P,
  *   U_i = sum_t sigma_i(ModUp_t(c1)) ksk_{i,t}   (Rot_i before its ModDown),
- *   P_j = Rescale(ModDown(sum_i B_i * diag'_{g, j n1 + i})),
- *   out = P_0 + sum_{j >= 1} Rot_{j n1}(P_j)   at level l-1,
+ *   (a_j, b_j) = sum_i B_i * diag'_{g, j n1 + i}   over Q_l U P,
+ *   out = (Rescale(ModDown(sum_j sigma_{j n1}(a_j))), Rescale(ModDown(b_0)))
+ *         + sum_{j >= 1} KeySwitch_{j n1}(sigma_{j n1}(Rescale(ModDown(b_j))))
+ * at level l-1 (the key switches sharing one ModDown; a rotation needs no
+ * key for the first polynomials, which are summed before their ModDown),
  * keys for rotations 1..n1-1 and j n1.  The scores approximate those of
  * fr_rotate_hoisted + fr_bsgs_diag_matvec with one ModDown per inner sum
  * instead of one per baby step; the words differ (other rounding).

@@ -1428,15 +1428,20 @@ or_ct *or_rotate_sum(const or_ctx *c, const or_keys *K, const or_ct *const *P, i
 }
 
 /* BSGS product with the ModDown of the baby steps hoisted past the inner
- * sums (double hoisting of the plaintext-matrix BSGS, §3.4.2 hoisting and double
- * hoisting).  Baby step i is kept over the extended basis Q_l U P,
+ * sums, and that of the inner sums' first polynomials past the giant-step
+ * sum (double hoisting of the plaintext-matrix BSGS, §3.4.2 hoisting and
+ * double hoisting).  Baby step i is kept over the extended basis Q_l U P,
  *   B_i = (P sigma_i(c0) + U0_i, U1_i),  U_i = sum_t sigma_i(ModUp_t(c1)) ksk_{i,t},
  *   B_0 = (P c0, P c1)  (zero on the special primes),
  * the diagonals are multiplied over Q_l U P (their special-prime limbs are
- * the residues of the plaintext's centered integer coefficients), and each
- * inner sum takes one ModDown and one rescale:
- *   P_j = Rescale(ModDown(sum_i B_i * diag'_{g, j n1 + i})),
- * followed by the same giant steps as or_bsgs_matvec.  ModDown(B_i) is
+ * the residues of the plaintext's centered integer coefficients) into the
+ * inner sums A_j = sum_i B_i * diag'_{g, j n1 + i} = (a_j, b_j).  A rotation
+ * acts on a_j without a key, so the first polynomials are rotated and summed
+ * over Q_l U P and take one ModDown and one rescale together; each b_j takes
+ * its own, and the giant steps key-switch them:
+ *   S = (Rescale(ModDown(sum_j sigma_{j n1}(a_j))), Rescale(ModDown(b_0)))
+ *       + sum_{j >= 1} KeySwitch_{j n1}(sigma_{j n1}(Rescale(ModDown(b_j)))),
+ * the key switches sharing one ModDown as in or_bsgs_matvec.  ModDown(B_i) is
  * Rot_i(ct), so the result approximates the same product. */
 or_ct *or_bsgs_matvec_hoisted(const or_ctx *c, const or_keys *K, const or_ct *x, int n1, or_db *db, int group) {
     int N = c->N, ell = db->ell, l = x->level, nP = c->nP;
@@ -1478,6 +1483,8 @@ or_ct *or_bsgs_matvec_hoisted(const or_ctx *c, const or_keys *K, const or_ct *x,
     }
     or_ct **P = calloc(n2, sizeof(or_ct *));
     uint64_t *acc = malloc(8 * (size_t)2 * nE * N);
+    uint64_t *asum = calloc((size_t)nE * N, 8), *b0 = malloc(8 * (size_t)nE * N);
+    double scale = x->scale * db->scale;
     for (int j = 0; j < n2; j++) {
         int nb = ell - j * n1 < n1 ? ell - j * n1 : n1;
         memset(acc, 0, 8 * (size_t)2 * nE * N);
@@ -1493,15 +1500,36 @@ or_ct *or_bsgs_matvec_hoisted(const or_ctx *c, const or_keys *K, const or_ct *x,
             }
             nega_inv(c, gm, d);
         }
-        or_ct *y = ct_alloc(c, l, x->scale * db->scale);
-        or_moddown(c, l, acc, CT0(c, y, 0));
-        or_moddown(c, l, acc + (size_t)nE * N, CT1(c, y, 0));
-        P[j] = or_rescale(c, y);
-        or_ct_free(y);
+        /* a_j: rotated by j n1 and summed over Q_l U P (coefficient form) */
+        uint64_t g = or_galois_element(c, j * n1);
+        #pragma omp parallel for
+        for (int e = 0; e < nE; e++) {
+            int gm = ext_gidx(c, l, e);
+            uint64_t q = c->mod[gm], *t = malloc(8 * (size_t)N);
+            or_automorphism(c, gm, g, acc + (size_t)e * N, t);
+            for (int k = 0; k < N; k++) asum[(size_t)e * N + k] = addmod(asum[(size_t)e * N + k], t[k], q);
+            free(t);
+        }
+        /* b_j: its own ModDown and rescale (b_0 joins the final ciphertext) */
+        if (j == 0) {
+            memcpy(b0, acc + (size_t)nE * N, 8 * (size_t)nE * N);
+        } else {
+            or_ct *y = ct_alloc(c, l, scale);
+            or_moddown(c, l, acc + (size_t)nE * N, CT1(c, y, 0));
+            P[j] = or_rescale(c, y);  /* (0, Rescale(ModDown(b_j))) */
+            or_ct_free(y);
+        }
     }
-    free(acc);
+    or_ct *y = ct_alloc(c, l, scale);
+    or_moddown(c, l, asum, CT0(c, y, 0));
+    or_moddown(c, l, b0, CT1(c, y, 0));
+    P[0] = or_rescale(c, y);
+    or_ct_free(y);
+    free(acc); free(asum); free(b0);
     for (int i = 0; i < n1; i++) free(bq[i]);
     free(bq);
+    /* the giant steps of or_bsgs_matvec: the first polynomials of P[j >= 1]
+     * are zero, so only the key switches of the b_j add to P[0] */
     return giant_sum(c, K, P, n2, n1);
 }
 

@@ -150,9 +150,12 @@ int or_db_slots(const or_ctx *ctx, const float *T, int K, int ell, int B, int n1
 or_ct *or_bsgs_matvec(const or_ctx *ctx, const or_keys *k, or_ct *const *baby, int n1,
                       const or_db *db, int group);
 /* The same product from the query itself, with the baby steps kept over
- * Q_l U P and one ModDown per inner sum (query and database at one level):
- * S_g = sum_j Rot_{j n1}( Rescale( ModDown( sum_i B_i * diag'_{g, j n1 + i} ) ) ),
- * B_i = Rot_i(ct) before its ModDown. */
+ * Q_l U P (query and database at one level): with (a_j, b_j) =
+ * sum_i B_i * diag'_{g, j n1 + i} over Q_l U P and B_i = Rot_i(ct) before
+ * its ModDown, S_g = (Rescale(ModDown(sum_j sigma_{j n1}(a_j))),
+ * Rescale(ModDown(b_0))) + sum_{j >= 1} KeySwitch_{j n1}(sigma_{j n1}(
+ * Rescale(ModDown(b_j)))): the first polynomials, which rotate without a
+ * key, take one ModDown together. */
 or_ct *or_bsgs_matvec_hoisted(const or_ctx *ctx, const or_keys *k, const or_ct *x, int n1,
                               or_db *db, int group);
 

@@ -492,7 +492,8 @@ class Context:
         return Ct(self, lib().or_bsgs_matvec(self.ptr, keys.ptr, arr, len(baby), db.ptr, group))
 
     def bsgs_matvec_hoisted(self, keys: Keys, ct: Ct, db: Db, group: int) -> Ct:
-        """The product from the query itself, baby steps held over Q_l U P (one ModDown per inner sum)."""
+        """The product from the query itself, baby steps held over Q_l U P (the inner sums' first
+        polynomials rotated and summed before one ModDown, one ModDown per second polynomial)."""
         return Ct(self, lib().or_bsgs_matvec_hoisted(self.ptr, keys.ptr, ct.ptr, db.n1, db.ptr, group))
 
     def chebyshev(self, keys: Keys, x: Ct, coeffs, d1: int) -> Ct:

@@ -1525,7 +1525,10 @@ extern "C" int fr_db_export(fr_ctx *c, const fr_db *db, int32_t g, int32_t d, ui
 // [qn][n2][2][l+1][N]: out[q] = R_{q,0} + sum_j Rot_{j n1}(R_{q,j}), every
 // rotation's key inner product summed over Q_l U P before one ModDown per
 // query (Eq. bsgs2).
-static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2, int n1, int l, u64 *const *outp) {
+// c0_summed: R_{q,0}.c0 already holds the first polynomials' rotated sum
+// (the R_{q,j}.c0 of j >= 1 are not read)
+static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2, int n1, int l, u64 *const *outp,
+                       bool c0_summed = false) {
     Scope sc(c->arena);
     const int N = c->N, nE = l + 1 + c->nP, ndig = num_digits(c, l);
     const size_t rw = (size_t)2 * (l + 1) * N, lwl = (size_t)(l + 1) * N, dstride = (size_t)ndig * nE * N;
@@ -1557,7 +1560,7 @@ static int giant_steps(fr_ctx *c, const fr_keys *K, const u64 *R, int qn, int n2
             frk::ks_inner_sum(c, U, U + (size_t)nE * N, D + (size_t)j0 * dstride, kp.data() + j0, gp.data() + j0, nj,
                               dstride, l, j0 > 0, qn, (size_t)n2 * dstride, (size_t)2 * nE * N);
         }
-        frk::automorph_sum(c, S, R + rw, gp.data(), n2 - 1, l + 1, qn, rw, rw, (size_t)n2 * rw);
+        if (!c0_summed) frk::automorph_sum(c, S, R + rw, gp.data(), n2 - 1, l + 1, qn, rw, rw, (size_t)n2 * rw);
         ks_moddown_into(c, U, qn, l, S, lwl, true);
     }
     if (qn > 1)
@@ -1798,23 +1801,38 @@ extern "C" int fr_db_extend(fr_ctx *c, fr_db *db) try {
 
 // out (np polynomials of l limbs) = Rescale(ModDown(U)) for np polynomials
 // U over Q_l U P (eval domain, nE limbs each; np even)
-static void moddown_rescale(fr_ctx *c, const u64 *U, int np, int l, u64 *out) {
+// out[p] = Rescale(ModDown(U[p])) for np polynomials over Q_l U P (U items
+// su words apart, default nE N; out items so apart, default l N)
+static void moddown_rescale(fr_ctx *c, const u64 *U, int np, int l, u64 *out, size_t su = 0, size_t so = 0) {
     Scope sc(c->arena);
     const int N = c->N, nE = l + 1 + c->nP;
+    const size_t ew = (size_t)nE * N, lw = (size_t)l * N;
+    if (!su) su = ew;
+    if (!so) so = lw;
     if (relin_folds(c)) {
         // the top limb and the P limbs in coefficient form drive one forward
         // transform of l limbs whose last pass writes the result
-        u64 *Xu = scratch(c, (size_t)np * nE * N);
+        u64 *Xu = scratch(c, (size_t)np * ew);
         LimbMap top_and_p{l, INT_MAX, 0, l + 1, c->L + 1};
-        frk::ntt_inv(c, Xu, c->nP + 1, top_and_p, np, (size_t)nE * N, U, (size_t)nE * N);
-        u64 *Z = scratch(c, (size_t)np * l * N);
-        frk::relin_rescale_prep(c, Z, Xu, nullptr, l, np, (size_t)l * N, (size_t)nE * N, 0, true);
-        frk::ntt_fwd_relin_rescale(c, Z, l, np, U, (size_t)nE * N, nullptr, 0, out, (size_t)l * N);
+        frk::ntt_inv(c, Xu, c->nP + 1, top_and_p, np, ew, U, su);
+        u64 *Z = scratch(c, (size_t)np * lw);
+        frk::relin_rescale_prep(c, Z, Xu, nullptr, l, np, lw, ew, 0, true);
+        frk::ntt_fwd_relin_rescale(c, Z, l, np, U, su, nullptr, 0, out, so);
         return;
     }
-    u64 *T = scratch(c, (size_t)np * (l + 1) * N);
-    ks_moddown_into(c, U, np / 2, l, T, (size_t)(l + 1) * N, false);
-    rescale_dev(c, T, l, out, np / 2);
+    // other rings: the ciphertext steps on a contiguous copy (an odd count
+    // takes a copy of its last polynomial as the partner of that one)
+    const int nc = (np + 1) / 2;
+    u64 *Uc = scratch(c, (size_t)2 * nc * ew);
+    (void)hipMemcpy2DAsync(Uc, ew * 8, U, su * 8, ew * 8, np, hipMemcpyDeviceToDevice, c->stream);
+    if (np & 1)
+        (void)hipMemcpyAsync(Uc + (size_t)np * ew, U + (size_t)(np - 1) * su, ew * 8, hipMemcpyDeviceToDevice,
+                             c->stream);
+    u64 *T = scratch(c, (size_t)2 * nc * (l + 1) * N);
+    ks_moddown_into(c, Uc, nc, l, T, (size_t)(l + 1) * N, false);
+    u64 *O = scratch(c, (size_t)2 * nc * lw);
+    rescale_dev(c, T, l, O, nc);
+    (void)hipMemcpy2DAsync(out, so * 8, O, lw * 8, lw * 8, np, hipMemcpyDeviceToDevice, c->stream);
 }
 
 // Queries q against group groups[q] of extended databases dbs[q] (one ell,
@@ -1903,11 +1921,21 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
         }
         frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), db0->stride, db0->lay, ell, nE - 1, nE - 1,
                       l, c->L - l);
+        // a rotation needs no key for an inner sum's first polynomial: those
+        // are rotated and summed over Q_l U P (Asum, one per query) and take
+        // one ModDown + rescale together; every second polynomial takes its
+        // own, for its key switch in the giant steps
+        u64 *Asum = scratch(c, (size_t)qn * nE * N);
+        std::vector<u64> gj(n2);
+        for (int j = 0; j < n2; ++j) gj[j] = galois_element(N, j * n1);
+        frk::automorph_sum(c, Asum, P, gj.data(), n2, nE, qn, (size_t)nE * N, pw, (size_t)n2 * pw, l, false);
+        // R = [qn][n2][2][l][N]: R_{q,j}.c1 for every j, and R_{q,0}.c0 the sum
         u64 *R = scratch(c, (size_t)qn * n2 * 2 * l * N);
-        moddown_rescale(c, P, qn * n2 * 2, l, R);
+        moddown_rescale(c, P + (size_t)nE * N, qn * n2, l, R + (size_t)l * N, pw, (size_t)2 * l * N);
+        moddown_rescale(c, Asum, qn, l, R, (size_t)nE * N, (size_t)n2 * 2 * l * N);
         std::vector<u64 *> op(qn);
         for (int qq = 0; qq < qn; ++qq) op[qq] = out[order[q0 + qq]].data;
-        if (int e = giant_steps(c, K, R, qn, n2, n1, l - 1, op.data())) return e;
+        if (int e = giant_steps(c, K, R, qn, n2, n1, l - 1, op.data(), true)) return e;
     }
     FR_HIP(hipGetLastError());
     for (int q = 0; q < nq; ++q) {

@@ -405,9 +405,10 @@ int ks_inner_sum_chunk(const fr_ctx *c, int level);
 // digits D + j sdj) of the key inner products, for `batch` items
 void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned char *const *ksk, const u64 *g, int nj,
                   size_t sdj, int level, bool accumulate, int batch, size_t sd, size_t su);
-// out[b] += sum_j sigma_{g_j}(in[b][j]) on nlimbs limbs of one polynomial
+// out[b] (+)= sum_j sigma_{g_j}(in[b][j]) on nlimbs limbs of one polynomial;
+// level >= 0: the limbs past it are the special primes (Q_level U P)
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
-                   size_t sij, size_t sib);
+                   size_t sij, size_t sib, int level = -1, bool accumulate = true);
 // Z[p][i] (i < level) for the merged ModDown + rescale of relinearised
 // products: Xu holds the coefficient forms of U's limbs level..level+nP at
 // their storage positions, Xd that of d's limb level; Xd null: U's limb

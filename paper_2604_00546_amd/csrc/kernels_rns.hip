@@ -606,14 +606,16 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *__restrict__ U0, u64 *
                                      accumulate);
 }
 
-// out[b][i][k] += sum_j in[b][j][i][auto_src(k, g_j)] (c0 parts of the giant
-// steps; in items sij words apart per j and sib per b, out sob per b)
+// out[b][i][k] (+)= sum_j in[b][j][i][auto_src(k, g_j)] (first polynomials of
+// the giant steps; in items sij words apart per j and sib per b, out sob per
+// b; limbs past `level` are the special primes, global index pbase + ...)
 __global__ __launch_bounds__(kT) void k_automorph_sum(u64 *__restrict__ out, const u64 *__restrict__ in, GiantKeys gk, int nj, int N, int logN,
-                                                      size_t sob, size_t sij, size_t sib, const ModConst *__restrict__ mods) {
+                                                      size_t sob, size_t sij, size_t sib, const ModConst *__restrict__ mods,
+                                                      int level, int pbase, int accumulate) {
     const int k = blockIdx.x * kT + threadIdx.x, i = blockIdx.y, b = blockIdx.z;
-    const u64 q = mods[i].q;
+    const u64 q = mods[i <= level ? i : pbase + (i - level - 1)].q;
     const u64 *ib = in + b * sib + (size_t)i * N;
-    u64 acc = out[b * sob + (size_t)i * N + k];
+    u64 acc = accumulate ? out[b * sob + (size_t)i * N + k] : 0;
     for (int jj = 0; jj < nj; ++jj) acc = addq(acc, ib[jj * sij + auto_src((u32)k, gk.g[jj], logN)], q);
     out[b * sob + (size_t)i * N + k] = acc;
 }
@@ -1461,14 +1463,15 @@ void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigne
 }
 
 void automorph_sum(const fr_ctx *c, u64 *out, const u64 *in, const u64 *g, int nj, int nlimbs, int nb, size_t sob,
-                   size_t sij, size_t sib) {
+                   size_t sij, size_t sib, int level, bool accumulate) {
     for (int j0 = 0; j0 < nj; j0 += kGiant) {
         const int n = std::min(kGiant, nj - j0);
         GiantKeys gk{};
         for (int j = 0; j < n; ++j) gk.g[j] = g[j0 + j];
-        ProfScope ps(c, K_ELEM, (n + 2.0) * nlimbs * nb * 8.0 * c->N);
+        const bool acc = accumulate || j0 > 0;
+        ProfScope ps(c, K_ELEM, (n + (acc ? 2.0 : 1.0)) * nlimbs * nb * 8.0 * c->N);
         hipLaunchKernelGGL(k_automorph_sum, grid(c, nlimbs, nb), dim3(kT), 0, c->stream, out, in + j0 * sij, gk, n,
-                           c->N, c->logN, sob, sij, sib, c->d_mod);
+                           c->N, c->logN, sob, sij, sib, c->d_mod, level < 0 ? nlimbs : level, c->L + 1, (int)acc);
     }
 }
 

@@ -1,5 +1,7 @@
 """GPU parity of the BSGS product with the baby steps' ModDown hoisted past
-the inner sums (baby steps held over Q_l U P, one ModDown per inner sum).
+the inner sums (baby steps held over Q_l U P; the inner sums' first
+polynomials rotated and summed before one ModDown, one ModDown per second
+polynomial).
 
 Every score ciphertext is compared bit-exactly with the oracle's
 or_bsgs_matvec_hoisted on the same keys, encryption seeds and integer
