@@ -124,6 +124,15 @@ int fr_ctx_reserve(fr_ctx *ctx, uint64_t bytes);
  * - FR_TUNE_MATVEC_CHUNK (1..16): queries per chunk of the batched products.
  * - FR_TUNE_CHEB_CHUNK (1..16): queries per pass of the batched Chebyshev
  *   evaluation.
+ * - FR_TUNE_CHEB_SCHED (0 or 1): order of the Chebyshev evaluation's launch
+ *   groups.  0: every node at its earliest depth, groups of a depth issued
+ *   scalar family, products, additions.  1: level adjustments and scalar
+ *   multiples at the latest depth before their first consumer, and the
+ *   groups of a depth issued longest remaining path first.
+ * - FR_TUNE_KSMAC (0 or 1): 1 = the hoisted product forms its baby steps
+ *   inside the diagonal MAC (never written to memory) where the shape
+ *   allows (n1 <= 32, ell = 16 n1, at most 3 digits); 0 = a key inner
+ *   product launch writes them and the MAC reads them.
  * FR_EINVAL for an unknown knob or a value out of range, and while a graph
  * capture is in progress. */
 enum {
@@ -134,7 +143,9 @@ enum {
     FR_TUNE_MODUP_MERGE = 4,
     FR_TUNE_MATVEC_CHUNK = 5,
     FR_TUNE_CHEB_CHUNK = 6,
-    FR_TUNE_COUNT = 7
+    FR_TUNE_CHEB_SCHED = 7,
+    FR_TUNE_KSMAC = 8,
+    FR_TUNE_COUNT = 9
 };
 int fr_ctx_set_tune(fr_ctx *ctx, int32_t knob, int32_t value);
 int fr_ctx_get_tune(const fr_ctx *ctx, int32_t knob, int32_t *value);

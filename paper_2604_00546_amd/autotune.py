@@ -11,6 +11,9 @@ variant and the work per launch change, so a choice is a speed decision):
   limbs per block of a launch;
 * the ModUp merge bound (inputs x digits up to which one conversion launch
   and one transform cover every digit);
+* the order of the Chebyshev evaluation's launch groups (as recorded, or
+  critical-first with level adjustments deferred to their consumers);
+* whether the hoisted product forms its baby steps inside the MAC;
 * the batched forms' queries per chunk (products and Chebyshev passes);
 * the Chebyshev baby-step degree d1 (a call parameter: fewer relinearised
   products against more levels and scalar work).
@@ -35,6 +38,8 @@ DEFAULT_SPACE = {
     "ntt_inv_rows4": NTT_CANDIDATES,
     "ntt_inv_cols4": NTT_CANDIDATES,
     "modup_merge": (3, 6, 12, 24, 48),
+    "cheb_sched": (0, 1),
+    "ksmac": (0, 1),
 }
 BATCH_SPACE = {"matvec_chunk": (2, 4, 8, 16), "cheb_chunk": (2, 4, 8, 16)}
 

@@ -741,8 +741,8 @@ extern "C" int fr_ctx_set_scratch_limit(fr_ctx *c, uint64_t bytes) try {
 extern "C" int fr_ctx_set_tune(fr_ctx *c, int32_t knob, int32_t value) {
     CHECK(c, FR_EINVAL, "null context");
     CHECK(knob >= 0 && knob < FR_TUNE_COUNT, FR_EINVAL, "fr_ctx_set_tune: unknown knob %d", knob);
-    static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1};
-    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16};
+    static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1, 0, 0};
+    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16, 1, 1};
     CHECK(value >= lo[knob] && value <= hi[knob], FR_EINVAL, "fr_ctx_set_tune: knob %d takes %d..%d, not %d", knob,
           lo[knob], hi[knob], value);
     CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_tune: a graph capture is in progress");
@@ -1891,36 +1891,54 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
                                       c->stream));
         u64 *D = scratch(c, (size_t)qn * dstride);
         ks_modup(c, C + lw, l, D, qn, 2 * lw);
-        // baby steps over Q_l U P: [qn][n1][2][nE][N]
-        u64 *Bb = scratch(c, (size_t)qn * bq);
-        frk::scale_ext(c, Bb, C, l, qn, bq, 2 * lw);
-        if (frk::ks_inner_multi_ok(c, l)) {
-            // every baby step from one read of the digit set and of c0
-            std::vector<const unsigned char *> kp(n1 - 1);
-            std::vector<u64> gp(n1 - 1);
-            for (int i = 1; i < n1; ++i) {
-                gp[i - 1] = galois_element(N, i);
-                kp[i - 1] = K->find(gp[i - 1])->data;
-            }
-            frk::ks_inner_multi(c, Bb + bw, bw, D, kp.data(), gp.data(), n1 - 1, l, qn, dstride, bq, C, 2 * lw);
-        } else {
-            for (int i = 1; i < n1; ++i) {
-                const u64 g = galois_element(N, i);
-                u64 *Ui = Bb + i * bw;
-                frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, qn, dstride, bq, nullptr,
-                              0, C, 2 * lw);
-            }
-        }
         // inner sums over Q_l U P: [qn][n2][2][nE][N]
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
-        std::vector<const u64 *> bp((size_t)qn * n1);
         std::vector<const unsigned char *> dp(qn);
-        for (int qq = 0; qq < qn; ++qq) {
-            dp[qq] = diag_of(order[q0 + qq]);
-            for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = Bb + qq * bq + i * bw;
+        for (int qq = 0; qq < qn; ++qq) dp[qq] = diag_of(order[q0 + qq]);
+        const bool fused = c->tune[FR_TUNE_KSMAC] && frk::bsgs_ksmac_ok(c, l, n1, ell, db0->lay);
+        if (fused) {
+            // baby step 0 (P times the query) in memory, the others formed
+            // inside the MAC from the digit set, c0 and their keys
+            u64 *B0 = scratch(c, (size_t)qn * bw);
+            frk::scale_ext(c, B0, C, l, qn, bw, 2 * lw);
+            std::vector<const u64 *> b0(qn);
+            for (int qq = 0; qq < qn; ++qq) b0[qq] = B0 + qq * bw;
+            std::vector<const unsigned char *> kp(n1);
+            std::vector<u64> gp(n1, 1);
+            for (int i = 1; i < n1; ++i) {
+                gp[i] = galois_element(N, i);
+                kp[i] = K->find(gp[i])->data;
+            }
+            frk::bsgs_ksmac(c, P, (size_t)n2 * pw, b0.data(), qn, n1, dp.data(), db0->stride, db0->lay, D, dstride,
+                            C, 2 * lw, kp.data(), gp.data(), l);
         }
-        frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), db0->stride, db0->lay, ell, nE - 1, nE - 1,
-                      l, c->L - l);
+        if (!fused) {
+            // baby steps over Q_l U P: [qn][n1][2][nE][N]
+            u64 *Bb = scratch(c, (size_t)qn * bq);
+            frk::scale_ext(c, Bb, C, l, qn, bq, 2 * lw);
+            if (frk::ks_inner_multi_ok(c, l)) {
+                // every baby step from one read of the digit set and of c0
+                std::vector<const unsigned char *> kp(n1 - 1);
+                std::vector<u64> gp(n1 - 1);
+                for (int i = 1; i < n1; ++i) {
+                    gp[i - 1] = galois_element(N, i);
+                    kp[i - 1] = K->find(gp[i - 1])->data;
+                }
+                frk::ks_inner_multi(c, Bb + bw, bw, D, kp.data(), gp.data(), n1 - 1, l, qn, dstride, bq, C, 2 * lw);
+            } else {
+                for (int i = 1; i < n1; ++i) {
+                    const u64 g = galois_element(N, i);
+                    u64 *Ui = Bb + i * bw;
+                    frk::ks_inner(c, Ui, Ui + (size_t)nE * N, D, K->find(g)->data, g, l, false, qn, dstride, bq,
+                                  nullptr, 0, C, 2 * lw);
+                }
+            }
+            std::vector<const u64 *> bp((size_t)qn * n1);
+            for (int qq = 0; qq < qn; ++qq)
+                for (int i = 0; i < n1; ++i) bp[(size_t)qq * n1 + i] = Bb + qq * bq + i * bw;
+            frk::bsgs_mac(c, P, (size_t)n2 * pw, bp.data(), qn, n1, dp.data(), db0->stride, db0->lay, ell, nE - 1,
+                          nE - 1, l, c->L - l);
+        }
         // a rotation needs no key for an inner sum's first polynomial: those
         // are rotated and summed over Q_l U P (Asum, one per query) and take
         // one ModDown + rescale together; every second polynomial takes its
@@ -2229,6 +2247,38 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         depth[i] = d;
         maxd = std::max(maxd, d);
     }
+    // Critical-first schedule: tail[i] estimates the time from node i's
+    // start to the output along its longest chain of consumers (per-node
+    // costs in microseconds of one query: a relinearised product about 200,
+    // a scalar wave with its rescale about 80, an addition about 12).  A
+    // level adjustment or scalar multiple moves to the depth just before its
+    // first consumer, where it no longer shares a wave (and its rescale) with
+    // the leaves of the critical chain; its inputs come from earlier depths
+    // still.  Nodes are recorded after their inputs, so consumers have the
+    // larger indices.
+    const bool crit = c->tune[FR_TUNE_CHEB_SCHED] != 0;
+    std::vector<int> tail(n, 0);
+    if (crit) {
+        std::vector<std::vector<int>> cons(n);
+        for (int i = 0; i < n; ++i) {
+            const CNode &nd = nodes[i];
+            if (nd.a >= 0) cons[nd.a].push_back(i);
+            if (nd.b >= 0 && nd.b != nd.a) cons[nd.b].push_back(i);
+            for (int x : nd.ins) cons[x].push_back(i);
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            const COp op = nodes[i].op;
+            const int cost = op == C_MUL ? 200 : (op == C_ADJUST || op == C_SCALAR || op == C_LEAF) ? 80
+                                                 : op == C_INPUT ? 0 : 12;
+            int t = 0, dl = INT_MAX;
+            for (int j : cons[i]) {
+                t = std::max(t, tail[j]);
+                dl = std::min(dl, depth[j] - 1);
+            }
+            tail[i] = t + cost;
+            if ((op == C_ADJUST || op == C_SCALAR) && dl != INT_MAX) depth[i] = dl;
+        }
+    }
     buf.assign((size_t)n * nq, nullptr);
     auto B_ = [&](int node, int q) -> u64 *& { return buf[(size_t)node * nq + q]; };
     for (int i = 0; i < n; ++i)
@@ -2419,8 +2469,17 @@ int cheb_execute(fr_ctx *c, const fr_keys *K, const std::vector<CNode> &nodes, c
         // depth took that stream already; else on the next free stream in
         // turn.  It waits for the events of the groups on other streams that
         // produced its inputs.
+        // issue order: as built, or (critical-first) longest tail first
+        std::vector<int> order(groups.size());
+        for (size_t g = 0; g < groups.size(); ++g) order[g] = (int)g;
+        if (crit) {
+            std::vector<int> prio(groups.size(), 0);
+            for (size_t g = 0; g < groups.size(); ++g)
+                for (int x : gout[g]) prio[g] = std::max(prio[g], tail[x]);
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return prio[x] > prio[y]; });
+        }
         std::vector<char> taken(nstream, 0);
-        for (size_t g = 0; g < groups.size(); ++g) {
+        for (const int g : order) {
             int st = -1, latest = -1;
             for (int x : gin[g])
                 if (prod_seq[x] > latest) latest = prod_seq[x], st = prod_st[x];

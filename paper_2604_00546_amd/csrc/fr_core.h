@@ -218,7 +218,7 @@ struct fr_ctx {
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;
     // tuning knobs (fr_ctx_set_tune; defaults are measured choices)
-    int tune[FR_TUNE_COUNT] = {32, 32, 48, 48, 12, 8, 8};
+    int tune[FR_TUNE_COUNT] = {32, 32, 48, 48, 12, 8, 8, 1, 1};
     // graph capture (fr_graph_begin / fr_graph_end): the calls of a capture
     // run on cap_stream in capture mode; arena_gen counts releases of the
     // arena, which invalidate graphs recorded before them
@@ -432,6 +432,16 @@ void rescale_prep(const fr_ctx *c, u64 *Y, const u64 *xtop, int level, int npoly
 // out[p][i] = (in[p][i] - Y[p][i]) q_level^-1
 void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int level, int npoly,
                     size_t so, size_t si, size_t sy);
+// the hoisted product's MAC with its baby steps i >= 1 formed inside it
+// from the ModUp digit set D (items sd words apart), c0 (queries C, sc
+// words apart, [2][level+1][N]) and the keys ksk[i] / Galois elements g[i]
+// (i = 1 .. n1-1); baby0[q] is baby step 0 ([2][nE][N]).  Outputs as
+// bsgs_mac over Q_level U P (nE limbs).  Only where bsgs_ksmac_ok holds:
+// n1 <= 32, ell = 16 n1, at most 3 digits, keys packed like the diagonals.
+bool bsgs_ksmac_ok(const fr_ctx *c, int level, int n1, int ell, const DbLayout &lay);
+void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+                const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D, size_t sd,
+                const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g, int level);
 // fused plaintext-diagonal multiply-accumulate of all giant steps for nq
 // queries: baby[q * n1 + i] is baby step i of query q, diag[q] the diagonal
 // group it is scored against (queries sharing a group should be adjacent);

@@ -1018,6 +1018,201 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
                             accumulate, lds);
 }
 
+// The hoisted product's baby steps formed inside the MAC (Eq. bsgs2 with
+// the key inner products of the hoisted rotations, §3.4.2): the words of
+// baby step i >= 1 are never written to memory.  A block's 128 outputs
+// k0 .. k0+127 of limb m take their sources, under every rotation, from
+// one aligned 128-word block S0 .. S0+127 (the automorphism maps aligned
+// 128-word blocks onto aligned 128-word blocks), so a stage carries, after
+// the NJ diagonal slices, that block of each of the ND ModUp digits and of
+// c0, and the 2 ND key slices of the outputs (digit t, part b then a).
+// Lane (k, c) forms
+//   b = [sum_t D_t[m][s] ksk_{i,t,c}[m][k] + (c = 0, m <= l) P c0[m][s]] 2^-64 mod q_m
+// with s = auto_src(k, g_i): the word the separate key inner product writes
+// for the baby step (same exact sum, same reduction), then accumulates it
+// against the diagonals as the MAC does.  Baby step 0 (P times the query)
+// is read from memory.  One launch covers n1 <= 32 baby steps, every giant
+// step of the tile inside the matrix (NJ = 16), packed or 64-bit limbs.
+struct KsMacSrc {
+    const u64 *baby0[kMacQ];           // baby step 0 of each query: [2][nE][N]
+    const unsigned char *diag[kMacQ];  // diagonal group of each query
+    const unsigned char *ksk[32];      // key of baby step i (i >= 1)
+    u64 g[32];                         // Galois element of baby step i
+};
+// A stage is made of whole 1 KiB chunks, each filled by one wave-wide
+// global-to-LDS load (lane l: bytes 16 l .. 16 l + 15) and each holding one
+// kind of word, so the wave that loads a chunk takes one scalar branch:
+//   diagonals: packed: 8 chunks of low words (slices 2c, 2c+1), 2 chunks of
+//     high bytes (8 slices each); 64-bit: one chunk per slice;
+//   then, for baby step 0: its c0 and c1 slices; for baby step i >= 1: the
+//     ND digit blocks, the c0 block, and the key slices (digit t's parts b
+//     and a at slices 2t, 2t+1): packed: ND chunks of low words and one of
+//     high bytes; 64-bit: one chunk per slice.
+template <int NJ, bool PK, int ND>
+struct KsMacShape {
+    static constexpr int CDL = PK ? NJ / 2 : NJ;              // chunks of diagonal low words / 64-bit slices
+    static constexpr int CD = PK ? CDL + NJ / 8 : NJ;         // diagonal chunks
+    static constexpr int CX = PK ? 2 * ND + 2 : 3 * ND + 1;   // chunks of a baby step i >= 1
+    static constexpr int NCH = CD + CX;
+    static constexpr int STG = NCH * 1024;
+    static_assert(NJ % 8 == 0 && CX >= 2, "chunk layout");
+};
+template <int NJ, bool PK, int ND>
+constexpr int ksmac_stage_bytes() {
+    return KsMacShape<NJ, PK, ND>::STG;
+}
+template <int NJ, bool PK, int ND>
+__device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks, int q, int tile, int m, int nb,
+                                           int n1, size_t dstride, unsigned loff, const u64 *D, size_t sd,
+                                           const u64 *C, size_t sc, unsigned koff, size_t kblock, int nE, int lq,
+                                           int logN, int N, u64 pm, const ModConst &mc, unsigned char *lds) {
+    using S = KsMacShape<NJ, PK, ND>;
+    constexpr int STG = S::STG, RX = S::CD * 1024;
+    const int t = threadIdx.x, lane = t & 63, p = lane >> 5;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int kk = wv * 32 + (lane & 31), k0 = tile * (kT / 2), k = k0 + kk;
+    const unsigned char *base = ks.diag[q] + loff;
+    const size_t jstride = (size_t)n1 * dstride;
+    P += q * pq;
+    const unsigned char *Db = reinterpret_cast<const unsigned char *>(D + q * sd);
+    const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C + q * sc);
+    const unsigned char *B0 = reinterpret_cast<const unsigned char *>(ks.baby0[q]);
+    auto dma = [&](int ii, int b) {
+        unsigned char *dst = lds + b * STG;
+        const u32 S0 = ii ? auto_src((u32)k0, ks.g[ii], logN) & ~127u : 0u;
+        const unsigned char *kl0 = ks.ksk[ii] + koff;
+        const unsigned char *drow = base + (size_t)ii * dstride;
+#pragma unroll
+        for (int c = wv; c < S::NCH; c += kT / 64) {
+            const void *src = nullptr;
+            if (c < S::CD) {
+                if (PK) {
+                    if (c < S::CDL)
+                        src = drow + (2 * c + (lane >> 5)) * jstride + 4 * (size_t)k0 + 16 * (lane & 31);
+                    else
+                        src = drow + (8 * (c - S::CDL) + (lane >> 3)) * jstride + 4 * (size_t)N + k0 + 16 * (lane & 7);
+                } else {
+                    src = drow + c * jstride + 8 * (size_t)k0 + 16 * lane;
+                }
+            } else {
+                const int x = c - S::CD;
+                if (ii == 0) {
+                    if (x < 2) src = B0 + (((size_t)x * nE + m) * N + k0) * 8 + 16 * lane;
+                } else if (x < ND) {
+                    src = Db + (((size_t)x * nE + m) * N + S0) * 8 + 16 * lane;
+                } else if (x == ND) {
+                    if (m <= lq) src = Cb + ((size_t)m * N + S0) * 8 + 16 * lane;
+                } else if (PK) {
+                    const int kx = x - ND - 1;
+                    if (kx < ND)
+                        src = kl0 + (size_t)(2 * kx + (lane >> 5)) * kblock + 4 * (size_t)k0 + 16 * (lane & 31);
+                    else if (lane < 2 * ND * 8)
+                        src = kl0 + (size_t)(lane >> 3) * kblock + 4 * (size_t)N + k0 + 16 * (lane & 7);
+                } else {
+                    src = kl0 + (size_t)(x - ND - 1) * kblock + 8 * (size_t)k0 + 16 * lane;
+                }
+            }
+            if (src)
+                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16,
+                                                 0, kCachePolicyNT);
+        }
+    };
+    // this lane's word of baby step ii (stage ii & 1); a c0 block left
+    // unloaded (limbs past l) only meets the weight 0
+    auto baby = [&](int ii) -> u64 {
+        const unsigned char *x = lds + (ii & 1) * STG + RX;
+        if (ii == 0) return reinterpret_cast<const u64 *>(x + p * 1024)[kk];
+        const u32 S0 = auto_src((u32)k0, ks.g[ii], logN) & ~127u;
+        const u32 r = auto_src((u32)k, ks.g[ii], logN) - S0;
+        const unsigned char *kx = x + (ND + 1) * 1024;
+        Dot30 s;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            u32 y0, y1;
+            split30(reinterpret_cast<const u64 *>(x + d * 1024)[r], y0, y1);
+            const int li = 2 * d + p;
+            const u64 w = PK ? ((u64)reinterpret_cast<const u32 *>(kx + li * 512)[kk] |
+                                ((u64)kx[ND * 1024 + li * 128 + kk] << 32))
+                             : reinterpret_cast<const u64 *>(kx + li * 1024)[kk];
+            s.add(y0, y1, w);
+        }
+        u32 c00, c01;
+        split30(reinterpret_cast<const u64 *>(x + ND * 1024)[r], c00, c01);
+        s.add(c00, c01, p == 0 ? pm : 0);
+        return s.redc(mc);
+    };
+    auto publish = [&]() {
+        __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0)
+        __syncthreads();
+    };
+    dma(0, 0);
+    if constexpr (PK) {
+        u64 A[NJ], Bm[NJ];
+        u32 Dh[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) A[jj] = Bm[jj] = 0, Dh[jj] = 0;
+        for (int ii = 0; ii < nb; ++ii) {
+            publish();
+            if (ii + 1 < nb) dma(ii + 1, (ii + 1) & 1);
+            const u64 b = baby(ii);
+            const unsigned char *st = lds + (ii & 1) * STG;
+            const u32 b0 = (u32)b & 0x7ffffffu, b1 = (u32)(b >> 27) & 0xffffffu, b0s = b0 << 5;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const u32 wl = reinterpret_cast<const u32 *>(st + jj * 512)[kk];
+                const u32 wh = st[S::CDL * 1024 + jj * 128 + kk];
+                A[jj] += (u64)b0 * wl;
+                Bm[jj] += (u64)b1 * wl;
+                Bm[jj] += (u64)b0s * wh;
+                Dh[jj] += b1 * wh;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const unsigned __int128 x =
+                (unsigned __int128)A[jj] + ((unsigned __int128)Bm[jj] << 27) + ((unsigned __int128)Dh[jj] << 59);
+            A[jj] = (u64)x;
+            Bm[jj] = (u64)(x >> 64);
+        }
+        mac3_store<NJ>(P, A, Bm, 0, NJ, p, nE - 1, m, N, k, mc, 0);
+    } else {
+        unsigned __int128 acc[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0;
+        for (int ii = 0; ii < nb; ++ii) {
+            publish();
+            if (ii + 1 < nb) dma(ii + 1, (ii + 1) & 1);
+            const u64 b = baby(ii);
+            const unsigned char *st = lds + (ii & 1) * STG;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj)
+                acc[jj] += (unsigned __int128)b * reinterpret_cast<const u64 *>(st + jj * 1024)[kk];
+        }
+        u64 lo[NJ], hi[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) lo[jj] = (u64)acc[jj], hi[jj] = (u64)(acc[jj] >> 64);
+        mac3_store<NJ>(P, lo, hi, 0, NJ, p, nE - 1, m, N, k, mc, 0);
+    }
+}
+
+template <int NJ, bool PK, int ND>
+__global__ __launch_bounds__(kT) void k_bsgs_ksmac(u64 *P, size_t pq, KsMacSrc ks, int nq, int nb, int n1,
+                                                   size_t dstride, DbLayout lay, KeyLayout kl, const u64 *D,
+                                                   size_t sd, const u64 *C, size_t sc, int nE, int lq, int pofs,
+                                                   int logN, int N, const ModConst *mods, const u64 *pmont,
+                                                   unsigned sel) {
+    __shared__ __align__(16) unsigned char lds[2 * ksmac_stage_bytes<NJ, PK, ND>()];
+    int q, tile;
+    item_tile(blockIdx.x, nq, N / (kT / 2), q, tile);
+    for (unsigned y = blockIdx.y; y; --y) sel &= sel - 1;
+    const int m = __builtin_ctz(sel);
+    const int gm = m <= lq ? m : m + pofs;
+    const ModConst mc = mods[gm];
+    const u64 pm = m <= lq ? pmont[m] : 0;
+    ksmac_body<NJ, PK, ND>(P, pq, ks, q, tile, m, nb, n1, dstride, lay.off[m], D, sd, C, sc, kl.off[gm], kl.block,
+                           nE, lq, logN, N, pm, mc, lds);
+}
+
 // 64-bit limbs <-> the packed diagonal layout (grid: N / kT, nl, nd)
 __global__ __launch_bounds__(kT) void k_db_pack(unsigned char *dst, size_t dstride, DbLayout lay, const u64 *src,
                                                 int nl, int N) {
@@ -1566,6 +1761,63 @@ static void bsgs_mac_nj(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *ba
             }
         }
     }
+}
+
+bool bsgs_ksmac_ok(const fr_ctx *c, int level, int n1, int ell, const DbLayout &lay) {
+    const int nE = level + 1 + c->nP, ndig = (level + c->alpha) / c->alpha;
+    if (n1 < 2 || n1 > 32 || ell != 16 * n1 || ndig < 1 || ndig > 3 || c->N < kT) return false;
+    for (int m = 0; m < nE; ++m) {
+        const int gm = m <= level ? m : c->L + 1 + (m - level - 1);
+        if ((lay.packed[m] != 0) != (c->klay.packed[gm] != 0)) return false;
+    }
+    return true;
+}
+
+template <int ND>
+static void bsgs_ksmac_nd(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+                          const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D,
+                          size_t sd, const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g,
+                          int level) {
+    const int nE = level + 1 + c->nP;
+    double dbytes = 0.0;  // bytes of one diagonal's limbs
+    for (int m = 0; m < nE; ++m) dbytes += (lay.packed[m] ? 5.0 : 8.0) * c->N;
+    for (int q0 = 0; q0 < nq; q0 += kMacQ) {
+        const int qn = std::min(kMacQ, nq - q0);
+        KsMacSrc ks{};
+        int ngroups = 0;
+        for (int qq = 0; qq < qn; ++qq) {
+            ks.baby0[qq] = baby0[q0 + qq];
+            ks.diag[qq] = diag[q0 + qq];
+            ngroups += qq == 0 || diag[q0 + qq] != diag[q0 + qq - 1];
+        }
+        for (int i = 1; i < n1; ++i) ks.ksk[i] = ksk[i], ks.g[i] = g[i];
+        ks.ksk[0] = ks.ksk[1];
+        // algorithmic bytes: every diagonal of the groups once, each query's
+        // digit set, c0, baby step 0 and outputs once, every key once
+        ProfScope ps(c, K_MAC,
+                     dbytes * ngroups * 16.0 * n1 +
+                         8.0 * c->N * qn * (ND * nE + (level + 1.0) + 2.0 * nE + 2.0 * 16 * nE) +
+                         (n1 - 1) * 2.0 * ND * key_limb_bytes(c, level));
+        for (int pk = 1; pk >= 0; --pk) {
+            unsigned sel = 0;
+            int nsel = 0;
+            for (int m = 0; m < nE; ++m)
+                if ((lay.packed[m] != 0) == (pk != 0)) sel |= 1u << m, ++nsel;
+            if (!nsel) continue;
+            auto kern = pk ? k_bsgs_ksmac<16, true, ND> : k_bsgs_ksmac<16, false, ND>;
+            hipLaunchKernelGGL(kern, dim3(c->N / (kT / 2) * qn, nsel, 1), dim3(kT), 0, c->stream, P + q0 * pq, pq, ks,
+                               qn, n1, n1, dstride, lay, c->klay, D + q0 * sd, sd, C + q0 * sc, sc, nE, level,
+                               c->L - level, c->logN, c->N, c->d_mod, pmont_tab(c), sel);
+        }
+    }
+}
+
+void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+                const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D, size_t sd,
+                const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g, int level) {
+    const int ndig = (level + c->alpha) / c->alpha;
+    auto f = ndig == 1 ? bsgs_ksmac_nd<1> : ndig == 2 ? bsgs_ksmac_nd<2> : bsgs_ksmac_nd<3>;
+    f(c, P, pq, baby0, nq, n1, diag, dstride, lay, D, sd, C, sc, ksk, g, level);
 }
 
 // giant steps per thread: 16, or the smallest power of two covering n2

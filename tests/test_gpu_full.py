@@ -102,6 +102,35 @@ def test_full_hoisted_bitexact(F, gctx, config2):
     assert np.max(np.abs(dec[len(exact):])) <= 2 ** -20
 
 
+@pytest.mark.timeout(900)
+def test_tuning_knobs_keep_the_words(F, gctx, config2):
+    """The tuning knobs choose launches only: with every knob away from its
+    default (each NTT pass always / never in its 4-word form, the ModUp
+    always / never merged over the digits, the Chebyshev groups in recorded
+    or critical-first order, the baby steps written by their own launch or
+    formed inside the MAC) the hoisted product and the Chebyshev step at
+    d1 = 8 give the oracle's words."""
+    g, c = gctx, config2
+    gdb = c["gdb"].extend()
+    os_ = c["o"].bsgs_matvec_hoisted(c["ko"], c["oq"], c["odb"], 0)
+    coeffs = F.cheb_step_coeffs(63, 0.3)
+    oy = c["o"].chebyshev(c["ko"], os_, coeffs, 8)
+    ntt = ("ntt_fwd_cols4", "ntt_fwd_rows4", "ntt_inv_rows4", "ntt_inv_cols4")
+    settings = [dict({k: 0 for k in ntt}, modup_merge=48, cheb_sched=0, ksmac=0),
+                dict({k: 1 << 20 for k in ntt}, modup_merge=0, cheb_sched=1, ksmac=1)]
+    start = g.tune_state()
+    try:
+        for kn in settings:
+            for k, v in kn.items():
+                g.set_tune(k, v)
+            gs = g.bsgs_matvec_hoisted(c["kg"], c["gq"], gdb, 0)
+            _same(g, gs, os_)
+            _same(g, g.chebyshev_eval(c["kg"], gs, coeffs, 8), oy)
+    finally:
+        for k, v in start.items():
+            g.set_tune(k, v)
+
+
 def test_full_size_encoder_within_one(F, gctx, config2):
     """Device encoder of the pre-rotated diagonals vs the oracle's, sampled diagonals."""
     g, c = gctx, config2

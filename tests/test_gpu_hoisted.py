@@ -65,10 +65,17 @@ def H(oracle_mod):
     return dict(fr=fr, g=g, o=o, kg=kg, ko=ko, wl=wl, odb=odb, gdb=gdb, Q=Q, gq=gq, oq=oq)
 
 
-@pytest.mark.parametrize("q,group", [(0, 0), (3, 1)])
-def test_hoisted_bitexact_paper_chain(H, q, group):
+@pytest.mark.parametrize("q,group,ksmac", [(0, 0, 1), (3, 1, 1), (3, 1, 0)])
+def test_hoisted_bitexact_paper_chain(H, q, group, ksmac):
+    """ksmac 1: baby steps formed inside the MAC; 0: written by the key
+    inner product launch and read back."""
     g, o = H["g"], H["o"]
-    gs = g.bsgs_matvec_hoisted(H["kg"], H["gq"][q], H["gdb"], group)
+    keep = g.get_tune("ksmac")
+    g.set_tune("ksmac", ksmac)
+    try:
+        gs = g.bsgs_matvec_hoisted(H["kg"], H["gq"][q], H["gdb"], group)
+    finally:
+        g.set_tune("ksmac", keep)
     os_ = o.bsgs_matvec_hoisted(H["ko"], H["oq"][q], H["odb"], group)
     _same_oracle(g, gs, os_)
     dec = g.decrypt_decode(H["kg"], gs)

@@ -224,15 +224,22 @@ def deep(F, oracle_mod):
     return (g, o), (g.keygen(seed, [1, 2, 3]), o.keygen(seed, [1, 2, 3]))
 
 
-@pytest.mark.parametrize("d1", [2, 8])
-def test_chebyshev_bitexact(deep, oracle_mod, d1):
+@pytest.mark.parametrize("d1,sched", [(2, 1), (8, 1), (8, 0)])
+def test_chebyshev_bitexact(deep, oracle_mod, d1, sched):
+    """Degree 63 on the deep chain, both launch-group orders (sched 0: as
+    recorded, 1: critical-first)."""
     pair, keys = deep
     g, o = pair
     rnd = np.random.default_rng(7)
     x = np.concatenate([rnd.uniform(-1, 1, g.N // 2 - 6), [0.29, 0.31, -1.0, 1.0, 0.0, 0.3]])
     gct, oct_ = _enc_pair(pair, keys, x, g.L - 1, 2.0 ** 40, 21)
     c = oracle_mod.cheb_step_coeffs(63, 0.3)
-    gy = g.chebyshev_eval(keys[0], gct, c, d1)
+    keep = g.get_tune("cheb_sched")
+    g.set_tune("cheb_sched", sched)
+    try:
+        gy = g.chebyshev_eval(keys[0], gct, c, d1)
+    finally:
+        g.set_tune("cheb_sched", keep)
     oy = o.chebyshev(keys[1], oct_, c, d1)
     _same(g, gy, oy)
     want = np.polynomial.chebyshev.chebval(x, c)
