@@ -801,8 +801,10 @@ def main():
                                f"(d1={args.d1}); RNS-CKKS N=2^16, Q=60+14x40 bits, P=5x60 bits, dnum=3, "
                                "scale 2^40", "templates": s["K"], "dim": s["ell"], "ring_dim": ctx.N,
                    "form": "plain, one query at a time",
-                   "route": ("baby steps held over Q_l U P; inner sums' first polynomials rotated and summed "
-                             "before one ModDown, one ModDown per second polynomial" if args.route == "hoisted"
+                   "route": (("baby steps held over Q_l U P" +
+                              (" and formed inside the MAC" if ctx.get_tune("ksmac") else "") +
+                              "; inner sums' first polynomials rotated and summed before one ModDown, one ModDown "
+                              "per second polynomial") if args.route == "hoisted"
                              else "hoisted rotations with one ModDown each, then the product")},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
@@ -837,7 +839,10 @@ def main():
         log("graph form ...")
         out["graph"] = graph_form(s, args.d1, args.steps)
     out["roofline_ks"] = hook_roofline(s, args.d1, "ks_inner", "key-switch inner product (k_ks_inner, k_ks_inner_sum)")
-    out["roofline_mac"] = hook_roofline(s, args.d1, "mac", "plaintext-diagonal MAC (k_bsgs_mac3)")
+    fused = args.route == "hoisted" and ctx.get_tune("ksmac") > 0
+    out["roofline_mac"] = hook_roofline(
+        s, args.d1, "mac", "plaintext-diagonal MAC with the baby steps' key inner products (k_bsgs_ksmac)" if fused
+        else "plaintext-diagonal MAC (k_bsgs_mac3)")
     if args.breakdown:
         ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev3[0].record(stream)

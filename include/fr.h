@@ -129,10 +129,11 @@ int fr_ctx_reserve(fr_ctx *ctx, uint64_t bytes);
  *   scalar family, products, additions.  1: level adjustments and scalar
  *   multiples at the latest depth before their first consumer, and the
  *   groups of a depth issued longest remaining path first.
- * - FR_TUNE_KSMAC (0 or 1): 1 = the hoisted product forms its baby steps
- *   inside the diagonal MAC (never written to memory) where the shape
- *   allows (n1 <= 32, ell = 16 n1, at most 3 digits); 0 = a key inner
- *   product launch writes them and the MAC reads them.
+ * - FR_TUNE_KSMAC (0..2): where the shape allows (n1 <= 32, ell = 16 n1, at
+ *   most 3 digits), the hoisted product forms its baby steps inside the
+ *   diagonal MAC (never written to memory): 0 never (a key inner product
+ *   launch writes them and the MAC reads them), 1 for chunks of one query,
+ *   2 for every chunk.
  * FR_EINVAL for an unknown knob or a value out of range, and while a graph
  * capture is in progress. */
 enum {

@@ -39,7 +39,7 @@ DEFAULT_SPACE = {
     "ntt_inv_cols4": NTT_CANDIDATES,
     "modup_merge": (3, 6, 12, 24, 48),
     "cheb_sched": (0, 1),
-    "ksmac": (0, 1),
+    "ksmac": (0, 1, 2),
 }
 BATCH_SPACE = {"matvec_chunk": (2, 4, 8, 16), "cheb_chunk": (2, 4, 8, 16)}
 

@@ -742,7 +742,7 @@ extern "C" int fr_ctx_set_tune(fr_ctx *c, int32_t knob, int32_t value) {
     CHECK(c, FR_EINVAL, "null context");
     CHECK(knob >= 0 && knob < FR_TUNE_COUNT, FR_EINVAL, "fr_ctx_set_tune: unknown knob %d", knob);
     static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1, 0, 0};
-    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16, 1, 1};
+    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16, 1, 2};
     CHECK(value >= lo[knob] && value <= hi[knob], FR_EINVAL, "fr_ctx_set_tune: knob %d takes %d..%d, not %d", knob,
           lo[knob], hi[knob], value);
     CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_tune: a graph capture is in progress");
@@ -1895,7 +1895,7 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
         u64 *P = scratch(c, (size_t)qn * n2 * pw);
         std::vector<const unsigned char *> dp(qn);
         for (int qq = 0; qq < qn; ++qq) dp[qq] = diag_of(order[q0 + qq]);
-        const bool fused = c->tune[FR_TUNE_KSMAC] && frk::bsgs_ksmac_ok(c, l, n1, ell, db0->lay);
+        const bool fused = c->tune[FR_TUNE_KSMAC] > (qn > 1 ? 1 : 0) && frk::bsgs_ksmac_ok(c, l, n1, ell, db0->lay);
         if (fused) {
             // baby step 0 (P times the query) in memory, the others formed
             // inside the MAC from the digit set, c0 and their keys

@@ -1062,7 +1062,7 @@ constexpr int ksmac_stage_bytes() {
     return KsMacShape<NJ, PK, ND>::STG;
 }
 template <int NJ, bool PK, int ND>
-__device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks, int q, int tile, int m, int nb,
+__device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks, int nq, int q, int tile, int m, int nb,
                                            int n1, size_t dstride, unsigned loff, const u64 *D, size_t sd,
                                            const u64 *C, size_t sc, unsigned koff, size_t kblock, int nE, int lq,
                                            int logN, int N, u64 pm, const ModConst &mc, unsigned char *lds) {
@@ -1112,9 +1112,14 @@ __device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks
                     src = kl0 + (size_t)(x - ND - 1) * kblock + 8 * (size_t)k0 + 16 * lane;
                 }
             }
-            if (src)
-                __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst + c * 1024), 16,
-                                                 0, kCachePolicyNT);
+            if (!src) continue;
+            auto *d = (__attribute__((address_space(3))) void *)(dst + c * 1024);
+            // the diagonals and keys are read once: non-temporal for one
+            // query; the digit and c0 blocks come back under every rotation
+            if (nq == 1 && (c < S::CD || c > S::CD + ND))
+                __builtin_amdgcn_global_load_lds(src, d, 16, 0, kCachePolicyNT);
+            else
+                __builtin_amdgcn_global_load_lds(src, d, 16, 0, 0);
         }
     };
     // this lane's word of baby step ii (stage ii & 1); a c0 block left
@@ -1209,7 +1214,7 @@ __global__ __launch_bounds__(kT) void k_bsgs_ksmac(u64 *P, size_t pq, KsMacSrc k
     const int gm = m <= lq ? m : m + pofs;
     const ModConst mc = mods[gm];
     const u64 pm = m <= lq ? pmont[m] : 0;
-    ksmac_body<NJ, PK, ND>(P, pq, ks, q, tile, m, nb, n1, dstride, lay.off[m], D, sd, C, sc, kl.off[gm], kl.block,
+    ksmac_body<NJ, PK, ND>(P, pq, ks, nq, q, tile, m, nb, n1, dstride, lay.off[m], D, sd, C, sc, kl.off[gm], kl.block,
                            nE, lq, logN, N, pm, mc, lds);
 }
 

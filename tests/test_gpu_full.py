@@ -117,7 +117,7 @@ def test_tuning_knobs_keep_the_words(F, gctx, config2):
     oy = c["o"].chebyshev(c["ko"], os_, coeffs, 8)
     ntt = ("ntt_fwd_cols4", "ntt_fwd_rows4", "ntt_inv_rows4", "ntt_inv_cols4")
     settings = [dict({k: 0 for k in ntt}, modup_merge=48, cheb_sched=0, ksmac=0),
-                dict({k: 1 << 20 for k in ntt}, modup_merge=0, cheb_sched=1, ksmac=1)]
+                dict({k: 1 << 20 for k in ntt}, modup_merge=0, cheb_sched=1, ksmac=2)]
     start = g.tune_state()
     try:
         for kn in settings:

@@ -84,13 +84,20 @@ def test_hoisted_bitexact_paper_chain(H, q, group, ksmac):
     assert np.max(np.abs(dec[: len(exact)] - exact)) <= 2 ** -20
 
 
-def test_hoisted_batch_equals_alone_and_oracle(H):
+@pytest.mark.parametrize("ksmac", [1, 2])
+def test_hoisted_batch_equals_alone_and_oracle(H, ksmac):
     """Ten queries (a full chunk of eight and a ragged chunk of two) over both
     groups of one database, interleaved: each output is the one-query word
-    set; two are checked against the oracle."""
+    set; two are checked against the oracle.  ksmac 2: the chunks' baby
+    steps formed inside the MAC too (1: only one-query chunks)."""
     g, o = H["g"], H["o"]
     groups = [q % 2 for q in range(NQ)]
-    outs = g.bsgs_matvec_hoisted_batch(H["kg"], H["gq"], H["gdb"], groups)
+    keep = g.get_tune("ksmac")
+    g.set_tune("ksmac", ksmac)
+    try:
+        outs = g.bsgs_matvec_hoisted_batch(H["kg"], H["gq"], H["gdb"], groups)
+    finally:
+        g.set_tune("ksmac", keep)
     for q in range(NQ):
         _same_ct(g, outs[q], g.bsgs_matvec_hoisted(H["kg"], H["gq"][q], H["gdb"], groups[q]))
     for q in (4, 9):
