@@ -134,6 +134,9 @@ int fr_ctx_reserve(fr_ctx *ctx, uint64_t bytes);
  *   diagonal MAC (never written to memory): 0 never (a key inner product
  *   launch writes them and the MAC reads them), 1 for chunks of one query,
  *   2 for every chunk.
+ * - FR_TUNE_KS_LDS (0 or 1): 1 = the giant steps' summed key inner products
+ *   (at most 3 digits) copy each giant step's key slices into LDS one step
+ *   ahead by wave-wide 16-byte loads; 0 = per-lane key loads.
  * FR_EINVAL for an unknown knob or a value out of range, and while a graph
  * capture is in progress. */
 enum {
@@ -146,7 +149,8 @@ enum {
     FR_TUNE_CHEB_CHUNK = 6,
     FR_TUNE_CHEB_SCHED = 7,
     FR_TUNE_KSMAC = 8,
-    FR_TUNE_COUNT = 9
+    FR_TUNE_KS_LDS = 9,
+    FR_TUNE_COUNT = 10
 };
 int fr_ctx_set_tune(fr_ctx *ctx, int32_t knob, int32_t value);
 int fr_ctx_get_tune(const fr_ctx *ctx, int32_t knob, int32_t *value);

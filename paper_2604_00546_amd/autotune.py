@@ -13,7 +13,8 @@ variant and the work per launch change, so a choice is a speed decision):
   and one transform cover every digit);
 * the order of the Chebyshev evaluation's launch groups (as recorded, or
   critical-first with level adjustments deferred to their consumers);
-* whether the hoisted product forms its baby steps inside the MAC;
+* whether the hoisted product forms its baby steps inside the MAC, and
+  whether the giant steps' key inner products stage their keys in LDS;
 * the batched forms' queries per chunk (products and Chebyshev passes);
 * the Chebyshev baby-step degree d1 (a call parameter: fewer relinearised
   products against more levels and scalar work).
@@ -40,6 +41,7 @@ DEFAULT_SPACE = {
     "modup_merge": (3, 6, 12, 24, 48),
     "cheb_sched": (0, 1),
     "ksmac": (0, 1, 2),
+    "ks_lds": (0, 1),
 }
 BATCH_SPACE = {"matvec_chunk": (2, 4, 8, 16), "cheb_chunk": (2, 4, 8, 16)}
 

@@ -741,8 +741,8 @@ extern "C" int fr_ctx_set_scratch_limit(fr_ctx *c, uint64_t bytes) try {
 extern "C" int fr_ctx_set_tune(fr_ctx *c, int32_t knob, int32_t value) {
     CHECK(c, FR_EINVAL, "null context");
     CHECK(knob >= 0 && knob < FR_TUNE_COUNT, FR_EINVAL, "fr_ctx_set_tune: unknown knob %d", knob);
-    static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1, 0, 0};
-    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16, 1, 2};
+    static const int lo[FR_TUNE_COUNT] = {0, 0, 0, 0, 0, 1, 1, 0, 0, 0};
+    static const int hi[FR_TUNE_COUNT] = {1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 16, 16, 1, 2, 1};
     CHECK(value >= lo[knob] && value <= hi[knob], FR_EINVAL, "fr_ctx_set_tune: knob %d takes %d..%d, not %d", knob,
           lo[knob], hi[knob], value);
     CHECK(!c->capturing, FR_EINVAL, "fr_ctx_set_tune: a graph capture is in progress");

@@ -218,7 +218,7 @@ struct fr_ctx {
     int *d_flag = nullptr;  // device error flag
     Prof *prof = nullptr;
     // tuning knobs (fr_ctx_set_tune; defaults are measured choices)
-    int tune[FR_TUNE_COUNT] = {32, 32, 48, 48, 12, 8, 8, 1, 1};
+    int tune[FR_TUNE_COUNT] = {32, 32, 48, 48, 12, 8, 8, 1, 1, 1};
     // graph capture (fr_graph_begin / fr_graph_end): the calls of a capture
     // run on cap_stream in capture mode; arena_gen counts releases of the
     // arena, which invalidate graphs recorded before them

@@ -396,6 +396,14 @@ struct MultiKeys {
 // (and, in the MAC, of diagonals past ell or nj)
 __device__ __align__(16) uint4 g_zero16 = {0u, 0u, 0u, 0u};
 
+// cache-policy operand of a global-to-LDS load: non-temporal.  A one-query
+// MAC streams its words once, and they should not displace what the caches
+// hold for the kernels around it; with several queries per launch the
+// blocks of one tile share it through the L2, and the default policy is
+// kept (measured: 2.84 -> 2.79 ms for the one-query product, 4.00 -> 3.96
+// ms per query batched when the batched launch keeps the default).
+constexpr int kCachePolicyNT = 2;
+
 // A block's 256 sources s map, for every rotation, onto one aligned block
 // of 256 outputs p (P0 ... P0 + 255).  So the key words a rotation needs are
 // whole 256-word slices of its 2 ND key limbs: they are copied from HBM into
@@ -604,6 +612,233 @@ __global__ __launch_bounds__(kT) void k_ks_inner_sum(u64 *__restrict__ U0, u64 *
     else
         ks_inner_sum_body<ND, false>(U0, U1, D, gk, nj, sdj, kl.off[gm], kl.block, p, e, N, logN, nE, ndig, m,
                                      accumulate);
+}
+
+// The same sums with the key words staged through LDS (ND = 1..3): a
+// block's 256 outputs P0 .. P0+255 read, for every giant step, whole
+// 256-word slices of its 2 ND key limbs; they are copied from HBM into one
+// of two LDS stages one giant step ahead by wave-wide 16-byte global-to-LDS
+// loads (the layout of the baby steps' kernel), and the digit words of the
+// next giant step are loaded per lane meanwhile.
+template <int ND, bool PK>
+__device__ __forceinline__ void ks_sum_lds_body(u64 *U0, u64 *U1, const u64 *D, const GiantKeys &gk, int nj,
+                                                size_t sdj, unsigned koff, size_t kblock, u32 P0, int e, int N,
+                                                int logN, int nE, const ModConst &m, int accumulate, bool nt,
+                                                unsigned char *lds) {
+    constexpr int NL = 2 * ND;
+    constexpr int LOP = PK ? 64 : 128;
+    constexpr int TOT = NL * LOP + (PK ? NL * 16 : 0);
+    constexpr int NCH = (TOT + 63) / 64, STG = NCH * 1024;
+    static_assert(STG == ks_multi_stage_bytes<ND, PK>(), "stage stride");
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const u32 p = P0 + t;
+    auto dma = [&](int jj, int st) {
+        const unsigned char *kl0 = gk.ksk[jj] + koff;
+        unsigned char *dst = lds + st * STG;
+#pragma unroll
+        for (int c = wv; c < NCH; c += kT / 64) {
+            const int i = c * 64 + lane;
+            const void *src = &g_zero16;
+            if (i < NL * LOP) {
+                const int li = i / LOP, w = i - li * LOP;
+                src = kl0 + (size_t)li * kblock + (PK ? 4 : 8) * (size_t)P0 + 16 * w;
+            } else if (i < TOT) {
+                const int j = i - NL * LOP, li = j >> 4;
+                src = kl0 + (size_t)li * kblock + 4 * (size_t)N + P0 + 16 * (j & 15);
+            }
+            auto *d = (__attribute__((address_space(3))) void *)(dst + c * 1024);
+            if (nt)
+                __builtin_amdgcn_global_load_lds(src, d, 16, 0, kCachePolicyNT);
+            else
+                __builtin_amdgcn_global_load_lds(src, d, 16, 0, 0);
+        }
+    };
+    auto digits = [&](int jj, u64 (&d)[ND]) {
+        const u32 src = auto_src(p, gk.g[jj], logN);
+        const u64 *Dj = D + jj * sdj;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) d[i] = Dj[((size_t)i * nE + e) * N + src];
+    };
+    unsigned __int128 t0 = 0, t1 = 0;
+    u64 d[ND];
+    dma(0, 0);
+    digits(0, d);
+    for (int jj = 0; jj < nj; ++jj) {
+        __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's stage jj and digit words
+        __syncthreads();                      // every wave's, and every wave done with stage jj - 1
+        u32 d0[ND], d1[ND];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) split30(d[i], d0[i], d1[i]);
+        if (jj + 1 < nj) {
+            dma(jj + 1, (jj + 1) & 1);
+            digits(jj + 1, d);
+        }
+        const unsigned char *st = lds + (jj & 1) * STG;
+        auto kw = [&](int li) -> u64 {
+            if (PK)
+                return (u64)reinterpret_cast<const u32 *>(st + li * 1024)[t] |
+                       ((u64)st[NL * 1024 + li * 256 + t] << 32);
+            return reinterpret_cast<const u64 *>(st + li * 2048)[t];
+        };
+        Dot30 s0, s1;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+            s0.add(d0[i], d1[i], kw(2 * i));
+            s1.add(d0[i], d1[i], kw(2 * i + 1));
+        }
+        t0 += s0.total();
+        t1 += s1.total();
+    }
+    u64 u0 = redc_any((u64)t0, (u64)(t0 >> 64), m), u1 = redc_any((u64)t1, (u64)(t1 >> 64), m);
+    const size_t w = (size_t)e * N + p;
+    if (accumulate) {
+        u0 = addq(u0, U0[w], m.q);
+        u1 = addq(u1, U1[w], m.q);
+    }
+    U0[w] = u0;
+    U1[w] = u1;
+}
+
+template <int ND>
+__global__ __launch_bounds__(kT) void k_ks_inner_sum_lds(u64 *__restrict__ U0, u64 *__restrict__ U1,
+                                                         const u64 *__restrict__ D, GiantKeys gk, KeyLayout kl, int nj,
+                                                         size_t sdj, int N, int logN, int nE, int level, int pbase,
+                                                         const ModConst *__restrict__ mods, int accumulate, size_t sd,
+                                                         size_t su, int batch) {
+    __shared__ __align__(16) unsigned char lds[2 * ks_multi_stage_bytes<ND, false>()];
+    int item, tile;
+    item_tile(blockIdx.x, batch, N / kT, item, tile);
+    const int e = blockIdx.y;
+    D += item * sd;
+    U0 += item * su;
+    U1 += item * su;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    const u32 P0 = tile * kT;
+    if (kl.packed[gm])
+        ks_sum_lds_body<ND, true>(U0, U1, D, gk, nj, sdj, kl.off[gm], kl.block, P0, e, N, logN, nE, m, accumulate,
+                                  batch == 1, lds);
+    else
+        ks_sum_lds_body<ND, false>(U0, U1, D, gk, nj, sdj, kl.off[gm], kl.block, P0, e, N, logN, nE, m, accumulate,
+                                   batch == 1, lds);
+}
+
+// k_ks_inner with the key words staged through LDS (ND = 1..3): one key
+// serves every item of the batch (a relinearisation wave, a batch of
+// rotations by one element), so a block takes one tile of 256 outputs for
+// all items: the tile's 2 ND key slices are copied into LDS once by
+// wave-wide 16-byte global-to-LDS loads, then the items' sums follow, with
+// the same epilogue (accumulation, fold, c0 term) as k_ks_inner.
+template <int ND, bool PK>
+__device__ __forceinline__ void ks_inner_lds_body(u64 *U0, u64 *U1, const u64 *D, const unsigned char *kl0,
+                                                  size_t kblock, u64 g, u32 P0, int e, int N, int logN, int nE,
+                                                  int level, const ModConst &m, int accumulate, int batch, size_t sd,
+                                                  size_t su, const u64 *fold_d, size_t fold_sd, u64 pinv_top,
+                                                  u64 pinv_top_sh, const u64 *rot_c0, size_t c0_sd, u64 pm,
+                                                  unsigned char *lds) {
+    constexpr int NL = 2 * ND;
+    constexpr int LOP = PK ? 64 : 128;
+    constexpr int TOT = NL * LOP + (PK ? NL * 16 : 0);
+    constexpr int NCH = (TOT + 63) / 64;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const u32 p = P0 + t;
+#pragma unroll
+    for (int c = wv; c < NCH; c += kT / 64) {
+        const int i = c * 64 + lane;
+        const void *src = &g_zero16;
+        if (i < NL * LOP) {
+            const int li = i / LOP, w = i - li * LOP;
+            src = kl0 + (size_t)li * kblock + (PK ? 4 : 8) * (size_t)P0 + 16 * w;
+        } else if (i < TOT) {
+            const int j = i - NL * LOP, li = j >> 4;
+            src = kl0 + (size_t)li * kblock + 4 * (size_t)N + P0 + 16 * (j & 15);
+        }
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(lds + c * 1024), 16, 0, 0);
+    }
+    const u32 src = g == 1 ? p : auto_src(p, g, logN);
+    const bool has_c0 = rot_c0 && e <= level;
+    auto load = [&](int item, u64 (&d)[ND], u64 &c0) {
+#pragma unroll
+        for (int i = 0; i < ND; ++i) d[i] = D[item * sd + ((size_t)i * nE + e) * N + src];
+        c0 = has_c0 ? rot_c0[item * c0_sd + (size_t)e * N + src] : 0;
+    };
+    u64 d[ND], c0;
+    load(0, d, c0);
+    __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's key pieces
+    __syncthreads();                      // every wave's
+    u64 kb[ND], ka[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+        auto kw = [&](int li) -> u64 {
+            if (PK)
+                return (u64)reinterpret_cast<const u32 *>(lds + li * 1024)[t] |
+                       ((u64)lds[NL * 1024 + li * 256 + t] << 32);
+            return reinterpret_cast<const u64 *>(lds + li * 2048)[t];
+        };
+        kb[i] = kw(2 * i);
+        ka[i] = kw(2 * i + 1);
+    }
+    const size_t w = (size_t)e * N + p;
+    for (int item = 0; item < batch; ++item) {
+        u64 dn[ND], cn = 0;
+        if (item + 1 < batch) load(item + 1, dn, cn);
+        Dot30 s0, s1;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+            u32 d0, d1;
+            split30(d[i], d0, d1);
+            s0.add(d0, d1, kb[i]);
+            s1.add(d0, d1, ka[i]);
+        }
+        if (has_c0) {
+            u32 c00, c01;
+            split30(c0, c00, c01);
+            s0.add(c00, c01, pm);
+        }
+        u64 u0 = s0.redc(m), u1 = s1.redc(m);
+        u64 *O0 = U0 + item * su, *O1 = U1 + item * su;
+        if (accumulate) {
+            u0 = addq(u0, O0[w], m.q);
+            u1 = addq(u1, O1[w], m.q);
+        }
+        if (fold_d && e == level) {
+            const u64 *dd = fold_d + item * fold_sd + w;
+            u0 = addq(dd[0], shoup(u0, pinv_top, pinv_top_sh, m.q), m.q);
+            u1 = addq(dd[(size_t)(level + 1) * N], shoup(u1, pinv_top, pinv_top_sh, m.q), m.q);
+        }
+        O0[w] = u0;
+        O1[w] = u1;
+        if (item + 1 < batch) {
+#pragma unroll
+            for (int i = 0; i < ND; ++i) d[i] = dn[i];
+            c0 = cn;
+        }
+    }
+}
+
+template <int ND>
+__global__ __launch_bounds__(kT) void k_ks_inner_lds(u64 *__restrict__ U0, u64 *__restrict__ U1,
+                                                     const u64 *__restrict__ D, const unsigned char *__restrict__ ksk,
+                                                     KeyLayout kl, u64 g, int N, int logN, int nE, int level, int pbase,
+                                                     const ModConst *__restrict__ mods, int accumulate, size_t sd,
+                                                     size_t su, int batch, const u64 *__restrict__ fold_d,
+                                                     size_t fold_sd, u64 pinv_top, u64 pinv_top_sh,
+                                                     const u64 *__restrict__ rot_c0, size_t c0_sd,
+                                                     const u64 *__restrict__ pmont) {
+    __shared__ __align__(16) unsigned char lds[ks_multi_stage_bytes<ND, false>()];
+    const int e = blockIdx.y;
+    const int gm = e <= level ? e : pbase + (e - level - 1);
+    const ModConst m = mods[gm];
+    const u32 P0 = blockIdx.x * kT;
+    const u64 pm = (rot_c0 && e <= level) ? pmont[e] : 0;
+    if (kl.packed[gm])
+        ks_inner_lds_body<ND, true>(U0, U1, D, ksk + kl.off[gm], kl.block, g, P0, e, N, logN, nE, level, m,
+                                    accumulate, batch, sd, su, fold_d, fold_sd, pinv_top, pinv_top_sh, rot_c0, c0_sd,
+                                    pm, lds);
+    else
+        ks_inner_lds_body<ND, false>(U0, U1, D, ksk + kl.off[gm], kl.block, g, P0, e, N, logN, nE, level, m,
+                                     accumulate, batch, sd, su, fold_d, fold_sd, pinv_top, pinv_top_sh, rot_c0, c0_sd,
+                                     pm, lds);
 }
 
 // out[b][i][k] (+)= sum_j in[b][j][i][auto_src(k, g_j)] (first polynomials of
@@ -867,13 +1102,6 @@ __device__ __forceinline__ void mac3_store(u64 *P, const u64 *lo, const u64 *hi,
     }
 }
 
-// cache-policy operand of a global-to-LDS load: non-temporal.  A one-query
-// MAC streams its words once, and they should not displace what the caches
-// hold for the kernels around it; with several queries per launch the
-// blocks of one tile share it through the L2, and the default policy is
-// kept (measured: 2.84 -> 2.79 ms for the one-query product, 4.00 -> 3.96
-// ms per query batched when the batched launch keeps the default).
-constexpr int kCachePolicyNT = 2;
 
 // stage stride of the MAC's LDS tile (NJ diagonal slices and two baby
 // limbs, in whole 1 KiB chunks)
@@ -1581,6 +1809,14 @@ void ks_inner(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigned ch
         pinv = c->P_inv_q[level];
         pinv_sh = c->P_inv_q_sh[level];
     }
+    if (c->tune[FR_TUNE_KS_LDS] && ndig >= 1 && ndig <= 3 && batch > 1) {
+        // one tile of outputs for every item: the key read once per tile
+        auto kern = ndig == 1 ? k_ks_inner_lds<1> : ndig == 2 ? k_ks_inner_lds<2> : k_ks_inner_lds<3>;
+        hipLaunchKernelGGL(kern, dim3(c->N / kT, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, c->klay, g, c->N,
+                           c->logN, nE, level, c->L + 1, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
+                           pinv, pinv_sh, rot_c0, c0_sd, pmont_tab(c));
+        return;
+    }
     auto kern = ndig == 1 ? k_ks_inner<1> : ndig == 2 ? k_ks_inner<2> : ndig == 3 ? k_ks_inner<3> : k_ks_inner<0>;
     hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, ksk, c->klay, g, c->N,
                        c->logN, nE, level, c->L + 1, ndig, c->d_mod, (int)accumulate, sd, su, batch, fold_d, fold_sd,
@@ -1654,6 +1890,12 @@ void ks_inner_sum(const fr_ctx *c, u64 *U0, u64 *U1, const u64 *D, const unsigne
     ProfScope ps(c, K_KS,
                  batch * ((double)nj * ndig * nE + (accumulate ? 4.0 : 2.0) * nE) * 8.0 * c->N +
                      2.0 * nj * ndig * key_limb_bytes(c, level));
+    if (c->tune[FR_TUNE_KS_LDS] && ndig >= 1 && ndig <= 3) {
+        auto kern = ndig == 1 ? k_ks_inner_sum_lds<1> : ndig == 2 ? k_ks_inner_sum_lds<2> : k_ks_inner_sum_lds<3>;
+        hipLaunchKernelGGL(kern, dim3(c->N / kT * batch, nE, 1), dim3(kT), 0, c->stream, U0, U1, D, gk, c->klay, nj,
+                           sdj, c->N, c->logN, nE, level, c->L + 1, c->d_mod, (int)accumulate, sd, su, batch);
+        return;
+    }
     auto kern = ndig == 1   ? k_ks_inner_sum<1>
                 : ndig == 2 ? k_ks_inner_sum<2>
                 : ndig == 3 ? k_ks_inner_sum<3>

@@ -322,7 +322,7 @@ class Context:
 
     # tuning knobs ------------------------------------------------------------------
     TUNE_KNOBS = {"ntt_fwd_cols4": 0, "ntt_fwd_rows4": 1, "ntt_inv_rows4": 2, "ntt_inv_cols4": 3,
-                  "modup_merge": 4, "matvec_chunk": 5, "cheb_chunk": 6, "cheb_sched": 7, "ksmac": 8}
+                  "modup_merge": 4, "matvec_chunk": 5, "cheb_chunk": 6, "cheb_sched": 7, "ksmac": 8, "ks_lds": 9}
 
     def set_tune(self, knob: str, value: int):
         _check(lib().fr_ctx_set_tune(self.ptr, self.TUNE_KNOBS[knob], int(value)), "fr_ctx_set_tune")

@@ -108,7 +108,8 @@ def test_tuning_knobs_keep_the_words(F, gctx, config2):
     default (each NTT pass always / never in its 4-word form, the ModUp
     always / never merged over the digits, the Chebyshev groups in recorded
     or critical-first order, the baby steps written by their own launch or
-    formed inside the MAC) the hoisted product and the Chebyshev step at
+    formed inside the MAC, the giant steps' keys staged in LDS or loaded
+    per lane) the hoisted product and the Chebyshev step at
     d1 = 8 give the oracle's words."""
     g, c = gctx, config2
     gdb = c["gdb"].extend()
@@ -116,8 +117,8 @@ def test_tuning_knobs_keep_the_words(F, gctx, config2):
     coeffs = F.cheb_step_coeffs(63, 0.3)
     oy = c["o"].chebyshev(c["ko"], os_, coeffs, 8)
     ntt = ("ntt_fwd_cols4", "ntt_fwd_rows4", "ntt_inv_rows4", "ntt_inv_cols4")
-    settings = [dict({k: 0 for k in ntt}, modup_merge=48, cheb_sched=0, ksmac=0),
-                dict({k: 1 << 20 for k in ntt}, modup_merge=0, cheb_sched=1, ksmac=2)]
+    settings = [dict({k: 0 for k in ntt}, modup_merge=48, cheb_sched=0, ksmac=0, ks_lds=0),
+                dict({k: 1 << 20 for k in ntt}, modup_merge=0, cheb_sched=1, ksmac=2, ks_lds=1)]
     start = g.tune_state()
     try:
         for kn in settings:
