@@ -838,11 +838,12 @@ def main():
     if args.graph:
         log("graph form ...")
         out["graph"] = graph_form(s, args.d1, args.steps)
+    fused = args.route == "hoisted" and ctx.get_tune("ksmac") > 0
     out["roofline_ks"] = hook_roofline(
         s, args.d1, "ks_inner",
-        "key-switch inner product (k_ks_inner, k_ks_inner_lds, k_ks_inner_sum_lds; the baby steps' run inside the MAC)"
-        if ctx.get_tune("ks_lds") else "key-switch inner product (k_ks_inner, k_ks_inner_sum)")
-    fused = args.route == "hoisted" and ctx.get_tune("ksmac") > 0
+        ("key-switch inner product (k_ks_inner, k_ks_inner_lds, k_ks_inner_sum_lds)" if ctx.get_tune("ks_lds")
+         else "key-switch inner product (k_ks_inner, k_ks_inner_sum)") +
+        ("; the baby steps' key inner products run inside the MAC" if fused else ""))
     out["roofline_mac"] = hook_roofline(
         s, args.d1, "mac", "plaintext-diagonal MAC with the baby steps' key inner products (k_bsgs_ksmac)" if fused
         else "plaintext-diagonal MAC (k_bsgs_mac3)")
