@@ -6,7 +6,7 @@ Workload (one "step" = one encrypted query, server side): 2^15 templates x
 scale 2^40.  The paper's packing puts B = N/2 / 512 = 64 blocks of 512 x 512 in
 each plaintext, so the whole database is one group of 512 pre-rotated
 diagonals resident in HBM.  A step is
-  31 hoisted baby-step rotations of the query (n1 = 32),
+  31 hoisted baby-step rotations of the query (n1 = 32), formed inside
   the fused plaintext-diagonal multiply-accumulate of the 16 inner sums,
   16 rescales and the giant-step rotate-sum (n2 = 16),
   the degree-63 Chebyshev threshold at 0.3 on the score ciphertext.
