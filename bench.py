@@ -51,7 +51,7 @@ ROOFLINE_KERNEL = {"class": "ntt", "bound": "alu"}
 # limbs, both passes), from the FETCH_SIZE / WRITE_SIZE counter runs recorded
 # in profiles/ntt_query_2p15_counters.txt; None when the kernels have changed
 # since those counters were taken
-NTT_TRAFFIC_BYTES_PER_LAUNCH = 120179870
+NTT_TRAFFIC_BYTES_PER_LAUNCH = 120250077
 
 
 def log(*a):

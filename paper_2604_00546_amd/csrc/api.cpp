@@ -1897,20 +1897,16 @@ static int matvec_hoisted_impl(fr_ctx *c, const fr_keys *K, const fr_ct *qs, int
         for (int qq = 0; qq < qn; ++qq) dp[qq] = diag_of(order[q0 + qq]);
         const bool fused = c->tune[FR_TUNE_KSMAC] > (qn > 1 ? 1 : 0) && frk::bsgs_ksmac_ok(c, l, n1, ell, db0->lay);
         if (fused) {
-            // baby step 0 (P times the query) in memory, the others formed
-            // inside the MAC from the digit set, c0 and their keys
-            u64 *B0 = scratch(c, (size_t)qn * bw);
-            frk::scale_ext(c, B0, C, l, qn, bw, 2 * lw);
-            std::vector<const u64 *> b0(qn);
-            for (int qq = 0; qq < qn; ++qq) b0[qq] = B0 + qq * bw;
+            // every baby step formed inside the MAC: step 0 from the query,
+            // the others from the digit set, c0 and their keys
             std::vector<const unsigned char *> kp(n1);
             std::vector<u64> gp(n1, 1);
             for (int i = 1; i < n1; ++i) {
                 gp[i] = galois_element(N, i);
                 kp[i] = K->find(gp[i])->data;
             }
-            frk::bsgs_ksmac(c, P, (size_t)n2 * pw, b0.data(), qn, n1, dp.data(), db0->stride, db0->lay, D, dstride,
-                            C, 2 * lw, kp.data(), gp.data(), l);
+            frk::bsgs_ksmac(c, P, (size_t)n2 * pw, qn, n1, dp.data(), db0->stride, db0->lay, D, dstride, C, 2 * lw,
+                            kp.data(), gp.data(), l);
         }
         if (!fused) {
             // baby steps over Q_l U P: [qn][n1][2][nE][N]

@@ -435,11 +435,11 @@ void rescale_finish(const fr_ctx *c, u64 *out, const u64 *in, const u64 *Y, int 
 // the hoisted product's MAC with its baby steps i >= 1 formed inside it
 // from the ModUp digit set D (items sd words apart), c0 (queries C, sc
 // words apart, [2][level+1][N]) and the keys ksk[i] / Galois elements g[i]
-// (i = 1 .. n1-1); baby0[q] is baby step 0 ([2][nE][N]).  Outputs as
+// (i = 1 .. n1-1); baby step 0 (P times the query) from C.  Outputs as
 // bsgs_mac over Q_level U P (nE limbs).  Only where bsgs_ksmac_ok holds:
 // n1 <= 32, ell = 16 n1, at most 3 digits, keys packed like the diagonals.
 bool bsgs_ksmac_ok(const fr_ctx *c, int level, int n1, int ell, const DbLayout &lay);
-void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, int nq, int n1,
                 const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D, size_t sd,
                 const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g, int level);
 // fused plaintext-diagonal multiply-accumulate of all giant steps for nq

@@ -1259,10 +1259,9 @@ __global__ __launch_bounds__(kT) void k_bsgs_mac3(u64 *P, size_t pq, BabyPtrs bp
 // with s = auto_src(k, g_i): the word the separate key inner product writes
 // for the baby step (same exact sum, same reduction), then accumulates it
 // against the diagonals as the MAC does.  Baby step 0 (P times the query)
-// is read from memory.  One launch covers n1 <= 32 baby steps, every giant
+// is formed the same way from the query's words.  One launch covers n1 <= 32 baby steps, every giant
 // step of the tile inside the matrix (NJ = 16), packed or 64-bit limbs.
 struct KsMacSrc {
-    const u64 *baby0[kMacQ];           // baby step 0 of each query: [2][nE][N]
     const unsigned char *diag[kMacQ];  // diagonal group of each query
     const unsigned char *ksk[32];      // key of baby step i (i >= 1)
     u64 g[32];                         // Galois element of baby step i
@@ -1272,7 +1271,7 @@ struct KsMacSrc {
 // kind of word, so the wave that loads a chunk takes one scalar branch:
 //   diagonals: packed: 8 chunks of low words (slices 2c, 2c+1), 2 chunks of
 //     high bytes (8 slices each); 64-bit: one chunk per slice;
-//   then, for baby step 0: its c0 and c1 slices; for baby step i >= 1: the
+//   then, for baby step 0: the query's c0 and c1 slices; for baby step i >= 1: the
 //     ND digit blocks, the c0 block, and the key slices (digit t's parts b
 //     and a at slices 2t, 2t+1): packed: ND chunks of low words and one of
 //     high bytes; 64-bit: one chunk per slice.
@@ -1304,7 +1303,6 @@ __device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks
     P += q * pq;
     const unsigned char *Db = reinterpret_cast<const unsigned char *>(D + q * sd);
     const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C + q * sc);
-    const unsigned char *B0 = reinterpret_cast<const unsigned char *>(ks.baby0[q]);
     auto dma = [&](int ii, int b) {
         unsigned char *dst = lds + b * STG;
         const u32 S0 = ii ? auto_src((u32)k0, ks.g[ii], logN) & ~127u : 0u;
@@ -1325,7 +1323,8 @@ __device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks
             } else {
                 const int x = c - S::CD;
                 if (ii == 0) {
-                    if (x < 2) src = B0 + (((size_t)x * nE + m) * N + k0) * 8 + 16 * lane;
+                    // the query's c0 and c1 slices (limbs up to l)
+                    if (x < 2 && m <= lq) src = Cb + (((size_t)x * (lq + 1) + m) * N + k0) * 8 + 16 * lane;
                 } else if (x < ND) {
                     src = Db + (((size_t)x * nE + m) * N + S0) * 8 + 16 * lane;
                 } else if (x == ND) {
@@ -1354,7 +1353,16 @@ __device__ __forceinline__ void ksmac_body(u64 *P, size_t pq, const KsMacSrc &ks
     // unloaded (limbs past l) only meets the weight 0
     auto baby = [&](int ii) -> u64 {
         const unsigned char *x = lds + (ii & 1) * STG + RX;
-        if (ii == 0) return reinterpret_cast<const u64 *>(x + p * 1024)[kk];
+        if (ii == 0) {
+            // baby step 0 = P times the query: P 2^64 (the weight pm) times
+            // the word, one reduction; 0 on the special primes
+            if (pm == 0) return 0;
+            u32 y0, y1;
+            split30(reinterpret_cast<const u64 *>(x + p * 1024)[kk], y0, y1);
+            Dot30 s0;
+            s0.add(y0, y1, pm);
+            return s0.redc(mc);
+        }
         const u32 S0 = auto_src((u32)k0, ks.g[ii], logN) & ~127u;
         const u32 r = auto_src((u32)k, ks.g[ii], logN) - S0;
         const unsigned char *kx = x + (ND + 1) * 1024;
@@ -2021,7 +2029,7 @@ bool bsgs_ksmac_ok(const fr_ctx *c, int level, int n1, int ell, const DbLayout &
 }
 
 template <int ND>
-static void bsgs_ksmac_nd(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+static void bsgs_ksmac_nd(const fr_ctx *c, u64 *P, size_t pq, int nq, int n1,
                           const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D,
                           size_t sd, const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g,
                           int level) {
@@ -2033,17 +2041,16 @@ static void bsgs_ksmac_nd(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *
         KsMacSrc ks{};
         int ngroups = 0;
         for (int qq = 0; qq < qn; ++qq) {
-            ks.baby0[qq] = baby0[q0 + qq];
             ks.diag[qq] = diag[q0 + qq];
             ngroups += qq == 0 || diag[q0 + qq] != diag[q0 + qq - 1];
         }
         for (int i = 1; i < n1; ++i) ks.ksk[i] = ksk[i], ks.g[i] = g[i];
         ks.ksk[0] = ks.ksk[1];
         // algorithmic bytes: every diagonal of the groups once, each query's
-        // digit set, c0, baby step 0 and outputs once, every key once
+        // digit set, the query and the outputs once, every key once
         ProfScope ps(c, K_MAC,
                      dbytes * ngroups * 16.0 * n1 +
-                         8.0 * c->N * qn * (ND * nE + (level + 1.0) + 2.0 * nE + 2.0 * 16 * nE) +
+                         8.0 * c->N * qn * (ND * nE + 2.0 * (level + 1.0) + 2.0 * 16 * nE) +
                          (n1 - 1) * 2.0 * ND * key_limb_bytes(c, level));
         for (int pk = 1; pk >= 0; --pk) {
             unsigned sel = 0;
@@ -2059,12 +2066,12 @@ static void bsgs_ksmac_nd(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *
     }
 }
 
-void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, const u64 *const *baby0, int nq, int n1,
+void bsgs_ksmac(const fr_ctx *c, u64 *P, size_t pq, int nq, int n1,
                 const unsigned char *const *diag, size_t dstride, const DbLayout &lay, const u64 *D, size_t sd,
                 const u64 *C, size_t sc, const unsigned char *const *ksk, const u64 *g, int level) {
     const int ndig = (level + c->alpha) / c->alpha;
     auto f = ndig == 1 ? bsgs_ksmac_nd<1> : ndig == 2 ? bsgs_ksmac_nd<2> : bsgs_ksmac_nd<3>;
-    f(c, P, pq, baby0, nq, n1, diag, dstride, lay, D, sd, C, sc, ksk, g, level);
+    f(c, P, pq, nq, n1, diag, dstride, lay, D, sd, C, sc, ksk, g, level);
 }
 
 // giant steps per thread: 16, or the smallest power of two covering n2

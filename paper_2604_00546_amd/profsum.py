@@ -41,8 +41,8 @@ def trace(path, steps, calib_mib):
     dur = lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     timed = rows[_calib_index(rows) + 1:]
     if steps <= 0:
-        # one k_scale_ext per hoisted product: the number of queries in the region
-        steps = sum(1 for r in timed if _short(r["Kernel_Name"]) == "k_scale_ext")
+        # one k_automorph_sum per hoisted product: the number of queries in the region
+        steps = sum(1 for r in timed if _short(r["Kernel_Name"]) == "k_automorph_sum")
     agg = collections.defaultdict(lambda: [0, 0])
     for r in timed:
         a = agg[_short(r["Kernel_Name"])]
@@ -143,7 +143,7 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("path")
     t.add_argument("--steps", type=int, default=0,
-                   help="queries in the timed region (default: counted, one k_scale_ext per hoisted product)")
+                   help="queries in the timed region (default: counted, one k_automorph_sum per hoisted product)")
     t.add_argument("--calib-mib", type=int, required=True)
     c = sub.add_parser("counters")
     c.add_argument("fetch")

@@ -36,7 +36,7 @@ def _trace_rows(steps_before, steps_after, with_downloads):
         t += us * 1000 + 500
 
     def query():
-        k("void (anonymous namespace)::k_scale_ext(unsigned long*)", 9, 20, 2)
+        k("void (anonymous namespace)::k_automorph_sum(unsigned long*)", 9, 20, 1)
         k("void (anonymous namespace)::k_fwd_cols2<4>(NttLaunch)", 40, 14, 32)
         k("void (anonymous namespace)::k_fwd_rows2<4, true>(NttLaunch)", 60, 32, 14)
         k("void (anonymous namespace)::k_inv_cols4(NttLaunch)", 10, 1, 2)
